@@ -1,0 +1,189 @@
+"""Dense-matrix schemes on tiny grids, with A and B assembled node by node.
+
+The operators of eq. (AMat) are assembled here directly from Maxwell's curl
+equations on the Yee grid -- one explicit loop over the dynamic nodes, each row
+written from the positions of the two neighbouring samples -- without using the
+vectorized difference code of ``yee``.  The vector u holds the dynamic nodes
+only (static normal H is carried aside; wall E is 0).
+
+Schemes are then the plain matrix formulae of Sec. II:
+  original:    (clsADI), (orgLOD), (orgSS2), (orgLOD2)+(orgLOD2i)+(orgLOD2o)
+  fundamental: (fasterADI)+(fastADIi)+(fasterADIo), (fastLOD), (fastSS2),
+               (fastLOD2)+(fastLOD2i)+(fastLOD2o)
+Every solve is ``numpy.linalg.solve`` on the dense system.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .yee import COMPONENTS, CIDX, EPS0, MU0, Grid, dynamic_mask
+
+
+class DenseSystem:
+    def __init__(self, g: Grid):
+        self.g = g
+        self.index = {}
+        self.nodes = []
+        for c in COMPONENTS:
+            m = dynamic_mask(c, g)
+            for k, j, i in zip(*np.nonzero(m)):
+                self.index[(c, int(k), int(j), int(i))] = len(self.nodes)
+                self.nodes.append((c, int(k), int(j), int(i)))
+        self.n = len(self.nodes)
+        self.A = np.zeros((self.n, self.n))
+        self.B = np.zeros((self.n, self.n))
+        self._assemble()
+        self.w = np.array([self._material(c, k, j, i) for c, k, j, i in self.nodes])
+
+    def _material(self, c, k, j, i):
+        g = self.g
+        kk, jj, ii = min(k, g.nz - 1), min(j, g.ny - 1), min(i, g.nx - 1)
+        if c[0] == "E":
+            return EPS0 * g.eps_r[kk, jj, ii]
+        return MU0 * g.mu_r[kk, jj, ii]
+
+    def _add(self, M, row, comp, k, j, i, val):
+        col = self.index.get((comp, k, j, i))
+        if col is None:
+            # only wall E (which is 0) may be referenced outside the dynamic set
+            assert comp[0] == "E", (comp, k, j, i)
+            return
+        M[row, col] += val
+
+    def _assemble(self):
+        g = self.g
+        dx, dy, dz = g.dx, g.dy, g.dz
+        A, B = self.A, self.B
+        for r, (c, k, j, i) in enumerate(self.nodes):
+            inv = 1.0 / self._material(c, k, j, i)
+            if c == "Ex":   # at (i+1/2, j, k)
+                # A: (1/eps) dHz/dy ; Hz at (i+1/2, j+-1/2, k)
+                self._add(A, r, "Hz", k, j, i, inv / dy)
+                self._add(A, r, "Hz", k, j - 1, i, -inv / dy)
+                # B: -(1/eps) dHy/dz ; Hy at (i+1/2, j, k+-1/2)
+                self._add(B, r, "Hy", k, j, i, -inv / dz)
+                self._add(B, r, "Hy", k - 1, j, i, inv / dz)
+            elif c == "Ey":  # at (i, j+1/2, k)
+                self._add(A, r, "Hx", k, j, i, inv / dz)       # dHx/dz, Hx at (i, j+1/2, k+-1/2)
+                self._add(A, r, "Hx", k - 1, j, i, -inv / dz)
+                self._add(B, r, "Hz", k, j, i, -inv / dx)      # -dHz/dx, Hz at (i+-1/2, j+1/2, k)
+                self._add(B, r, "Hz", k, j, i - 1, inv / dx)
+            elif c == "Ez":  # at (i, j, k+1/2)
+                self._add(A, r, "Hy", k, j, i, inv / dx)       # dHy/dx, Hy at (i+-1/2, j, k+1/2)
+                self._add(A, r, "Hy", k, j, i - 1, -inv / dx)
+                self._add(B, r, "Hx", k, j, i, -inv / dy)      # -dHx/dy, Hx at (i, j+-1/2, k+1/2)
+                self._add(B, r, "Hx", k, j - 1, i, inv / dy)
+            elif c == "Hx":  # at (i, j+1/2, k+1/2)
+                self._add(A, r, "Ey", k + 1, j, i, inv / dz)   # dEy/dz, Ey at (i, j+1/2, k+1/2+-1/2)
+                self._add(A, r, "Ey", k, j, i, -inv / dz)
+                self._add(B, r, "Ez", k, j + 1, i, -inv / dy)  # -dEz/dy, Ez at (i, j+1/2+-1/2, k+1/2)
+                self._add(B, r, "Ez", k, j, i, inv / dy)
+            elif c == "Hy":  # at (i+1/2, j, k+1/2)
+                self._add(A, r, "Ez", k, j, i + 1, inv / dx)   # dEz/dx
+                self._add(A, r, "Ez", k, j, i, -inv / dx)
+                self._add(B, r, "Ex", k + 1, j, i, -inv / dz)  # -dEx/dz
+                self._add(B, r, "Ex", k, j, i, inv / dz)
+            elif c == "Hz":  # at (i+1/2, j+1/2, k)
+                self._add(A, r, "Ex", k, j + 1, i, inv / dy)   # dEx/dy
+                self._add(A, r, "Ex", k, j, i, -inv / dy)
+                self._add(B, r, "Ey", k, j, i + 1, -inv / dx)  # -dEy/dx
+                self._add(B, r, "Ey", k, j, i, inv / dx)
+
+    # -- conversions --------------------------------------------------------
+    def to_vec(self, u) -> np.ndarray:
+        return np.array([u[CIDX[c]][k, j, i] for c, k, j, i in self.nodes])
+
+    def from_vec(self, x: np.ndarray, template) -> list:
+        out = [np.array(a, dtype=np.float64, copy=True) for a in template]
+        for n, c in enumerate(COMPONENTS):
+            if c[0] == "E":
+                out[n][~dynamic_mask(c, self.g)] = 0.0
+        for v, (c, k, j, i) in zip(x, self.nodes):
+            out[CIDX[c]][k, j, i] = v
+        return out
+
+    def op(self, name: str) -> np.ndarray:
+        return {"A": self.A, "B": self.B}[name]
+
+    def src_vec(self, source, val: float) -> np.ndarray:
+        gvec = np.zeros(self.n)
+        if source is not None and val != 0.0:
+            gvec[self.index[("Ez", source.k, source.j, source.i)]] = val
+        return gvec
+
+    def energy(self, x: np.ndarray) -> float:
+        return float(np.sum(self.w * x * x))
+
+
+# ----------------------------------------------------------------------------
+# matrix schemes
+# ----------------------------------------------------------------------------
+
+_ORIG = {  # (X, Y, theta/dt, source time within the step)
+    "adi": (("A", "B", 0.5, 0.25), ("B", "A", 0.5, 0.75)),
+    "lod1": (("A", "A", 0.5, 0.25), ("B", "B", 0.5, 0.75)),
+    "ss2": (("A", "A", 0.25, 0.125), ("B", "B", 0.5, 0.5), ("A", "A", 0.25, 0.875)),
+    "lod2": (("A", "A", 0.5, 0.5), ("B", "B", 0.5, 1.0)),
+}
+
+
+def run_original(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int, source=None):
+    """Original splitting formulae; returns (x at step `steps`, invariant trace)."""
+    g, I = ds.g, np.eye(ds.n)
+    x = x0.copy()
+    if scheme == "lod2":  # (orgLOD2i)
+        th = 0.25 * g.dt
+        x = np.linalg.solve(I - th * ds.B, (I + th * ds.B) @ x)
+    trace = [_invariant_orig(ds, scheme, x)]
+    for n in range(steps):
+        for xo, yo, tf, tt in _ORIG[scheme]:
+            th = tf * g.dt
+            rhs = (I + th * ds.op(yo)) @ x
+            if source is not None:
+                rhs = rhs + ds.src_vec(source, source.g(th, (n + tt) * g.dt))
+            x = np.linalg.solve(I - th * ds.op(xo), rhs)
+        trace.append(_invariant_orig(ds, scheme, x))
+    if scheme == "lod2":  # (orgLOD2o)
+        th = 0.25 * g.dt
+        x = np.linalg.solve(I + th * ds.B, (I - th * ds.B) @ x)
+    return x, trace
+
+
+def _invariant_orig(ds, scheme, x):
+    if scheme == "adi":
+        return 0.25 * ds.energy(x + 0.5 * ds.g.dt * (ds.B @ x))
+    return ds.energy(x)
+
+
+def run_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int, source=None):
+    """Fundamental matrix iterations; returns (x at step `steps`, invariant trace)."""
+    g, I = ds.g, np.eye(ds.n)
+    dt = g.dt
+    if scheme == "adi":
+        # (fastADIi), (uTldCol); iteration (fasterADI); output (fasterADIo)
+        v = (I - 0.5 * dt * ds.B) @ x0          # v^{-1/2}
+        ut = 2.0 * x0
+        trace = [0.25 * ds.energy(ut - v)]
+        for n in range(steps):
+            v = ut - v + ds.src_vec(source, source.g(0.5 * dt, (n + 0.25) * dt) if source else 0.0)
+            ut = np.linalg.solve(0.5 * I - 0.25 * dt * ds.A, v)
+            v = ut - v + ds.src_vec(source, source.g(0.5 * dt, (n + 0.75) * dt) if source else 0.0)
+            ut = np.linalg.solve(0.5 * I - 0.25 * dt * ds.B, v)
+            trace.append(0.25 * ds.energy(ut - v))
+        return 0.5 * ut, trace
+    u = x0.copy()
+    if scheme == "lod2":  # (fastLOD2i)
+        vq = np.linalg.solve(0.5 * I - dt / 8 * ds.B, u)
+        u = vq - u
+    trace = [ds.energy(u)]
+    for n in range(steps):
+        for xo, _, tf, tt in _ORIG[scheme]:
+            th = tf * dt
+            gval = source.g(th, (n + tt) * dt) if source is not None else 0.0
+            v = np.linalg.solve(0.5 * I - 0.5 * th * ds.op(xo), u + 0.5 * ds.src_vec(source, gval))
+            u = v - u
+        trace.append(ds.energy(u))
+    if scheme == "lod2":  # (fastLOD2o)
+        v = np.linalg.solve(0.5 * I + dt / 8 * ds.B, u)
+        u = v - u
+    return u, trace

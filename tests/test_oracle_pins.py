@@ -1,0 +1,276 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+* brute force: numpy.linalg.solve of every tridiagonal and every implicit stage;
+* the dense matrix formulae of Sec. II (operators assembled node by node);
+* closed forms: the PEC cavity modes (exact eigenvectors of the Yee operators)
+  and the closed-form ADI dispersion relation;
+* invariants: skew-adjointness of A and B, exact energy conservation of the
+  Cayley sub-steps, the fundamental == original equivalence (Sec. II-A
+  closing paragraph, Sec. II-B construction), the ADI <-> LOD link (Sec. II-E);
+* the temporal orders of Table I (2, 1, 2, 2).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import dense, yee
+from oracle.implicit import solve_implicit
+from oracle.source import Source
+from oracle.tridiag import thomas
+
+from . import _analytic as an
+
+
+def small_grid(nx=4, ny=3, nz=5, cfl=4.0, seed=0, mu=True, spacing=(1e-3, 1.2e-3, 0.8e-3)):
+    rng = np.random.default_rng(seed)
+    eps = rng.uniform(1, 12, (nz, ny, nx))
+    mur = rng.uniform(1, 3, (nz, ny, nx)) if mu else None
+    dt = yee.cfl_dt(*spacing, cfl)
+    return yee.Grid(nx, ny, nz, *spacing, dt, eps, mur)
+
+
+# --------------------------------------------------------------------------
+# tridiagonal solver
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta", [1 / 24, 4 / 24 * 25, 400 / 24])
+def test_thomas_matches_dense_solve(beta):
+    rng = np.random.default_rng(1)
+    n, lines = 17, 5
+    a = -beta * rng.uniform(0.5, 1.5, (lines, n))
+    c = -beta * rng.uniform(0.5, 1.5, (lines, n))
+    b = 0.5 - a - c  # the fundamental scaling: 1/2 + sum of |off-diagonals|
+    d = rng.standard_normal((lines, n))
+    x = thomas(a, b, c, d)
+    for L in range(lines):
+        M = np.diag(b[L]) + np.diag(a[L, 1:], -1) + np.diag(c[L, :-1], 1)
+        ref = np.linalg.solve(M, d[L])
+        assert np.allclose(x[L], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
+# operators
+# --------------------------------------------------------------------------
+
+def test_dense_operators_skew_adjoint_in_energy_norm():
+    g = small_grid()
+    ds = dense.DenseSystem(g)
+    Wm = np.diag(ds.w)
+    for M in (ds.A, ds.B):
+        assert np.abs(M.T @ Wm + Wm @ M).max() <= 1e-14 * np.abs(Wm @ M).max()
+
+
+@pytest.mark.parametrize("mnp", [(1, 1, 1), (2, 1, 3), (3, 2, 1)])
+def test_operators_on_cavity_mode(mnp):
+    nx, ny, nz, dx, dy, dz = 8, 6, 7, 1e-3, 1.3e-3, 0.9e-3
+    g = yee.Grid(nx, ny, nz, dx, dy, dz, 1e-12)
+    a = np.random.default_rng(2).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, dx, dy, dz, *mnp)
+    u = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, a)
+    ds = dense.DenseSystem(g)
+    for name, M6 in (("A", A6), ("B", B6)):
+        ref = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, M6 @ a)
+        got = yee.apply_operator(name, u, g)
+        for x, y in zip(got, ref):
+            assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-300) + 1e-300
+        gd = ds.op(name) @ ds.to_vec(u)
+        assert np.allclose(gd, ds.to_vec(ref), rtol=1e-12, atol=1e-12 * np.abs(gd).max())
+
+
+# --------------------------------------------------------------------------
+# implicit stages: line elimination vs dense solve
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("op", ["A", "B"])
+@pytest.mark.parametrize("theta_scale", [0.5, 0.25, -0.25])
+def test_implicit_stage_matches_dense(op, theta_scale):
+    g = small_grid(seed=3)
+    ds = dense.DenseSystem(g)
+    theta = theta_scale * g.dt
+    f = W.random_fields(g.nx, g.ny, g.nz, 7)
+    got = solve_implicit(op, yee.PAIRS[op], yee.clean(f, g), theta, g)
+    ref = np.linalg.solve(np.eye(ds.n) - theta * ds.op(op), ds.to_vec(f))
+    assert np.allclose(ds.to_vec(got), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # static normal H untouched
+    for n, c in enumerate(yee.COMPONENTS):
+        if c[0] == "H":
+            st = ~yee.dynamic_mask(c, g)
+            assert np.array_equal(got[n][st], f[n][st])
+
+
+# --------------------------------------------------------------------------
+# whole schemes: component form vs dense matrix formula
+# --------------------------------------------------------------------------
+
+def _src(g):
+    return Source(1, 1, 2, amp=1e12, t0=2 * g.dt, tau=3 * g.dt, f0=1 / (8 * g.dt))
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+@pytest.mark.parametrize("form", oracle.FORMS)
+def test_scheme_matches_dense_formula(scheme, form):
+    g = small_grid(seed=5)
+    ds = dense.DenseSystem(g)
+    u0 = W.random_fields(g.nx, g.ny, g.nz, 11)
+    src = _src(g)
+    x_ref, _ = dense.run_original(ds, scheme, ds.to_vec(u0), 12, src)
+    u, _ = oracle.run(scheme, form, g, u0, 12, src)
+    got = ds.to_vec(u)
+    scale = np.sqrt(ds.w)
+    err = np.linalg.norm((got - x_ref) * scale) / np.linalg.norm(x_ref * scale)
+    assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_dense_fundamental_equals_original(scheme):
+    """The paper's algebra (proveADIi/a/c; the LOD auxiliary v) on matrices."""
+    g = small_grid(seed=6, cfl=20.0)
+    ds = dense.DenseSystem(g)
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 12))
+    src = _src(g)
+    xo, to = dense.run_original(ds, scheme, x0, 15, src)
+    xf, tf = dense.run_fundamental(ds, scheme, x0, 15, src)
+    scale = np.sqrt(ds.w)
+    assert np.linalg.norm((xf - xo) * scale) / np.linalg.norm(xo * scale) < 1e-12
+    assert np.allclose(to, tf, rtol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_fundamental_equals_conventional_larger_grid(scheme):
+    nx, ny, nz = 12, 10, 11
+    eps = W.random_box_eps(nx, ny, nz, seed=2, nboxes=8)
+    g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, 10.0), eps)
+    u0 = W.random_fields(nx, ny, nz, 3)
+    src = Source(*W.interior_cell(nx, ny, nz, 4, margin=2), amp=1e12, t0=4 * g.dt,
+                 tau=4 * g.dt, f0=1 / (10 * g.dt))
+    uf, tf = oracle.run(scheme, "fundamental", g, u0, 30, src, 1)
+    uc, tc = oracle.run(scheme, "conventional", g, u0, 30, src, 1)
+    assert yee.weighted_rel_l2(uf, uc, g) < 1e-11
+    assert np.allclose(tf, tc, rtol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+@pytest.mark.parametrize("cfl", [1.0, 5.0, 20.0])
+def test_energy_invariant_conserved(scheme, cfl):
+    nx, ny, nz = 9, 8, 7
+    eps = W.random_box_eps(nx, ny, nz, seed=9, nboxes=6)
+    g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, cfl), eps)
+    u0 = W.random_fields(nx, ny, nz, 10)
+    u, tr = oracle.run(scheme, "fundamental", g, u0, 40, None, 1)
+    tr = np.array(tr)
+    assert np.abs(tr - tr[0]).max() / tr[0] < 1e-12
+    if scheme == "adi":
+        # W(u^n) <= W((I + dt/2 B) u^n) = 4 * invariant: bounded for any CFL
+        assert yee.energy(u, g) <= 4 * tr[-1] * (1 + 1e-12)
+
+
+def test_adi_lod_link():
+    """Sec. II-E: LOD1 fundamental iterations started from
+    u^0 = (1/2 I + dt/4 B) v^0 give v^{n+1} (from (fastLODc)) = ADI fields."""
+    from oracle import fundamental
+    g = small_grid(nx=6, ny=5, nz=7, seed=12, cfl=8.0)
+    phi0 = yee.clean(W.random_fields(g.nx, g.ny, g.nz, 13), g)
+    bu = yee.apply_operator("B", phi0, g)
+    U = [0.5 * a + 0.25 * g.dt * b for a, b in zip(phi0, bu)]
+    adi = fundamental.FundamentalADI(phi0, g)
+    for n in range(10):
+        U = fundamental.lod_substep(U, "A", 0.5 * g.dt, g)
+        Unew = fundamental.lod_substep(U, "B", 0.5 * g.dt, g)
+        V = [a + b for a, b in zip(Unew, U)]  # v^{n+1} = u^{n+1} + u^{n+1/2}
+        U = Unew
+        adi.step()
+        assert yee.weighted_rel_l2(V, adi.fields(), g) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# closed forms: cavity modes and dispersion
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_cavity_mode_evolution_matches_6x6_matrix_power(scheme):
+    nx, ny, nz, dx, dy, dz = 10, 8, 9, 1e-3, 1.1e-3, 0.9e-3
+    mnp = (2, 1, 3)
+    dt = yee.cfl_dt(dx, dy, dz, 6.0)
+    g = yee.Grid(nx, ny, nz, dx, dy, dz, dt)
+    a = np.random.default_rng(4).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, dx, dy, dz, *mnp)
+    M = an.scheme_matrix(scheme, A6, B6, dt)
+    N = 25
+    amp = np.linalg.matrix_power(M, N) @ a
+    if scheme == "lod2":
+        Min, Mout = an.lod2_io(B6, dt)
+        amp = Mout @ np.linalg.matrix_power(M, N) @ Min @ a
+    ref = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, amp)
+    u0 = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, a)
+    for form in oracle.FORMS:
+        u, _ = oracle.run(scheme, form, g, u0, N)
+        assert yee.weighted_rel_l2(u, ref, g) < 1e-12
+
+
+@pytest.mark.parametrize("cfl", [1.0, 4.0, 20.0])
+@pytest.mark.parametrize("mnp", [(1, 1, 0), (1, 1, 1), (2, 1, 1), (5, 3, 7)])
+def test_adi_dispersion_closed_form(cfl, mnp):
+    """Eigenvalues of the ADI amplification: {1, 1, e^{+-i w dt} (x2)} with the
+    closed-form cos(w dt); as dt -> 0 the frequency tends to the Yee one."""
+    n, h = 24, 1e-3
+    dt = yee.cfl_dt(h, h, h, cfl)
+    A6, B6 = an.mode_matrices(n, n, n, h, h, h, *mnp)
+    M = an.scheme_matrix("adi", A6, B6, dt)
+    ev = np.linalg.eigvals(M)
+    assert np.allclose(np.abs(ev), 1.0, atol=1e-12)  # non-dissipative
+    cosw = an.adi_dispersion_cos(n, n, n, h, h, h, *mnp, dt)
+    re = np.sort(ev.real)
+    assert abs(re[0] - cosw) < 1e-12 and abs(re[1] - cosw) < 1e-12
+    assert np.all(re >= cosw - 1e-12)
+
+
+def test_dispersion_worked_example_config1():
+    """24^3 cavity, 1 mm, CFL 4: ADI frequency of the (1,1,0) mode vs the Yee
+    semi-discrete and the analytic resonance."""
+    n, h = 24, 1e-3
+    dt = yee.cfl_dt(h, h, h, 4.0)
+    cosw = an.adi_dispersion_cos(n, n, n, h, h, h, 1, 1, 0, dt)
+    f_adi = math.acos(cosw) / (2 * math.pi * dt)
+    _, K = an.wavenumbers(n, n, n, h, h, h, 1, 1, 0)
+    f_yee = an.C0 * math.sqrt(sum(k * k for k in K)) / (2 * math.pi)
+    f_exact = an.C0 / 2 * math.sqrt(2) / (n * h)
+    assert f_adi < f_yee < f_exact  # ADI slows the wave; Yee slows it less
+    assert abs(f_exact - 8.83272e9) < 1e4
+    assert abs(f_adi - 8.74373e9) < 1e4 and abs(f_yee - 8.82642e9) < 1e4
+
+
+# --------------------------------------------------------------------------
+# temporal orders (Table I, last row)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme,order", [("adi", 2), ("lod1", 1), ("ss2", 2), ("lod2", 2)])
+def test_temporal_order(scheme, order):
+    """Global error at a fixed time T against the exact semi-discrete evolution
+    expm(T (A + B)) of a cavity mode.  The oracle reproduces the 6x6 scheme
+    matrices to 1e-12 (test above), so these orders are the oracle's orders."""
+    nx, ny, nz, h = 8, 7, 6, 1e-3
+    mnp = (1, 1, 1)
+    a = np.random.default_rng(5).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, h, h, h, *mnp)
+    T = 40 * yee.cfl_dt(h, h, h, 1.0)
+    ref = an.exact(A6, B6, T) @ a
+    w = np.r_[[an.EPS0] * 3, [an.MU0] * 3]
+    errs = []
+    for N in (640, 1280, 2560):
+        dt = T / N
+        M = an.scheme_matrix(scheme, A6, B6, dt)
+        if scheme == "lod2":
+            Min, Mout = an.lod2_io(B6, dt)
+            x = Mout @ np.linalg.matrix_power(M, N) @ Min @ a
+        else:
+            x = np.linalg.matrix_power(M, N) @ a
+        errs.append(math.sqrt(np.sum(w * (x - ref) ** 2) / np.sum(w * ref ** 2)))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(s - order) < 0.1 for s in slopes), (errs, slopes)
