@@ -1,0 +1,134 @@
+/*
+ * fdtd.h -- C ABI of the MI355X implicit FDTD library (libfdtd.so).
+ *
+ * Time-steps Maxwell's equations for a lossless isotropic medium in a PEC
+ * box on a Yee grid with the unconditionally stable splitting schemes of
+ * E. L. Tan, "Fundamental Schemes for Efficient Unconditionally Stable
+ * Implicit FDTD Methods" (arXiv 2011.14043):
+ *   ADI   -- Sec. II-A, eq. (clsADI) / fundamental (fasterADI)
+ *   LOD1  -- Sec. II-B, eq. (orgLOD)  / fundamental (fastLOD)   (== SS1)
+ *   SS2   -- Sec. II-C, eq. (orgSS2)  / fundamental (fastSS2)
+ *   LOD2  -- Sec. II-D, eq. (orgLOD2) / fundamental (fastLOD2), with the
+ *            input/output processing (orgLOD2i/o), (fastLOD2i/o)
+ * using the operators A, B of eq. (AMat) with b = dt/(2 eps), d = dt/(2 mu)
+ * (eq. (bd)) and second-order central differences on Yee cells (Sec. III).
+ * "Fundamental" runs the matrix-operator-free right-hand sides of Sec. III;
+ * "conventional" runs the original splitting formulae with the same line
+ * solver, for comparison (Table I).
+ *
+ * Field layout (caller's arrays).  Each of Ex, Ey, Ez, Hx, Hy, Hz is a dense
+ * row-major device array of shape (nz+1, ny+1, nx+1), index [k][j][i], x
+ * fastest, element type double for FDTD_F64, else float.  The entry
+ * [k][j][i] of a component is its Yee sample nearest to node (i, j, k):
+ * Ex (i+1/2, j, k), Ey (i, j+1/2, k), Ez (i, j, k+1/2), Hx (i, j+1/2, k+1/2),
+ * Hy (i+1/2, j, k+1/2), Hz (i+1/2, j+1/2, k), in units of dx, dy, dz.
+ * Entries outside the box are ignored on input and left untouched on output;
+ * E tangential to a wall is treated as 0 on input and written as 0 on output;
+ * H normal to a wall is static and passed through.
+ *
+ * Every call returns an fdtd_status (0 = OK); no C++ exception crosses the
+ * ABI.  Arguments are validated before any device work; on an error other
+ * than FDTD_ENONFINITE the plan and the caller's buffers are unchanged.
+ * A plan is not re-entrant; distinct plans are independent.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_plan_s* fdtd_plan_t;
+
+typedef enum {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,        /* bad argument (NULL, sizes, time step, cell index ...) */
+    FDTD_ENOMEM = -2,        /* device allocation failed                             */
+    FDTD_EDEVICE = -3,       /* HIP runtime error                                    */
+    FDTD_EUNSUPPORTED = -4,  /* valid request this build does not implement          */
+    FDTD_ENONFINITE = -5     /* NaN/Inf found in the energy after stepping           */
+} fdtd_status;
+
+typedef enum { FDTD_ADI = 0, FDTD_LOD1 = 1 /* == SS1 */, FDTD_SS2 = 2, FDTD_LOD2 = 3 } fdtd_scheme;
+typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
+/* Precision: FDTD_F32 keeps fields in FP32 and solves in FP32; FDTD_F64 uses
+ * FP64 for both; FDTD_F32_F64SOLVE keeps fields in FP32 (FP32 HBM traffic)
+ * but forms every right-hand side, tridiagonal solve and update in FP64
+ * registers, rounding once per stored value. */
+typedef enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_F32_F64SOLVE = 2 } fdtd_dtype;
+
+typedef struct {
+    int nx, ny, nz;            /* cells per axis, each >= 2                               */
+    double dt;                 /* time step [s], > 0 (any size: the schemes are           */
+                               /* unconditionally stable)                                 */
+    double dx, dy, dz;         /* cell sizes [m], > 0                                     */
+    int scheme;                /* fdtd_scheme                                             */
+    int form;                  /* fdtd_form                                               */
+    int dtype;                 /* fdtd_dtype; nx, ny, nz <= 1024 (FDTD_F32), <= 512 else  */
+    const float* eps_r;        /* relative permittivity per cell, (nz, ny, nx) row-major, */
+                               /* x fastest, > 0; host or device pointer, copied by       */
+                               /* fdtd_plan (may be freed afterwards).  NULL means 1.     */
+                               /* The E sample stored at [k][j][i] uses cell [k][j][i].   */
+    const float* mu_r;         /* relative permeability per cell; only NULL (== 1) is     */
+                               /* implemented (else FDTD_EUNSUPPORTED)                    */
+    int boundary;              /* 0 = PEC on all faces (the only value)                   */
+} fdtd_desc;
+
+/* Ez point source in cell (i, j, k) (1 <= i < nx, 1 <= j < ny, 0 <= k < nz).
+ * The paper omits nonhomogeneous terms (Sec. II); the library adds, in every
+ * sub-step written as (I - theta X) u' = (I + theta Y) u + g, the vector g
+ * with the single entry  theta * amp * p(t_k)  at that Ez sample, where
+ * p(t) = exp(-((t - t0)/tau)^2) sin(2 pi f0 (t - t0)) and t_k is the middle
+ * of the sub-step's time interval (ADI, LOD1: n+1/4, n+3/4; SS2: n+1/8, n+1/2,
+ * n+7/8; LOD2: n+1/2, n+1; times dt, n counted from the plan's step counter).
+ * The fundamental forms add the same term so that both forms agree. */
+typedef struct { int i, j, k; double f0, tau, t0, amp; } fdtd_source;
+
+/* Create a plan: validates `d`, copies eps_r, allocates the internal state
+ * (6 arrays; 12 for conventional ADI) and scratch on the current device.
+ * `hip_stream` (hipStream_t or NULL for the default stream) is used by every
+ * later call.  The step counter starts at 0. */
+fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out);
+
+/* Advance the caller's fields by `nsteps` >= 0 full time steps:
+ *   input processing (ADI: u^0 -> (1/2 I + dt/4 B) u^0, the link of
+ *   Sec. II-E; LOD2: (fastLOD2i)/(orgLOD2i)), nsteps main iterations, output
+ *   processing (ADI: the field v of the last B sub-step; LOD2:
+ *   (fastLOD2o)/(orgLOD2o)).
+ * E[3] = {Ex, Ey, Ez}, H[3] = {Hx, Hy, Hz}: device pointers, read on entry and
+ * overwritten on return (the same arrays may be reused by the next call).
+ * `src` may be NULL.  If `energy` is non-NULL (host array of
+ * nsteps/energy_every + 1 doubles, energy_every >= 1), energy[m] receives the
+ * FP64 energy sum eps |E|^2 + mu |H|^2 over all samples of the main-iteration
+ * state at step m*energy_every (ADI: the state (1/2 I + dt/4 B) u, whose
+ * energy the scheme conserves); the call then synchronizes the stream and
+ * returns FDTD_ENONFINITE if any value is not finite.  Without `energy` the
+ * call is asynchronous on the plan's stream.  The step counter advances by
+ * nsteps. */
+fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps,
+                     const fdtd_source* src, double* energy, int energy_every);
+
+/* fdtd_run with nsteps = 1 and no energy. */
+fdtd_status fdtd_step(fdtd_plan_t p, void* const E[3], void* const H[3], const fdtd_source* src);
+
+/* Set the plan's step counter (the source time origin). */
+fdtd_status fdtd_set_step(fdtd_plan_t p, long long n);
+
+/* Timing of the most recent fdtd_run (synchronizes the plan's stream).
+ * main_ms: milliseconds between HIP events recorded on the plan's stream
+ * around the main iterations (input/output processing excluded).
+ * If per-launch timing was enabled with fdtd_set_timing(p, 1) before the run,
+ * HIP events bracket every line pass on the plan's stream and
+ * pass_ms_avg[f] / pass_launches[f] give the mean duration [ms] and count of
+ * the launches of family f (0 = y/z-line passes, 1 = x-line passes);
+ * otherwise both are 0.  Either output pointer may be NULL (arrays of 2). */
+fdtd_status fdtd_set_timing(fdtd_plan_t p, int per_launch);
+fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* pass_ms_avg, int* pass_launches);
+
+fdtd_status fdtd_destroy(fdtd_plan_t p);
+const char* fdtd_strerror(fdtd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H */

@@ -1,0 +1,151 @@
+"""MI355X implicit FDTD: fundamental and conventional ADI / LOD1 / SS2 / LOD2.
+
+Thin Python front end of libfdtd.so (C ABI in include/fdtd.h).  PyTorch is
+used only for device memory and the current HIP stream; the computation runs
+in the library's HIP kernels.
+
+    plan = Plan(nx, ny, nz, dt, dx, dy, dz, scheme="adi", form="fundamental",
+                dtype=torch.float32, eps_r=eps)       # eps: (nz, ny, nx) float32
+    energies = plan.run(E, H, nsteps, source=Source(...), energy_every=1)
+
+E = [Ex, Ey, Ez], H = [Hx, Hy, Hz]: contiguous device tensors of shape
+(nz+1, ny+1, nx+1), updated in place.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib
+
+__all__ = ["Plan", "Source", "FdtdError", "load_library"]
+
+FdtdError = _lib.FdtdError
+
+
+def load_library():
+    return _lib.lib()
+
+
+@dataclass(frozen=True)
+class Source:
+    """Ez point source in cell (i, j, k); see fdtd_source in include/fdtd.h."""
+    i: int
+    j: int
+    k: int
+    f0: float = 10e9
+    tau: float = 0.1e-9
+    t0: float = 0.4e-9
+    amp: float = 1.0e10
+
+    def _c(self):
+        return _lib.FdtdSource(self.i, self.j, self.k, self.f0, self.tau, self.t0, self.amp)
+
+
+def _ptrs(ts, dtype, shape, device):
+    import torch
+    if len(ts) != 3:
+        raise ValueError("need three components")
+    for t in ts:
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or tuple(t.shape) != shape \
+                or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"field must be a contiguous {dtype} device tensor of shape {shape}")
+        if device is not None and t.device != device:
+            raise ValueError("fields must live on the plan's device")
+    return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+
+class Plan:
+    """One simulation plan (fdtd_plan).  Not thread-safe."""
+
+    def __init__(self, nx, ny, nz, dt, dx, dy, dz, scheme="adi", form="fundamental",
+                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None):
+        """dtype: field storage (float32/float64); solve_dtype: arithmetic of the
+        line solves (defaults to dtype; float64 with float32 fields selects
+        FDTD_F32_F64SOLVE)."""
+        import torch
+        L = _lib.lib()
+        self.dtype = dtype if dtype is not None else torch.float32
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        solve = solve_dtype if solve_dtype is not None else self.dtype
+        if self.dtype == torch.float64 and solve != torch.float64:
+            raise ValueError("float64 fields need float64 solves")
+        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else 0)
+        self.shape = (nz + 1, ny + 1, nx + 1)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        eps_ptr = None
+        self._eps_keep = None
+        if eps_r is not None:
+            e = eps_r
+            if not isinstance(e, torch.Tensor):
+                e = torch.as_tensor(e)
+            e = e.to(dtype=torch.float32).contiguous()
+            if tuple(e.shape) != (nz, ny, nx):
+                raise ValueError("eps_r must have shape (nz, ny, nx)")
+            self._eps_keep = e
+            eps_ptr = e.data_ptr()
+        desc = _lib.FdtdDesc(nx, ny, nz, dt, dx, dy, dz, _lib.SCHEMES[scheme], _lib.FORMS[form],
+                             code, eps_ptr, None, 0)
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            h = ctypes.c_void_p()
+            _lib.check(L.fdtd_plan(ctypes.byref(desc), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)),
+                       "fdtd_plan")
+        self._h = h
+        self._eps_keep = None
+        self.scheme, self.form = scheme, form
+
+    def run(self, E, H, nsteps, source: Source | None = None, energy_every: int = 0):
+        """Advance E, H in place by nsteps; returns the energy trace (list) if
+        energy_every > 0, else None (asynchronous on the plan's stream)."""
+        L = _lib.lib()
+        pe = _ptrs(E, self.dtype, self.shape, self.device)
+        ph = _ptrs(H, self.dtype, self.shape, self.device)
+        src = ctypes.byref(source._c()) if source is not None else None
+        if energy_every > 0:
+            n = nsteps // energy_every + 1
+            buf = (ctypes.c_double * n)()
+            _lib.check(L.fdtd_run(self._h, pe, ph, int(nsteps), src, buf, int(energy_every)), "fdtd_run")
+            return list(buf)
+        _lib.check(L.fdtd_run(self._h, pe, ph, int(nsteps), src, None, 1), "fdtd_run")
+        return None
+
+    def step(self, E, H, source: Source | None = None):
+        L = _lib.lib()
+        src = ctypes.byref(source._c()) if source is not None else None
+        _lib.check(L.fdtd_step(self._h, _ptrs(E, self.dtype, self.shape, self.device),
+                               _ptrs(H, self.dtype, self.shape, self.device), src), "fdtd_step")
+
+    def set_step(self, n: int):
+        _lib.check(_lib.lib().fdtd_set_step(self._h, int(n)), "fdtd_set_step")
+
+    def set_timing(self, per_launch: bool):
+        _lib.check(_lib.lib().fdtd_set_timing(self._h, 1 if per_launch else 0), "fdtd_set_timing")
+
+    def last_timing(self):
+        """{'main_ms', 'yz_ms_avg', 'x_ms_avg', 'yz_launches', 'x_launches'}."""
+        main = ctypes.c_double()
+        avg = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int * 2)()
+        _lib.check(_lib.lib().fdtd_last_timing(self._h, ctypes.byref(main), avg, cnt), "fdtd_last_timing")
+        return {"main_ms": main.value, "yz_ms_avg": avg[0], "x_ms_avg": avg[1],
+                "yz_launches": cnt[0], "x_launches": cnt[1]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().fdtd_destroy(self._h), "fdtd_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

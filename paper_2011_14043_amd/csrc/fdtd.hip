@@ -1,0 +1,543 @@
+// fdtd.hip -- plan, scheme tables and the C ABI of libfdtd.so.
+//
+// Schemes (Sec. II of the paper) as sequences of sub-steps; each sub-step
+// applies the Cayley factor of A or B with half-span theta through three
+// fused line passes, one per (E, H) pair of the operator (eq. (AMat)):
+//   ADI  (fasterADI) in the link scaling of Sec. II-E:  A dt/2, B dt/2,
+//        input U = (1/2 I + dt/4 B) u, output u = V of the last B sub-step;
+//   LOD1 (fastLOD):   A dt/2, B dt/2;
+//   SS2  (fastSS2):   A dt/4, B dt/2, A dt/4;
+//   LOD2 (fastLOD2):  A dt/2, B dt/2 on the n+1/4 levels, input B dt/4
+//        (fastLOD2i), output B -dt/4 (fastLOD2o).
+// The original forms (clsADI), (orgLOD), (orgSS2), (orgLOD2) run the same
+// sequences with the original right-hand sides (modes CONV_*).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "aux_kernels.hpp"
+#include "pass_kernels.hpp"
+
+namespace fdtd {
+
+static constexpr double kEps0 = 8.8541878128e-12;
+static constexpr double kMu0 = 1.25663706212e-6;
+
+// Pairs of eq. (AMat): E component, H component, line axis, e axis, t axis, sign.
+// Components 0..5 = Ex Ey Ez Hx Hy Hz; axes 0..2 = x y z.
+struct PairDef { int ce, ch, w, e, t, s; };
+static const PairDef kPairs[2][3] = {
+    {{0, 5, 1, 0, 2, +1}, {1, 3, 2, 1, 0, +1}, {2, 4, 0, 2, 1, +1}},   // A
+    {{0, 4, 2, 0, 1, -1}, {1, 5, 0, 1, 2, -1}, {2, 3, 1, 2, 0, -1}},   // B
+};
+
+struct SubStep { int op; double theta_frac; double t_frac; };
+struct SchemeDef { int nsub; SubStep sub[3]; };
+static const SchemeDef kSchemes[4] = {
+    {2, {{0, 0.5, 0.25}, {1, 0.5, 0.75}, {0, 0, 0}}},          // ADI
+    {2, {{0, 0.5, 0.25}, {1, 0.5, 0.75}, {0, 0, 0}}},          // LOD1
+    {3, {{0, 0.25, 0.125}, {1, 0.5, 0.5}, {0, 0.25, 0.875}}},  // SS2
+    {2, {{0, 0.5, 0.5}, {1, 0.5, 1.0}, {0, 0, 0}}},            // LOD2
+};
+
+struct Timing {
+    bool per_launch = false;
+    hipEvent_t main0 = nullptr, main1 = nullptr;
+    std::vector<hipEvent_t> ev;   // pairs
+    std::vector<int> fam;         // family of each pair (0 = yz lines, 1 = x lines)
+    size_t used = 0;
+};
+
+}  // namespace fdtd
+
+struct fdtd_plan_s {
+    fdtd_desc d;
+    hipStream_t stream;
+    int device;
+    fdtd::Dims dims;
+    size_t esz;
+    void* state = nullptr;    // 6 (or 12 for original ADI) arrays, padded layout
+    void* snap = nullptr;     // ADI: state before the last B sub-step
+    float* eps = nullptr;     // node layout, padded
+    double* partial = nullptr;
+    int npartial = 0;
+    double* energy_dev = nullptr;
+    int energy_cap = 0;
+    long long step = 0;
+    fdtd::Timing tm;
+    double last_main_ms = 0.0;
+    double fam_ms[2] = {0, 0};
+    int fam_n[2] = {0, 0};
+    unsigned magic = 0xFD7DFD7Du;
+};
+
+namespace fdtd {
+
+static fdtd_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return FDTD_OK;
+    if (e == hipErrorOutOfMemory) return FDTD_ENOMEM;
+    return FDTD_EDEVICE;
+}
+#define HIPCHK(x)                                       \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return from_hip(e_);      \
+    } while (0)
+
+static int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+template <typename T>
+static T* comp_ptr(fdtd_plan_s* p, int set, int c) {
+    return reinterpret_cast<T*>(p->state) + (size_t)(set * 6 + c) * p->dims.comp;
+}
+
+static long long axis_stride(const Dims& d, int ax) { return ax == 0 ? 1 : (ax == 1 ? d.px : d.plane); }
+static int axis_cells(const Dims& d, int ax) { return ax == 0 ? d.nx : (ax == 1 ? d.ny : d.nz); }
+static double axis_h(const fdtd_desc& d, int ax) { return ax == 0 ? d.dx : (ax == 1 ? d.dy : d.dz); }
+
+// ---------------------------------------------------------------------------
+// one line pass
+// ---------------------------------------------------------------------------
+template <typename T, typename S>
+static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, int set_in, int set_out,
+                               const fdtd_source* src, double gval, bool timed) {
+    const PairDef& pd = kPairs[op][k];
+    const Dims& d = p->dims;
+    PassArgs<T, S> a;
+    std::memset(&a, 0, sizeof(a));
+    a.Ein = comp_ptr<T>(p, set_in, pd.ce);
+    a.Hin = comp_ptr<T>(p, set_in, pd.ch);
+    a.Eout = comp_ptr<T>(p, set_out, pd.ce);
+    a.Hout = comp_ptr<T>(p, set_out, pd.ch);
+    a.eps = p->eps;
+    a.sw = axis_stride(d, pd.w);
+    a.n_w = axis_cells(d, pd.w);
+    const double h = axis_h(p->d, pd.w);
+    const double mu = kMu0;
+    const double s = double(pd.s);
+    a.Ks = kEps0 * mu * h * h / (theta * theta);
+    const double qd = s * theta / (mu * h);
+    double kap = (mode == CONV_ADI) ? s * mu * h / theta : 2.0 * s * mu * h / theta;
+    a.q = S(qd);
+    a.kap_hi = S(kap);
+    a.kap_lo = (sizeof(S) == 4) ? S(kap - double(S(kap))) : S(0);
+    if (mode == CONV_ADI) {
+        // Y = the other operator; H2 = partner of E in Y, E3 = partner of H in Y
+        const int yo = 1 - op;
+        int h2 = -1, e3 = -1;
+        for (int m = 0; m < 3; ++m) {
+            if (kPairs[yo][m].ce == pd.ce) h2 = kPairs[yo][m].ch;
+            if (kPairs[yo][m].ch == pd.ch) e3 = kPairs[yo][m].ce;
+        }
+        const double sy = (op == 0) ? -1.0 : 1.0;
+        const double ht = axis_h(p->d, pd.t), he = axis_h(p->d, pd.e);
+        a.H2 = comp_ptr<T>(p, set_in, h2);
+        a.E3 = comp_ptr<T>(p, set_in, e3);
+        a.s_t = axis_stride(d, pd.t);
+        a.s_e = axis_stride(d, pd.e);
+        a.cH2 = S(sy * h * h * mu / (ht * theta));
+        a.hE3 = S(sy * theta / (mu * he));
+    }
+    a.src = -1;
+    if (src && gval != 0.0 && pd.ce == 2) {
+        a.src = (long long)src->k * d.plane + (long long)src->j * d.px + src->i;
+        if (mode == FUND) {
+            a.src_pre = S(0.5 * gval);
+            a.src_post = (p->d.scheme == FDTD_ADI) ? S(0.5 * gval) : S(0);
+        } else {
+            a.src_pre = S(gval);
+        }
+    }
+    const int ne = axis_cells(d, pd.e), nt = axis_cells(d, pd.t);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int fam = (pd.w == 0) ? 1 : 0;
+    if (timed) {
+        Timing& tm = p->tm;
+        if (tm.used + 2 > tm.ev.size()) {
+            for (int m = 0; m < 64; ++m) {
+                hipEvent_t ev;
+                HIPCHK(hipEventCreate(&ev));
+                tm.ev.push_back(ev);
+            }
+        }
+        e0 = tm.ev[tm.used];
+        e1 = tm.ev[tm.used + 1];
+        tm.fam.push_back(fam);
+        tm.used += 2;
+        HIPCHK(hipEventRecord(e0, p->stream));
+    }
+    if (pd.w == 0) {
+        // x lines: a = e axis, b = t axis
+        a.sa = axis_stride(d, pd.e);
+        a.sb = axis_stride(d, pd.t);
+        a.a_lo = 0; a.na = ne;
+        a.b_lo = 1; a.nb = nt - 1;
+        const int M = (a.n_w <= 512) ? 8 : 16;
+        a.P = next_pow2((a.n_w + M - 1) / M);
+        const long long nlines = (long long)a.na * a.nb;
+        const long long lines_per_block = 4LL * (64 / a.P);
+        const dim3 grid((unsigned)((nlines + lines_per_block - 1) / lines_per_block));
+#define LAUNCH_X(MM, MO) hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO>), grid, dim3(256), 0, p->stream, a)
+        if (M == 8) {
+            if (mode == FUND) LAUNCH_X(8, FUND); else if (mode == CONV_LOD) LAUNCH_X(8, CONV_LOD); else LAUNCH_X(8, CONV_ADI);
+        } else {
+            if (mode == FUND) LAUNCH_X(16, FUND); else if (mode == CONV_LOD) LAUNCH_X(16, CONV_LOD); else LAUNCH_X(16, CONV_ADI);
+        }
+#undef LAUNCH_X
+    } else {
+        // y/z lines: a = x axis (lanes), b = the other transverse axis
+        const int other = (pd.e == 0) ? pd.t : pd.e;
+        a.sa = 1;
+        a.sb = axis_stride(d, other);
+        if (pd.e == 0) { a.a_lo = 0; a.na = d.nx; a.b_lo = 1; a.nb = nt - 1; }
+        else { a.a_lo = 1; a.na = d.nx - 1; a.b_lo = 0; a.nb = ne; }
+        // chunk size M, x positions per block TX, block bound NT (= TX * max P)
+        constexpr bool f32solve = sizeof(S) == 4;
+        int M, TX;
+        if (f32solve) { if (a.n_w <= 512) { M = 16; TX = 32; } else { M = 32; TX = 16; } }
+        else { M = 16; TX = 16; }
+        a.P = next_pow2((a.n_w + M - 1) / M);
+        const dim3 block(TX * a.P);
+        const dim3 grid((unsigned)((a.a_lo + a.na + TX - 1) / TX), (unsigned)a.nb);
+        const size_t lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
+#define LAUNCH_YZ(MM, MO, TT, NN) \
+    hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN>), grid, block, lds, p->stream, a)
+#define LAUNCH_YZ3(MM, TT, NN)                                              \
+    do {                                                                    \
+        if (mode == FUND) LAUNCH_YZ(MM, FUND, TT, NN);                      \
+        else if (mode == CONV_LOD) LAUNCH_YZ(MM, CONV_LOD, TT, NN);         \
+        else LAUNCH_YZ(MM, CONV_ADI, TT, NN);                               \
+    } while (0)
+        if constexpr (f32solve) {
+            if (M == 16) LAUNCH_YZ3(16, 32, 1024);
+            else LAUNCH_YZ3(32, 16, 512);
+        } else {
+            LAUNCH_YZ3(16, 16, 512);
+        }
+#undef LAUNCH_YZ3
+#undef LAUNCH_YZ
+    }
+    HIPCHK(hipGetLastError());
+    if (timed) HIPCHK(hipEventRecord(e1, p->stream));
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& cur, const fdtd_source* src,
+                           double gval, bool timed) {
+    const int out = (mode == CONV_ADI) ? 1 - cur : cur;
+    for (int k = 0; k < 3; ++k) {
+        fdtd_status st = launch_pass<T, S>(p, op, k, theta, mode, cur, out, src, gval, timed);
+        if (st != FDTD_OK) return st;
+    }
+    cur = out;
+    return FDTD_OK;
+}
+
+static double source_value(const fdtd_source* src, double theta, double t) {
+    if (!src) return 0.0;
+    const double x = (t - src->t0) / src->tau;
+    return theta * src->amp * std::exp(-x * x) * std::sin(2.0 * M_PI * src->f0 * (t - src->t0));
+}
+
+template <typename T>
+static FieldPtrs<T> state_ptrs(fdtd_plan_s* p, int set) {
+    FieldPtrs<T> f;
+    for (int c = 0; c < 6; ++c) f.c[c] = comp_ptr<T>(p, set, c);
+    return f;
+}
+template <typename T>
+static FieldPtrsW<T> state_ptrs_w(fdtd_plan_s* p, int set) {
+    FieldPtrsW<T> f;
+    for (int c = 0; c < 6; ++c) f.c[c] = comp_ptr<T>(p, set, c);
+    return f;
+}
+
+template <typename T>
+static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst) {
+    AuxCoef k{kEps0, kMu0, p->d.dx, p->d.dy, p->d.dz, 0.0};
+    if (p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL) k.link = 0.25 * p->d.dt;
+    hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
+                       state_ptrs<T>(p, set), p->eps, p->dims, k, p->partial);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, p->partial, p->npartial, dst);
+    HIPCHK(hipGetLastError());
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
+                            double* energy, int every) {
+    const fdtd_desc& d = p->d;
+    const Dims& dm = p->dims;
+    const bool adi = d.scheme == FDTD_ADI;
+    const bool conv = d.form == FDTD_CONVENTIONAL;
+    const int mode = conv ? (adi ? CONV_ADI : CONV_LOD) : FUND;
+    const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+    const unsigned gblocks = (unsigned)((nn + 255) / 256);
+    FieldPtrs<T> caller;
+    FieldPtrsW<T> caller_w;
+    for (int c = 0; c < 3; ++c) {
+        caller.c[c] = static_cast<const T*>(E[c]);
+        caller.c[3 + c] = static_cast<const T*>(H[c]);
+        caller_w.c[c] = static_cast<T*>(E[c]);
+        caller_w.c[3 + c] = static_cast<T*>(H[c]);
+    }
+    const int nrec = energy ? nsteps / every + 1 : 0;
+    if (nrec > p->energy_cap) {
+        if (p->energy_dev) HIPCHK(hipFree(p->energy_dev));
+        p->energy_dev = nullptr;
+        HIPCHK(hipMalloc(&p->energy_dev, sizeof(double) * nrec));
+        p->energy_cap = nrec;
+    }
+    // input processing
+    AuxCoef kin{kEps0, kMu0, d.dx, d.dy, d.dz, (adi && !conv) ? 0.25 * d.dt : 0.0};
+    hipLaunchKernelGGL((load_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
+                       p->eps, dm, kin);
+    HIPCHK(hipGetLastError());
+    int cur = 0;
+    if (adi && conv) {
+        HIPCHK(hipMemcpyAsync(comp_ptr<T>(p, 1, 0), comp_ptr<T>(p, 0, 0), sizeof(T) * dm.comp * 6,
+                              hipMemcpyDeviceToDevice, p->stream));
+    }
+    if (d.scheme == FDTD_LOD2) {
+        fdtd_status st = substep<T, S>(p, 1, 0.25 * d.dt, mode, cur, nullptr, 0.0, false);
+        if (st != FDTD_OK) return st;
+    }
+    const SchemeDef& sd = kSchemes[d.scheme];
+    Timing& tm = p->tm;
+    tm.used = 0;
+    tm.fam.clear();
+    if (!tm.main0) {
+        HIPCHK(hipEventCreate(&tm.main0));
+        HIPCHK(hipEventCreate(&tm.main1));
+    }
+    HIPCHK(hipEventRecord(tm.main0, p->stream));
+    if (energy) {
+        fdtd_status st = energy_into<T>(p, cur, p->energy_dev);
+        if (st != FDTD_OK) return st;
+    }
+    double last_b_g = 0.0;   // source term of the last B sub-step (ADI output correction)
+    for (int n = 0; n < nsteps; ++n) {
+        const long long nglob = p->step + n;
+        for (int u = 0; u < sd.nsub; ++u) {
+            const SubStep& ss = sd.sub[u];
+            const double theta = ss.theta_frac * d.dt;
+            const double g = source_value(src, theta, (double(nglob) + ss.t_frac) * d.dt);
+            if (adi && !conv && n == nsteps - 1 && ss.op == 1) {
+                HIPCHK(hipMemcpyAsync(p->snap, comp_ptr<T>(p, cur, 0), sizeof(T) * dm.comp * 6,
+                                      hipMemcpyDeviceToDevice, p->stream));
+            }
+            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, src, g, tm.per_launch);
+            if (st != FDTD_OK) return st;
+            if (ss.op == 1) last_b_g = g;
+        }
+        if (energy && (n + 1) % every == 0) {
+            fdtd_status st = energy_into<T>(p, cur, p->energy_dev + (n + 1) / every);
+            if (st != FDTD_OK) return st;
+        }
+    }
+    HIPCHK(hipEventRecord(tm.main1, p->stream));
+    // output processing
+    if (nsteps > 0) {
+        if (d.scheme == FDTD_LOD2) {
+            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, 0.0, false);
+            if (st != FDTD_OK) return st;
+        }
+        const bool add_old = adi && !conv;
+        FieldPtrs<T> old;
+        for (int c = 0; c < 6; ++c) old.c[c] = reinterpret_cast<const T*>(p->snap ? p->snap : p->state) + (size_t)c * dm.comp;
+        const long long src_off = src ? (long long)src->k * dm.plane + (long long)src->j * dm.px + src->i : -1;
+        hipLaunchKernelGGL((store_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, state_ptrs<T>(p, cur),
+                           old, caller_w, dm, add_old ? 1 : 0, src_off, 0.5 * last_b_g);
+        HIPCHK(hipGetLastError());
+    }
+    p->step += nsteps;
+    if (energy) {
+        HIPCHK(hipMemcpyAsync(energy, p->energy_dev, sizeof(double) * nrec, hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        for (int m = 0; m < nrec; ++m)
+            if (!std::isfinite(energy[m])) return FDTD_ENONFINITE;
+    }
+    return FDTD_OK;
+}
+
+}  // namespace fdtd
+
+using namespace fdtd;
+
+static bool plan_ok(fdtd_plan_t p) { return p != nullptr && p->magic == 0xFD7DFD7Du; }
+
+extern "C" {
+
+const char* fdtd_strerror(fdtd_status s) {
+    switch (s) {
+        case FDTD_OK: return "ok";
+        case FDTD_EINVAL: return "invalid argument";
+        case FDTD_ENOMEM: return "device out of memory";
+        case FDTD_EDEVICE: return "HIP runtime error";
+        case FDTD_EUNSUPPORTED: return "not supported by this build";
+        case FDTD_ENONFINITE: return "non-finite energy after stepping";
+    }
+    return "unknown status";
+}
+
+fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
+    if (!d || !out) return FDTD_EINVAL;
+    *out = nullptr;
+    if (d->nx < 2 || d->ny < 2 || d->nz < 2) return FDTD_EINVAL;
+    if (!(d->dt > 0) || !(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return FDTD_EINVAL;
+    if (!std::isfinite(d->dt) || !std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz))
+        return FDTD_EINVAL;
+    if (d->scheme < 0 || d->scheme > 3 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 2)
+        return FDTD_EINVAL;
+    if (d->boundary != 0) return FDTD_EUNSUPPORTED;
+    if (d->mu_r != nullptr) return FDTD_EUNSUPPORTED;
+    const int nmax = std::max(d->nx, std::max(d->ny, d->nz));
+    if (nmax > (d->dtype == FDTD_F32 ? 1024 : 512)) return FDTD_EUNSUPPORTED;   // register budget
+    const long long ncells = (long long)d->nx * d->ny * d->nz;
+    std::vector<float> eps_host;
+    if (d->eps_r) {
+        eps_host.resize(ncells);
+        if (hipMemcpy(eps_host.data(), d->eps_r, sizeof(float) * ncells, hipMemcpyDefault) != hipSuccess)
+            return FDTD_EINVAL;
+        for (long long c = 0; c < ncells; ++c)
+            if (!(eps_host[c] > 0.0f) || !std::isfinite(eps_host[c])) return FDTD_EINVAL;
+    }
+    fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
+    if (!p) return FDTD_ENOMEM;
+    p->d = *d;
+    p->d.eps_r = nullptr;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&p->device);
+    p->esz = d->dtype == FDTD_F64 ? 8 : 4;
+    Dims& dm = p->dims;
+    dm.nx = d->nx; dm.ny = d->ny; dm.nz = d->nz;
+    const int align = d->dtype == FDTD_F64 ? 16 : 32;   // 128-byte rows
+    dm.px = ((d->nx + 1 + align - 1) / align) * align;
+    dm.plane = dm.px * (d->ny + 1);
+    dm.comp = dm.plane * (d->nz + 1);
+    dm.cplane = (long long)(d->nx + 1) * (d->ny + 1);
+    dm.ccomp = dm.cplane * (d->nz + 1);
+    const int sets = (d->scheme == FDTD_ADI && d->form == FDTD_CONVENTIONAL) ? 2 : 1;
+    auto fail = [&](fdtd_status st) {
+        if (p->state) (void)hipFree(p->state);
+        if (p->snap) (void)hipFree(p->snap);
+        if (p->eps) (void)hipFree(p->eps);
+        if (p->partial) (void)hipFree(p->partial);
+        delete p;
+        return st;
+    };
+    if (std::getenv("FDTD_TEST_FAIL_ALLOC")) return fail(FDTD_ENOMEM);
+    hipError_t e;
+    if ((e = hipMalloc(&p->state, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
+    if ((e = hipMemset(p->state, 0, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
+    if (d->scheme == FDTD_ADI && d->form == FDTD_FUNDAMENTAL) {
+        if ((e = hipMalloc(&p->snap, p->esz * dm.comp * 6)) != hipSuccess) return fail(from_hip(e));
+    }
+    // eps_r at node indices (owned index, clamped to the last cell), padded rows
+    std::vector<float> en((size_t)dm.comp, 1.0f);
+    for (int k = 0; k <= d->nz; ++k)
+        for (int j = 0; j <= d->ny; ++j)
+            for (int i = 0; i <= d->nx; ++i) {
+                const int kk = std::min(k, d->nz - 1), jj = std::min(j, d->ny - 1), ii = std::min(i, d->nx - 1);
+                en[(size_t)k * dm.plane + (size_t)j * dm.px + i] =
+                    eps_host.empty() ? 1.0f : eps_host[((size_t)kk * d->ny + jj) * d->nx + ii];
+            }
+    if ((e = hipMalloc(&p->eps, sizeof(float) * dm.comp)) != hipSuccess) return fail(from_hip(e));
+    if ((e = hipMemcpy(p->eps, en.data(), sizeof(float) * dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(from_hip(e));
+    p->npartial = 1024;
+    if ((e = hipMalloc(&p->partial, sizeof(double) * p->npartial)) != hipSuccess) return fail(from_hip(e));
+    *out = p;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
+                     double* energy, int energy_every) {
+    if (!plan_ok(p) || !E || !H || nsteps < 0) return FDTD_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!E[c] || !H[c]) return FDTD_EINVAL;
+    if (energy && energy_every < 1) return FDTD_EINVAL;
+    if (src) {
+        if (src->i < 1 || src->i >= p->d.nx || src->j < 1 || src->j >= p->d.ny || src->k < 0 || src->k >= p->d.nz)
+            return FDTD_EINVAL;
+        if (!(src->tau > 0) || !std::isfinite(src->f0) || !std::isfinite(src->t0) || !std::isfinite(src->amp))
+            return FDTD_EINVAL;
+    }
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    fdtd_status st;
+    if (p->d.dtype == FDTD_F32) st = run_impl<float, float>(p, E, H, nsteps, src, energy, energy_every);
+    else if (p->d.dtype == FDTD_F64) st = run_impl<double, double>(p, E, H, nsteps, src, energy, energy_every);
+    else st = run_impl<float, double>(p, E, H, nsteps, src, energy, energy_every);
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    return st;
+}
+
+fdtd_status fdtd_step(fdtd_plan_t p, void* const E[3], void* const H[3], const fdtd_source* src) {
+    return fdtd_run(p, E, H, 1, src, nullptr, 1);
+}
+
+fdtd_status fdtd_set_step(fdtd_plan_t p, long long n) {
+    if (!plan_ok(p) || n < 0) return FDTD_EINVAL;
+    p->step = n;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_set_timing(fdtd_plan_t p, int per_launch) {
+    if (!plan_ok(p)) return FDTD_EINVAL;
+    p->tm.per_launch = per_launch != 0;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* fam_ms_avg, int* fam_launches) {
+    if (!plan_ok(p)) return FDTD_EINVAL;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    float ms = 0.0f;
+    if (p->tm.main0) HIPCHK(hipEventElapsedTime(&ms, p->tm.main0, p->tm.main1));
+    if (main_ms) *main_ms = ms;
+    double tot[2] = {0, 0};
+    int cnt[2] = {0, 0};
+    for (size_t m = 0; m < p->tm.fam.size(); ++m) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, p->tm.ev[2 * m], p->tm.ev[2 * m + 1]));
+        tot[p->tm.fam[m]] += t;
+        cnt[p->tm.fam[m]] += 1;
+    }
+    for (int f = 0; f < 2; ++f) {
+        if (fam_ms_avg) fam_ms_avg[f] = cnt[f] ? tot[f] / cnt[f] : 0.0;
+        if (fam_launches) fam_launches[f] = cnt[f];
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_destroy(fdtd_plan_t p) {
+    if (!plan_ok(p)) return FDTD_EINVAL;
+    (void)hipStreamSynchronize(p->stream);
+    if (p->state) (void)hipFree(p->state);
+    if (p->snap) (void)hipFree(p->snap);
+    if (p->eps) (void)hipFree(p->eps);
+    if (p->partial) (void)hipFree(p->partial);
+    if (p->energy_dev) (void)hipFree(p->energy_dev);
+    for (hipEvent_t e : p->tm.ev) (void)hipEventDestroy(e);
+    if (p->tm.main0) (void)hipEventDestroy(p->tm.main0);
+    if (p->tm.main1) (void)hipEventDestroy(p->tm.main1);
+    p->magic = 0;
+    delete p;
+    return FDTD_OK;
+}
+
+}  // extern "C"

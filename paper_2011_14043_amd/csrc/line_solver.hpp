@@ -1,0 +1,149 @@
+// line_solver.hpp -- register-resident tridiagonal line solver for gfx950.
+//
+// Every implicit update of the method reduces, per grid line of the solve axis
+// w, to the scaled tridiagonal system
+//
+//     -V[j-1] + (2 + sigma[j]) V[j] - V[j+1] = r[j],   j = 0 .. n-1,
+//
+// (the fundamental equation 1/2 E~ - (b d / 2) d_w^2 E~ = e + s b d_w h of
+// Sec. III-A, and the original (I - theta X) systems, multiplied by
+// 2 sigma or sigma, sigma = 1/(p q), p = b/dw, q = d/dw).  It is strictly
+// diagonally dominant, so no pivoting is needed.  PEC walls (Dirichlet V = 0)
+// are rows whose diagonal is BIG = 2^100: they decouple from their neighbours
+// below working precision in FP32 and FP64.
+//
+// A line is split into P chunks of M consecutive slots, one chunk per thread.
+// The last slot of each chunk is a separator S_l.  The M-1 interior slots of
+// chunk l depend only on S_{l-1} and S_l:
+//     x_i = y_i + alpha_i S_{l-1} + gamma_i S_l,
+// with y = T^{-1} r, alpha = T^{-1} e_0, gamma = T^{-1} e_{M-2} from one LU
+// sweep of the chunk (Thomas' forward elimination with running products).
+// Eliminating the interiors leaves a P x P tridiagonal system in the separators
+// (a Schur complement, again diagonally dominant), solved by parallel cyclic
+// reduction across the P threads.  Each thread then finishes its own slots.
+// No per-slot data leaves the registers; HBM sees only the line's inputs and
+// outputs once.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fdtd {
+
+template <typename T> struct Big;
+template <> struct Big<float> { static constexpr float v = 1.2676506e30f; };   // 2^100
+template <> struct Big<double> { static constexpr double v = 1.2676506002282294e30; };
+
+// Reciprocal: v_rcp_f32 refined by one Newton step (about 0.5 ulp) / IEEE divide in FP64.
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Per-thread state of one chunk after local elimination, folded with the
+// outputs so that 4 words per slot stay live:
+//   W[i] = y_i + CE * ue_i,   Z[i] = uh_i + q * (y_{i+1} - y_i + CH (ue_{i+1} - ue_i))
+// for interior slots; slot M-1 (the separator) keeps ue, uh.
+template <typename T, int M>
+struct Chunk {
+    T W[M], Z[M], al[M], ga[M];
+    T a0, g0, y0;   // alpha_0, gamma_0, y_0   (needed by the previous chunk)
+    T aL, gL, yL;   // alpha_{M-2}, gamma_{M-2}, y_{M-2}
+    T dgS, rS;      // separator row: diagonal and right side
+};
+
+// Local elimination of one chunk.  CE = -1: E' = V - U_e (fundamental);
+// CE = 0: E' = V (original forms).  CH = 1 adds U_e to the H difference
+// (original LOD family: H' = H + q d_w(E + E')).
+template <typename T, int M, int CE, int CH>
+__device__ __forceinline__ void chunk_eliminate(const T (&dg)[M], const T (&r)[M], const T (&ue)[M],
+                                                const T (&uh)[M], T q, Chunk<T, M>& c) {
+    static_assert(M >= 2, "chunk needs an interior slot and a separator");
+    T g[M - 1], d[M - 1], p[M - 1];
+    g[0] = recip(dg[0]);
+    d[0] = r[0] * g[0];
+    p[0] = g[0];
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+        g[i] = recip(dg[i] - g[i - 1]);
+        d[i] = (r[i] + d[i - 1]) * g[i];
+        p[i] = p[i - 1] * g[i];
+    }
+    T y = d[M - 2], a = p[M - 2], gm = g[M - 2];
+    c.yL = y; c.aL = a; c.gL = gm;
+    c.W[M - 2] = y + T(CE) * ue[M - 2];
+    c.Z[M - 2] = uh[M - 2] + q * ((T(0) - y) + T(CH) * (ue[M - 1] - ue[M - 2]));
+    c.al[M - 2] = a;
+    c.ga[M - 2] = gm;
+#pragma unroll
+    for (int i = M - 3; i >= 0; --i) {
+        const T yi = d[i] + g[i] * y;
+        const T ai = p[i] + g[i] * a;
+        const T gi = g[i] * gm;
+        c.W[i] = yi + T(CE) * ue[i];
+        c.Z[i] = uh[i] + q * ((y - yi) + T(CH) * (ue[i + 1] - ue[i]));
+        c.al[i] = ai;
+        c.ga[i] = gi;
+        y = yi; a = ai; gm = gi;
+    }
+    c.y0 = y; c.a0 = a; c.g0 = gm;
+    c.W[M - 1] = ue[M - 1];
+    c.Z[M - 1] = uh[M - 1];
+    c.al[M - 1] = T(0);
+    c.ga[M - 1] = T(1);
+    c.dgS = dg[M - 1];
+    c.rS = r[M - 1];
+}
+
+// Separator row l from chunk l (own) and chunk l+1 (next; zeros past the end).
+template <typename T>
+struct Row { T A, B, C, D; };
+
+template <typename T>
+__device__ __forceinline__ Row<T> separator_row(T aL, T gL, T yL, T dgS, T rS, T a0n, T g0n, T y0n) {
+    Row<T> w;
+    w.A = -aL;
+    w.B = dgS - gL - a0n;
+    w.C = -g0n;
+    w.D = rS + yL + y0n;
+    return w;
+}
+
+// Parallel cyclic reduction over segments of `P` consecutive lanes of a wave
+// (P a power of two <= 64; lane's position in its segment is `ls`).  Rows
+// outside the segment are identity rows.  Returns S_ls.
+template <typename T>
+__device__ __forceinline__ T pcr_wave(Row<T> w, int ls, int P) {
+    for (int s = 1; s < P; s <<= 1) {
+        const T Am = __shfl_up(w.A, s, P), Bm = __shfl_up(w.B, s, P);
+        const T Cm = __shfl_up(w.C, s, P), Dm = __shfl_up(w.D, s, P);
+        const T Ap = __shfl_down(w.A, s, P), Bp = __shfl_down(w.B, s, P);
+        const T Cp = __shfl_down(w.C, s, P), Dp = __shfl_down(w.D, s, P);
+        const bool hm = ls - s >= 0, hp = ls + s < P;
+        const T k1 = hm ? w.A * recip(Bm) : T(0);
+        const T k2 = hp ? w.C * recip(Bp) : T(0);
+        Row<T> n;
+        n.A = hm ? -k1 * Am : T(0);
+        n.C = hp ? -k2 * Cp : T(0);
+        n.B = w.B - (hm ? k1 * Cm : T(0)) - (hp ? k2 * Ap : T(0));
+        n.D = w.D - (hm ? k1 * Dm : T(0)) - (hp ? k2 * Dp : T(0));
+        w = n;
+    }
+    return w.D * recip(w.B);
+}
+
+// Final values of one chunk given S_{l-1} (Sp), S_l (S) and the first slot of
+// chunk l+1 (xn, with its U_e value uen for CH = 1).  Writes E' and H' for
+// slot i into eo[i], ho[i].
+template <typename T, int M, int CE, int CH>
+__device__ __forceinline__ void chunk_finish(const Chunk<T, M>& c, T Sp, T S, T xn, T uen, T q,
+                                             T (&eo)[M], T (&ho)[M]) {
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) {
+        eo[i] = c.W[i] + c.al[i] * Sp + c.ga[i] * S;
+        ho[i] = c.Z[i] + q * ((c.al[i + 1] - c.al[i]) * Sp + (c.ga[i + 1] - c.ga[i]) * S);
+    }
+    eo[M - 1] = S + T(CE) * c.W[M - 1];
+    ho[M - 1] = c.Z[M - 1] + q * ((xn - S) + T(CH) * (uen - c.W[M - 1]));
+}
+
+}  // namespace fdtd

@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every symbol of include/fdtd.h and rejects
+invalid arguments before any device work (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2011_14043_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfdtd.so not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_exports_every_header_symbol(L):
+    syms = _header_symbols()
+    assert "fdtd_plan" in syms and "fdtd_run" in syms and "fdtd_destroy" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_binding_names_match_header():
+    from paper_2011_14043_amd import _lib
+    assert sorted(_lib.EXPORTS) == _header_symbols()
+
+
+def test_strerror(L):
+    for code, name in ((0, b"ok"), (-1, b"invalid argument"), (-4, b"not supported by this build")):
+        assert L.fdtd_strerror(code) == name
+
+
+def _desc(**kw):
+    from paper_2011_14043_amd import _lib
+    d = dict(nx=8, ny=8, nz=8, dt=1e-12, dx=1e-3, dy=1e-3, dz=1e-3, scheme=0, form=0, dtype=0,
+             eps_r=None, mu_r=None, boundary=0)
+    d.update(kw)
+    return _lib.FdtdDesc(**d)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=1), -1), (dict(ny=0), -1), (dict(nz=-3), -1), (dict(dt=0.0), -1), (dict(dt=-1e-12), -1),
+    (dict(dx=0.0), -1), (dict(dt=float("nan")), -1), (dict(dz=float("inf")), -1),
+    (dict(scheme=4), -1), (dict(form=2), -1), (dict(dtype=7), -1),
+    (dict(boundary=1), -4), (dict(mu_r=12345), -4), (dict(nx=2000), -4), (dict(nz=600, dtype=1), -4),
+])
+def test_plan_rejects_invalid(L, kw, status):
+    d = _desc(**kw)
+    h = ctypes.c_void_p()
+    assert L.fdtd_plan(ctypes.byref(d), None, ctypes.byref(h)) == status
+    assert not h.value
+
+
+def test_null_arguments(L):
+    h = ctypes.c_void_p()
+    assert L.fdtd_plan(None, None, ctypes.byref(h)) == -1
+    assert L.fdtd_plan(ctypes.byref(_desc()), None, None) == -1
+    assert L.fdtd_run(None, None, None, 1, None, None, 1) == -1
+    assert L.fdtd_step(None, None, None, None) == -1
+    assert L.fdtd_set_step(None, 0) == -1
+    assert L.fdtd_destroy(None) == -1
+    assert L.fdtd_last_timing(None, None, None, None) == -1
+
+
+def test_forced_allocation_failure(L, monkeypatch):
+    monkeypatch.setenv("FDTD_TEST_FAIL_ALLOC", "1")
+    h = ctypes.c_void_p()
+    assert L.fdtd_plan(ctypes.byref(_desc()), None, ctypes.byref(h)) == -2
+    assert not h.value

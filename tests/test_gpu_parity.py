@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (energy-weighted relative L2 over all six components, see
+DESIGN.md "Parity bar"): FP64 path 1e-11; FP32 path 2e-6 per 10 steps of
+growth allowance on these short runs (1e-4 is the bar after 1000 steps).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.source import Source as OSource
+
+from . import _analytic as an
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _lib():
+    from paper_2011_14043_amd import Plan, Source
+    return Plan, Source
+
+
+PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
+        "f32s64": (torch.float32, torch.float64)}
+
+
+def gpu_run(scheme, form, dtype, nx, ny, nz, dt, h, eps, u0, steps, src=None, every=0):
+    """dtype: a key of PREC or a torch dtype."""
+    Plan, Source = _lib()
+    dtype, solve = PREC[dtype] if isinstance(dtype, str) else (dtype, dtype)
+    dev = torch.device(DEV)
+    hx, hy, hz = h if isinstance(h, tuple) else (h, h, h)
+    E = [torch.tensor(a, dtype=dtype, device=dev) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=dtype, device=dev) for a in u0[3:]]
+    plan = Plan(nx, ny, nz, dt, hx, hy, hz, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
+                eps_r=None if eps is None else torch.tensor(eps))
+    s = None
+    if src is not None:
+        s = Source(src.i, src.j, src.k, f0=src.f0, tau=src.tau, t0=src.t0, amp=src.amp)
+    tr = plan.run(E, H, steps, source=s, energy_every=every)
+    torch.cuda.synchronize()
+    plan.close()
+    return [t.double().cpu().numpy() for t in E + H], tr
+
+
+TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
+
+
+@pytest.fixture(scope="module")
+def ragged_case():
+    """37 x 45 x 70 cells: ragged x tiles, several chunks per line, CFL 10,
+    random boxes, random fields, a point source; oracle per scheme."""
+    nx, ny, nz, h = 37, 45, 70, 1e-3
+    dt = W.yee_dt(h, h, h, 10.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=2, nboxes=8)
+    u0 = W.random_fields(nx, ny, nz, seed=3)
+    ci = W.interior_cell(nx, ny, nz, seed=4)
+    src = OSource(*ci, amp=1e12, t0=3 * dt, tau=3 * dt, f0=1 / (12 * dt))
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    refs = {s: oracle.run(s, "fundamental", g, u0, 12, src, 3) for s in oracle.SCHEMES}
+    return dict(nx=nx, ny=ny, nz=nz, h=h, dt=dt, eps=eps, u0=u0, src=src, g=g, refs=refs)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s64"])
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_ragged_parity(ragged_case, scheme, form, dtype):
+    c = ragged_case
+    print(f"[case] ragged 37x45x70 {scheme}/{form}/{dtype}", flush=True)
+    got, tr = gpu_run(scheme, form, dtype, c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], c["u0"], 12,
+                      c["src"], 3)
+    ref, tr_ref = c["refs"][scheme]
+    err = oracle.yee.weighted_rel_l2(got, ref, c["g"])
+    terr = np.max(np.abs(np.array(tr) - np.array(tr_ref)) / np.abs(np.array(tr_ref)))
+    print(f"  rel-L2 {err:.3e}  energy {terr:.3e}")
+    assert err < TOL[dtype]
+    assert terr < 10 * TOL[dtype]
+    # outside-the-box entries untouched, wall-tangential E exactly 0
+    for n, comp in enumerate(W.COMPONENTS):
+        if comp[0] == "E":
+            wall = W.wall_tangential_mask(comp, c["nx"], c["ny"], c["nz"]) & \
+                W.extent_mask(comp, c["nx"], c["ny"], c["nz"])
+            assert np.all(got[n][wall] == 0.0)
+        out = ~W.extent_mask(comp, c["nx"], c["ny"], c["nz"])
+        assert np.array_equal(got[n][out], c["u0"][n][out].astype(got[n].dtype))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s64"])
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+def test_config1_cavity_200_steps(dtype, form):
+    """24^3 vacuum PEC cavity, 1 mm, CFL 4, N(0,1) fields, 200 steps, energy
+    trace every step (the small configuration)."""
+    n, h = 24, 1e-3
+    dt = W.yee_dt(h, h, h, 4.0)
+    u0 = W.random_fields(n, n, n, seed=1)
+    g = oracle.Grid(n, n, n, h, h, h, dt)
+    ref, tr_ref = oracle.run("adi", "fundamental", g, u0, 200, None, 1)
+    got, tr = gpu_run("adi", form, dtype, n, n, n, dt, h, None, u0, 200, None, 1)
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    tr, tr_ref = np.array(tr), np.array(tr_ref)
+    drift = np.max(np.abs(tr - tr[0])) / tr[0]
+    print(f"[case] config1 {form}/{dtype}: rel-L2 {err:.3e}, drift {drift:.3e}")
+    tol = {"f64": 1e-11, "f32": 1e-5, "f32s64": 2e-6}[dtype]
+    assert err < tol
+    assert np.max(np.abs(tr - tr_ref) / tr_ref) < tol
+    assert drift < {"f64": 1e-12, "f32": 1e-5, "f32s64": 1e-6}[dtype]
+
+
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+def test_anisotropic_long_lines(scheme, form):
+    """Unequal cell sizes and a 600-cell axis (larger chunks) in FP32 and FP64."""
+    nx, ny, nz = 600, 9, 7
+    hs = (0.9e-3, 1.3e-3, 1.1e-3)
+    dt = W.yee_dt(*hs, 6.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=5, nboxes=10)
+    u0 = W.random_fields(nx, ny, nz, seed=6)
+    g = oracle.Grid(nx, ny, nz, *hs, dt, eps)
+    ref, _ = oracle.run(scheme, "fundamental", g, u0, 6)
+    got, _ = gpu_run(scheme, form, "f32", nx, ny, nz, dt, hs, eps, u0, 6)
+    assert oracle.yee.weighted_rel_l2(got, ref, g) < 1e-5
+    g2 = oracle.Grid(7, 9, 300, *hs, dt)  # z-long lines in FP64 (<= 512 cells)
+    u1 = W.random_fields(7, 9, 300, seed=7)
+    ref2, _ = oracle.run(scheme, "fundamental", g2, u1, 4)
+    got2, _ = gpu_run(scheme, form, "f64", 7, 9, 300, dt, hs, None, u1, 4)
+    assert oracle.yee.weighted_rel_l2(got2, ref2, g2) < 1e-11
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (2, 3, 4), (5, 2, 3), (64, 2, 2)])
+def test_degenerate_small_grids(dims):
+    nx, ny, nz = dims
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 3.0)
+    u0 = W.random_fields(nx, ny, nz, seed=8)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt)
+    for scheme in ("adi", "lod2"):
+        ref, _ = oracle.run(scheme, "fundamental", g, u0, 5)
+        for form in ("fundamental", "conventional"):
+            got, _ = gpu_run(scheme, form, "f64", nx, ny, nz, dt, h, None, u0, 5)
+            assert oracle.yee.weighted_rel_l2(got, ref, g) < 1e-11
+
+
+def test_zero_steps_leaves_fields():
+    n, h = 8, 1e-3
+    dt = W.yee_dt(h, h, h, 2.0)
+    u0 = W.random_fields(n, n, n, seed=9)
+    got, tr = gpu_run("adi", "fundamental", "f64", n, n, n, dt, h, None, u0, 0, None, 1)
+    for a, b in zip(got, u0):
+        assert np.array_equal(a, b)
+    g = oracle.Grid(n, n, n, h, h, h, dt)
+    assert abs(tr[0] - oracle.conventional.invariant("adi", oracle.yee.clean(u0, g), g)) < 1e-12 * tr[0]
+
+
+def _mode_on_gpu(nx, ny, nz, h, mnp, amps, dtype):
+    """Cavity mode (m, n, p) sampled on the GPU (test-side helper)."""
+    (kx, ky, kz), _ = an.wavenumbers(nx, ny, nz, h, h, h, *mnp)
+    dev = torch.device(DEV)
+    f64 = torch.float64
+
+    def ax(n_, k_, half):
+        x = (torch.arange(n_ + 1, device=dev, dtype=f64) + half) * h * k_
+        return x
+
+    xi, xh = ax(nx, kx, 0.0), ax(nx, kx, 0.5)
+    yi, yh = ax(ny, ky, 0.0), ax(ny, ky, 0.5)
+    zi, zh = ax(nz, kz, 0.0), ax(nz, kz, 0.5)
+    s, c = torch.sin, torch.cos
+    prof = [
+        (s(zi), s(yi), c(xh)), (s(zi), c(yh), s(xi)), (c(zh), s(yi), s(xi)),
+        (c(zh), c(yh), s(xi)), (c(zh), s(yi), c(xh)), (s(zi), c(yh), c(xh)),
+    ]
+    out = []
+    for n_, (pz, py, px) in enumerate(prof):
+        a = amps[n_] * pz[:, None, None] * py[None, :, None] * px[None, None, :]
+        comp = W.COMPONENTS[n_]
+        # extent, wall-tangential E
+        if comp in ("Ex", "Hy", "Hz"):
+            a[:, :, nx] = 0
+        if comp in ("Ey", "Hx", "Hz"):
+            a[:, ny, :] = 0
+        if comp in ("Ez", "Hx", "Hy"):
+            a[nz, :, :] = 0
+        if comp == "Ex":
+            a[:, [0, ny], :] = 0
+            a[[0, nz], :, :] = 0
+        if comp == "Ey":
+            a[:, :, [0, nx]] = 0
+            a[[0, nz], :, :] = 0
+        if comp == "Ez":
+            a[:, :, [0, nx]] = 0
+            a[:, [0, ny], :] = 0
+        out.append(a.to(dtype).contiguous())
+    return out
+
+
+@pytest.mark.parametrize("n,prec,steps", [(128, "f64", 20), (512, "f32", 10), (512, "f32s64", 10)],
+                         ids=["128-f64", "512-f32", "512-f32s64"])
+def test_cavity_mode_at_full_size(n, prec, steps):
+    """A PEC cavity mode evolves by the exact 6x6 ADI amplification matrix at
+    any grid size (property pin at the benchmark size, 512^3)."""
+    Plan, _ = _lib()
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    mnp = (3, 2, 5)
+    a = np.random.default_rng(11).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(n, n, n, h, h, h, *mnp)
+    M = an.scheme_matrix("adi", A6, B6, dt)
+    amp = np.linalg.matrix_power(M, steps) @ a
+    dtype, solve = PREC[prec]
+    fields = _mode_on_gpu(n, n, n, h, mnp, a, dtype)
+    plan = Plan(n, n, n, dt, h, h, h, scheme="adi", form="fundamental", dtype=dtype, solve_dtype=solve)
+    plan.run(fields[:3], fields[3:], steps)
+    torch.cuda.synchronize()
+    plan.close()
+    ref = _mode_on_gpu(n, n, n, h, mnp, amp, torch.float64)
+    w = [8.8541878128e-12] * 3 + [1.25663706212e-6] * 3
+    num = sum(wi * float(torch.sum((f.double() - r) ** 2)) for wi, f, r in zip(w, fields, ref))
+    den = sum(wi * float(torch.sum(r ** 2)) for wi, r in zip(w, ref))
+    err = math.sqrt(num / den)
+    print(f"[case] cavity mode {n}^3 {prec}: rel-L2 {err:.3e}")
+    assert err < {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}[prec]
+
+
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_energy_conserved_cfl20(scheme):
+    n, h = 40, 1e-3
+    dt = W.yee_dt(h, h, h, 20.0)
+    eps = W.random_box_eps(n, n, n, seed=12, nboxes=8)
+    u0 = W.random_fields(n, n, n, seed=13)
+    # pure FP32 solves drift by ~2e-7 per step at CFL 20 (coherent rounding of
+    # the pivots 2 + sigma - g when sigma = 1/(2 beta) << 1); FP64 solves on
+    # FP32 fields drift only by random storage rounding
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-4), ("f32s64", 2e-6)):
+        _, tr = gpu_run(scheme, "fundamental", dtype, n, n, n, dt, h, eps, u0, 100, None, 10)
+        tr = np.array(tr)
+        drift = np.max(np.abs(tr - tr[0])) / tr[0]
+        print(f"[case] energy {scheme} {dtype} drift {drift:.3e}")
+        assert drift < tol
