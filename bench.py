@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--variants", default="all", help="'all', 'none' or comma list scheme/form/prec")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -133,6 +135,15 @@ def main():
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import torch
+    if args.copy_probe:
+        nel = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nel * 4, "copies": 5}), flush=True)
+        return
     n = args.n
     inputs = make_inputs(n)
     log(f"[bench] {n}^3, {args.steps} steps, warmup {args.warmup}")
