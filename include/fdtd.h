@@ -125,6 +125,29 @@ fdtd_status fdtd_set_step(fdtd_plan_t p, long long n);
 fdtd_status fdtd_set_timing(fdtd_plan_t p, int per_launch);
 fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* pass_ms_avg, int* pass_launches);
 
+/* Kernel configuration of the line passes along one axis (0 = x, 1 = y, 2 = z):
+ *   chunk          slots of a line held by one thread (8, 16 or 32)
+ *   tile_x         y/z lines: consecutive x positions per block (8, 16, 32); 0 for x
+ *   block_threads  x lines: threads per block (64, 128, 256);
+ *                  y/z lines: block-size bound of the variant (256, 512, 1024)
+ *   remap          1 = XCD-aware block order, 0 = plain order
+ * Every configuration computes the same result up to rounding order.
+ * fdtd_set_kernel_config returns FDTD_EINVAL for a variant that is not built
+ * or does not fit the axis length. */
+typedef struct { int chunk, tile_x, block_threads, remap; } fdtd_kernel_config;
+fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* c);
+fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_config* c);
+
+/* Autotuner: times every valid configuration of the A-operator pass of each
+ * axis (`reps` launches each, HIP events on the plan's stream, on the plan's
+ * internal state, whose contents it overwrites) and keeps the fastest.  If
+ * the environment variable FDTD_TUNE_CACHE names a file, a cached choice for
+ * the same (nx, ny, nz, dtype, scheme, form) is used instead of timing, and a
+ * new choice is appended to the file (one JSON object per line).
+ * best_ms (host array of 3, may be NULL) receives the best mean launch time
+ * per axis (0 when taken from the cache).  Synchronizes the stream. */
+fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms);
+
 fdtd_status fdtd_destroy(fdtd_plan_t p);
 const char* fdtd_strerror(fdtd_status s);
 

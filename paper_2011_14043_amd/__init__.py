@@ -133,6 +133,23 @@ class Plan:
         return {"main_ms": main.value, "yz_ms_avg": avg[0], "x_ms_avg": avg[1],
                 "yz_launches": cnt[0], "x_launches": cnt[1]}
 
+    def kernel_config(self, axis: int) -> dict:
+        """Kernel configuration of the passes along axis 0 (x), 1 (y), 2 (z)."""
+        c = _lib.FdtdKernelConfig()
+        _lib.check(_lib.lib().fdtd_get_kernel_config(self._h, axis, ctypes.byref(c)), "fdtd_get_kernel_config")
+        return {"chunk": c.chunk, "tile_x": c.tile_x, "block_threads": c.block_threads, "remap": c.remap}
+
+    def set_kernel_config(self, axis: int, chunk: int, tile_x: int = 0, block_threads: int = 256, remap: int = 1):
+        c = _lib.FdtdKernelConfig(chunk, tile_x, block_threads, remap)
+        _lib.check(_lib.lib().fdtd_set_kernel_config(self._h, axis, ctypes.byref(c)), "fdtd_set_kernel_config")
+
+    def autotune(self, reps: int = 3):
+        """Time every valid kernel configuration per axis and keep the fastest;
+        returns the best mean launch time per axis [ms]."""
+        best = (ctypes.c_double * 3)()
+        _lib.check(_lib.lib().fdtd_autotune(self._h, int(reps), best), "fdtd_autotune")
+        return list(best)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(_lib.lib().fdtd_destroy(self._h), "fdtd_destroy")

@@ -19,7 +19,8 @@ FORMS = {"fundamental": 0, "conventional": 1}
 DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2}
 
 EXPORTS = ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
-           "fdtd_last_timing", "fdtd_destroy", "fdtd_strerror")
+           "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
+           "fdtd_destroy", "fdtd_strerror")
 
 
 class FdtdDesc(ctypes.Structure):
@@ -34,6 +35,11 @@ class FdtdSource(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int), ("j", ctypes.c_int), ("k", ctypes.c_int),
                 ("f0", ctypes.c_double), ("tau", ctypes.c_double), ("t0", ctypes.c_double),
                 ("amp", ctypes.c_double)]
+
+
+class FdtdKernelConfig(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int), ("tile_x", ctypes.c_int), ("block_threads", ctypes.c_int),
+                ("remap", ctypes.c_int)]
 
 
 class FdtdError(RuntimeError):
@@ -63,11 +69,15 @@ def lib() -> ctypes.CDLL:
     L.fdtd_set_timing.argtypes = [vp, ctypes.c_int]
     L.fdtd_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int)]
+    L.fdtd_get_kernel_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FdtdKernelConfig)]
+    L.fdtd_set_kernel_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FdtdKernelConfig)]
+    L.fdtd_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.fdtd_destroy.argtypes = [vp]
     L.fdtd_strerror.argtypes = [ctypes.c_int]
     L.fdtd_strerror.restype = ctypes.c_char_p
     for name in ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
-                 "fdtd_last_timing", "fdtd_destroy"):
+                 "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
+                 "fdtd_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/fdtd.h"
@@ -47,6 +48,16 @@ static const SchemeDef kSchemes[4] = {
     {2, {{0, 0.5, 0.5}, {1, 0.5, 1.0}, {0, 0, 0}}},            // LOD2
 };
 
+// Kernel configuration of the passes along one line axis.
+//   x lines: M (slots per lane), wpb (waves per block), remap
+//   y/z lines: M (slots per thread), TX (x positions per block),
+//              NT (block-size bound of the instantiation), remap
+struct KCfg { int M, TX, NT, wpb, remap; };
+
+// Instantiated y/z-line variants {M, TX, NT} by solve precision.
+static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {8, 8, 512}, {32, 16, 512}, {32, 8, 256}};
+static const int kYzF64[][3] = {{16, 16, 512}, {16, 8, 256}, {8, 8, 512}};
+
 struct Timing {
     bool per_launch = false;
     hipEvent_t main0 = nullptr, main1 = nullptr;
@@ -72,6 +83,8 @@ struct fdtd_plan_s {
     int energy_cap = 0;
     long long step = 0;
     fdtd::Timing tm;
+    fdtd::KCfg cfg[3];        // per line axis x, y, z
+    int tuned = 0;
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
     int fam_n[2] = {0, 0};
@@ -149,9 +162,12 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         a.cH2 = S(sy * h * h * mu / (ht * theta));
         a.hE3 = S(sy * theta / (mu * he));
     }
-    a.src = -1;
-    if (src && gval != 0.0 && pd.ce == 2) {
-        a.src = (long long)src->k * d.plane + (long long)src->j * d.px + src->i;
+    a.comp = d.comp;
+    a.src_a = a.src_b = a.src_j = -1;
+    int src_idx[3] = {0, 0, 0};
+    const bool has_src = src && gval != 0.0 && pd.ce == 2;
+    if (has_src) {
+        src_idx[0] = src->i; src_idx[1] = src->j; src_idx[2] = src->k;
         if (mode == FUND) {
             a.src_pre = S(0.5 * gval);
             a.src_post = (p->d.scheme == FDTD_ADI) ? S(0.5 * gval) : S(0);
@@ -177,18 +193,29 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         tm.used += 2;
         HIPCHK(hipEventRecord(e0, p->stream));
     }
+    const KCfg& cf = p->cfg[pd.w];
+    a.remap = cf.remap;
     if (pd.w == 0) {
-        // x lines: a = e axis, b = t axis
-        a.sa = axis_stride(d, pd.e);
-        a.sb = axis_stride(d, pd.t);
-        a.a_lo = 0; a.na = ne;
-        a.b_lo = 1; a.nb = nt - 1;
-        const int M = (a.n_w <= 512) ? 8 : 16;
+        // x lines: a = y (fast), b = z (slow), so that line order is memory
+        // order and every line of a wave lies after the wave's first line.
+        // The e axis starts at 0, the t axis at 1 (t = 0 is a PEC wall plane).
+        a.sa = axis_stride(d, 1);
+        a.sb = axis_stride(d, 2);
+        if (pd.e == 1) { a.a_lo = 0; a.na = d.ny; a.b_lo = 1; a.nb = d.nz - 1; }
+        else { a.a_lo = 1; a.na = d.ny - 1; a.b_lo = 0; a.nb = d.nz; }
+        if (has_src) { a.src_a = src_idx[1]; a.src_b = src_idx[2]; a.src_j = src_idx[0]; }
+        const int M = cf.M;
         a.P = next_pow2((a.n_w + M - 1) / M);
         const long long nlines = (long long)a.na * a.nb;
-        const long long lines_per_block = 4LL * (64 / a.P);
-        const dim3 grid((unsigned)((nlines + lines_per_block - 1) / lines_per_block));
-#define LAUNCH_X(MM, MO) hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO>), grid, dim3(256), 0, p->stream, a)
+        const long long lines_per_block = (long long)cf.wpb * (64 / a.P);
+        a.nblk = (int)((nlines + lines_per_block - 1) / lines_per_block);
+        const dim3 grid((unsigned)a.nblk), block(64 * cf.wpb);
+        const bool full = a.P * M == a.n_w;
+#define LAUNCH_X(MM, MO)                                                                                   \
+    do {                                                                                                   \
+        if (full) hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO, true>), grid, block, 0, p->stream, a);   \
+        else hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO, false>), grid, block, 0, p->stream, a);       \
+    } while (0)
         if (M == 8) {
             if (mode == FUND) LAUNCH_X(8, FUND); else if (mode == CONV_LOD) LAUNCH_X(8, CONV_LOD); else LAUNCH_X(8, CONV_ADI);
         } else {
@@ -202,29 +229,33 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         a.sb = axis_stride(d, other);
         if (pd.e == 0) { a.a_lo = 0; a.na = d.nx; a.b_lo = 1; a.nb = nt - 1; }
         else { a.a_lo = 1; a.na = d.nx - 1; a.b_lo = 0; a.nb = ne; }
-        // chunk size M, x positions per block TX, block bound NT (= TX * max P)
-        constexpr bool f32solve = sizeof(S) == 4;
-        int M, TX;
-        if (f32solve) { if (a.n_w <= 512) { M = 16; TX = 32; } else { M = 32; TX = 16; } }
-        else { M = 16; TX = 16; }
+        if (has_src) { a.src_a = src_idx[0]; a.src_b = src_idx[other]; a.src_j = src_idx[pd.w]; }
+        const int M = cf.M, TX = cf.TX, NT = cf.NT;
         a.P = next_pow2((a.n_w + M - 1) / M);
-        const dim3 block(TX * a.P);
-        const dim3 grid((unsigned)((a.a_lo + a.na + TX - 1) / TX), (unsigned)a.nb);
+        a.ntx = (a.a_lo + a.na + TX - 1) / TX;
+        a.nblk = a.ntx * a.nb;
+        const dim3 block(TX * a.P), grid((unsigned)a.nblk);
         const size_t lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
-#define LAUNCH_YZ(MM, MO, TT, NN) \
-    hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN>), grid, block, lds, p->stream, a)
+        const bool full = a.P * M == a.n_w;
+#define LAUNCH_YZ(MM, MO, TT, NN)                                                                              \
+    do {                                                                                                       \
+        if (full) hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN, true>), grid, block, lds, p->stream, a); \
+        else hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN, false>), grid, block, lds, p->stream, a);     \
+    } while (0)
 #define LAUNCH_YZ3(MM, TT, NN)                                              \
     do {                                                                    \
         if (mode == FUND) LAUNCH_YZ(MM, FUND, TT, NN);                      \
         else if (mode == CONV_LOD) LAUNCH_YZ(MM, CONV_LOD, TT, NN);         \
         else LAUNCH_YZ(MM, CONV_ADI, TT, NN);                               \
     } while (0)
-        if constexpr (f32solve) {
-            if (M == 16) LAUNCH_YZ3(16, 32, 1024);
-            else LAUNCH_YZ3(32, 16, 512);
+#define CASE_YZ(MM, TT, NN) if (M == MM && TX == TT && NT == NN) { LAUNCH_YZ3(MM, TT, NN); } else
+        if constexpr (sizeof(S) == 4) {
+            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(8, 8, 512)
+            CASE_YZ(32, 16, 512) CASE_YZ(32, 8, 256) return FDTD_EUNSUPPORTED;
         } else {
-            LAUNCH_YZ3(16, 16, 512);
+            CASE_YZ(16, 16, 512) CASE_YZ(16, 8, 256) CASE_YZ(8, 8, 512) return FDTD_EUNSUPPORTED;
         }
+#undef CASE_YZ
 #undef LAUNCH_YZ3
 #undef LAUNCH_YZ
     }
@@ -243,6 +274,150 @@ static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& 
     }
     cur = out;
     return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel configurations and the autotuner
+// ---------------------------------------------------------------------------
+static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
+    const int n = axis_cells(p->dims, axis);
+    if (c.remap != 0 && c.remap != 1) return false;
+    if (axis == 0) {
+        if (c.M != 8 && c.M != 16) return false;
+        if (c.wpb < 1 || c.wpb > 4) return false;
+        return next_pow2((n + c.M - 1) / c.M) <= 64;
+    }
+    bool inst = false;
+    if (p->d.dtype == FDTD_F32) {
+        for (const auto& v : kYzF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
+    } else {
+        for (const auto& v : kYzF64) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
+    }
+    if (!inst) return false;
+    const int P = next_pow2((n + c.M - 1) / c.M);
+    return P <= 64 && c.TX * P <= c.NT;
+}
+
+static std::vector<KCfg> cfg_candidates(const fdtd_plan_s* p, int axis) {
+    std::vector<KCfg> out;
+    for (int remap = 1; remap >= 0; --remap) {
+        if (axis == 0) {
+            for (int M : {8, 16})
+                for (int wpb : {4, 2, 1}) {
+                    KCfg c{M, 0, 0, wpb, remap};
+                    if (cfg_valid(p, axis, c)) out.push_back(c);
+                }
+        } else if (p->d.dtype == FDTD_F32) {
+            for (const auto& v : kYzF32) {
+                KCfg c{v[0], v[1], v[2], 0, remap};
+                if (cfg_valid(p, axis, c)) out.push_back(c);
+            }
+        } else {
+            for (const auto& v : kYzF64) {
+                KCfg c{v[0], v[1], v[2], 0, remap};
+                if (cfg_valid(p, axis, c)) out.push_back(c);
+            }
+        }
+    }
+    return out;
+}
+
+// Untuned default: the first valid entry of the preference order.
+static void default_cfg(fdtd_plan_s* p) {
+    for (int axis = 0; axis < 3; ++axis) {
+        std::vector<KCfg> pref;
+        if (axis == 0) {
+            pref = {{8, 0, 0, 4, 1}, {16, 0, 0, 4, 1}};
+        } else if (p->d.dtype == FDTD_F32) {
+            pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {32, 8, 256, 0, 1},
+                    {8, 8, 512, 0, 1}, {8, 16, 1024, 0, 1}};
+        } else {
+            pref = {{16, 16, 512, 0, 1}, {16, 8, 256, 0, 1}, {8, 8, 512, 0, 1}};
+        }
+        for (const KCfg& c : pref)
+            if (cfg_valid(p, axis, c)) { p->cfg[axis] = c; break; }
+    }
+}
+
+template <typename T, typename S>
+static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
+    const bool adi = p->d.scheme == FDTD_ADI, conv = p->d.form == FDTD_CONVENTIONAL;
+    const int mode = conv ? (adi ? CONV_ADI : CONV_LOD) : FUND;
+    const double theta = 0.5 * p->d.dt;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    fdtd_status st = FDTD_OK;
+    for (int axis = 0; axis < 3 && st == FDTD_OK; ++axis) {
+        int k = 0;
+        while (kPairs[0][k].w != axis) ++k;
+        const std::vector<KCfg> cand = cfg_candidates(p, axis);
+        KCfg best = p->cfg[axis];
+        float tbest = 1e30f;
+        for (const KCfg& c : cand) {
+            p->cfg[axis] = c;
+            st = launch_pass<T, S>(p, 0, k, theta, mode, 0, conv && adi ? 1 : 0, nullptr, 0.0, false);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e0, p->stream) != hipSuccess) { st = FDTD_EDEVICE; break; }
+            for (int r = 0; r < reps && st == FDTD_OK; ++r)
+                st = launch_pass<T, S>(p, 0, k, theta, mode, 0, conv && adi ? 1 : 0, nullptr, 0.0, false);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = FDTD_EDEVICE;
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < tbest) { tbest = ms; best = c; }
+        }
+        p->cfg[axis] = best;
+        if (best_ms) best_ms[axis] = tbest / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == FDTD_OK) p->tuned = 1;
+    return st;
+}
+
+// Text cache of tuned configurations: one line per key
+//   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>", "cfg": [[M,TX,NT,wpb,remap],[...],[...]]}
+static std::string tune_key(const fdtd_plan_s* p) {
+    char b[160];
+    std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme, p->d.form);
+    return b;
+}
+
+static bool tune_cache_lookup(fdtd_plan_s* p, const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string key = tune_key(p);
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[160];
+        KCfg c[3];
+        if (std::sscanf(line, " {\"key\": \"%159[^\"]\", \"cfg\": [[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d]]}", k,
+                        &c[0].M, &c[0].TX, &c[0].NT, &c[0].wpb, &c[0].remap, &c[1].M, &c[1].TX, &c[1].NT, &c[1].wpb,
+                        &c[1].remap, &c[2].M, &c[2].TX, &c[2].NT, &c[2].wpb, &c[2].remap) != 16)
+            continue;
+        if (key != k) continue;
+        if (cfg_valid(p, 0, c[0]) && cfg_valid(p, 1, c[1]) && cfg_valid(p, 2, c[2])) {
+            for (int a = 0; a < 3; ++a) p->cfg[a] = c[a];
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_cache_store(const fdtd_plan_s* p, const char* path) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    const KCfg* c = p->cfg;
+    std::fprintf(f, "{\"key\": \"%s\", \"cfg\": [[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d]]}\n",
+                 tune_key(p).c_str(), c[0].M, c[0].TX, c[0].NT, c[0].wpb, c[0].remap, c[1].M, c[1].TX, c[1].NT,
+                 c[1].wpb, c[1].remap, c[2].M, c[2].TX, c[2].NT, c[2].wpb, c[2].remap);
+    std::fclose(f);
 }
 
 static double source_value(const fdtd_source* src, double theta, double t) {
@@ -458,6 +633,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if ((e = hipMalloc(&p->eps, sizeof(float) * dm.comp)) != hipSuccess) return fail(from_hip(e));
     if ((e = hipMemcpy(p->eps, en.data(), sizeof(float) * dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(from_hip(e));
+    default_cfg(p);
     p->npartial = 1024;
     if ((e = hipMalloc(&p->partial, sizeof(double) * p->npartial)) != hipSuccess) return fail(from_hip(e));
     *out = p;
@@ -521,6 +697,46 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* fam_ms_avg,
         if (fam_ms_avg) fam_ms_avg[f] = cnt[f] ? tot[f] / cnt[f] : 0.0;
         if (fam_launches) fam_launches[f] = cnt[f];
     }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
+    if (!plan_ok(p) || reps < 1) return FDTD_EINVAL;
+    const char* cache = std::getenv("FDTD_TUNE_CACHE");
+    if (cache && *cache && tune_cache_lookup(p, cache)) {
+        p->tuned = 2;
+        if (best_ms) best_ms[0] = best_ms[1] = best_ms[2] = 0.0;
+        return FDTD_OK;
+    }
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    fdtd_status st;
+    if (p->d.dtype == FDTD_F32) st = autotune_impl<float, float>(p, reps, best_ms);
+    else if (p->d.dtype == FDTD_F64) st = autotune_impl<double, double>(p, reps, best_ms);
+    else st = autotune_impl<float, double>(p, reps, best_ms);
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    if (st == FDTD_OK && cache && *cache) tune_cache_store(p, cache);
+    return st;
+}
+
+fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* c) {
+    if (!plan_ok(p) || axis < 0 || axis > 2 || !c) return FDTD_EINVAL;
+    const KCfg& k = p->cfg[axis];
+    c->chunk = k.M;
+    c->tile_x = axis == 0 ? 0 : k.TX;
+    c->block_threads = axis == 0 ? 64 * k.wpb : k.NT;
+    c->remap = k.remap;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_config* c) {
+    if (!plan_ok(p) || axis < 0 || axis > 2 || !c) return FDTD_EINVAL;
+    KCfg k{c->chunk, axis == 0 ? 0 : c->tile_x, axis == 0 ? 0 : c->block_threads,
+           axis == 0 ? c->block_threads / 64 : 0, c->remap};
+    if (axis == 0 && c->block_threads % 64 != 0) return FDTD_EINVAL;
+    if (!cfg_valid(p, axis, k)) return FDTD_EINVAL;
+    p->cfg[axis] = k;
     return FDTD_OK;
 }
 

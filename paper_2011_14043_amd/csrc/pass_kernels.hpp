@@ -25,6 +25,12 @@
 // read from the previous state and written to the other buffer set.  With
 // H* = H + s3 d d_e E3 the right side is E + s b d_w H* + s2 b d_t H2, so the
 // kernel forms H* once per H sample and uses it in both equations.
+//
+// Memory access: every wave addresses its data through buffer resources whose
+// 64-bit base is wave-uniform (SGPRs) and whose size is the rest of the
+// array; a lane adds one 32-bit byte offset and each slot of a line adds a
+// uniform scalar offset, so the per-slot address arithmetic costs no vector
+// instructions, and loads past the end of an array return 0.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "line_solver.hpp"
@@ -42,158 +48,216 @@ struct PassArgs {
     const T* H2;          // CONV_ADI: H component of Y's E row (shifted along t)
     const T* E3;          // CONV_ADI: E component of Y's H row (shifted along e)
     const float* eps;     // relative permittivity at node index (node layout)
-    long long sw;         // stride along the line
+    long long sw;         // stride along the line (elements)
     long long sa, sb;     // strides of the transverse line indices a, b
     long long s_t, s_e;   // CONV_ADI: strides along t and e
+    long long comp;       // elements per component array
     int n_w;              // slots per line: 0 .. n_w-1 (slot 0 = wall)
     int a_lo, na, b_lo, nb;
     int P;                // chunks per line (power of two <= 64)
+    int ntx;              // y/z lines: x tiles per row of blocks
+    int nblk;             // number of blocks in the (1-D) grid
+    int remap;            // 1: XCD-aware block order
     double Ks;            // sigma = Ks * eps_r
     S kap_hi, kap_lo;     // coefficient of the H difference (double-float if S = float)
     S q;                  // H update coefficient
     S cH2, hE3;           // CONV_ADI cross-term coefficients
-    long long src;        // offset of the source sample in E (or -1)
+    int src_a, src_b, src_j;   // source sample in line coordinates (src_a < 0: none)
     S src_pre, src_post;
 };
+
+// Blocks are dispatched round-robin over the 8 XCDs (block L -> XCD L % 8),
+// each with its own L2.  With remap, XCD c receives a contiguous range of
+// work items, so spatially adjacent tiles (which share 128-byte lines and
+// neighbour rows) run on the same XCD at about the same time.
+__device__ __forceinline__ int xcd_remap(int L, int G) {
+    const int c = L & 7, q = L >> 3;
+    const int per = G >> 3, rem = G & 7;
+    return c * per + (c < rem ? c : rem) + q;
+}
 
 template <int MODE> struct ModeCE { static constexpr int v = (MODE == FUND) ? -1 : 0; };
 template <int MODE> struct ModeCH { static constexpr int v = (MODE == CONV_LOD) ? 1 : 0; };
 
-template <typename S> __device__ __forceinline__ S make_sigma(double Ks, float eps) {
-    return S(Ks * double(eps));
+// ---------------------------------------------------------------------------
+// buffer addressing
+// ---------------------------------------------------------------------------
+using Rsrc = __amdgpu_buffer_rsrc_t;
+using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(Rsrc(), 0, 0, 0));
+using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(Rsrc(), 0, 0, 0));
+
+// Buffer resource for array `arr` (n_elem elements of `esz` bytes) starting at
+// element `off` (may be past the end: then every access returns 0).
+__device__ __forceinline__ Rsrc make_rsrc(const void* arr, long long off, long long n_elem, int esz) {
+    const long long rem = (n_elem - off) * esz;
+    const unsigned nr = rem <= 0 ? 0u : (rem > 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned)rem);
+    const char* p = static_cast<const char*>(arr) + off * esz;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, (int)nr, 0x00020000);
+}
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    static __device__ __forceinline__ float ld(Rsrc r, int vo, int so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(float v, Rsrc r, int vo, int so) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
+};
+template <> struct Buf<double> {
+    static __device__ __forceinline__ double ld(Rsrc r, int vo, int so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(double v, Rsrc r, int vo, int so) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, vo, so, 0);
+    }
+};
+
+// Contiguous chunk of M elements at byte offset vo (16-byte aligned).
+template <typename T, int M>
+__device__ __forceinline__ void ld_chunk(Rsrc r, int vo, T (&v)[M]) {
+    constexpr int V = 16 / sizeof(T);
+    static_assert(M % V == 0, "chunk must be a multiple of 16 bytes");
+#pragma unroll
+    for (int b = 0; b < M / V; ++b) {
+        const V4 x = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16 * b, 0, 0);
+        if constexpr (sizeof(T) == 4) {
+            const float4 f = __builtin_bit_cast(float4, x);
+            v[4 * b] = f.x; v[4 * b + 1] = f.y; v[4 * b + 2] = f.z; v[4 * b + 3] = f.w;
+        } else {
+            const double2 f = __builtin_bit_cast(double2, x);
+            v[2 * b] = f.x; v[2 * b + 1] = f.y;
+        }
+    }
+}
+template <typename T, int M>
+__device__ __forceinline__ void st_chunk(Rsrc r, int vo, const T (&v)[M]) {
+    constexpr int V = 16 / sizeof(T);
+#pragma unroll
+    for (int b = 0; b < M / V; ++b) {
+        V4 x;
+        if constexpr (sizeof(T) == 4) {
+            x = __builtin_bit_cast(V4, make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]));
+        } else {
+            x = __builtin_bit_cast(V4, make_double2(v[2 * b], v[2 * b + 1]));
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, vo + 16 * b, 0, 0);
+    }
 }
 
-// Right side and diagonal of one slot.  ue_m/ue_p: U_e at j-1, j+1 (CONV_LOD);
-// uh_m: U_h at j-1; x2: CONV_ADI cross contribution (already scaled).
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// per-slot right-hand side
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ S make_sigma(double Ks, float eps) {
+    if constexpr (sizeof(S) == 4) return float(Ks) * eps;
+    else return Ks * double(eps);
+}
+
+// rhs and diagonal of one slot; x2 = CONV_ADI cross term (scaled)
 template <typename T, typename S, int MODE>
-__device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, bool dirichlet, bool is_src, float eps,
-                                         S ue, S uh, S uh_m, S ue_m, S ue_p, S x2, S& dg, S& r) {
-    if (dirichlet) {
-        dg = Big<S>::v;
-        r = S(0);
-        return;
-    }
+__device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, float eps, S ue, S uh, S uh_m, S ue_m, S ue_p,
+                                         S x2, S& dg, S& r) {
     const S sig = make_sigma<S>(a.Ks, eps);
     dg = S(2) + sig;
     const S dh = uh - uh_m;
-    const S hterm = dh * a.kap_hi + dh * a.kap_lo;
-    const S e0 = is_src ? ue + a.src_pre : ue;
+    S hterm = dh * a.kap_hi;
+    if constexpr (sizeof(S) == 4) hterm = __builtin_fmaf(dh, a.kap_lo, hterm);
     if constexpr (MODE == FUND) {
-        r = S(2) * sig * e0 + hterm;
+        r = (sig + sig) * ue + hterm;
     } else if constexpr (MODE == CONV_LOD) {
-        r = sig * e0 + hterm + ((ue_p + ue_m) - S(2) * ue);
+        r = sig * ue + hterm + ((ue_p + ue_m) - S(2) * ue);
     } else {
-        r = sig * e0 + hterm + x2;
+        r = sig * ue + hterm + x2;
     }
 }
 
-// ----------------------------------------------------------------------------
+// Source term at slot si of this chunk (rhs: 2 sigma pre or sigma pre).
+template <typename T, typename S, int MODE, int M>
+__device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, const float (&ep)[M], S (&r)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const S sig = make_sigma<S>(a.Ks, ep[i]);
+        const S coef = (MODE == FUND) ? sig + sig : sig;
+        r[i] += (i == si) ? coef * a.src_pre : S(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x lines: contiguous axis.  One line per segment of P lanes of a wave; lane
-// `ls` owns slots [ls*M, ls*M+M).  Rows are 128-byte aligned, so chunks are
-// loaded with 16-byte vector loads.  The separator system is solved with
-// cross-lane PCR (no LDS, no barrier).
-// ----------------------------------------------------------------------------
-template <typename T, int M>
-__device__ __forceinline__ void load_row_chunk(const T* p, int j0, int lim, T (&v)[M]) {
-    if (j0 + M <= lim) {
-        constexpr int V = 16 / sizeof(T);
-        static_assert(M % V == 0, "chunk must be a multiple of 16 bytes");
-        using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-        const V16* q = reinterpret_cast<const V16*>(p + j0);
-#pragma unroll
-        for (int b = 0; b < M / V; ++b) {
-            V16 x = q[b];
-            const T* xs = reinterpret_cast<const T*>(&x);
-#pragma unroll
-            for (int e = 0; e < V; ++e) v[b * V + e] = xs[e];
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < M; ++i) v[i] = (j0 + i < lim) ? p[j0 + i] : T(0);
-    }
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void load_row_chunk_f(const float* p, int j0, int lim, float (&v)[M]) {
-    if (j0 + M <= lim) {
-        const float4* q = reinterpret_cast<const float4*>(p + j0);
-#pragma unroll
-        for (int b = 0; b < M / 4; ++b) {
-            float4 x = q[b];
-            v[4 * b] = x.x; v[4 * b + 1] = x.y; v[4 * b + 2] = x.z; v[4 * b + 3] = x.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < M; ++i) v[i] = (j0 + i < lim) ? p[j0 + i] : 1.0f;
-    }
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void store_row_chunk(T* p, int j0, int lo, int hi, const T (&v)[M]) {
-    if (j0 >= lo && j0 + M <= hi) {
-        constexpr int V = 16 / sizeof(T);
-        using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-        V16* q = reinterpret_cast<V16*>(p + j0);
-#pragma unroll
-        for (int b = 0; b < M / V; ++b) {
-            V16 x;
-            T* xs = reinterpret_cast<T*>(&x);
-#pragma unroll
-            for (int e = 0; e < V; ++e) xs[e] = v[b * V + e];
-            q[b] = x;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-            if (j0 + i >= lo && j0 + i < hi) p[j0 + i] = v[i];
-    }
-}
-
-template <typename T, typename S, int M, int MODE>
+// `ls` owns slots [ls*M, ls*M+M), loaded with 16-byte buffer loads (rows are
+// 128-byte aligned).  The separator system is solved with cross-lane PCR.
+// FULL: P*M == n_w (no slot beyond the line).
+// ---------------------------------------------------------------------------
+template <typename T, typename S, int M, int MODE, bool FULL>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
+    constexpr int ES = (int)sizeof(T);
     const int P = a.P;
     const int lane = threadIdx.x & 63;
     const int ls = lane & (P - 1);
-    const long long line = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / P) + lane / P;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int blk = a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x);
     const long long nlines = (long long)a.na * a.nb;
+    const long long raw0 = ((long long)blk * (blockDim.x >> 6) + wave) * (64 / P);
+    const long long line = raw0 + lane / P;
     const bool live = line < nlines;
-    const long long L = live ? line : 0;
+    const long long line0 = raw0 < nlines ? raw0 : nlines - 1;   // wave base line (clamped)
+    const long long L = live ? line : line0;
     const int ia = a.a_lo + int(L % a.na), ib = a.b_lo + int(L / a.na);
-    const long long base = ia * a.sa + ib * a.sb;
+    const long long wbase = (long long)(a.a_lo + int(line0 % a.na)) * a.sa + (long long)(a.b_lo + int(line0 / a.na)) * a.sb;
+    const long long base = (long long)ia * a.sa + (long long)ib * a.sb;
     const int n = a.n_w;
     const int j0 = ls * M;
+    const int lel = int(base - wbase) + j0;           // element offset of the chunk from the wave base
+    const int vo = lel * ES, vo_e = lel * 4;
+    const Rsrc rE = make_rsrc(a.Ein, wbase, a.comp, ES), rH = make_rsrc(a.Hin, wbase, a.comp, ES);
+    const Rsrc rP = make_rsrc(a.eps, wbase, a.comp, 4);
 
     S ue[M], uh[M];
     float ep[M];
     {
         T te[M], th[M];
-        load_row_chunk<T, M>(a.Ein + base, j0, n + 1, te);
-        load_row_chunk<T, M>(a.Hin + base, j0, n, th);
+        ld_chunk<T, M>(rE, vo, te);
+        ld_chunk<T, M>(rH, vo, th);
+        ld_chunk<float, M>(rP, vo_e, ep);
 #pragma unroll
-        for (int i = 0; i < M; ++i) { ue[i] = S(te[i]); uh[i] = S(th[i]); }
+        for (int i = 0; i < M; ++i) {
+            const bool in = FULL || j0 + i < n;
+            ue[i] = in ? S(te[i]) : S(0);
+            uh[i] = in ? S(th[i]) : S(0);
+            ep[i] = in ? ep[i] : 1.0f;
+        }
     }
-    load_row_chunk_f<T, M>(a.eps + base, j0, n, ep);
-    const S uh_prev = (j0 > 0) ? S(a.Hin[base + j0 - 1]) : S(0);
+    const bool first = j0 == 0;
+    const bool beyond = j0 > n;
+    const int vo_prev = (first || beyond) ? vo : vo - ES;
+    const S uh_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rH, vo_prev, 0));
     S ue_prev = S(0), ue_next = S(0);
     if constexpr (MODE == CONV_LOD) {
-        ue_prev = (j0 > 0) ? S(a.Ein[base + j0 - 1]) : S(0);
-        ue_next = (j0 + M <= n) ? S(a.Ein[base + j0 + M]) : S(0);
+        ue_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rE, vo_prev, 0));
+        ue_next = (j0 + M <= n) ? S(Buf<T>::ld(rE, vo, M * ES)) : S(0);   // slot n (wall) exists
     }
     S x2[M];
     S uh_m_eff = uh_prev;
     if constexpr (MODE == CONV_ADI) {
+        const Rsrc r3 = make_rsrc(a.E3, wbase, a.comp, ES);
+        const Rsrc r2 = make_rsrc(a.H2, wbase, a.comp, ES);
+        const Rsrc r2m = make_rsrc(a.H2, wbase - a.s_t, a.comp, ES);   // the t-1 neighbour rows
+        const int se = (int)(a.s_e * ES);
+        T e3a[M], e3b[M], h2a[M], h2b[M];
+        ld_chunk<T, M>(r3, vo, e3a);
+        ld_chunk<T, M>(r3, vo + se, e3b);
+        ld_chunk<T, M>(r2, vo, h2a);
+        ld_chunk<T, M>(r2m, vo, h2b);
         S D[M + 1];
-#pragma unroll
-        for (int i = -1; i < M; ++i) {
-            const int j = j0 + i;
-            D[i + 1] = (j >= 0 && j < n) ? S(a.E3[base + j + a.s_e]) - S(a.E3[base + j]) : S(0);
-        }
+        D[0] = (first || beyond) ? S(0) : S(Buf<T>::ld(r3, vo_prev, se)) - S(Buf<T>::ld(r3, vo_prev, 0));
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-            const int j = j0 + i;
-            const S h2 = (j >= 1 && j < n) ? S(a.H2[base + j]) - S(a.H2[base + j - a.s_t]) : S(0);
-            x2[i] = a.cH2 * h2;
+            const bool in = FULL || j0 + i < n;
+            D[i + 1] = in ? S(e3b[i]) - S(e3a[i]) : S(0);
+            x2[i] = in ? a.cH2 * (S(h2a[i]) - S(h2b[i])) : S(0);
             uh[i] += a.hE3 * D[i + 1];
         }
         uh_m_eff += a.hE3 * D[0];
@@ -202,20 +266,27 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     S dg[M], r[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const int j = j0 + i;
-        const bool dir = (j == 0) || (j >= n);
-        const bool is_src = (a.src >= 0) && (base + j == a.src);
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        slot_rhs<T, S, MODE>(a, dir, is_src, ep[i], ue[i], uh[i], um, em, epv,
-                             (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        slot_rhs<T, S, MODE>(a, ep[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        if (!FULL) {
+            const bool out = j0 + i >= n;
+            dg[i] = out ? Big<S>::v : dg[i];
+            r[i] = out ? S(0) : r[i];
+        }
     }
+    dg[0] = first ? Big<S>::v : dg[0];   // the wall at slot 0
+    r[0] = first ? S(0) : r[0];
+    // point source (one sample of one line): wave-uniform branch
+    const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
+    const bool src_here = si >= 0 && si < M;
+    const bool src_wave = __ballot(src_here) != 0;
+    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, ep, r);
     Chunk<S, M> c;
     chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
 
-    // Separator system across the P lanes of the line.  Every lane executes
-    // every shuffle (a lane must not read from a lane that skipped it).
+    // separator system across the P lanes of the line (all lanes shuffle)
     const bool has_next = ls + 1 < P;
     const S a0n_r = __shfl_down(c.a0, 1, P), g0n_r = __shfl_down(c.g0, 1, P), y0n_r = __shfl_down(c.y0, 1, P);
     const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0), y0n = has_next ? y0n_r : S(0);
@@ -227,31 +298,42 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 
     S eo[M], ho[M];
     chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    eo[0] = first ? S(0) : eo[0];
+    if (MODE == FUND && __builtin_expect(src_wave, 0)) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
+    }
     T te[M], th[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-        const int j = j0 + i;
-        S e = eo[i];
-        if (MODE == FUND && a.src >= 0 && base + j == a.src) e -= a.src_post;
-        if (j == 0 || j >= n) e = S(0);
-        te[i] = T(e);
-        th[i] = T(ho[i]);
-    }
-    if (live) {
-        store_row_chunk<T, M>(a.Eout + base, j0, 1, n, te);
-        store_row_chunk<T, M>(a.Hout + base, j0, 0, n, th);
+    for (int i = 0; i < M; ++i) { te[i] = T(eo[i]); th[i] = T(ho[i]); }
+    if (!live) return;
+    const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
+    if (FULL || j0 + M <= n) {
+        st_chunk<T, M>(wE, vo, te);
+        st_chunk<T, M>(wH, vo, th);
+    } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (j0 + i < n) {
+                Buf<T>::st(te[i], wE, vo, i * ES);
+                Buf<T>::st(th[i], wH, vo, i * ES);
+            }
+        }
     }
 }
 
-// ----------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
 // y and z lines: strided axis.  A block holds TX consecutive x positions (the
 // transverse index a) times P chunks; thread t = tx + TX p.  Loads and stores
 // are coalesced across tx.  The separator rows go through LDS to segments of P
 // consecutive lanes, are reduced by cross-lane PCR, and S returns through LDS.
-// ----------------------------------------------------------------------------
-template <typename T, typename S, int M, int MODE, int TX, int NT>
+// FULL: P*M == n_w.
+// ---------------------------------------------------------------------------
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL>
 __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int CPW = 64 / TX;                  // chunks per wave
     extern __shared__ unsigned char smem_raw[];
     S* sm = reinterpret_cast<S*>(smem_raw);
     const int P = a.P;
@@ -263,43 +345,61 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     auto EP = [&](int k, int pp, int xx) -> S& { return ep_[(k * P + pp) * LD + xx]; };
     auto SB = [&](int pp, int xx) -> S& { return sb_[pp * LD + xx]; };
 
-    const int ia = blockIdx.x * TX + tx;
-    const int ib = a.b_lo + blockIdx.y;
+    const int blk = a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x);
+    const int tile0 = (blk % a.ntx) * TX;
+    const int ib = a.b_lo + blk / a.ntx;
+    const int ia = tile0 + tx;
     const bool live = ia >= a.a_lo && ia < a.a_lo + a.na;
-    const long long base = (long long)(live ? ia : a.a_lo) * a.sa + (long long)ib * a.sb;
+    const int wave = wave_uniform(t >> 6);
+    const int pw0 = wave * CPW;                  // first chunk of this wave
     const int n = a.n_w;
     const int j0 = p * M;
     const long long sw = a.sw;
+    // wave base: line (tile0, ib), slot pw0*M; lane element offset tx + (p-pw0)*M*sw
+    const long long wbase = (long long)tile0 * a.sa + (long long)ib * a.sb + (long long)pw0 * M * sw;
+    const int swb = (int)(sw * ES), swf = (int)(sw * 4);
+    const int lel = tx + (p - pw0) * M * (int)sw;
+    const int vo = lel * ES, vo_e = lel * 4;
+    const Rsrc rE = make_rsrc(a.Ein, wbase, a.comp, ES), rH = make_rsrc(a.Hin, wbase, a.comp, ES);
+    const Rsrc rP = make_rsrc(a.eps, wbase, a.comp, 4);
 
     S ue[M], uh[M], x2[M];
     float ep[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const int j = j0 + i;
-        const bool in = j < n;
-        ue[i] = in ? S(a.Ein[base + j * sw]) : S(0);
-        uh[i] = in ? S(a.Hin[base + j * sw]) : S(0);
-        ep[i] = in ? a.eps[base + j * sw] : 1.0f;
+        const T e = Buf<T>::ld(rE, vo, i * swb);
+        const T h = Buf<T>::ld(rH, vo, i * swb);
+        const float f = Buf<float>::ld(rP, vo_e, i * swf);
+        const bool in = FULL || j0 + i < n;
+        ue[i] = in ? S(e) : S(0);
+        uh[i] = in ? S(h) : S(0);
+        ep[i] = in ? f : 1.0f;
     }
-    const S uh_prev = (j0 > 0 && j0 <= n) ? S(a.Hin[base + (j0 - 1) * sw]) : S(0);
+    const bool first = (p == 0);
+    const bool beyond = j0 > n;                   // chunk entirely past the far wall
+    // slot j0-1 through resources based one slot earlier (offsets stay >= 0)
+    const Rsrc rHm = make_rsrc(a.Hin, wbase - sw, a.comp, ES);
+    const S uh_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rHm, vo, 0));
     S ue_prev = S(0), ue_next = S(0);
     if constexpr (MODE == CONV_LOD) {
-        ue_prev = (j0 > 0 && j0 <= n) ? S(a.Ein[base + (j0 - 1) * sw]) : S(0);
-        ue_next = (j0 + M <= n) ? S(a.Ein[base + (j0 + M) * sw]) : S(0);
+        const Rsrc rEm = make_rsrc(a.Ein, wbase - sw, a.comp, ES);
+        ue_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rEm, vo, 0));
+        ue_next = (j0 + M <= n) ? S(Buf<T>::ld(rE, vo, M * swb)) : S(0);
     }
     S uh_m_eff = uh_prev;
     if constexpr (MODE == CONV_ADI) {
+        const Rsrc r3 = make_rsrc(a.E3, wbase, a.comp, ES), r3m = make_rsrc(a.E3, wbase - sw, a.comp, ES);
+        const Rsrc r2 = make_rsrc(a.H2, wbase, a.comp, ES), r2t = make_rsrc(a.H2, wbase - a.s_t, a.comp, ES);
+        const int se = (int)(a.s_e * ES);
         S D[M + 1];
-#pragma unroll
-        for (int i = -1; i < M; ++i) {
-            const int j = j0 + i;
-            D[i + 1] = (j >= 0 && j < n) ? S(a.E3[base + j * sw + a.s_e]) - S(a.E3[base + j * sw]) : S(0);
-        }
+        D[0] = (first || beyond) ? S(0) : S(Buf<T>::ld(r3m, vo, se)) - S(Buf<T>::ld(r3m, vo, 0));
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-            const int j = j0 + i;
-            const S h2 = (j >= 1 && j < n) ? S(a.H2[base + j * sw]) - S(a.H2[base + j * sw - a.s_t]) : S(0);
-            x2[i] = a.cH2 * h2;
+            const bool in = FULL || j0 + i < n;
+            const S d = S(Buf<T>::ld(r3, vo, i * swb + se)) - S(Buf<T>::ld(r3, vo, i * swb));
+            const S h2 = S(Buf<T>::ld(r2, vo, i * swb)) - S(Buf<T>::ld(r2t, vo, i * swb));
+            D[i + 1] = in ? d : S(0);
+            x2[i] = in ? a.cH2 * h2 : S(0);
             uh[i] += a.hE3 * D[i + 1];
         }
         uh_m_eff += a.hE3 * D[0];
@@ -308,15 +408,22 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     S dg[M], r[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const int j = j0 + i;
-        const bool dir = (j == 0) || (j >= n);
-        const bool is_src = (a.src >= 0) && (base + j * sw == a.src);
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        slot_rhs<T, S, MODE>(a, dir, is_src, ep[i], ue[i], uh[i], um, em, epv,
-                             (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        slot_rhs<T, S, MODE>(a, ep[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        if (!FULL) {
+            const bool out = j0 + i >= n;
+            dg[i] = out ? Big<S>::v : dg[i];
+            r[i] = out ? S(0) : r[i];
+        }
     }
+    dg[0] = first ? Big<S>::v : dg[0];
+    r[0] = first ? S(0) : r[0];
+    const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
+    const bool src_here = si >= 0 && si < M;
+    const bool src_wave = __ballot(src_here) != 0;
+    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, ep, r);
     Chunk<S, M> c;
     chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
 
@@ -336,7 +443,7 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     }
     __syncthreads();
     const S Sl = SB(p, tx);
-    const S Sp = (p > 0) ? SB(p - 1, tx) : S(0);
+    const S Sp = first ? S(0) : SB(p - 1, tx);
     const bool hn = p + 1 < P;
     const int pn = hn ? p + 1 : p;
     const S Sn = hn ? SB(pn, tx) : S(0);
@@ -344,15 +451,19 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
 
     S eo[M], ho[M];
     chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    eo[0] = first ? S(0) : eo[0];
+    if (MODE == FUND && __builtin_expect(src_wave, 0)) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
+    }
     if (!live) return;
+    const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const int j = j0 + i;
-        if (j >= n) break;
-        S e = eo[i];
-        if (MODE == FUND && a.src >= 0 && base + j * sw == a.src) e -= a.src_post;
-        if (j >= 1) a.Eout[base + j * sw] = T(e);
-        a.Hout[base + j * sw] = T(ho[i]);
+        if (FULL || j0 + i < n) {
+            Buf<T>::st(T(eo[i]), wE, vo, i * swb);
+            Buf<T>::st(T(ho[i]), wH, vo, i * swb);
+        }
     }
 }
 

@@ -106,10 +106,13 @@ def test_config1_cavity_200_steps(dtype, form):
     tr, tr_ref = np.array(tr), np.array(tr_ref)
     drift = np.max(np.abs(tr - tr[0])) / tr[0]
     print(f"[case] config1 {form}/{dtype}: rel-L2 {err:.3e}, drift {drift:.3e}")
-    tol = {"f64": 1e-11, "f32": 1e-5, "f32s64": 2e-6}[dtype]
+    # pure FP32 solves: the pivots 2 + sigma - g are rounded the same way at
+    # every node of a uniform region, a coherent error of ~eps (1 + sqrt(sigma))
+    # / sigma in sigma, so drift and field error grow ~linearly (~5e-8 / step here)
+    tol = {"f64": 1e-11, "f32": 3e-5, "f32s64": 2e-6}[dtype]
     assert err < tol
     assert np.max(np.abs(tr - tr_ref) / tr_ref) < tol
-    assert drift < {"f64": 1e-12, "f32": 1e-5, "f32s64": 1e-6}[dtype]
+    assert drift < {"f64": 1e-12, "f32": 3e-5, "f32s64": 1e-6}[dtype]
 
 
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
