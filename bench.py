@@ -42,10 +42,12 @@ def make_inputs(n, seed_eps=2, seed_src=2):
     return h, dt, eps, ci
 
 
-def bytes_per_node(dtype_code):
-    # read E, H, eps_r; write E, H  (eps_r is FP32)
+def bytes_per_node(dtype_code, material_index=True):
+    # read E, H and the medium; write E, H.  The medium is a one-byte material
+    # index when the plan has <= 256 distinct eps_r values (this workload has
+    # 33), else an FP32 eps_r.
     w = 8 if dtype_code == "f64" else 4
-    return 4 * w + 4
+    return 4 * w + (1 if material_index else 4)
 
 
 def pass_nodes(n):
@@ -53,7 +55,7 @@ def pass_nodes(n):
     return n * (n - 1) * n
 
 
-def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True):
+def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, tune=True):
     import torch
     from paper_2011_14043_amd import Plan, Source
     h, dt, eps, ci = inputs
@@ -66,6 +68,9 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True):
     src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.from_numpy(eps))
+    if tune:
+        plan.autotune(3)
+    cfg = [plan.kernel_config(ax) for ax in range(3)]
     if warmup:
         plan.run(E, H, warmup, source=src)
     torch.cuda.synchronize()
@@ -93,7 +98,7 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True):
     out = dict(scheme=scheme, form=form, prec=prec, ms_per_step=ms, mcells_per_s=mcells,
                alg_bytes_per_step=alg_bytes_step, hbm_frac_alg=hbm_frac, main_ms=tm["main_ms"],
                yz_ms_avg=tm["yz_ms_avg"], x_ms_avg=tm["x_ms_avg"], yz_launches=tm["yz_launches"],
-               x_launches=tm["x_launches"], finite=finite)
+               x_launches=tm["x_launches"], finite=finite, kernel_config=cfg)
     log(json.dumps(out))
     return out
 

@@ -13,6 +13,7 @@
 // sequences with the original right-hand sides (modes CONV_*).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -55,8 +56,8 @@ static const SchemeDef kSchemes[4] = {
 struct KCfg { int M, TX, NT, wpb, remap; };
 
 // Instantiated y/z-line variants {M, TX, NT} by solve precision.
-static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {8, 8, 512}, {32, 16, 512}, {32, 8, 256}};
-static const int kYzF64[][3] = {{16, 16, 512}, {16, 8, 256}, {8, 8, 512}};
+static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}};
+static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}};
 
 struct Timing {
     bool per_launch = false;
@@ -77,6 +78,9 @@ struct fdtd_plan_s {
     void* state = nullptr;    // 6 (or 12 for original ADI) arrays, padded layout
     void* snap = nullptr;     // ADI: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
+    unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
+    float* mat_eps = nullptr;       // eps_r per material
+    int nmat = 0;
     double* partial = nullptr;
     int npartial = 0;
     double* energy_dev = nullptr;
@@ -120,6 +124,43 @@ static int axis_cells(const Dims& d, int ax) { return ax == 0 ? d.nx : (ax == 1 
 static double axis_h(const fdtd_desc& d, int ax) { return ax == 0 ? d.dx : (ax == 1 ? d.dy : d.dz); }
 
 // ---------------------------------------------------------------------------
+// kernel launch helpers (variants: full lines, material-index eps_r)
+// ---------------------------------------------------------------------------
+template <typename T, typename S, int M, int MODE>
+static void launch_x(bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+    if (full) {
+        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, false>), g, b, 0, st, a);
+    } else {
+        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, false>), g, b, 0, st, a);
+    }
+}
+template <typename T, typename S, int M>
+static void launch_x_mode(int mode, bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+    if (mode == FUND) launch_x<T, S, M, FUND>(full, mat, g, b, st, a);
+    else if (mode == CONV_LOD) launch_x<T, S, M, CONV_LOD>(full, mat, g, b, st, a);
+    else launch_x<T, S, M, CONV_ADI>(full, mat, g, b, st, a);
+}
+template <typename T, typename S, int M, int TX, int NT, int MODE>
+static void launch_yz(bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
+    if (full) {
+        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, false>), g, b, lds, st, a);
+    } else {
+        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, false>), g, b, lds, st, a);
+    }
+}
+template <typename T, typename S, int M, int TX, int NT>
+static void launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                           const PassArgs<T, S>& a) {
+    if (mode == FUND) launch_yz<T, S, M, TX, NT, FUND>(full, mat, g, b, lds, st, a);
+    else if (mode == CONV_LOD) launch_yz<T, S, M, TX, NT, CONV_LOD>(full, mat, g, b, lds, st, a);
+    else launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
+}
+
+// ---------------------------------------------------------------------------
 // one line pass
 // ---------------------------------------------------------------------------
 template <typename T, typename S>
@@ -134,6 +175,10 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     a.Eout = comp_ptr<T>(p, set_out, pd.ce);
     a.Hout = comp_ptr<T>(p, set_out, pd.ch);
     a.eps = p->eps;
+    a.mat = p->mat;
+    a.mat_eps = p->mat_eps;
+    a.nmat = p->nmat;
+    const bool mat = p->mat != nullptr;
     a.sw = axis_stride(d, pd.w);
     a.n_w = axis_cells(d, pd.w);
     const double h = axis_h(p->d, pd.w);
@@ -211,17 +256,8 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         a.nblk = (int)((nlines + lines_per_block - 1) / lines_per_block);
         const dim3 grid((unsigned)a.nblk), block(64 * cf.wpb);
         const bool full = a.P * M == a.n_w;
-#define LAUNCH_X(MM, MO)                                                                                   \
-    do {                                                                                                   \
-        if (full) hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO, true>), grid, block, 0, p->stream, a);   \
-        else hipLaunchKernelGGL((pass_x_kernel<T, S, MM, MO, false>), grid, block, 0, p->stream, a);       \
-    } while (0)
-        if (M == 8) {
-            if (mode == FUND) LAUNCH_X(8, FUND); else if (mode == CONV_LOD) LAUNCH_X(8, CONV_LOD); else LAUNCH_X(8, CONV_ADI);
-        } else {
-            if (mode == FUND) LAUNCH_X(16, FUND); else if (mode == CONV_LOD) LAUNCH_X(16, CONV_LOD); else LAUNCH_X(16, CONV_ADI);
-        }
-#undef LAUNCH_X
+        if (M == 8) launch_x_mode<T, S, 8>(mode, full, mat, grid, block, p->stream, a);
+        else launch_x_mode<T, S, 16>(mode, full, mat, grid, block, p->stream, a);
     } else {
         // y/z lines: a = x axis (lanes), b = the other transverse axis
         const int other = (pd.e == 0) ? pd.t : pd.e;
@@ -237,27 +273,14 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         const dim3 block(TX * a.P), grid((unsigned)a.nblk);
         const size_t lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
         const bool full = a.P * M == a.n_w;
-#define LAUNCH_YZ(MM, MO, TT, NN)                                                                              \
-    do {                                                                                                       \
-        if (full) hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN, true>), grid, block, lds, p->stream, a); \
-        else hipLaunchKernelGGL((pass_yz_kernel<T, S, MM, MO, TT, NN, false>), grid, block, lds, p->stream, a);     \
-    } while (0)
-#define LAUNCH_YZ3(MM, TT, NN)                                              \
-    do {                                                                    \
-        if (mode == FUND) LAUNCH_YZ(MM, FUND, TT, NN);                      \
-        else if (mode == CONV_LOD) LAUNCH_YZ(MM, CONV_LOD, TT, NN);         \
-        else LAUNCH_YZ(MM, CONV_ADI, TT, NN);                               \
-    } while (0)
-#define CASE_YZ(MM, TT, NN) if (M == MM && TX == TT && NT == NN) { LAUNCH_YZ3(MM, TT, NN); } else
+#define CASE_YZ(MM, TT, NN) \
+    if (M == MM && TX == TT && NT == NN) { launch_yz_mode<T, S, MM, TT, NN>(mode, full, mat, grid, block, lds, p->stream, a); } else
         if constexpr (sizeof(S) == 4) {
-            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(8, 8, 512)
-            CASE_YZ(32, 16, 512) CASE_YZ(32, 8, 256) return FDTD_EUNSUPPORTED;
+            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) return FDTD_EUNSUPPORTED;
         } else {
-            CASE_YZ(16, 16, 512) CASE_YZ(16, 8, 256) CASE_YZ(8, 8, 512) return FDTD_EUNSUPPORTED;
+            CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) return FDTD_EUNSUPPORTED;
         }
 #undef CASE_YZ
-#undef LAUNCH_YZ3
-#undef LAUNCH_YZ
     }
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(e1, p->stream));
@@ -329,10 +352,9 @@ static void default_cfg(fdtd_plan_s* p) {
         if (axis == 0) {
             pref = {{8, 0, 0, 4, 1}, {16, 0, 0, 4, 1}};
         } else if (p->d.dtype == FDTD_F32) {
-            pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {32, 8, 256, 0, 1},
-                    {8, 8, 512, 0, 1}, {8, 16, 1024, 0, 1}};
+            pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {8, 16, 1024, 0, 1}};
         } else {
-            pref = {{16, 16, 512, 0, 1}, {16, 8, 256, 0, 1}, {8, 8, 512, 0, 1}};
+            pref = {{16, 16, 512, 0, 1}, {8, 8, 512, 0, 1}};
         }
         for (const KCfg& c : pref)
             if (cfg_valid(p, axis, c)) { p->cfg[axis] = c; break; }
@@ -611,6 +633,8 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
         if (p->snap) (void)hipFree(p->snap);
         if (p->eps) (void)hipFree(p->eps);
         if (p->partial) (void)hipFree(p->partial);
+        if (p->mat) (void)hipFree(p->mat);
+        if (p->mat_eps) (void)hipFree(p->mat_eps);
         delete p;
         return st;
     };
@@ -633,6 +657,28 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if ((e = hipMalloc(&p->eps, sizeof(float) * dm.comp)) != hipSuccess) return fail(from_hip(e));
     if ((e = hipMemcpy(p->eps, en.data(), sizeof(float) * dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(from_hip(e));
+    // Piecewise-constant media: at most 256 distinct eps_r values are stored as
+    // a one-byte material index per node (the passes then read 17 instead of
+    // 20 bytes per FP32 slot); the table of values lives in LDS.
+    if (!std::getenv("FDTD_NO_MATERIAL_INDEX")) {
+        std::vector<float> uniq(eps_host.begin(), eps_host.end());
+        uniq.push_back(1.0f);
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        if (uniq.size() <= 256) {
+            std::vector<unsigned char> idx((size_t)dm.comp);
+            for (size_t m = 0; m < idx.size(); ++m)
+                idx[m] = (unsigned char)(std::lower_bound(uniq.begin(), uniq.end(), en[m]) - uniq.begin());
+            p->nmat = (int)uniq.size();
+            if ((e = hipMalloc(&p->mat, (size_t)dm.comp)) != hipSuccess) return fail(from_hip(e));
+            if ((e = hipMemcpy(p->mat, idx.data(), (size_t)dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
+                return fail(from_hip(e));
+            if ((e = hipMalloc(&p->mat_eps, sizeof(float) * 256)) != hipSuccess) return fail(from_hip(e));
+            if ((e = hipMemcpy(p->mat_eps, uniq.data(), sizeof(float) * uniq.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+                return fail(from_hip(e));
+        }
+    }
     default_cfg(p);
     p->npartial = 1024;
     if ((e = hipMalloc(&p->partial, sizeof(double) * p->npartial)) != hipSuccess) return fail(from_hip(e));
@@ -748,6 +794,8 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->eps) (void)hipFree(p->eps);
     if (p->partial) (void)hipFree(p->partial);
     if (p->energy_dev) (void)hipFree(p->energy_dev);
+    if (p->mat) (void)hipFree(p->mat);
+    if (p->mat_eps) (void)hipFree(p->mat_eps);
     for (hipEvent_t e : p->tm.ev) (void)hipEventDestroy(e);
     if (p->tm.main0) (void)hipEventDestroy(p->tm.main0);
     if (p->tm.main1) (void)hipEventDestroy(p->tm.main1);

@@ -48,6 +48,9 @@ struct PassArgs {
     const T* H2;          // CONV_ADI: H component of Y's E row (shifted along t)
     const T* E3;          // CONV_ADI: E component of Y's H row (shifted along e)
     const float* eps;     // relative permittivity at node index (node layout)
+    const unsigned char* mat;   // MAT variants: material index at node index (node layout)
+    const float* mat_eps;       // MAT variants: eps_r of each material (<= 256 entries)
+    int nmat;
     long long sw;         // stride along the line (elements)
     long long sa, sb;     // strides of the transverse line indices a, b
     long long s_t, s_e;   // CONV_ADI: strides along t and e
@@ -146,6 +149,23 @@ __device__ __forceinline__ void st_chunk(Rsrc r, int vo, const T (&v)[M]) {
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Material table: eps_r of each material index, copied to LDS once per block.
+__device__ __forceinline__ void load_mat_table(float* tab, const float* src, int nmat) {
+    for (int k = threadIdx.x; k < 256; k += blockDim.x) tab[k] = k < nmat ? src[k] : 1.0f;
+    __syncthreads();
+}
+// M consecutive material bytes at byte offset vo (8-byte aligned).
+template <int M>
+__device__ __forceinline__ void ld_bytes(Rsrc r, int vo, unsigned (&id)[M]) {
+    static_assert(M % 8 == 0, "byte chunk must be a multiple of 8");
+#pragma unroll
+    for (int b = 0; b < M / 8; ++b) {
+        const V2 x = __builtin_amdgcn_raw_buffer_load_b64(r, vo + 8 * b, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) id[8 * b + e] = (x[e / 4] >> (8 * (e % 4))) & 0xFFu;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-slot right-hand side
 // ---------------------------------------------------------------------------
@@ -190,9 +210,11 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 // 128-byte aligned).  The separator system is solved with cross-lane PCR.
 // FULL: P*M == n_w (no slot beyond the line).
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int M, int MODE, bool FULL>
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
+    __shared__ float mtab[MAT ? 256 : 1];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
     constexpr int ES = (int)sizeof(T);
     const int P = a.P;
     const int lane = threadIdx.x & 63;
@@ -221,7 +243,14 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
         T te[M], th[M];
         ld_chunk<T, M>(rE, vo, te);
         ld_chunk<T, M>(rH, vo, th);
-        ld_chunk<float, M>(rP, vo_e, ep);
+        if constexpr (MAT) {
+            unsigned id[M];
+            ld_bytes<M>(make_rsrc(a.mat, wbase, a.comp, 1), lel, id);
+#pragma unroll
+            for (int i = 0; i < M; ++i) ep[i] = mtab[id[i]];
+        } else {
+            ld_chunk<float, M>(rP, vo_e, ep);
+        }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const bool in = FULL || j0 + i < n;
@@ -329,9 +358,11 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // consecutive lanes, are reduced by cross-lane PCR, and S returns through LDS.
 // FULL: P*M == n_w.
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL>
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
 __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
+    __shared__ float mtab[MAT ? 256 : 1];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
     constexpr int ES = (int)sizeof(T);
     constexpr int CPW = 64 / TX;                  // chunks per wave
     extern __shared__ unsigned char smem_raw[];
@@ -365,11 +396,14 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
 
     S ue[M], uh[M], x2[M];
     float ep[M];
+    const Rsrc rM = make_rsrc(a.mat, wbase, a.comp, 1);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const T e = Buf<T>::ld(rE, vo, i * swb);
         const T h = Buf<T>::ld(rH, vo, i * swb);
-        const float f = Buf<float>::ld(rP, vo_e, i * swf);
+        float f;
+        if constexpr (MAT) f = mtab[__builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0)];
+        else f = Buf<float>::ld(rP, vo_e, i * swf);
         const bool in = FULL || j0 + i < n;
         ue[i] = in ? S(e) : S(0);
         uh[i] = in ? S(h) : S(0);

@@ -245,3 +245,20 @@ def test_energy_conserved_cfl20(scheme):
         drift = np.max(np.abs(tr - tr[0])) / tr[0]
         print(f"[case] energy {scheme} {dtype} drift {drift:.3e}")
         assert drift < tol
+
+
+@pytest.mark.parametrize("scheme", ["adi", "ss2"])
+def test_per_cell_eps_float_path(scheme):
+    """More than 256 distinct eps_r values: the passes read eps_r as FP32 per
+    node instead of a material index (both layouts must agree with the oracle)."""
+    nx, ny, nz, h = 30, 31, 33, 1e-3
+    dt = W.yee_dt(h, h, h, 7.0)
+    eps = np.random.default_rng(21).uniform(1.0, 12.0, (nz, ny, nx)).astype(np.float32)
+    u0 = W.random_fields(nx, ny, nz, seed=22)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    ref, _ = oracle.run(scheme, "fundamental", g, u0, 8)
+    for form in ("fundamental", "conventional"):
+        got, _ = gpu_run(scheme, form, "f64", nx, ny, nz, dt, h, eps, u0, 8)
+        assert oracle.yee.weighted_rel_l2(got, ref, g) < 1e-11
+        got, _ = gpu_run(scheme, form, "f32", nx, ny, nz, dt, h, eps, u0, 8)
+        assert oracle.yee.weighted_rel_l2(got, ref, g) < 2e-5
