@@ -148,6 +148,36 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
  * per axis (0 when taken from the cache).  Synchronizes the stream. */
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms);
 
+/* Gradient of a probe objective with respect to eps_r (fundamental ADI
+ * plans only, else FDTD_EUNSUPPORTED).
+ *   J = dt * sum_{n=1..nsteps} (Ex^2 + Ey^2 + Ez^2)(u^n) at the E samples stored
+ *   at the probe node (probe_i, probe_j, probe_k), 1 <= probe_* < n_*,
+ * where u^n are the fields fdtd_run would return after n steps from the
+ * caller's E, H (read only here, not modified) with source `src` (may be
+ * NULL), source times counted from the plan's step counter (unchanged).
+ * J_out (host) receives J, accumulated in FP64.  If grad_out is non-NULL it
+ * receives dJ/d eps_r for the design cells
+ *   design_box = {i0, i1, j0, j1, k0, k1}: cells i0 <= i < i1, ... (host array,
+ *   0 <= i0 < i1 <= nx, likewise for y, z),
+ * as a device FP64 array [k1-k0][j1-j0][i1-i0], x fastest, overwritten.
+ * Method: the adjoint of the ADI time stepping in the link scaling of
+ * Sec. II-E.  The transpose of a sub-step's Cayley factor is the same factor
+ * with theta -> -theta in the variables scaled by diag(eps, mu)^-1 (X = M^-1 K
+ * with K skew-symmetric for eq. (AMat) on the Yee grid), so the reverse sweep
+ * runs the fundamental line passes of Sec. III backwards in time; the
+ * gradient terms are accumulated in FP64 on the device.  The forward sweep
+ * stores the state every `ckpt_every` >= 1 steps; the reverse sweep
+ * recomputes each segment from its checkpoint (about two forward runs plus
+ * one adjoint run in total; device memory about (nsteps/ckpt_every + 1)
+ * states plus (2 ckpt_every + 1) x 3 design-box arrays, kept by the plan for
+ * reuse and released by fdtd_destroy).  With grad_out NULL only the forward
+ * sweep runs and design_box, ckpt_every are ignored.  The internal state is
+ * overwritten.  Synchronizes the plan's stream; FDTD_ENONFINITE if J is not
+ * finite. */
+fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps,
+                          const fdtd_source* src, int probe_i, int probe_j, int probe_k,
+                          const int* design_box, int ckpt_every, double* J_out, double* grad_out);
+
 fdtd_status fdtd_destroy(fdtd_plan_t p);
 const char* fdtd_strerror(fdtd_status s);
 

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 from . import _lib
 
-__all__ = ["Plan", "Source", "FdtdError", "load_library"]
+__all__ = ["Plan", "Source", "FdtdError", "load_library", "ProbeEnergy", "probe_energy"]
 
 FdtdError = _lib.FdtdError
 
@@ -150,6 +150,36 @@ class Plan:
         _lib.check(_lib.lib().fdtd_autotune(self._h, int(reps), best), "fdtd_autotune")
         return list(best)
 
+    def grad_eps(self, E, H, nsteps, probe, source: Source | None = None, design_box=None,
+                 ckpt_every: int = 50):
+        """Probe objective J = dt * sum_n |E(u^n)|^2 at node `probe` = (i, j, k)
+        over nsteps steps from the fields E, H (not modified), and, if
+        design_box = (i0, i1, j0, j1, k0, k1) is given, dJ/d eps_r over those
+        cells as a float64 device tensor of shape (k1-k0, j1-j0, i1-i0)
+        (fdtd_grad_eps; fundamental ADI plans).  Returns (J, grad or None)."""
+        import torch
+        L = _lib.lib()
+        pe = _ptrs(E, self.dtype, self.shape, self.device)
+        ph = _ptrs(H, self.dtype, self.shape, self.device)
+        src = ctypes.byref(source._c()) if source is not None else None
+        J = ctypes.c_double()
+        i, j, k = (int(v) for v in probe)
+        if design_box is None:
+            _lib.check(L.fdtd_grad_eps(self._h, pe, ph, int(nsteps), src, i, j, k, None, int(ckpt_every),
+                                       ctypes.byref(J), None), "fdtd_grad_eps")
+            return J.value, None
+        b = [int(v) for v in design_box]
+        if len(b) != 6:
+            raise ValueError("design_box = (i0, i1, j0, j1, k0, k1)")
+        shape = (max(b[5] - b[4], 0), max(b[3] - b[2], 0), max(b[1] - b[0], 0))
+        # never hand over a NULL buffer (that selects J only): the library
+        # itself rejects an empty or out-of-range box
+        buf = torch.empty(max(shape[0] * shape[1] * shape[2], 1), dtype=torch.float64, device=self.device)
+        box = (ctypes.c_int * 6)(*b)
+        _lib.check(L.fdtd_grad_eps(self._h, pe, ph, int(nsteps), src, i, j, k, box, int(ckpt_every),
+                                   ctypes.byref(J), ctypes.c_void_p(buf.data_ptr())), "fdtd_grad_eps")
+        return J.value, buf.view(shape)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(_lib.lib().fdtd_destroy(self._h), "fdtd_destroy")
@@ -166,3 +196,6 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+from .autograd import ProbeEnergy, probe_energy  # noqa: E402

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/fdtd.h"
+#include "adjoint_kernels.hpp"
 #include "aux_kernels.hpp"
 #include "pass_kernels.hpp"
 
@@ -85,6 +86,8 @@ struct fdtd_plan_s {
     int npartial = 0;
     double* energy_dev = nullptr;
     int energy_cap = 0;
+    void* gbuf = nullptr;     // adjoint: checkpoints, records, adjoint state (grown on demand)
+    size_t gcap = 0;
     long long step = 0;
     fdtd::Timing tm;
     fdtd::KCfg cfg[3];        // per line axis x, y, z
@@ -163,17 +166,50 @@ static void launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t
 // ---------------------------------------------------------------------------
 // one line pass
 // ---------------------------------------------------------------------------
+// Right-hand-side injection of one sub-step at the E samples stored at node
+// (i, j, k): component c (bit c of mask) gets `pre` added to its state before
+// the solve (FUND; the conventional forms add it to the right-hand side) and
+// `post` subtracted from the FUND output.  pre_dev (device, 3 doubles),
+// if set, supplies the pre values instead.
+struct Inject {
+    int i = 0, j = 0, k = 0;
+    unsigned mask = 0;
+    double pre[3] = {0, 0, 0}, post[3] = {0, 0, 0};
+    const double* pre_dev = nullptr;
+};
+
+// The physical source of a sub-step with source term g (fdtd_source).
+static Inject source_inject(const fdtd_plan_s* p, const fdtd_source* src, double g, int mode) {
+    Inject in;
+    if (!src || g == 0.0) return in;
+    in.i = src->i; in.j = src->j; in.k = src->k;
+    in.mask = 4u;   // Ez
+    if (mode == FUND) {
+        in.pre[2] = 0.5 * g;
+        in.post[2] = (p->d.scheme == FDTD_ADI) ? 0.5 * g : 0.0;
+    } else {
+        in.pre[2] = g;
+    }
+    return in;
+}
+
+template <typename T>
+static T* set_ptr(fdtd_plan_s* p, int set) {
+    return reinterpret_cast<T*>(p->state) + (size_t)set * 6 * p->dims.comp;
+}
+
 template <typename T, typename S>
-static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, int set_in, int set_out,
-                               const fdtd_source* src, double gval, bool timed) {
+static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
+                               const Inject* inj, bool timed) {
     const PairDef& pd = kPairs[op][k];
     const Dims& d = p->dims;
     PassArgs<T, S> a;
     std::memset(&a, 0, sizeof(a));
-    a.Ein = comp_ptr<T>(p, set_in, pd.ce);
-    a.Hin = comp_ptr<T>(p, set_in, pd.ch);
-    a.Eout = comp_ptr<T>(p, set_out, pd.ce);
-    a.Hout = comp_ptr<T>(p, set_out, pd.ch);
+    const size_t cs = (size_t)d.comp;
+    a.Ein = set_in + pd.ce * cs;
+    a.Hin = set_in + pd.ch * cs;
+    a.Eout = set_out + pd.ce * cs;
+    a.Hout = set_out + pd.ch * cs;
     a.eps = p->eps;
     a.mat = p->mat;
     a.mat_eps = p->mat_eps;
@@ -200,8 +236,8 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         }
         const double sy = (op == 0) ? -1.0 : 1.0;
         const double ht = axis_h(p->d, pd.t), he = axis_h(p->d, pd.e);
-        a.H2 = comp_ptr<T>(p, set_in, h2);
-        a.E3 = comp_ptr<T>(p, set_in, e3);
+        a.H2 = set_in + h2 * cs;
+        a.E3 = set_in + e3 * cs;
         a.s_t = axis_stride(d, pd.t);
         a.s_e = axis_stride(d, pd.e);
         a.cH2 = S(sy * h * h * mu / (ht * theta));
@@ -210,15 +246,12 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     a.comp = d.comp;
     a.src_a = a.src_b = a.src_j = -1;
     int src_idx[3] = {0, 0, 0};
-    const bool has_src = src && gval != 0.0 && pd.ce == 2;
+    const bool has_src = inj && ((inj->mask >> pd.ce) & 1u);
     if (has_src) {
-        src_idx[0] = src->i; src_idx[1] = src->j; src_idx[2] = src->k;
-        if (mode == FUND) {
-            a.src_pre = S(0.5 * gval);
-            a.src_post = (p->d.scheme == FDTD_ADI) ? S(0.5 * gval) : S(0);
-        } else {
-            a.src_pre = S(gval);
-        }
+        src_idx[0] = inj->i; src_idx[1] = inj->j; src_idx[2] = inj->k;
+        a.src_pre = S(inj->pre[pd.ce]);
+        a.src_post = S(inj->post[pd.ce]);
+        a.src_pre_dev = inj->pre_dev ? inj->pre_dev + pd.ce : nullptr;
     }
     const int ne = axis_cells(d, pd.e), nt = axis_cells(d, pd.t);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -288,11 +321,11 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
 }
 
 template <typename T, typename S>
-static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& cur, const fdtd_source* src,
-                           double gval, bool timed) {
+static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& cur, const Inject* inj,
+                           bool timed) {
     const int out = (mode == CONV_ADI) ? 1 - cur : cur;
     for (int k = 0; k < 3; ++k) {
-        fdtd_status st = launch_pass<T, S>(p, op, k, theta, mode, cur, out, src, gval, timed);
+        fdtd_status st = launch_pass<T, S>(p, op, k, theta, mode, set_ptr<T>(p, cur), set_ptr<T>(p, out), inj, timed);
         if (st != FDTD_OK) return st;
     }
     cur = out;
@@ -378,11 +411,13 @@ static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
         float tbest = 1e30f;
         for (const KCfg& c : cand) {
             p->cfg[axis] = c;
-            st = launch_pass<T, S>(p, 0, k, theta, mode, 0, conv && adi ? 1 : 0, nullptr, 0.0, false);
+            T* s0 = set_ptr<T>(p, 0);
+            T* s1 = set_ptr<T>(p, conv && adi ? 1 : 0);
+            st = launch_pass<T, S>(p, 0, k, theta, mode, s0, s1, nullptr, false);
             if (st != FDTD_OK) break;
             if (hipEventRecord(e0, p->stream) != hipSuccess) { st = FDTD_EDEVICE; break; }
             for (int r = 0; r < reps && st == FDTD_OK; ++r)
-                st = launch_pass<T, S>(p, 0, k, theta, mode, 0, conv && adi ? 1 : 0, nullptr, 0.0, false);
+                st = launch_pass<T, S>(p, 0, k, theta, mode, s0, s1, nullptr, false);
             if (st != FDTD_OK) break;
             if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 st = FDTD_EDEVICE;
@@ -509,7 +544,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
                               hipMemcpyDeviceToDevice, p->stream));
     }
     if (d.scheme == FDTD_LOD2) {
-        fdtd_status st = substep<T, S>(p, 1, 0.25 * d.dt, mode, cur, nullptr, 0.0, false);
+        fdtd_status st = substep<T, S>(p, 1, 0.25 * d.dt, mode, cur, nullptr, false);
         if (st != FDTD_OK) return st;
     }
     const SchemeDef& sd = kSchemes[d.scheme];
@@ -536,7 +571,8 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
                 HIPCHK(hipMemcpyAsync(p->snap, comp_ptr<T>(p, cur, 0), sizeof(T) * dm.comp * 6,
                                       hipMemcpyDeviceToDevice, p->stream));
             }
-            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, src, g, tm.per_launch);
+            const Inject inj = source_inject(p, src, g, mode);
+            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, tm.per_launch);
             if (st != FDTD_OK) return st;
             if (ss.op == 1) last_b_g = g;
         }
@@ -549,7 +585,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // output processing
     if (nsteps > 0) {
         if (d.scheme == FDTD_LOD2) {
-            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, 0.0, false);
+            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false);
             if (st != FDTD_OK) return st;
         }
         const bool add_old = adi && !conv;
@@ -568,6 +604,161 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
             if (!std::isfinite(energy[m])) return FDTD_ENONFINITE;
     }
     return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint gradient of the probe objective (fundamental ADI)
+// ---------------------------------------------------------------------------
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename T, typename S>
+static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
+                             const int probe[3], const int* dbox, int K, double* J_out, double* grad_out) {
+    const fdtd_desc& d = p->d;
+    const Dims& dm = p->dims;
+    const double theta = 0.5 * d.dt;
+    const bool want = grad_out != nullptr;
+    FieldPtrs<T> caller;
+    for (int c = 0; c < 3; ++c) {
+        caller.c[c] = static_cast<const T*>(E[c]);
+        caller.c[3 + c] = static_cast<const T*>(H[c]);
+    }
+    Box b{0, 0, 0, 1, 1, 1};
+    if (want) b = Box{dbox[0], dbox[2], dbox[4], dbox[1] - dbox[0], dbox[3] - dbox[2], dbox[5] - dbox[4]};
+    const long long nb = (long long)b.bi * b.bj * b.bk;
+    const int nseg = want ? (nsteps + K - 1) / K : 0;
+    const int nrec = want ? 2 * std::min(K, std::max(nsteps, 1)) + 1 : 0;
+    const size_t ssz = sizeof(T) * 6 * (size_t)dm.comp;
+    // scratch layout: scalars | probe records | design records | adjoint state | checkpoints
+    const size_t o_prb = 256;
+    const size_t o_rec = o_prb + align256(sizeof(double) * 3 * std::max(nrec, 2));
+    const size_t o_adj = o_rec + align256(sizeof(T) * 3 * (size_t)nb * nrec);
+    const size_t o_ckp = o_adj + (want ? align256(ssz) : 0);
+    const size_t need = o_ckp + (size_t)nseg * align256(ssz);
+    if (need > p->gcap) {
+        if (p->gbuf) HIPCHK(hipFree(p->gbuf));
+        p->gbuf = nullptr;
+        p->gcap = 0;
+        HIPCHK(hipMalloc(&p->gbuf, need));
+        p->gcap = need;
+    }
+    char* g0 = static_cast<char*>(p->gbuf);
+    double* Jd = reinterpret_cast<double*>(g0);
+    double* seed = Jd + 1;
+    double* prb = reinterpret_cast<double*>(g0 + o_prb);
+    T* rec = reinterpret_cast<T*>(g0 + o_rec);
+    T* adj = want ? reinterpret_cast<T*>(g0 + o_adj) : nullptr;
+    auto ckpt = [&](int sidx) { return reinterpret_cast<T*>(g0 + o_ckp + (size_t)sidx * align256(ssz)); };
+    auto recp = [&](int m) { return rec + (size_t)m * 3 * nb; };
+    const long long probe_off = (long long)probe[2] * dm.plane + (long long)probe[1] * dm.px + probe[0];
+    const bool src_at_probe = src && src->i == probe[0] && src->j == probe[1] && src->k == probe[2];
+    long long src_idx = -1;
+    if (want && src && src->i >= b.i0 && src->i < b.i0 + b.bi && src->j >= b.j0 && src->j < b.j0 + b.bj &&
+        src->k >= b.k0 && src->k < b.k0 + b.bk)
+        src_idx = ((long long)(src->k - b.k0) * b.bj + (src->j - b.j0)) * b.bi + (src->i - b.i0);
+    const unsigned rblocks = (unsigned)std::max<long long>(1, (nb + 255) / 256);
+    const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+    const unsigned gblocks = (unsigned)((nn + 255) / 256);
+    T* st0 = set_ptr<T>(p, 0);
+    auto fptrs = [&](T* base) {
+        FieldPtrs<T> f;
+        for (int c = 0; c < 6; ++c) f.c[c] = base + (size_t)c * dm.comp;
+        return f;
+    };
+    auto record = [&](T* dst, double* pdst) -> fdtd_status {
+        hipLaunchKernelGGL((record_kernel<T>), dim3(dst ? rblocks : 1), dim3(256), 0, p->stream, fptrs(st0), dm, b,
+                           dst, probe_off, pdst);
+        HIPCHK(hipGetLastError());
+        return FDTD_OK;
+    };
+    auto fwd_sub = [&](int op, long long glob, double tf, double* g_out) -> fdtd_status {
+        const double g = source_value(src, theta, (double(glob) + tf) * d.dt);
+        *g_out = g;
+        const Inject inj = source_inject(p, src, g, FUND);
+        int cur = 0;
+        return substep<T, S>(p, op, theta, FUND, cur, &inj, false);
+    };
+#define GCHK(x)                                   \
+    do {                                          \
+        fdtd_status s_ = (x);                     \
+        if (s_ != FDTD_OK) return s_;             \
+    } while (0)
+
+    // forward sweep: J, checkpoints every K steps
+    AuxCoef kin{kEps0, kMu0, d.dx, d.dy, d.dz, 0.25 * d.dt};
+    hipLaunchKernelGGL((load_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
+                       p->eps, dm, kin);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemsetAsync(Jd, 0, 256, p->stream));
+    for (int n = 0; n < nsteps; ++n) {
+        if (want && n % K == 0) HIPCHK(hipMemcpyAsync(ckpt(n / K), st0, ssz, hipMemcpyDeviceToDevice, p->stream));
+        const long long glob = p->step + n;
+        double gA, gB;
+        GCHK(fwd_sub(0, glob, 0.25, &gA));
+        GCHK(record(nullptr, prb));
+        GCHK(fwd_sub(1, glob, 0.75, &gB));
+        GCHK(record(nullptr, prb + 3));
+        hipLaunchKernelGGL(probe_kernel, dim3(1), dim3(64), 0, p->stream, prb, prb + 3,
+                           src_at_probe ? 0.5 * gB : 0.0, p->eps, probe_off, kEps0, d.dt, Jd, nullptr);
+        HIPCHK(hipGetLastError());
+    }
+    if (want) {
+        HIPCHK(hipMemsetAsync(adj, 0, ssz, p->stream));
+        HIPCHK(hipMemsetAsync(grad_out, 0, sizeof(double) * nb, p->stream));
+        const FieldPtrs<T> lam = fptrs(adj);
+        const double scale = -0.5 * kEps0;
+        auto acc = [&](int m, double g) -> fdtd_status {
+            hipLaunchKernelGGL((grad_acc_kernel<T>), dim3(rblocks), dim3(256), 0, p->stream, lam, dm, b, recp(m),
+                               recp(m + 1), src_idx, 0.5 * g, scale, grad_out);
+            HIPCHK(hipGetLastError());
+            return FDTD_OK;
+        };
+        auto adj_sub = [&](int op, const Inject* inj) -> fdtd_status {
+            for (int k = 0; k < 3; ++k) GCHK((launch_pass<T, S>(p, op, k, -theta, FUND, adj, adj, inj, false)));
+            return FDTD_OK;
+        };
+        Inject seed_inj;
+        seed_inj.i = probe[0]; seed_inj.j = probe[1]; seed_inj.k = probe[2];
+        seed_inj.mask = 7u;
+        seed_inj.pre_dev = seed;
+        std::vector<double> gs(2 * (size_t)K);
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int n0 = sg * K, L = std::min(nsteps, n0 + K) - n0;
+            // recompute the segment from its checkpoint, recording every sub-step state
+            HIPCHK(hipMemcpyAsync(st0, ckpt(sg), ssz, hipMemcpyDeviceToDevice, p->stream));
+            GCHK(record(recp(0), prb));
+            for (int q = 0; q < L; ++q) {
+                const long long glob = p->step + n0 + q;
+                GCHK(fwd_sub(0, glob, 0.25, &gs[2 * q]));
+                GCHK(record(recp(2 * q + 1), prb + 3 * (2 * q + 1)));
+                GCHK(fwd_sub(1, glob, 0.75, &gs[2 * q + 1]));
+                GCHK(record(recp(2 * q + 2), prb + 3 * (2 * q + 2)));
+            }
+            // reverse sub-steps
+            for (int q = L - 1; q >= 0; --q) {
+                const int mB = 2 * q + 1, mA = 2 * q;
+                const double gB = gs[mB], gA = gs[mA];
+                hipLaunchKernelGGL(probe_kernel, dim3(1), dim3(64), 0, p->stream, prb + 3 * mB, prb + 3 * (mB + 1),
+                                   src_at_probe ? 0.5 * gB : 0.0, p->eps, probe_off, kEps0, d.dt, nullptr, seed);
+                HIPCHK(hipGetLastError());
+                GCHK(acc(mB, gB));
+                GCHK(adj_sub(1, &seed_inj));
+                GCHK(acc(mB, gB));
+                GCHK(acc(mA, gA));
+                GCHK(adj_sub(0, nullptr));
+                GCHK(acc(mA, gA));
+            }
+        }
+        if (nsteps > 0) {
+            hipLaunchKernelGGL((grad_link_kernel<T>), dim3(rblocks), dim3(256), 0, p->stream, lam, caller, dm, b,
+                               recp(0), -kEps0, grad_out);
+            HIPCHK(hipGetLastError());
+        }
+    }
+#undef GCHK
+    HIPCHK(hipMemcpyAsync(J_out, Jd, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return std::isfinite(*J_out) ? FDTD_OK : FDTD_ENONFINITE;
 }
 
 }  // namespace fdtd
@@ -786,6 +977,44 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
     return FDTD_OK;
 }
 
+fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
+                          int probe_i, int probe_j, int probe_k, const int* design_box, int ckpt_every,
+                          double* J_out, double* grad_out) {
+    if (!plan_ok(p) || !E || !H || nsteps < 0 || !J_out) return FDTD_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!E[c] || !H[c]) return FDTD_EINVAL;
+    const fdtd_desc& d = p->d;
+    if (probe_i < 1 || probe_i >= d.nx || probe_j < 1 || probe_j >= d.ny || probe_k < 1 || probe_k >= d.nz)
+        return FDTD_EINVAL;
+    if (src) {
+        if (src->i < 1 || src->i >= d.nx || src->j < 1 || src->j >= d.ny || src->k < 0 || src->k >= d.nz)
+            return FDTD_EINVAL;
+        if (!(src->tau > 0) || !std::isfinite(src->f0) || !std::isfinite(src->t0) || !std::isfinite(src->amp))
+            return FDTD_EINVAL;
+    }
+    if (grad_out) {
+        if (!design_box || ckpt_every < 1) return FDTD_EINVAL;
+        const int* b = design_box;
+        if (b[0] < 0 || b[1] <= b[0] || b[1] > d.nx || b[2] < 0 || b[3] <= b[2] || b[3] > d.ny || b[4] < 0 ||
+            b[5] <= b[4] || b[5] > d.nz)
+            return FDTD_EINVAL;
+    }
+    if (d.scheme != FDTD_ADI || d.form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    const int probe[3] = {probe_i, probe_j, probe_k};
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    fdtd_status st;
+    if (d.dtype == FDTD_F32)
+        st = grad_impl<float, float>(p, E, H, nsteps, src, probe, design_box, ckpt_every, J_out, grad_out);
+    else if (d.dtype == FDTD_F64)
+        st = grad_impl<double, double>(p, E, H, nsteps, src, probe, design_box, ckpt_every, J_out, grad_out);
+    else
+        st = grad_impl<float, double>(p, E, H, nsteps, src, probe, design_box, ckpt_every, J_out, grad_out);
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    return st;
+}
+
 fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (!plan_ok(p)) return FDTD_EINVAL;
     (void)hipStreamSynchronize(p->stream);
@@ -796,6 +1025,7 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->energy_dev) (void)hipFree(p->energy_dev);
     if (p->mat) (void)hipFree(p->mat);
     if (p->mat_eps) (void)hipFree(p->mat_eps);
+    if (p->gbuf) (void)hipFree(p->gbuf);
     for (hipEvent_t e : p->tm.ev) (void)hipEventDestroy(e);
     if (p->tm.main0) (void)hipEventDestroy(p->tm.main0);
     if (p->tm.main1) (void)hipEventDestroy(p->tm.main1);

@@ -67,6 +67,7 @@ struct PassArgs {
     S cH2, hE3;           // CONV_ADI cross-term coefficients
     int src_a, src_b, src_j;   // source sample in line coordinates (src_a < 0: none)
     S src_pre, src_post;
+    const double* src_pre_dev; // if set, the value of src_pre is read from device memory
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block L -> XCD L % 8),
@@ -196,11 +197,12 @@ __device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, float eps, S u
 // Source term at slot si of this chunk (rhs: 2 sigma pre or sigma pre).
 template <typename T, typename S, int MODE, int M>
 __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, const float (&ep)[M], S (&r)[M]) {
+    const S pre = a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const S sig = make_sigma<S>(a.Ks, ep[i]);
         const S coef = (MODE == FUND) ? sig + sig : sig;
-        r[i] += (i == si) ? coef * a.src_pre : S(0);
+        r[i] += (i == si) ? coef * pre : S(0);
     }
 }
 

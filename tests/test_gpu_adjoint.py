@@ -1,0 +1,242 @@
+"""GPU adjoint gradient (fdtd_grad_eps, ProbeEnergy) against the FP64 oracle's
+reverse-mode gradient on tiny grids and against central finite differences
+of the library's own FP64 objective on the 128 x 128 x 64 design workload."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint, yee
+from oracle.source import Source as OSource
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
+        "f32s64": (torch.float32, torch.float64)}
+
+
+def _plan(nx, ny, nz, dt, h, eps, prec, scheme="adi", form="fundamental"):
+    from paper_2011_14043_amd import Plan
+    dtype, solve = PREC[prec]
+    return Plan(nx, ny, nz, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
+                eps_r=torch.tensor(np.asarray(eps, dtype=np.float32)))
+
+
+def _fields(u0, prec):
+    dtype = PREC[prec][0]
+    E = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[3:]]
+    return E, H
+
+
+def _gsrc(s):
+    from paper_2011_14043_amd import Source
+    return Source(s.i, s.j, s.k, f0=s.f0, tau=s.tau, t0=s.t0, amp=s.amp)
+
+
+def _tiny(seed, probe_at_source=False):
+    """5 x 4 x 6 cells, eps_r U[1,12] per cell (FP32 values), random initial
+    fields (so the input-processing term counts), CFL 5, a source inside."""
+    nx, ny, nz, h = 5, 4, 6, 1e-3
+    rng = np.random.default_rng(seed)
+    eps = rng.uniform(1, 12, (nz, ny, nx)).astype(np.float32)
+    dt = W.yee_dt(h, h, h, 5.0)
+    u0 = W.random_fields(nx, ny, nz, seed + 7)
+    src = OSource(2, 1, 3, amp=1e12, t0=3 * dt, tau=3 * dt, f0=1 / (10 * dt))
+    probe = (2, 1, 3) if probe_at_source else (3, 2, 2)
+    g = yee.Grid(nx, ny, nz, h, h, h, dt, eps.astype(np.float64))
+    return dict(nx=nx, ny=ny, nz=nz, h=h, dt=dt, eps=eps, u0=u0, src=src, probe=probe, g=g)
+
+
+# FP64 path: the same arithmetic up to rounding order; FP32 paths: rounding of
+# the stored fields and solves over 2 x 10 sub-steps (forward and adjoint).
+GRAD_TOL = {"f64": 1e-9, "f32s64": 2e-5, "f32": 2e-4}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32"])
+@pytest.mark.parametrize("seed,at_src", [(0, False), (1, True)])
+def test_gradient_vs_oracle_tiny(prec, seed, at_src):
+    c = _tiny(seed, at_src)
+    steps, K = 10, 3
+    print(f"[case] adjoint tiny 5x4x6 {prec} seed={seed} probe_at_source={at_src}", flush=True)
+    J_ref, g_ref = adjoint.gradient(c["g"], c["u0"], steps, c["src"], c["probe"])
+    plan = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], prec)
+    E, H = _fields(c["u0"], prec)
+    E_before = [t.clone() for t in E]
+    box = (0, c["nx"], 0, c["ny"], 0, c["nz"])
+    J, grad = plan.grad_eps(E, H, steps, c["probe"], _gsrc(c["src"]), box, K)
+    plan.close()
+    grad = grad.cpu().numpy()
+    tol = GRAD_TOL[prec]
+    assert abs(J - J_ref) <= tol * abs(J_ref), (J, J_ref)
+    err = np.abs(grad - g_ref).max() / np.abs(g_ref).max()
+    print(f"  J rel {abs(J - J_ref) / J_ref:.2e}  grad rel(max) {err:.2e}", flush=True)
+    assert err <= tol, err
+    for a, b in zip(E, E_before):                 # inputs are read only
+        assert torch.equal(a, b)
+
+
+def test_gradient_design_box_subset_and_zero_steps():
+    c = _tiny(2)
+    plan = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], "f64")
+    E, H = _fields(c["u0"], "f64")
+    full_box = (0, c["nx"], 0, c["ny"], 0, c["nz"])
+    _, full = plan.grad_eps(E, H, 6, c["probe"], _gsrc(c["src"]), full_box, 2)
+    sub_box = (1, 4, 0, 3, 2, 5)
+    _, sub = plan.grad_eps(E, H, 6, c["probe"], _gsrc(c["src"]), sub_box, 2)
+    assert sub.shape == (3, 3, 3)
+    torch.testing.assert_close(sub, full[2:5, 0:3, 1:4], rtol=0, atol=0)
+    J0, g0 = plan.grad_eps(E, H, 0, c["probe"], _gsrc(c["src"]), full_box, 2)
+    assert J0 == 0.0 and float(g0.abs().max()) == 0.0
+    plan.close()
+
+
+def test_checkpoint_interval_does_not_change_result():
+    """Recomputation from checkpoints is deterministic: every interval gives
+    the same bits."""
+    c = _tiny(3)
+    plan = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], "f32")
+    E, H = _fields(c["u0"], "f32")
+    box = (0, c["nx"], 0, c["ny"], 0, c["nz"])
+    outs = [plan.grad_eps(E, H, 9, c["probe"], _gsrc(c["src"]), box, K) for K in (1, 2, 4, 9, 50)]
+    plan.close()
+    for J, g in outs[1:]:
+        assert J == outs[0][0]
+        assert torch.equal(g, outs[0][1])
+
+
+def test_objective_equals_stepwise_run():
+    """J of fdtd_grad_eps equals dt * sum |E|^2 at the probe over fdtd_step
+    calls (the ADI output is exact at every step)."""
+    c = _tiny(4)
+    steps = 8
+    plan = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], "f64")
+    E, H = _fields(c["u0"], "f64")
+    J, g = plan.grad_eps(E, H, steps, c["probe"], _gsrc(c["src"]))
+    assert g is None
+    i, j, k = c["probe"]
+    acc = 0.0
+    for n in range(steps):
+        plan.set_step(n)
+        plan.step(E, H, _gsrc(c["src"]))
+        acc += c["dt"] * sum(float(E[m][k, j, i]) ** 2 for m in range(3))
+    plan.close()
+    assert abs(J - acc) <= 1e-12 * acc
+
+
+def test_invalid_arguments():
+    from paper_2011_14043_amd import FdtdError
+    c = _tiny(5)
+    plan = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], "f32")
+    E, H = _fields(c["u0"], "f32")
+    box = (0, c["nx"], 0, c["ny"], 0, c["nz"])
+    for probe in [(0, 1, 1), (1, c["ny"], 1), (1, 1, 0), (c["nx"], 1, 1)]:
+        with pytest.raises(FdtdError, match="EINVAL"):
+            plan.grad_eps(E, H, 3, probe, None, box, 2)
+    for b in [(0, 0, 0, 1, 0, 1), (0, c["nx"] + 1, 0, 1, 0, 1), (-1, 2, 0, 1, 0, 1), (2, 1, 0, 1, 0, 1)]:
+        with pytest.raises(FdtdError, match="EINVAL"):
+            plan.grad_eps(E, H, 3, (2, 2, 2), None, b, 2)
+    with pytest.raises(FdtdError, match="EINVAL"):
+        plan.grad_eps(E, H, 3, (2, 2, 2), None, box, 0)
+    plan.close()
+    for scheme, form in [("adi", "conventional"), ("lod1", "fundamental"), ("ss2", "fundamental")]:
+        p2 = _plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], "f32", scheme, form)
+        with pytest.raises(FdtdError, match="EUNSUPPORTED"):
+            p2.grad_eps(E, H, 3, (2, 2, 2), None, box, 2)
+        p2.close()
+
+
+# ---------------------------------------------------------------------------
+# the 128 x 128 x 64 design workload: 500 steps at CFL 5, checkpoints every 50
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def design():
+    p = W.design_problem(seed=5)
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    src = OSource(*p["src"])          # 10 GHz modulated Gaussian, t0 = 0.4 ns
+    rng = np.random.default_rng(11)
+    i0, i1, j0, j1, k0, k1 = p["design_box"]
+    vox = [(int(rng.integers(k0, k1)), int(rng.integers(j0, j1)), int(rng.integers(i0, i1))) for _ in range(20)]
+    return dict(p, h=h, dt=dt, srcs=src, vox=vox, steps=500, K=50)
+
+
+def _J(d, eps, prec="f64"):
+    n = d["nx"], d["ny"], d["nz"]
+    plan = _plan(*n, d["dt"], d["h"], eps, prec)
+    E, H = _fields(W.zero_fields(*n), prec)
+    J, _ = plan.grad_eps(E, H, d["steps"], d["probe"], _gsrc(d["srcs"]))
+    plan.close()
+    return J
+
+
+@pytest.fixture(scope="module")
+def design_fd(design):
+    """Central differences of the FP64 objective on the 20 seeded voxels,
+    step 1e-3 in eps_r (the FP32-rounded perturbation is used exactly)."""
+    d = design
+    fd = []
+    for (k, j, i) in d["vox"]:
+        e0 = d["eps"][k, j, i]
+        ep, em = d["eps"].copy(), d["eps"].copy()
+        ep[k, j, i] = np.float32(e0 + 1e-3)
+        em[k, j, i] = np.float32(e0 - 1e-3)
+        fd.append((_J(d, ep) - _J(d, em)) / (float(ep[k, j, i]) - float(em[k, j, i])))
+    return np.array(fd)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 2e-5), ("f32s64", 1e-3), ("f32", 1e-3)])
+def test_design_gradient_vs_central_fd(design, design_fd, prec, tol):
+    d = design
+    print(f"[case] adjoint 128x128x64 design box, 500 steps, {prec}", flush=True)
+    n = d["nx"], d["ny"], d["nz"]
+    plan = _plan(*n, d["dt"], d["h"], d["eps"], prec)
+    E, H = _fields(W.zero_fields(*n), prec)
+    J, grad = plan.grad_eps(E, H, d["steps"], d["probe"], _gsrc(d["srcs"]), d["design_box"], d["K"])
+    plan.close()
+    i0, _, j0, _, k0, _ = d["design_box"]
+    adj = np.array([float(grad[k - k0, j - j0, i - i0]) for (k, j, i) in d["vox"]])
+    fd = design_fd
+    rel = np.linalg.norm(adj - fd) / np.linalg.norm(fd)
+    worst = np.max(np.abs(adj - fd) / np.abs(fd))
+    print(f"  J={J:.6e} rel L2 {rel:.2e} worst voxel {worst:.2e}", flush=True)
+    assert rel <= tol, (rel, adj, fd)
+    assert worst <= 10 * tol, (worst, adj, fd)
+
+
+def test_autograd_function_matches_directional_fd():
+    """ProbeEnergy.backward returns dJ/d eps_design: its inner product with a
+    random direction matches the central difference of J along it (FP64)."""
+    from paper_2011_14043_amd import Source
+    from paper_2011_14043_amd.autograd import ProbeProblem, probe_energy
+    p = W.design_problem(seed=8, nx=40, ny=36, nz=30, box_size=(16, 16, 8))
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    i0, i1, j0, j1, k0, k1 = p["design_box"]
+    pb = ProbeProblem(p["nx"], p["ny"], p["nz"], dt, h, h, h, torch.tensor(p["eps"]), p["design_box"], 150,
+                      p["probe"], Source(*p["src"], t0=0.1e-9, tau=0.03e-9), dtype=torch.float64, ckpt_every=40)
+    x0 = torch.tensor(p["eps"][k0:k1, j0:j1, i0:i1], dtype=torch.float64, device=DEV)
+    x = x0.clone().requires_grad_(True)
+    J = probe_energy(x, pb)
+    J.backward()
+    g = x.grad
+    assert g.shape == x.shape and g.dtype == torch.float64
+    rng = np.random.default_rng(3)
+    v = torch.tensor(rng.standard_normal(x.shape), device=DEV)
+
+    def ratio(t):
+        # the plan stores eps_r in FP32: use the rounded perturbation exactly
+        xp = (x0 + t * v).float().double()
+        xm = (x0 - t * v).float().double()
+        return (float(probe_energy(xp, pb)) - float(probe_energy(xm, pb))) / float((g * (xp - xm)).sum())
+
+    # central differences have an O(t^2) error: Richardson-extrapolate t, 2t
+    r1, r2 = ratio(1e-3), ratio(2e-3)
+    r = (4 * r1 - r2) / 3
+    print(f"  directional FD / adjoint: t {r1:.9f}  2t {r2:.9f}  extrapolated {r:.9f}", flush=True)
+    assert abs(r1 - 1) <= 1e-4
+    assert abs(r - 1) <= 1e-6
+    with torch.no_grad():
+        J2 = probe_energy(x0, pb)
+    assert float(J2) == float(J)

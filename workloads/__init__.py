@@ -132,3 +132,23 @@ def cavity_batch(count: int, seed: int, lo: int = 16, hi: int = 96) -> list[tupl
     """`count` cavity sizes (nx, ny, nz), each uniform in [lo, hi]."""
     rng = np.random.default_rng(seed)
     return [tuple(int(v) for v in rng.integers(lo, hi + 1, 3)) for _ in range(count)]
+
+
+def design_problem(seed: int, nx: int = 128, ny: int = 128, nz: int = 64,
+                   box_size: tuple[int, int, int] = (64, 64, 16)) -> dict:
+    """Differentiable-cavity workload: a centred design box of box_size cells
+    (eps_r U[1,12] per voxel, 1 elsewhere), an Ez source cell below the box
+    and a probe node above it, both seeded.  Returns a dict with nx, ny, nz,
+    design_box = (i0, i1, j0, j1, k0, k1), eps (nz, ny, nx) FP32, src, probe."""
+    sx, sy, sz = box_size
+    x0, y0, z0 = (nx - sx) // 2, (ny - sy) // 2, (nz - sz) // 2
+    eps = design_region_eps(nx, ny, nz, (x0, y0, z0, sx, sy, sz), seed)
+    rng = np.random.default_rng(seed + 1000)
+    def cell(klo, khi):
+        return (int(rng.integers(max(1, nx // 4), max(2, 3 * nx // 4))),
+                int(rng.integers(max(1, ny // 4), max(2, 3 * ny // 4))),
+                int(rng.integers(klo, max(klo + 1, khi))))
+    src = cell(max(1, z0 // 3), max(2, z0 - 2))
+    probe = cell(min(nz - 2, z0 + sz + 2), max(z0 + sz + 3, nz - max(1, z0 // 3)))
+    return dict(nx=nx, ny=ny, nz=nz, design_box=(x0, x0 + sx, y0, y0 + sy, z0, z0 + sz), eps=eps,
+                src=src, probe=probe)
