@@ -178,6 +178,27 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
                           const fdtd_source* src, int probe_i, int probe_j, int probe_k,
                           const int* design_box, int ckpt_every, double* J_out, double* grad_out);
 
+/* Batch of independent grids stepped together (fundamental forms only, else
+ * FDTD_EUNSUPPORTED).  d[0..n-1] describe the grids (each validated as by
+ * fdtd_plan; sizes, dt, dx, dy, dz and eps_r may differ; scheme, form and
+ * dtype must be equal, else FDTD_EINVAL).  Every line pass of a sub-step
+ * runs as ONE launch over all grids: the plan keeps a device table of the
+ * grids' pass arguments and a work list of (grid, block) items, and one time
+ * step of the main iteration is captured once as a HIP graph (on a private
+ * stream) and replayed on `hip_stream`.  Per-grid state and eps_r as in
+ * fdtd_plan.  fdtd_autotune, fdtd_get/set_kernel_config (a configuration
+ * must fit every grid), fdtd_set_timing/fdtd_last_timing (main_ms only) and
+ * fdtd_destroy accept a batch plan; fdtd_run, fdtd_step and fdtd_grad_eps
+ * return FDTD_EINVAL for it. */
+fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_plan_t* out);
+
+/* Advance every grid of a batch plan by `nsteps` >= 0 steps, with the input
+ * and output processing of fdtd_run and no source.  E and H are host arrays
+ * of 3n device pointers: E[3g + c] is component c (x, y, z) of grid g, with
+ * the layout of fdtd_run, read on entry and overwritten on return.
+ * Asynchronous on the plan's stream. */
+fdtd_status fdtd_run_batch(fdtd_plan_t p, void* const* E, void* const* H, int nsteps);
+
 fdtd_status fdtd_destroy(fdtd_plan_t p);
 const char* fdtd_strerror(fdtd_status s);
 

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 from . import _lib
 
-__all__ = ["Plan", "Source", "FdtdError", "load_library", "ProbeEnergy", "probe_energy"]
+__all__ = ["Plan", "BatchPlan", "Source", "FdtdError", "load_library", "ProbeEnergy", "probe_energy"]
 
 FdtdError = _lib.FdtdError
 
@@ -196,6 +196,69 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+
+class BatchPlan(Plan):
+    """Independent grids stepped together, one launch per line pass over all
+    grids and one captured HIP graph per time step (fdtd_plan_batch;
+    fundamental forms).  grids: list of (nx, ny, nz, eps_r or None)."""
+
+    def __init__(self, grids, dt, dx, dy, dz, scheme="adi", dtype=None, stream=None, device=None,
+                 solve_dtype=None):
+        import torch
+        L = _lib.lib()
+        self.dtype = dtype if dtype is not None else torch.float32
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        solve = solve_dtype if solve_dtype is not None else self.dtype
+        if self.dtype == torch.float64 and solve != torch.float64:
+            raise ValueError("float64 fields need float64 solves")
+        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else 0)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.shapes = []
+        keep = []
+        descs = (_lib.FdtdDesc * len(grids))()
+        for g, (nx, ny, nz, eps_r) in enumerate(grids):
+            eps_ptr = None
+            if eps_r is not None:
+                e = eps_r if isinstance(eps_r, torch.Tensor) else torch.as_tensor(eps_r)
+                e = e.to(dtype=torch.float32).contiguous()
+                if tuple(e.shape) != (nz, ny, nx):
+                    raise ValueError(f"eps_r of grid {g} must have shape {(nz, ny, nx)}")
+                keep.append(e)
+                eps_ptr = e.data_ptr()
+            descs[g] = _lib.FdtdDesc(nx, ny, nz, dt, dx, dy, dz, _lib.SCHEMES[scheme], _lib.FORMS["fundamental"],
+                                     code, eps_ptr, None, 0)
+            self.shapes.append((nz + 1, ny + 1, nx + 1))
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            h = ctypes.c_void_p()
+            _lib.check(L.fdtd_plan_batch(descs, len(grids), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)),
+                       "fdtd_plan_batch")
+        self._h = h
+        self.scheme, self.form = scheme, "fundamental"
+
+    def run(self, fields, nsteps):
+        """fields: list of (E, H) per grid, updated in place (asynchronous)."""
+        if len(fields) != len(self.shapes):
+            raise ValueError(f"need fields for {len(self.shapes)} grids")
+        pe = (ctypes.c_void_p * (3 * len(fields)))()
+        ph = (ctypes.c_void_p * (3 * len(fields)))()
+        for g, (E, H) in enumerate(fields):
+            e = _ptrs(E, self.dtype, self.shapes[g], self.device)
+            h = _ptrs(H, self.dtype, self.shapes[g], self.device)
+            for c in range(3):
+                pe[3 * g + c] = e[c]
+                ph[3 * g + c] = h[c]
+        _lib.check(_lib.lib().fdtd_run_batch(self._h, pe, ph, int(nsteps)), "fdtd_run_batch")
+
+    def step(self, *a, **k):
+        raise TypeError("BatchPlan has no step(); use run(fields, 1)")
+
+    def grad_eps(self, *a, **k):
+        raise TypeError("the adjoint gradient is defined for single-grid plans")
 
 
 from .autograd import ProbeEnergy, probe_energy  # noqa: E402

@@ -20,7 +20,7 @@ DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2}
 
 EXPORTS = ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
            "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-           "fdtd_grad_eps", "fdtd_destroy", "fdtd_strerror")
+           "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_destroy", "fdtd_strerror")
 
 
 class FdtdDesc(ctypes.Structure):
@@ -75,12 +75,14 @@ def lib() -> ctypes.CDLL:
     L.fdtd_grad_eps.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
                                 ctypes.POINTER(FdtdSource), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+    L.fdtd_plan_batch.argtypes = [ctypes.POINTER(FdtdDesc), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.fdtd_run_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int]
     L.fdtd_destroy.argtypes = [vp]
     L.fdtd_strerror.argtypes = [ctypes.c_int]
     L.fdtd_strerror.restype = ctypes.c_char_p
     for name in ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
                  "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-                 "fdtd_grad_eps", "fdtd_destroy"):
+                 "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -58,7 +58,7 @@ struct KCfg { int M, TX, NT, wpb, remap; };
 
 // Instantiated y/z-line variants {M, TX, NT} by solve precision.
 static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}};
-static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}};
+static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
 
 struct Timing {
     bool per_launch = false;
@@ -66,6 +66,26 @@ struct Timing {
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<int> fam;         // family of each pair (0 = yz lines, 1 = x lines)
     size_t used = 0;
+};
+
+// Batch plans (fdtd_plan_batch): one pass of every grid of the batch per
+// launch.  For each (operator, pair, theta) the batch keeps a device table of
+// the grids' pass arguments and a work list of (grid, block) items.
+struct BatchPass {
+    int op = 0, k = 0;
+    double frac = 0.0;        // theta = frac * dt of each grid
+    void* tab = nullptr;      // device PassArgs<T, S>[ngrids]
+    void* items = nullptr;    // device int2[nitems]
+    int nitems = 0;
+    int Pmax = 1;             // y/z lines: largest chunk count (block = TX * Pmax)
+};
+struct Batch {
+    std::vector<fdtd_plan_s*> subs;
+    bool mat = false;         // every grid has a material index
+    std::vector<BatchPass> passes;
+    hipStream_t cap = nullptr;        // private stream for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;    // one time step of the main iteration
 };
 
 }  // namespace fdtd
@@ -95,6 +115,7 @@ struct fdtd_plan_s {
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
     int fam_n[2] = {0, 0};
+    fdtd::Batch* batch = nullptr;   // batch plan: the grids and their tables
     unsigned magic = 0xFD7DFD7Du;
 };
 
@@ -198,12 +219,23 @@ static T* set_ptr(fdtd_plan_s* p, int set) {
     return reinterpret_cast<T*>(p->state) + (size_t)set * 6 * p->dims.comp;
 }
 
+// Launch shape of one pass.
+struct PassShape {
+    int w = 0;            // line axis
+    dim3 grid, block;
+    size_t lds = 0;
+    bool full = false;    // every line fills its P*M slots exactly
+    bool mat = false;     // material-index variant
+};
+
+// Arguments and launch shape of the pass of pair k of operator op (half-span
+// theta, mode) from state set `set_in` to `set_out` of plan p, with the plan's
+// kernel configuration for the line axis.
 template <typename T, typename S>
-static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
-                               const Inject* inj, bool timed) {
+static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
+                       const Inject* inj, PassArgs<T, S>& a, PassShape& sh) {
     const PairDef& pd = kPairs[op][k];
     const Dims& d = p->dims;
-    PassArgs<T, S> a;
     std::memset(&a, 0, sizeof(a));
     const size_t cs = (size_t)d.comp;
     a.Ein = set_in + pd.ce * cs;
@@ -214,7 +246,8 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     a.mat = p->mat;
     a.mat_eps = p->mat_eps;
     a.nmat = p->nmat;
-    const bool mat = p->mat != nullptr;
+    sh.mat = p->mat != nullptr;
+    sh.w = pd.w;
     a.sw = axis_stride(d, pd.w);
     a.n_w = axis_cells(d, pd.w);
     const double h = axis_h(p->d, pd.w);
@@ -254,23 +287,6 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         a.src_pre_dev = inj->pre_dev ? inj->pre_dev + pd.ce : nullptr;
     }
     const int ne = axis_cells(d, pd.e), nt = axis_cells(d, pd.t);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int fam = (pd.w == 0) ? 1 : 0;
-    if (timed) {
-        Timing& tm = p->tm;
-        if (tm.used + 2 > tm.ev.size()) {
-            for (int m = 0; m < 64; ++m) {
-                hipEvent_t ev;
-                HIPCHK(hipEventCreate(&ev));
-                tm.ev.push_back(ev);
-            }
-        }
-        e0 = tm.ev[tm.used];
-        e1 = tm.ev[tm.used + 1];
-        tm.fam.push_back(fam);
-        tm.used += 2;
-        HIPCHK(hipEventRecord(e0, p->stream));
-    }
     const KCfg& cf = p->cfg[pd.w];
     a.remap = cf.remap;
     if (pd.w == 0) {
@@ -287,10 +303,9 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         const long long nlines = (long long)a.na * a.nb;
         const long long lines_per_block = (long long)cf.wpb * (64 / a.P);
         a.nblk = (int)((nlines + lines_per_block - 1) / lines_per_block);
-        const dim3 grid((unsigned)a.nblk), block(64 * cf.wpb);
-        const bool full = a.P * M == a.n_w;
-        if (M == 8) launch_x_mode<T, S, 8>(mode, full, mat, grid, block, p->stream, a);
-        else launch_x_mode<T, S, 16>(mode, full, mat, grid, block, p->stream, a);
+        sh.grid = dim3((unsigned)a.nblk);
+        sh.block = dim3(64 * cf.wpb);
+        sh.lds = 0;
     } else {
         // y/z lines: a = x axis (lanes), b = the other transverse axis
         const int other = (pd.e == 0) ? pd.t : pd.e;
@@ -299,19 +314,53 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         if (pd.e == 0) { a.a_lo = 0; a.na = d.nx; a.b_lo = 1; a.nb = nt - 1; }
         else { a.a_lo = 1; a.na = d.nx - 1; a.b_lo = 0; a.nb = ne; }
         if (has_src) { a.src_a = src_idx[0]; a.src_b = src_idx[other]; a.src_j = src_idx[pd.w]; }
-        const int M = cf.M, TX = cf.TX, NT = cf.NT;
+        const int M = cf.M, TX = cf.TX;
         a.P = next_pow2((a.n_w + M - 1) / M);
         a.ntx = (a.a_lo + a.na + TX - 1) / TX;
         a.nblk = a.ntx * a.nb;
-        const dim3 block(TX * a.P), grid((unsigned)a.nblk);
-        const size_t lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
-        const bool full = a.P * M == a.n_w;
-#define CASE_YZ(MM, TT, NN) \
-    if (M == MM && TX == TT && NT == NN) { launch_yz_mode<T, S, MM, TT, NN>(mode, full, mat, grid, block, lds, p->stream, a); } else
+        sh.block = dim3(TX * a.P);
+        sh.grid = dim3((unsigned)a.nblk);
+        sh.lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
+    }
+    sh.full = a.P * cf.M == a.n_w;
+}
+
+template <typename T, typename S>
+static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
+                               const Inject* inj, bool timed) {
+    PassArgs<T, S> a;
+    PassShape sh;
+    build_pass<T, S>(p, op, k, theta, mode, set_in, set_out, inj, a, sh);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        Timing& tm = p->tm;
+        if (tm.used + 2 > tm.ev.size()) {
+            for (int m = 0; m < 64; ++m) {
+                hipEvent_t ev;
+                HIPCHK(hipEventCreate(&ev));
+                tm.ev.push_back(ev);
+            }
+        }
+        e0 = tm.ev[tm.used];
+        e1 = tm.ev[tm.used + 1];
+        tm.fam.push_back(sh.w == 0 ? 1 : 0);
+        tm.used += 2;
+        HIPCHK(hipEventRecord(e0, p->stream));
+    }
+    const KCfg& cf = p->cfg[sh.w];
+    if (sh.w == 0) {
+        if (cf.M == 8) launch_x_mode<T, S, 8>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+        else launch_x_mode<T, S, 16>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+    } else {
+        const int M = cf.M, TX = cf.TX, NT = cf.NT;
+#define CASE_YZ(MM, TT, NN)                                                                                    \
+    if (M == MM && TX == TT && NT == NN) {                                                                     \
+        launch_yz_mode<T, S, MM, TT, NN>(mode, sh.full, sh.mat, sh.grid, sh.block, sh.lds, p->stream, a);     \
+    } else
         if constexpr (sizeof(S) == 4) {
             CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) return FDTD_EUNSUPPORTED;
         } else {
-            CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) return FDTD_EUNSUPPORTED;
+            CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) CASE_YZ(8, 16, 1024) return FDTD_EUNSUPPORTED;
         }
 #undef CASE_YZ
     }
@@ -761,6 +810,316 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
     return std::isfinite(*J_out) ? FDTD_OK : FDTD_ENONFINITE;
 }
 
+// ---------------------------------------------------------------------------
+// batch plans
+// ---------------------------------------------------------------------------
+static void batch_clear(Batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (BatchPass& bp : b->passes) {
+        if (bp.tab) (void)hipFree(bp.tab);
+        if (bp.items) (void)hipFree(bp.items);
+    }
+    b->passes.clear();
+}
+
+// Chunks per line of a grid in a batched pass (y/z: at least 64/TX, so that a
+// sub-block of TX * P threads is whole waves).
+static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
+    const int P = next_pow2((axis_cells(g->dims, axis) + c.M - 1) / c.M);
+    return axis == 0 ? P : std::max(P, 64 / c.TX);
+}
+
+static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
+    int Pmax = 1;
+    for (const fdtd_plan_s* g : p->batch->subs) {
+        if (!cfg_valid(g, axis, c)) return false;
+        Pmax = std::max(Pmax, batch_P(g, axis, c));
+    }
+    if (Pmax > 64) return false;
+    return axis == 0 || c.TX * Pmax <= c.NT;
+}
+
+static void batch_default_cfg(fdtd_plan_s* p) {
+    for (int axis = 0; axis < 3; ++axis) {
+        std::vector<KCfg> pref;
+        if (axis == 0) pref = {{8, 0, 0, 4, 0}, {16, 0, 0, 4, 0}};
+        else if (p->d.dtype == FDTD_F32) pref = {{8, 16, 1024, 0, 0}, {16, 32, 1024, 0, 0}, {16, 16, 512, 0, 0}, {32, 16, 512, 0, 0}};
+        else pref = {{8, 8, 512, 0, 0}, {16, 16, 512, 0, 0}};
+        for (const KCfg& c : pref)
+            if (batch_cfg_valid(p, axis, c)) { p->cfg[axis] = c; break; }
+    }
+}
+
+// The table of pass (op, k) with theta = frac * dt for every grid (built on
+// first use with the current kernel configuration).
+template <typename T, typename S>
+static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const BatchPass** out) {
+    Batch* b = p->batch;
+    for (const BatchPass& bp : b->passes)
+        if (bp.op == op && bp.k == k && bp.frac == frac) { *out = &bp; return FDTD_OK; }
+    const int w = kPairs[op][k].w;
+    const KCfg& cf = p->cfg[w];
+    const int n = (int)b->subs.size();
+    std::vector<PassArgs<T, S>> tab(n);
+    int Pmax = 1;
+    for (int g = 0; g < n; ++g) {
+        fdtd_plan_s* sub = b->subs[g];
+        sub->cfg[w] = cf;
+        PassShape sh;
+        build_pass<T, S>(sub, op, k, frac * sub->d.dt, FUND, set_ptr<T>(sub, 0), set_ptr<T>(sub, 0), nullptr,
+                         tab[g], sh);
+        tab[g].P = batch_P(sub, w, cf);
+        tab[g].remap = 0;
+        Pmax = std::max(Pmax, tab[g].P);
+    }
+    std::vector<int2> items;
+    for (int g = 0; g < n; ++g) {
+        const int per = (w == 0) ? 1 : Pmax / tab[g].P;   // virtual blocks per block
+        const int nit = (tab[g].nblk + per - 1) / per;
+        for (int q = 0; q < nit; ++q) items.push_back(make_int2(g, q));
+    }
+    BatchPass bp;
+    bp.op = op; bp.k = k; bp.frac = frac; bp.Pmax = Pmax;
+    bp.nitems = (int)items.size();
+    HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * n));
+    hipError_t e = hipMalloc(&bp.items, sizeof(int2) * items.size());
+    if (e == hipSuccess) e = hipMemcpy(bp.tab, tab.data(), sizeof(PassArgs<T, S>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bp.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(bp.tab);
+        if (bp.items) (void)hipFree(bp.items);
+        return from_hip(e);
+    }
+    b->passes.push_back(bp);
+    *out = &b->passes.back();
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
+    const int w = kPairs[bp.op][bp.k].w;
+    const KCfg& cf = p->cfg[w];
+    const bool mat = p->batch->mat;
+    const auto* tab = static_cast<const PassArgs<T, S>*>(bp.tab);
+    const auto* items = static_cast<const int2*>(bp.items);
+    const dim3 grid((unsigned)bp.nitems);
+    if (w == 0) {
+        const dim3 block(64 * cf.wpb);
+        if (cf.M == 8) {
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, FUND, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, FUND, false>), grid, block, 0, st, tab, items);
+        } else {
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, FUND, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, FUND, false>), grid, block, 0, st, tab, items);
+        }
+    } else {
+        const int M = cf.M, TX = cf.TX, NT = cf.NT;
+        const dim3 block(TX * bp.Pmax);
+        const size_t lds = (size_t)9 * bp.Pmax * (TX + 1) * sizeof(S);
+#define CASE_YZB(MM, TT, NN)                                                                                  \
+    if (M == MM && TX == TT && NT == NN) {                                                                    \
+        if (mat)                                                                                              \
+            hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, FUND, TT, NN, true>), grid, block, lds, st, tab, items); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, FUND, TT, NN, false>), grid, block, lds, st, tab, items); \
+    } else
+        if constexpr (sizeof(S) == 4) {
+            CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) return FDTD_EUNSUPPORTED;
+        } else {
+            CASE_YZB(16, 16, 512) CASE_YZB(8, 8, 512) CASE_YZB(8, 16, 1024) return FDTD_EUNSUPPORTED;
+        }
+#undef CASE_YZB
+    }
+    HIPCHK(hipGetLastError());
+    return FDTD_OK;
+}
+
+// One sub-step (operator op, theta = frac * dt) of every grid: three launches.
+template <typename T, typename S>
+static fdtd_status batch_substep(fdtd_plan_s* p, int op, double frac, hipStream_t st) {
+    for (int k = 0; k < 3; ++k) {
+        const BatchPass* bp = nullptr;
+        fdtd_status s = batch_pass<T, S>(p, op, k, frac, &bp);
+        if (s != FDTD_OK) return s;
+        s = batch_launch<T, S>(p, *bp, st);
+        if (s != FDTD_OK) return s;
+    }
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status batch_tables(fdtd_plan_s* p) {
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    for (int u = 0; u < sd.nsub; ++u)
+        for (int k = 0; k < 3; ++k) {
+            const BatchPass* bp = nullptr;
+            fdtd_status s = batch_pass<T, S>(p, sd.sub[u].op, k, sd.sub[u].theta_frac, &bp);
+            if (s != FDTD_OK) return s;
+        }
+    if (p->d.scheme == FDTD_LOD2)
+        for (double f : {0.25, -0.25})
+            for (int k = 0; k < 3; ++k) {
+                const BatchPass* bp = nullptr;
+                fdtd_status s = batch_pass<T, S>(p, 1, k, f, &bp);
+                if (s != FDTD_OK) return s;
+            }
+    return FDTD_OK;
+}
+
+// Capture one time step of the main iteration (all sub-steps) as a graph.
+template <typename T, typename S>
+static fdtd_status batch_graph(fdtd_plan_s* p) {
+    Batch* b = p->batch;
+    if (b->exec) return FDTD_OK;
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    fdtd_status st = FDTD_OK;
+    for (int u = 0; u < sd.nsub && st == FDTD_OK; ++u) st = batch_substep<T, S>(p, sd.sub[u].op, sd.sub[u].theta_frac, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != FDTD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(e);
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H, int nsteps) {
+    Batch* b = p->batch;
+    const fdtd_desc& d = p->d;
+    const bool adi = d.scheme == FDTD_ADI;
+    const int n = (int)b->subs.size();
+    auto caller = [&](int g) {
+        FieldPtrs<T> f;
+        for (int c = 0; c < 3; ++c) {
+            f.c[c] = static_cast<const T*>(E[3 * g + c]);
+            f.c[3 + c] = static_cast<const T*>(H[3 * g + c]);
+        }
+        return f;
+    };
+    fdtd_status st = batch_tables<T, S>(p);
+    if (st != FDTD_OK) return st;
+    for (int g = 0; g < n; ++g) {
+        fdtd_plan_s* sub = b->subs[g];
+        const Dims& dm = sub->dims;
+        const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+        AuxCoef kin{kEps0, kMu0, sub->d.dx, sub->d.dy, sub->d.dz, adi ? 0.25 * sub->d.dt : 0.0};
+        hipLaunchKernelGGL((load_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
+                           caller(g), state_ptrs_w<T>(sub, 0), sub->eps, dm, kin);
+        HIPCHK(hipGetLastError());
+    }
+    if (d.scheme == FDTD_LOD2) {
+        st = batch_substep<T, S>(p, 1, 0.25, p->stream);
+        if (st != FDTD_OK) return st;
+    }
+    const int ngraph = nsteps > 0 ? (adi ? nsteps - 1 : nsteps) : 0;
+    if (ngraph > 0) {
+        st = batch_graph<T, S>(p);
+        if (st != FDTD_OK) return st;
+    }
+    Timing& tm = p->tm;
+    tm.used = 0;
+    tm.fam.clear();
+    if (!tm.main0) {
+        HIPCHK(hipEventCreate(&tm.main0));
+        HIPCHK(hipEventCreate(&tm.main1));
+    }
+    HIPCHK(hipEventRecord(tm.main0, p->stream));
+    for (int m = 0; m < ngraph; ++m) HIPCHK(hipGraphLaunch(b->exec, p->stream));
+    if (adi && nsteps > 0) {
+        // last step: the state before the B sub-step is kept for the output
+        st = batch_substep<T, S>(p, 0, 0.5, p->stream);
+        if (st != FDTD_OK) return st;
+        for (fdtd_plan_s* sub : b->subs)
+            HIPCHK(hipMemcpyAsync(sub->snap, sub->state, sizeof(T) * sub->dims.comp * 6, hipMemcpyDeviceToDevice,
+                                  p->stream));
+        st = batch_substep<T, S>(p, 1, 0.5, p->stream);
+        if (st != FDTD_OK) return st;
+    }
+    HIPCHK(hipEventRecord(tm.main1, p->stream));
+    if (nsteps > 0) {
+        if (d.scheme == FDTD_LOD2) {
+            st = batch_substep<T, S>(p, 1, -0.25, p->stream);
+            if (st != FDTD_OK) return st;
+        }
+        for (int g = 0; g < n; ++g) {
+            fdtd_plan_s* sub = b->subs[g];
+            const Dims& dm = sub->dims;
+            const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+            FieldPtrsW<T> out;
+            for (int c = 0; c < 3; ++c) {
+                out.c[c] = static_cast<T*>(E[3 * g + c]);
+                out.c[3 + c] = static_cast<T*>(H[3 * g + c]);
+            }
+            FieldPtrs<T> old;
+            for (int c = 0; c < 6; ++c)
+                old.c[c] = reinterpret_cast<const T*>(adi ? sub->snap : sub->state) + (size_t)c * dm.comp;
+            hipLaunchKernelGGL((store_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
+                               state_ptrs<T>(sub, 0), old, out, dm, adi ? 1 : 0, -1LL, 0.0);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    p->step += nsteps;
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status batch_autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
+    Batch* b = p->batch;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    fdtd_status st = FDTD_OK;
+    for (int axis = 0; axis < 3 && st == FDTD_OK; ++axis) {
+        int k = 0;
+        while (kPairs[0][k].w != axis) ++k;
+        std::vector<KCfg> cand;
+        if (axis == 0) {
+            for (int M : {8, 16})
+                for (int wpb : {4, 2, 1}) cand.push_back(KCfg{M, 0, 0, wpb, 0});
+        } else if (p->d.dtype == FDTD_F32) {
+            for (const auto& v : kYzF32) cand.push_back(KCfg{v[0], v[1], v[2], 0, 0});
+        } else {
+            for (const auto& v : kYzF64) cand.push_back(KCfg{v[0], v[1], v[2], 0, 0});
+        }
+        KCfg best = p->cfg[axis];
+        float tbest = 1e30f;
+        for (const KCfg& c : cand) {
+            if (!batch_cfg_valid(p, axis, c)) continue;
+            p->cfg[axis] = c;
+            batch_clear(b);
+            const BatchPass* bp = nullptr;
+            st = batch_pass<T, S>(p, 0, k, 0.5, &bp);
+            if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, p->stream);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e0, p->stream) != hipSuccess) { st = FDTD_EDEVICE; break; }
+            for (int r = 0; r < reps && st == FDTD_OK; ++r) st = batch_launch<T, S>(p, *bp, p->stream);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = FDTD_EDEVICE;
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < tbest) { tbest = ms; best = c; }
+        }
+        p->cfg[axis] = best;
+        if (best_ms) best_ms[axis] = tbest / reps;
+    }
+    batch_clear(b);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == FDTD_OK) p->tuned = 1;
+    return st;
+}
+
 }  // namespace fdtd
 
 using namespace fdtd;
@@ -879,7 +1238,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
 
 fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
                      double* energy, int energy_every) {
-    if (!plan_ok(p) || !E || !H || nsteps < 0) return FDTD_EINVAL;
+    if (!plan_ok(p) || p->batch || !E || !H || nsteps < 0) return FDTD_EINVAL;
     for (int c = 0; c < 3; ++c)
         if (!E[c] || !H[c]) return FDTD_EINVAL;
     if (energy && energy_every < 1) return FDTD_EINVAL;
@@ -939,7 +1298,7 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* fam_ms_avg,
 
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
     if (!plan_ok(p) || reps < 1) return FDTD_EINVAL;
-    const char* cache = std::getenv("FDTD_TUNE_CACHE");
+    const char* cache = p->batch ? nullptr : std::getenv("FDTD_TUNE_CACHE");
     if (cache && *cache && tune_cache_lookup(p, cache)) {
         p->tuned = 2;
         if (best_ms) best_ms[0] = best_ms[1] = best_ms[2] = 0.0;
@@ -949,7 +1308,11 @@ fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
     (void)hipGetDevice(&dev_now);
     if (dev_now != p->device) (void)hipSetDevice(p->device);
     fdtd_status st;
-    if (p->d.dtype == FDTD_F32) st = autotune_impl<float, float>(p, reps, best_ms);
+    if (p->batch) {
+        if (p->d.dtype == FDTD_F32) st = batch_autotune_impl<float, float>(p, reps, best_ms);
+        else if (p->d.dtype == FDTD_F64) st = batch_autotune_impl<double, double>(p, reps, best_ms);
+        else st = batch_autotune_impl<float, double>(p, reps, best_ms);
+    } else if (p->d.dtype == FDTD_F32) st = autotune_impl<float, float>(p, reps, best_ms);
     else if (p->d.dtype == FDTD_F64) st = autotune_impl<double, double>(p, reps, best_ms);
     else st = autotune_impl<float, double>(p, reps, best_ms);
     if (dev_now != p->device) (void)hipSetDevice(dev_now);
@@ -972,7 +1335,13 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
     KCfg k{c->chunk, axis == 0 ? 0 : c->tile_x, axis == 0 ? 0 : c->block_threads,
            axis == 0 ? c->block_threads / 64 : 0, c->remap};
     if (axis == 0 && c->block_threads % 64 != 0) return FDTD_EINVAL;
-    if (!cfg_valid(p, axis, k)) return FDTD_EINVAL;
+    if (p->batch) {
+        if (!batch_cfg_valid(p, axis, k)) return FDTD_EINVAL;
+        (void)hipStreamSynchronize(p->stream);
+        batch_clear(p->batch);
+    } else if (!cfg_valid(p, axis, k)) {
+        return FDTD_EINVAL;
+    }
     p->cfg[axis] = k;
     return FDTD_OK;
 }
@@ -980,7 +1349,7 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
 fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
                           int probe_i, int probe_j, int probe_k, const int* design_box, int ckpt_every,
                           double* J_out, double* grad_out) {
-    if (!plan_ok(p) || !E || !H || nsteps < 0 || !J_out) return FDTD_EINVAL;
+    if (!plan_ok(p) || p->batch || !E || !H || nsteps < 0 || !J_out) return FDTD_EINVAL;
     for (int c = 0; c < 3; ++c)
         if (!E[c] || !H[c]) return FDTD_EINVAL;
     const fdtd_desc& d = p->d;
@@ -1015,9 +1384,75 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
     return st;
 }
 
+fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_plan_t* out) {
+    if (!d || !out || n < 1) return FDTD_EINVAL;
+    *out = nullptr;
+    for (int g = 0; g < n; ++g) {
+        if (d[g].scheme != d[0].scheme || d[g].form != d[0].form || d[g].dtype != d[0].dtype) return FDTD_EINVAL;
+        if (d[g].scheme < 0 || d[g].scheme > 3 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 2)
+            return FDTD_EINVAL;
+    }
+    if (d[0].form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
+    if (!p) return FDTD_ENOMEM;
+    p->batch = new (std::nothrow) Batch();
+    if (!p->batch) {
+        delete p;
+        return FDTD_ENOMEM;
+    }
+    p->d = d[0];
+    p->d.eps_r = nullptr;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&p->device);
+    p->esz = d[0].dtype == FDTD_F64 ? 8 : 4;
+    fdtd_status st = FDTD_OK;
+    for (int g = 0; g < n && st == FDTD_OK; ++g) {
+        fdtd_plan_t sub = nullptr;
+        st = fdtd_plan(&d[g], hip_stream, &sub);
+        if (st == FDTD_OK) p->batch->subs.push_back(sub);
+    }
+    if (st == FDTD_OK && hipStreamCreateWithFlags(&p->batch->cap, hipStreamNonBlocking) != hipSuccess)
+        st = FDTD_EDEVICE;
+    if (st != FDTD_OK) {
+        for (fdtd_plan_s* sub : p->batch->subs) (void)fdtd_destroy(sub);
+        delete p->batch;
+        delete p;
+        return st;
+    }
+    bool mat = true;
+    for (const fdtd_plan_s* sub : p->batch->subs) mat = mat && sub->mat != nullptr;
+    p->batch->mat = mat;
+    batch_default_cfg(p);
+    *out = p;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_run_batch(fdtd_plan_t p, void* const* E, void* const* H, int nsteps) {
+    if (!plan_ok(p) || !p->batch || !E || !H || nsteps < 0) return FDTD_EINVAL;
+    const size_t n = p->batch->subs.size();
+    for (size_t m = 0; m < 3 * n; ++m)
+        if (!E[m] || !H[m]) return FDTD_EINVAL;
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    fdtd_status st;
+    if (p->d.dtype == FDTD_F32) st = run_batch_impl<float, float>(p, E, H, nsteps);
+    else if (p->d.dtype == FDTD_F64) st = run_batch_impl<double, double>(p, E, H, nsteps);
+    else st = run_batch_impl<float, double>(p, E, H, nsteps);
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    return st;
+}
+
 fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (!plan_ok(p)) return FDTD_EINVAL;
     (void)hipStreamSynchronize(p->stream);
+    if (p->batch) {
+        batch_clear(p->batch);
+        for (fdtd_plan_s* sub : p->batch->subs) (void)fdtd_destroy(sub);
+        if (p->batch->cap) (void)hipStreamDestroy(p->batch->cap);
+        delete p->batch;
+        p->batch = nullptr;
+    }
     if (p->state) (void)hipFree(p->state);
     if (p->snap) (void)hipFree(p->snap);
     if (p->eps) (void)hipFree(p->eps);

@@ -32,12 +32,19 @@ template <typename T> struct Big;
 template <> struct Big<float> { static constexpr float v = 1.2676506e30f; };   // 2^100
 template <> struct Big<double> { static constexpr double v = 1.2676506002282294e30; };
 
-// Reciprocal: v_rcp_f32 refined by one Newton step (about 0.5 ulp) / IEEE divide in FP64.
+// Reciprocal of a positive normal number (pivots, diagonals): the hardware
+// estimate refined by Newton-Raphson steps r <- r + r (1 - x r), one for FP32
+// and two for FP64 (each step squares the relative error), which ends within
+// about an ulp without the scaling and fix-up steps of an IEEE division.
 __device__ __forceinline__ float recip(float x) {
     float r = __builtin_amdgcn_rcpf(x);
     return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 
 // Per-thread state of one chunk after local elimination, folded with the
 // outputs so that 4 words per slot stay live:

@@ -170,9 +170,15 @@ __device__ __forceinline__ void ld_bytes(Rsrc r, int vo, unsigned (&id)[M]) {
 // ---------------------------------------------------------------------------
 // per-slot right-hand side
 // ---------------------------------------------------------------------------
+// sigma of a slot.  In FP32 the diagonal 2 + sigma is rounded to the spacing
+// of numbers near 2, which is coarse relative to a sigma << 1 (large time
+// steps); sigma is therefore returned as fl(2 + sigma) - 2 (exact), so the
+// diagonal and the right-hand side use the same value and every sub-step
+// stays an exact Cayley factor of a (very slightly) perturbed medium instead
+// of losing energy coherently step after step.
 template <typename S>
 __device__ __forceinline__ S make_sigma(double Ks, float eps) {
-    if constexpr (sizeof(S) == 4) return float(Ks) * eps;
+    if constexpr (sizeof(S) == 4) return (2.0f + float(Ks) * eps) - 2.0f;
     else return Ks * double(eps);
 }
 
@@ -212,17 +218,16 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 // 128-byte aligned).  The separator system is solved with cross-lane PCR.
 // FULL: P*M == n_w (no slot beyond the line).
 // ---------------------------------------------------------------------------
+// Body of one block of x-line work: block `blk` of the pass described by `a`
+// (lines blk * waves * 64/P ...); mtab = the material table in LDS (MAT).
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
-__global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
+__device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const float* mtab) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
-    __shared__ float mtab[MAT ? 256 : 1];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
     constexpr int ES = (int)sizeof(T);
     const int P = a.P;
     const int lane = threadIdx.x & 63;
     const int ls = lane & (P - 1);
     const int wave = wave_uniform(threadIdx.x >> 6);
-    const int blk = a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x);
     const long long nlines = (long long)a.na * a.nb;
     const long long raw0 = ((long long)blk * (blockDim.x >> 6) + wave) * (64 / P);
     const long long line = raw0 + lane / P;
@@ -353,6 +358,24 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     }
 }
 
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
+__global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
+    __shared__ float mtab[MAT ? 256 : 1];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    pass_x_body<T, S, M, MODE, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), mtab);
+}
+
+// Batched x lines: block b runs work item items[b] = (entry of tab, block of
+// that entry's pass); one launch covers the passes of many grids.
+template <typename T, typename S, int M, int MODE, bool MAT>
+__global__ void __launch_bounds__(256) pass_x_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
+    __shared__ float mtab[MAT ? 256 : 1];
+    const int2 it = items[blockIdx.x];
+    const PassArgs<T, S> a = tab[it.x];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    pass_x_body<T, S, M, MODE, false, MAT>(a, it.y, mtab);
+}
+
 // ---------------------------------------------------------------------------
 // y and z lines: strided axis.  A block holds TX consecutive x positions (the
 // transverse index a) times P chunks; thread t = tx + TX p.  Loads and stores
@@ -360,17 +383,17 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // consecutive lanes, are reduced by cross-lane PCR, and S returns through LDS.
 // FULL: P*M == n_w.
 // ---------------------------------------------------------------------------
+// Body of one (virtual) block of TX * P threads: thread t, block index blk of
+// the pass (blk < a.nblk when valid; an invalid block computes nothing and
+// stores nothing but takes part in the barriers), LDS area sm of
+// 9 P (TX+1) elements.  TX * P must be a multiple of 64 (whole waves).
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
-__global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
+__device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const float* mtab,
+                                             bool valid) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
-    __shared__ float mtab[MAT ? 256 : 1];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
     constexpr int ES = (int)sizeof(T);
     constexpr int CPW = 64 / TX;                  // chunks per wave
-    extern __shared__ unsigned char smem_raw[];
-    S* sm = reinterpret_cast<S*>(smem_raw);
     const int P = a.P;
-    const int t = threadIdx.x;
     const int tx = t % TX, p = t / TX;
     constexpr int LD = TX + 1;                   // padded row (bank conflicts)
     S* ep_ = sm;                                 // [8][P][LD]
@@ -378,11 +401,10 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
     auto EP = [&](int k, int pp, int xx) -> S& { return ep_[(k * P + pp) * LD + xx]; };
     auto SB = [&](int pp, int xx) -> S& { return sb_[pp * LD + xx]; };
 
-    const int blk = a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x);
     const int tile0 = (blk % a.ntx) * TX;
     const int ib = a.b_lo + blk / a.ntx;
     const int ia = tile0 + tx;
-    const bool live = ia >= a.a_lo && ia < a.a_lo + a.na;
+    const bool live = valid && ia >= a.a_lo && ia < a.a_lo + a.na;
     const int wave = wave_uniform(t >> 6);
     const int pw0 = wave * CPW;                  // first chunk of this wave
     const int n = a.n_w;
@@ -501,6 +523,44 @@ __global__ void __launch_bounds__(NT) pass_yz_kernel(PassArgs<T, S> a) {
             Buf<T>::st(T(ho[i]), wH, vo, i * swb);
         }
     }
+}
+
+// Waves per SIMD the register allocation must allow: FP32 solves with 8-slot
+// chunks (modes without the cross-term arrays) fit in 64 VGPRs, so two
+// 1024-thread blocks share a CU and one block's loads overlap the other's LDS
+// phase.
+template <typename S, int M, int MODE, int NT>
+struct YzOcc {
+    static constexpr int v = (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI) ? 8 : 1;
+};
+
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
+__global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT>::v)) pass_yz_kernel(PassArgs<T, S> a) {
+    __shared__ float mtab[MAT ? 256 : 1];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    extern __shared__ unsigned char smem_raw[];
+    pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
+                                                   threadIdx.x, reinterpret_cast<S*>(smem_raw), mtab, true);
+}
+
+// Batched y/z lines: block b runs work item items[b] = (entry e of tab, item
+// index q).  The block has blockDim.x = TX * Pmax threads; entry e has P <=
+// Pmax chunks per line, so the block splits into Pmax/P sub-blocks of TX * P
+// threads, which run the virtual blocks q * (Pmax/P) + sub of that entry.
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool MAT>
+__global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
+    __shared__ float mtab[MAT ? 256 : 1];
+    extern __shared__ unsigned char smem_raw[];
+    const int2 it = items[blockIdx.x];
+    const PassArgs<T, S> a = tab[it.x];
+    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    const int sub_n = TX * a.P;
+    const int spb = blockDim.x / sub_n;
+    const int sub = threadIdx.x / sub_n;
+    const int vb = it.y * spb + sub;
+    S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * 9 * a.P * (TX + 1);
+    const bool valid = vb < a.nblk;
+    pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, mtab, valid);
 }
 
 }  // namespace fdtd

@@ -1,0 +1,195 @@
+"""Batched grids (fdtd_plan_batch / fdtd_run_batch): one launch per line pass
+over all grids, one captured HIP graph per time step.  Checked against the
+FP64 oracle per grid on small uneven grids and against the single-grid GPU
+path on the 64-cavity workload (sizes U[16, 96], 500 steps, CFL 5)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
+        "f32s64": (torch.float32, torch.float64)}
+TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
+
+
+def _fields(u0, dtype):
+    return ([torch.tensor(a, dtype=dtype, device=DEV) for a in u0[:3]],
+            [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[3:]])
+
+
+def _grids(sizes, seed):
+    out = []
+    for g, (nx, ny, nz) in enumerate(sizes):
+        eps = W.random_box_eps(nx, ny, nz, seed=seed + g, nboxes=32)
+        u0 = W.random_fields(nx, ny, nz, seed=seed + 100 + g)
+        out.append((nx, ny, nz, eps, u0))
+    return out
+
+
+SMALL = [(16, 18, 17), (21, 16, 25), (17, 23, 16), (30, 19, 22), (16, 16, 16)]
+
+
+@pytest.fixture(scope="module")
+def small_refs():
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    grids = _grids(SMALL, seed=40)
+    refs = {}
+    for scheme in oracle.SCHEMES:
+        refs[scheme] = [oracle.run(scheme, "fundamental", oracle.Grid(nx, ny, nz, h, h, h, dt, eps), u0, 10)[0]
+                        for (nx, ny, nz, eps, u0) in grids]
+    return dict(h=h, dt=dt, grids=grids, refs=refs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32"])
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_batch_vs_oracle_small(small_refs, scheme, prec):
+    from paper_2011_14043_amd import BatchPlan
+    c = small_refs
+    dtype, solve = PREC[prec]
+    print(f"[case] batch 5 grids {scheme}/{prec}", flush=True)
+    plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in c["grids"]], c["dt"], c["h"],
+                     c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve)
+    fields = [_fields(u0, dtype) for (*_, u0) in c["grids"]]
+    plan.run(fields, 10)
+    torch.cuda.synchronize()
+    plan.close()
+    for g, ((nx, ny, nz, eps, _), (E, H)) in enumerate(zip(c["grids"], fields)):
+        got = [t.double().cpu().numpy() for t in E + H]
+        gr = oracle.Grid(nx, ny, nz, c["h"], c["h"], c["h"], c["dt"], eps)
+        err = oracle.yee.weighted_rel_l2(got, c["refs"][scheme][g], gr)
+        assert err <= TOL[prec], (g, err)
+
+
+def test_batch_split_runs_and_configs_agree(small_refs):
+    """12 steps in one call == 7 + 5 steps (input/output processing between
+    calls is exact for ADI); every kernel configuration gives the same
+    result to rounding; the graph is rebuilt after a configuration change."""
+    from paper_2011_14043_amd import BatchPlan
+    c = small_refs
+    grids = [(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in c["grids"]]
+    plan = BatchPlan(grids, c["dt"], c["h"], c["h"], c["h"], scheme="adi", dtype=torch.float64)
+    f1 = [_fields(u0, torch.float64) for (*_, u0) in c["grids"]]
+    f2 = [_fields(u0, torch.float64) for (*_, u0) in c["grids"]]
+    plan.run(f1, 12)
+    plan.run(f2, 7)
+    plan.run(f2, 5)
+    torch.cuda.synchronize()
+    for (E1, H1), (E2, H2) in zip(f1, f2):
+        for a, b in zip(E1 + H1, E2 + H2):
+            torch.testing.assert_close(a, b, rtol=0, atol=1e-12 * float(a.abs().max()) + 1e-300)
+    plan.set_kernel_config(0, chunk=16, block_threads=128)
+    plan.set_kernel_config(1, chunk=8, tile_x=8, block_threads=512)
+    f3 = [_fields(u0, torch.float64) for (*_, u0) in c["grids"]]
+    plan.run(f3, 12)
+    torch.cuda.synchronize()
+    plan.close()
+    for (E1, H1), (E3, H3) in zip(f1, f3):
+        for a, b in zip(E1 + H1, E3 + H3):
+            torch.testing.assert_close(a, b, rtol=0, atol=1e-12 * float(a.abs().max()) + 1e-300)
+
+
+def test_batch_invalid():
+    from paper_2011_14043_amd import BatchPlan, FdtdError, _lib
+    import ctypes
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    L = _lib.lib()
+    d = (_lib.FdtdDesc * 2)(_lib.FdtdDesc(16, 16, 16, dt, h, h, h, 0, 1, 0, None, None, 0),
+                            _lib.FdtdDesc(16, 16, 16, dt, h, h, h, 0, 1, 0, None, None, 0))
+    hnd = ctypes.c_void_p()
+    assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -4       # conventional form
+    d[1].form = 0
+    assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # mixed forms
+    d[0].form = 0
+    d[1].scheme = 1
+    assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # mixed schemes
+    d[1].scheme = 0
+    d[1].nx = 1
+    assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # invalid grid
+    assert L.fdtd_plan_batch(d, 0, None, ctypes.byref(hnd)) == -1
+    plan = BatchPlan([(16, 17, 18, None)], dt, h, h, h)
+    E = [torch.zeros((19, 18, 17), device=DEV) for _ in range(3)]
+    pe = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in E])
+    # single-grid entry points reject a batch plan
+    assert L.fdtd_run(plan._h, pe, pe, 1, None, None, 1) == -1
+    with pytest.raises(FdtdError, match="EINVAL"):
+        plan.set_kernel_config(1, chunk=16, tile_x=24, block_threads=512)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# the 64-cavity workload
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cavities():
+    sizes = W.cavity_batch(64, seed=4)
+    return _grids(sizes, seed=1000)
+
+
+@pytest.fixture(scope="module")
+def cavities_single_f64(cavities):
+    """Each cavity alone through the single-grid FP64 path, 500 steps."""
+    from paper_2011_14043_amd import Plan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    out = []
+    for (nx, ny, nz, eps, u0) in cavities:
+        E, H = _fields(u0, torch.float64)
+        p = Plan(nx, ny, nz, dt, h, h, h, scheme="adi", dtype=torch.float64, eps_r=torch.tensor(eps))
+        p.run(E, H, 500)
+        p.close()
+        out.append([t.cpu().numpy() for t in E + H])
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32s64", 2e-5), ("f32", 1e-4)])
+def test_64_cavities_vs_single_grid(cavities, cavities_single_f64, prec, tol):
+    from paper_2011_14043_amd import BatchPlan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    dtype, solve = PREC[prec]
+    print(f"[case] 64 cavities U[16,96], 500 steps, {prec}", flush=True)
+    plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in cavities], dt, h, h, h,
+                     scheme="adi", dtype=dtype, solve_dtype=solve)
+    plan.autotune(2)
+    fields = [_fields(u0, dtype) for (*_, u0) in cavities]
+    plan.run(fields, 500)
+    torch.cuda.synchronize()
+    plan.close()
+    worst = 0.0
+    for g, ((nx, ny, nz, eps, _), (E, H)) in enumerate(zip(cavities, fields)):
+        got = [t.double().cpu().numpy() for t in E + H]
+        gr = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+        err = oracle.yee.weighted_rel_l2(got, cavities_single_f64[g], gr)
+        worst = max(worst, err)
+    print(f"  worst cavity rel-L2 vs single-grid FP64: {worst:.2e}", flush=True)
+    assert worst <= tol
+
+
+def test_64_cavities_smallest_vs_oracle(cavities):
+    """The three smallest cavities of the batch after 500 steps (FP64 batch)
+    against the oracle."""
+    from paper_2011_14043_amd import BatchPlan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    order = sorted(range(len(cavities)), key=lambda g: np.prod(cavities[g][:3]))[:3]
+    plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in cavities], dt, h, h, h,
+                     scheme="adi", dtype=torch.float64)
+    fields = [_fields(u0, torch.float64) for (*_, u0) in cavities]
+    plan.run(fields, 500)
+    torch.cuda.synchronize()
+    plan.close()
+    for g in order:
+        nx, ny, nz, eps, u0 = cavities[g]
+        gr = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+        ref, _ = oracle.run("adi", "fundamental", gr, u0, 500)
+        got = [t.cpu().numpy() for t in fields[g][0] + fields[g][1]]
+        err = oracle.yee.weighted_rel_l2(got, ref, gr)
+        print(f"  cavity {g} {nx}x{ny}x{nz}: rel-L2 vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-10
