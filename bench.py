@@ -28,6 +28,44 @@ METRIC = "Mcell-updates/s per step, fundamental vs conventional ADI, FP32 vs FP6
 HBM_PEAK_GBS = 8000.0
 
 
+# HBM traffic of the dominant kernel from rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch, averaged over the y and z passes of the
+# timed steps; calibration factors from a 1 GiB device copy).  Valid only for
+# the kernel sources whose hash is recorded and the profiled y/z
+# configuration; otherwise the bench reports traffic = null.
+PROFILED = {
+    "kernel_hash": "b41612cc146b25ca",
+    "config": [16, 32, 1024],                                # chunk, tile_x, block_threads (y and z)
+    "fetch_kib": {"y": 596562.6, "z": 785810.1},
+    "write_kib": {"y": 1047552.0, "z": 1092026.6},
+    "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
+    "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
+    "profile": "profiles/pass_kernels_adi_fundamental_f32_512cube.md",
+}
+
+
+def kernel_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in ("pass_kernels.hpp", "line_solver.hpp"):
+        with open(os.path.join(ROOT, "paper_2011_14043_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def profiled_traffic(cfg_y, cfg_z):
+    pr = PROFILED
+    if not pr or pr["kernel_hash"] != kernel_hash():
+        return None
+    want = pr["config"]
+    for c in (cfg_y, cfg_z):
+        if [c["chunk"], c["tile_x"], c["block_threads"]] != want:
+            return None
+    fetch = sum(pr["fetch_kib"].values()) / len(pr["fetch_kib"]) * 1024 * pr["fetch_factor"]
+    write = sum(pr["write_kib"].values()) / len(pr["write_kib"]) * 1024 * pr["write_factor"]
+    return fetch + write
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -55,7 +93,7 @@ def pass_nodes(n):
     return n * (n - 1) * n
 
 
-def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, tune=True):
+def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, tune=True, tune_reps=5):
     import torch
     from paper_2011_14043_amd import Plan, Source
     h, dt, eps, ci = inputs
@@ -69,7 +107,7 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, t
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.from_numpy(eps))
     if tune:
-        plan.autotune(3)
+        plan.autotune(tune_reps)
     cfg = [plan.kernel_config(ax) for ax in range(3)]
     if warmup:
         plan.run(E, H, warmup, source=src)
@@ -103,7 +141,88 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, t
     return out
 
 
-def cpu_baseline(n=256, steps=1):
+def run_batch(steps, warmup, prec="f32"):
+    """64 independent PEC cavities, sizes U[16, 96] per axis (seed 4), random-box
+    eps_r and N(0,1) fields per cavity, fundamental ADI, CFL 5: one launch per
+    line pass over all cavities, one captured graph per step."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2011_14043_amd import BatchPlan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    sizes = W.cavity_batch(64, seed=4)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    solve = torch.float64 if prec in ("f64", "f32s64") else torch.float32
+    dev = torch.device("cuda", 0)
+    grids, fields = [], []
+    for g, (nx, ny, nz) in enumerate(sizes):
+        eps = W.random_box_eps(nx, ny, nz, seed=1000 + g, nboxes=32)
+        u0 = W.random_fields(nx, ny, nz, seed=1100 + g)
+        grids.append((nx, ny, nz, torch.from_numpy(eps)))
+        fields.append(([torch.tensor(a, dtype=dtype, device=dev) for a in u0[:3]],
+                       [torch.tensor(a, dtype=dtype, device=dev) for a in u0[3:]]))
+    plan = BatchPlan(grids, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve)
+    plan.autotune(3)
+    cfg = [plan.kernel_config(ax) for ax in range(3)]
+    plan.run(fields, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(fields, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = plan.last_timing()
+    finite = all(bool(torch.isfinite(t).all()) for E, H in fields for t in E + H)
+    plan.close()
+    cells = int(sum(np.prod(sz) for sz in sizes))
+    ms = (t1 - t0) * 1e3 / steps
+    main_ms = tm["main_ms"] / steps
+    out = dict(workload="64 cavities U[16,96]^3, fundamental ADI, CFL 5", prec=prec, cells=cells, steps=steps,
+               ms_per_step=ms, mcells_per_s=cells / (ms * 1e-3) / 1e6, main_ms_per_step=main_ms,
+               hbm_frac_alg=6 * cells * bytes_per_node(prec) / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               kernel_config=cfg, finite=finite)
+    log(json.dumps(out))
+    return out
+
+
+def run_adjoint(prec="f32", steps=500, ckpt=50):
+    """dJ/d eps_r of the probe energy over a 64 x 64 x 16 design box in a
+    128 x 128 x 64 PEC box, 500 steps at CFL 5, checkpoints every 50 steps."""
+    import torch
+    import workloads as W
+    from paper_2011_14043_amd import Plan, Source
+    p = W.design_problem(seed=5)
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    solve = torch.float64 if prec in ("f64", "f32s64") else torch.float32
+    dev = torch.device("cuda", 0)
+    shape = (p["nz"] + 1, p["ny"] + 1, p["nx"] + 1)
+    E = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
+    H = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
+    plan = Plan(p["nx"], p["ny"], p["nz"], dt, h, h, h, dtype=dtype, solve_dtype=solve,
+                eps_r=torch.from_numpy(p["eps"]))
+    plan.autotune(3)
+    src = Source(*p["src"])
+    plan.grad_eps(E, H, 20, p["probe"], src, p["design_box"], ckpt)      # warm-up, allocations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J0, _ = plan.grad_eps(E, H, steps, p["probe"], src)
+    t1 = time.perf_counter()
+    J, g = plan.grad_eps(E, H, steps, p["probe"], src, p["design_box"], ckpt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plan.close()
+    cells = p["nx"] * p["ny"] * p["nz"]
+    out = dict(workload="adjoint dJ/deps_r, 128x128x64, design box 64x64x16, 500 steps, CFL 5, ckpt 50",
+               prec=prec, forward_ms=(t1 - t0) * 1e3, gradient_ms=(t2 - t1) * 1e3,
+               gradient_over_forward=(t2 - t1) / (t1 - t0),
+               forward_mcells_per_s=cells * steps / (t1 - t0) / 1e6, J=J, finite=bool(torch.isfinite(g).all()))
+    log(json.dumps(out))
+    return out
+
+
+def cpu_baseline(n=256, steps=3):
     """The FP64 oracle (fundamental ADI) on the host, single thread, on a
     bounded sample of the same workload (n^3 cells, `steps` steps)."""
     import numpy as np
@@ -131,6 +250,10 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--variants", default="all", help="'all', 'none' or comma list scheme/form/prec")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-cavity and adjoint lines")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+                    help="run only the batched-cavity or the adjoint measurement and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,11 +272,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nel * 4, "copies": 5}), flush=True)
         return
+    if args.only == "batch":
+        print(json.dumps(run_batch(args.batch_steps, 5)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(run_adjoint()), flush=True)
+        return
     n = args.n
     inputs = make_inputs(n)
     log(f"[bench] {n}^3, {args.steps} steps, warmup {args.warmup}")
-    head = run_variant(n, "adi", "fundamental", "f32", args.steps, args.warmup, inputs)
+    head = run_variant(n, "adi", "fundamental", "f32", args.steps, args.warmup, inputs, tune_reps=10)
     variants = []
+    extras = {}
+    if not args.no_extras:
+        extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
+        extras["adjoint_gradient"] = run_adjoint()
     if args.variants != "none":
         todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32s64"), ("adi", "conventional", "f32s64"),
                 ("adi", "fundamental", "f64"), ("adi", "conventional", "f64"),
@@ -170,7 +303,8 @@ def main():
     yz_ms = head["yz_ms_avg"]
     achieved = yz_bytes / (yz_ms * 1e-3) / 1e9 if yz_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(head["kernel_config"][1], head["kernel_config"][2]),
             "kernel": "pass_yz_kernel (fundamental, FP32)", "bytes_per_launch": yz_bytes,
             "avg_launch_ms": yz_ms, "launches": head["yz_launches"]}
     cpu = None
@@ -188,6 +322,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 

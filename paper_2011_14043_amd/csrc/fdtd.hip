@@ -26,6 +26,7 @@
 #include "../../include/fdtd.h"
 #include "adjoint_kernels.hpp"
 #include "aux_kernels.hpp"
+#include "batch_kernels.hpp"
 #include "pass_kernels.hpp"
 
 namespace fdtd {
@@ -392,6 +393,10 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
         if (c.wpb < 1 || c.wpb > 4) return false;
         return next_pow2((n + c.M - 1) / c.M) <= 64;
     }
+    // FP64 conventional ADI (two extra arrays per pass) exceeds the register
+    // budget of the 1024-thread FP64 variant
+    if (p->d.dtype == FDTD_F64 && p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL && c.NT == 1024)
+        return false;
     bool inst = false;
     if (p->d.dtype == FDTD_F32) {
         for (const auto& v : kYzF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
@@ -458,7 +463,10 @@ static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
         const std::vector<KCfg> cand = cfg_candidates(p, axis);
         KCfg best = p->cfg[axis];
         float tbest = 1e30f;
-        for (const KCfg& c : cand) {
+        // two rounds over the candidates; each keeps its best time (clock
+        // and neighbour noise only ever add time)
+        for (int round = 0; round < 2 * (int)cand.size() && st == FDTD_OK; ++round) {
+            const KCfg& c = cand[round % cand.size()];
             p->cfg[axis] = c;
             T* s0 = set_ptr<T>(p, 0);
             T* s1 = set_ptr<T>(p, conv && adi ? 1 : 0);

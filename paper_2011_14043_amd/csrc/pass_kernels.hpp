@@ -248,15 +248,21 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     float ep[M];
     {
         T te[M], th[M];
-        ld_chunk<T, M>(rE, vo, te);
-        ld_chunk<T, M>(rH, vo, th);
-        if constexpr (MAT) {
-            unsigned id[M];
-            ld_bytes<M>(make_rsrc(a.mat, wbase, a.comp, 1), lel, id);
+        if (!FULL && j0 >= n) {
+            // chunk past the end of its line (power-of-two padding): no loads
 #pragma unroll
-            for (int i = 0; i < M; ++i) ep[i] = mtab[id[i]];
+            for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); ep[i] = 1.0f; }
         } else {
-            ld_chunk<float, M>(rP, vo_e, ep);
+            ld_chunk<T, M>(rE, vo, te);
+            ld_chunk<T, M>(rH, vo, th);
+            if constexpr (MAT) {
+                unsigned id[M];
+                ld_bytes<M>(make_rsrc(a.mat, wbase, a.comp, 1), lel, id);
+#pragma unroll
+                for (int i = 0; i < M; ++i) ep[i] = mtab[id[i]];
+            } else {
+                ld_chunk<float, M>(rP, vo_e, ep);
+            }
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -365,17 +371,6 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     pass_x_body<T, S, M, MODE, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), mtab);
 }
 
-// Batched x lines: block b runs work item items[b] = (entry of tab, block of
-// that entry's pass); one launch covers the passes of many grids.
-template <typename T, typename S, int M, int MODE, bool MAT>
-__global__ void __launch_bounds__(256) pass_x_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
-    __shared__ float mtab[MAT ? 256 : 1];
-    const int2 it = items[blockIdx.x];
-    const PassArgs<T, S> a = tab[it.x];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
-    pass_x_body<T, S, M, MODE, false, MAT>(a, it.y, mtab);
-}
-
 // ---------------------------------------------------------------------------
 // y and z lines: strided axis.  A block holds TX consecutive x positions (the
 // transverse index a) times P chunks; thread t = tx + TX p.  Loads and stores
@@ -421,17 +416,26 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     S ue[M], uh[M], x2[M];
     float ep[M];
     const Rsrc rM = make_rsrc(a.mat, wbase, a.comp, 1);
+    T te[M], th[M];
+    if (!FULL && j0 >= n) {
+        // chunk past the end of its line (power-of-two padding): no loads
+#pragma unroll
+        for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); ep[i] = 1.0f; }
+    } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            te[i] = Buf<T>::ld(rE, vo, i * swb);
+            th[i] = Buf<T>::ld(rH, vo, i * swb);
+            if constexpr (MAT) ep[i] = mtab[__builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0)];
+            else ep[i] = Buf<float>::ld(rP, vo_e, i * swf);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const T e = Buf<T>::ld(rE, vo, i * swb);
-        const T h = Buf<T>::ld(rH, vo, i * swb);
-        float f;
-        if constexpr (MAT) f = mtab[__builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0)];
-        else f = Buf<float>::ld(rP, vo_e, i * swf);
         const bool in = FULL || j0 + i < n;
-        ue[i] = in ? S(e) : S(0);
-        uh[i] = in ? S(h) : S(0);
-        ep[i] = in ? f : 1.0f;
+        ue[i] = in ? S(te[i]) : S(0);
+        uh[i] = in ? S(th[i]) : S(0);
+        ep[i] = in ? ep[i] : 1.0f;
     }
     const bool first = (p == 0);
     const bool beyond = j0 > n;                   // chunk entirely past the far wall
@@ -541,26 +545,6 @@ __global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT>::v)) pass_yz_kernel
     extern __shared__ unsigned char smem_raw[];
     pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
                                                    threadIdx.x, reinterpret_cast<S*>(smem_raw), mtab, true);
-}
-
-// Batched y/z lines: block b runs work item items[b] = (entry e of tab, item
-// index q).  The block has blockDim.x = TX * Pmax threads; entry e has P <=
-// Pmax chunks per line, so the block splits into Pmax/P sub-blocks of TX * P
-// threads, which run the virtual blocks q * (Pmax/P) + sub of that entry.
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool MAT>
-__global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
-    __shared__ float mtab[MAT ? 256 : 1];
-    extern __shared__ unsigned char smem_raw[];
-    const int2 it = items[blockIdx.x];
-    const PassArgs<T, S> a = tab[it.x];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
-    const int sub_n = TX * a.P;
-    const int spb = blockDim.x / sub_n;
-    const int sub = threadIdx.x / sub_n;
-    const int vb = it.y * spb + sub;
-    S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * 9 * a.P * (TX + 1);
-    const bool valid = vb < a.nblk;
-    pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, mtab, valid);
 }
 
 }  // namespace fdtd
