@@ -89,6 +89,8 @@ struct Batch {
     bool mat = false;         // every grid has a material index
     std::vector<BatchPass> passes;
     hipStream_t cap = nullptr;        // private stream for graph capture
+    hipStream_t fork[2] = {nullptr, nullptr};   // capture branches: the three pair passes of a
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // sub-step are independent and run side by side
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;    // one time step of the main iteration
 };
@@ -1054,9 +1056,31 @@ static fdtd_status batch_graph(fdtd_plan_s* p) {
     Batch* b = p->batch;
     if (b->exec) return FDTD_OK;
     const SchemeDef& sd = kSchemes[p->d.scheme];
+    // The three pair passes of a sub-step update disjoint arrays: capture them
+    // as parallel branches (fork on events, join before the next sub-step).
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     fdtd_status st = FDTD_OK;
-    for (int u = 0; u < sd.nsub && st == FDTD_OK; ++u) st = batch_substep<T, S>(p, sd.sub[u].op, sd.sub[u].theta_frac, b->cap);
+    auto branch = [&](int k, hipStream_t str, int op, double frac) -> fdtd_status {
+        const BatchPass* bp = nullptr;
+        fdtd_status s2 = batch_pass<T, S>(p, op, k, frac, &bp);
+        return s2 == FDTD_OK ? batch_launch<T, S>(p, *bp, str) : s2;
+    };
+    for (int u = 0; u < sd.nsub && st == FDTD_OK; ++u) {
+        const int op = sd.sub[u].op;
+        const double frac = sd.sub[u].theta_frac;
+        if (hipEventRecord(b->ev[0], b->cap) != hipSuccess || hipStreamWaitEvent(b->fork[0], b->ev[0], 0) != hipSuccess ||
+            hipStreamWaitEvent(b->fork[1], b->ev[0], 0) != hipSuccess) {
+            st = FDTD_EDEVICE;
+            break;
+        }
+        st = branch(0, b->cap, op, frac);
+        if (st == FDTD_OK) st = branch(1, b->fork[0], op, frac);
+        if (st == FDTD_OK) st = branch(2, b->fork[1], op, frac);
+        if (st == FDTD_OK &&
+            (hipEventRecord(b->ev[1], b->fork[0]) != hipSuccess || hipEventRecord(b->ev[2], b->fork[1]) != hipSuccess ||
+             hipStreamWaitEvent(b->cap, b->ev[1], 0) != hipSuccess || hipStreamWaitEvent(b->cap, b->ev[2], 0) != hipSuccess))
+            st = FDTD_EDEVICE;
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (st != FDTD_OK) {
@@ -1494,8 +1518,17 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     }
     if (st == FDTD_OK && hipStreamCreateWithFlags(&p->batch->cap, hipStreamNonBlocking) != hipSuccess)
         st = FDTD_EDEVICE;
+    for (int f = 0; f < 2 && st == FDTD_OK; ++f)
+        if (hipStreamCreateWithFlags(&p->batch->fork[f], hipStreamNonBlocking) != hipSuccess) st = FDTD_EDEVICE;
+    for (int f = 0; f < 3 && st == FDTD_OK; ++f)
+        if (hipEventCreateWithFlags(&p->batch->ev[f], hipEventDisableTiming) != hipSuccess) st = FDTD_EDEVICE;
     if (st != FDTD_OK) {
         for (fdtd_plan_s* sub : p->batch->subs) (void)fdtd_destroy(sub);
+        if (p->batch->cap) (void)hipStreamDestroy(p->batch->cap);
+        for (hipStream_t f : p->batch->fork)
+            if (f) (void)hipStreamDestroy(f);
+        for (hipEvent_t e : p->batch->ev)
+            if (e) (void)hipEventDestroy(e);
         delete p->batch;
         delete p;
         return st;
@@ -1531,6 +1564,10 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
         batch_clear(p->batch);
         for (fdtd_plan_s* sub : p->batch->subs) (void)fdtd_destroy(sub);
         if (p->batch->cap) (void)hipStreamDestroy(p->batch->cap);
+        for (hipStream_t f : p->batch->fork)
+            if (f) (void)hipStreamDestroy(f);
+        for (hipEvent_t e : p->batch->ev)
+            if (e) (void)hipEventDestroy(e);
         delete p->batch;
         p->batch = nullptr;
     }
