@@ -34,10 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources whose hash is recorded and the profiled y/z
 # configuration; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "b41612cc146b25ca",
-    "config": [16, 32, 1024],                                # chunk, tile_x, block_threads (y and z)
-    "fetch_kib": {"y": 596562.6, "z": 785810.1},
-    "write_kib": {"y": 1047552.0, "z": 1092026.6},
+    "kernel_hash": "d402bdb016f40571",
+    "config": [16, 32, 1024, 1],                             # chunk, tile_x, block_threads, remap (y and z)
+    "fetch_kib": {"y": 596547.8, "z": 596904.4},
+    "write_kib": {"y": 1047552.0, "z": 1047552.0},
     "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
     "profile": "profiles/pass_kernels_adi_fundamental_f32_512cube.md",
@@ -59,7 +59,7 @@ def profiled_traffic(cfg_y, cfg_z):
         return None
     want = pr["config"]
     for c in (cfg_y, cfg_z):
-        if [c["chunk"], c["tile_x"], c["block_threads"]] != want:
+        if [c["chunk"], c["tile_x"], c["block_threads"], c["remap"]] != want:
             return None
     fetch = sum(pr["fetch_kib"].values()) / len(pr["fetch_kib"]) * 1024 * pr["fetch_factor"]
     write = sum(pr["write_kib"].values()) / len(pr["write_kib"]) * 1024 * pr["write_factor"]

@@ -131,13 +131,10 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* pass_ms_avg
  *   block_threads  x lines: threads per block (64, 128, 256);
  *                  y/z lines: block-size bound of the variant (256, 512, 1024)
  *   remap          1 = XCD-aware block order, 0 = plain order
- *   pipeline       y/z lines, FP32 plans other than conventional ADI, single-grid
- *                  plans: 1 = persistent blocks that load the next tile while
- *                  solving the current one; 0 = one block per tile
  * Every configuration computes the same result up to rounding order.
  * fdtd_set_kernel_config returns FDTD_EINVAL for a variant that is not built
  * or does not fit the axis length. */
-typedef struct { int chunk, tile_x, block_threads, remap, pipeline; } fdtd_kernel_config;
+typedef struct { int chunk, tile_x, block_threads, remap; } fdtd_kernel_config;
 fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* c);
 fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_config* c);
 

@@ -137,12 +137,10 @@ class Plan:
         """Kernel configuration of the passes along axis 0 (x), 1 (y), 2 (z)."""
         c = _lib.FdtdKernelConfig()
         _lib.check(_lib.lib().fdtd_get_kernel_config(self._h, axis, ctypes.byref(c)), "fdtd_get_kernel_config")
-        return {"chunk": c.chunk, "tile_x": c.tile_x, "block_threads": c.block_threads, "remap": c.remap,
-                "pipeline": c.pipeline}
+        return {"chunk": c.chunk, "tile_x": c.tile_x, "block_threads": c.block_threads, "remap": c.remap}
 
-    def set_kernel_config(self, axis: int, chunk: int, tile_x: int = 0, block_threads: int = 256, remap: int = 1,
-                          pipeline: int = 0):
-        c = _lib.FdtdKernelConfig(chunk, tile_x, block_threads, remap, pipeline)
+    def set_kernel_config(self, axis: int, chunk: int, tile_x: int = 0, block_threads: int = 256, remap: int = 1):
+        c = _lib.FdtdKernelConfig(chunk, tile_x, block_threads, remap)
         _lib.check(_lib.lib().fdtd_set_kernel_config(self._h, axis, ctypes.byref(c)), "fdtd_set_kernel_config")
 
     def autotune(self, reps: int = 3):

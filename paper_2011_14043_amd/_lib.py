@@ -39,7 +39,7 @@ class FdtdSource(ctypes.Structure):
 
 class FdtdKernelConfig(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("tile_x", ctypes.c_int), ("block_threads", ctypes.c_int),
-                ("remap", ctypes.c_int), ("pipeline", ctypes.c_int)]
+                ("remap", ctypes.c_int)]
 
 
 class FdtdError(RuntimeError):

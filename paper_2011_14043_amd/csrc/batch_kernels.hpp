@@ -13,11 +13,11 @@ namespace fdtd {
 // block of that entry's pass); one launch covers the passes of many grids.
 template <typename T, typename S, int M, int MODE, bool MAT>
 __global__ void __launch_bounds__(256) pass_x_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
-    __shared__ float mtab[MAT ? 256 : 1];
+    __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];   // neighbouring items on one XCD
     const PassArgs<T, S> a = tab[it.x];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
-    pass_x_body<T, S, M, MODE, false, MAT>(a, it.y, mtab);
+    if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
+    pass_x_body<T, S, M, MODE, false, MAT>(a, it.y, ctab);
 }
 
 // Batched y/z lines: block b runs work item items[remap(b)] = (entry e of
@@ -26,18 +26,18 @@ __global__ void __launch_bounds__(256) pass_x_batch_kernel(const PassArgs<T, S>*
 // threads, which run the virtual blocks q * (Pmax/P) + sub of that entry.
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool MAT>
 __global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
-    __shared__ float mtab[MAT ? 256 : 1];
+    __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     extern __shared__ unsigned char smem_raw[];
     const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];   // neighbouring tiles on one XCD
     const PassArgs<T, S> a = tab[it.x];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     const int sub_n = TX * a.P;
     const int spb = blockDim.x / sub_n;
     const int sub = threadIdx.x / sub_n;
     const int vb = it.y * spb + sub;
     S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * 9 * a.P * (TX + 1);
     const bool valid = vb < a.nblk;
-    pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, mtab, valid);
+    pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, ctab, valid);
 }
 
 }  // namespace fdtd

@@ -55,15 +55,11 @@ static const SchemeDef kSchemes[4] = {
 //   x lines: M (slots per lane), wpb (waves per block), remap
 //   y/z lines: M (slots per thread), TX (x positions per block),
 //              NT (block-size bound of the instantiation), remap
-//   pipe: y/z lines through the persistent software-pipelined kernel
-struct KCfg { int M, TX, NT, wpb, remap; int pipe = 0; };
+struct KCfg { int M, TX, NT, wpb, remap; };
 
 // Instantiated y/z-line variants {M, TX, NT} by solve precision.
 static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}};
 static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
-// Pipelined (persistent) y/z variants, FP32 fields and solves.
-// (16-slot chunks exceed 128 VGPRs with the next tile in flight.)
-static const int kYzPipeF32[][3] = {{8, 16, 1024}};
 
 struct Timing {
     bool per_launch = false;
@@ -118,9 +114,6 @@ struct fdtd_plan_s {
     long long step = 0;
     fdtd::Timing tm;
     fdtd::KCfg cfg[3];        // per line axis x, y, z
-    // persistent grid of the pipelined y/z kernel per axis, for the kernel and LDS size it was computed for
-    struct { const void* k; size_t lds; int G; } pipe_grid[3] = {{nullptr, 0, 0}, {nullptr, 0, 0}, {nullptr, 0, 0}};
-    int ncu = 0;              // compute units of the plan's device
     int tuned = 0;
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
@@ -192,41 +185,6 @@ static void launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t
     if (mode == FUND) launch_yz<T, S, M, TX, NT, FUND>(full, mat, g, b, lds, st, a);
     else if (mode == CONV_LOD) launch_yz<T, S, M, TX, NT, CONV_LOD>(full, mat, g, b, lds, st, a);
     else launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
-}
-
-// Persistent pipelined y/z pass: the grid is the number of blocks that fit
-// on the device at once (occupancy x compute units), computed once per axis.
-template <typename T, typename S>
-static fdtd_status launch_pipe_kernel(fdtd_plan_s* p, int axis, const void* kern, int nblk, dim3 block, size_t lds,
-                                      hipStream_t st, const PassArgs<T, S>& a);
-
-template <typename T, typename S, int M, int TX, int NT, int MODE>
-static fdtd_status launch_yz_pipe(fdtd_plan_s* p, int axis, bool full, bool mat, int nblk, dim3 b, size_t lds,
-                                  hipStream_t st, const PassArgs<T, S>& a) {
-    const void* k;
-    if (full) k = mat ? reinterpret_cast<const void*>(&pass_yz_pipe_kernel<T, S, M, MODE, TX, NT, true, true>)
-                      : reinterpret_cast<const void*>(&pass_yz_pipe_kernel<T, S, M, MODE, TX, NT, true, false>);
-    else k = mat ? reinterpret_cast<const void*>(&pass_yz_pipe_kernel<T, S, M, MODE, TX, NT, false, true>)
-                 : reinterpret_cast<const void*>(&pass_yz_pipe_kernel<T, S, M, MODE, TX, NT, false, false>);
-    return launch_pipe_kernel<T, S>(p, axis, k, nblk, b, lds, st, a);
-}
-
-template <typename T, typename S>
-static fdtd_status launch_pipe_kernel(fdtd_plan_s* p, int axis, const void* kern, int nblk, dim3 block, size_t lds,
-                                      hipStream_t st, const PassArgs<T, S>& a) {
-    auto& pg = p->pipe_grid[axis];
-    if (pg.k != kern || pg.lds != lds || pg.G == 0) {
-        int nb = 0;
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, (int)(block.x * block.y * block.z), lds));
-        pg.k = kern;
-        pg.lds = lds;
-        pg.G = std::max(1, nb) * std::max(1, p->ncu);
-    }
-    const dim3 grid((unsigned)std::min(nblk, pg.G));
-    PassArgs<T, S> arg = a;
-    void* args[] = {&arg};
-    HIPCHK(hipLaunchKernel(kern, grid, block, args, lds, st));
-    return FDTD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -396,23 +354,6 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     if (sh.w == 0) {
         if (cf.M == 8) launch_x_mode<T, S, 8>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
         else launch_x_mode<T, S, 16>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
-    } else if (cf.pipe) {
-        if constexpr (sizeof(S) == 4 && sizeof(T) == 4) {
-            const int M = cf.M, TX = cf.TX, NT = cf.NT;
-            fdtd_status st2 = FDTD_EUNSUPPORTED;
-#define CASE_PIPE(MM, TT, NN)                                                                                           \
-    if (M == MM && TX == TT && NT == NN) {                                                                              \
-        if (mode == FUND)                                                                                               \
-            st2 = launch_yz_pipe<T, S, MM, TT, NN, FUND>(p, sh.w, sh.full, sh.mat, a.nblk, sh.block, sh.lds, p->stream, a); \
-        else if (mode == CONV_LOD)                                                                                      \
-            st2 = launch_yz_pipe<T, S, MM, TT, NN, CONV_LOD>(p, sh.w, sh.full, sh.mat, a.nblk, sh.block, sh.lds, p->stream, a); \
-    }
-            CASE_PIPE(8, 16, 1024)
-#undef CASE_PIPE
-            if (st2 != FDTD_OK) return st2;
-        } else {
-            return FDTD_EUNSUPPORTED;
-        }
     } else {
         const int M = cf.M, TX = cf.TX, NT = cf.NT;
 #define CASE_YZ(MM, TT, NN)                                                                                    \
@@ -450,7 +391,6 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     const int n = axis_cells(p->dims, axis);
     if (c.remap != 0 && c.remap != 1) return false;
     if (axis == 0) {
-        if (c.pipe) return false;
         if (c.M != 8 && c.M != 16) return false;
         if (c.wpb < 1 || c.wpb > 4) return false;
         return next_pow2((n + c.M - 1) / c.M) <= 64;
@@ -460,11 +400,7 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     if (p->d.dtype == FDTD_F64 && p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL && c.NT == 1024)
         return false;
     bool inst = false;
-    if (c.pipe) {
-        if (c.pipe != 1 || p->d.dtype != FDTD_F32) return false;
-        if (p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL) return false;
-        for (const auto& v : kYzPipeF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
-    } else if (p->d.dtype == FDTD_F32) {
+    if (p->d.dtype == FDTD_F32) {
         for (const auto& v : kYzF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
     } else {
         for (const auto& v : kYzF64) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
@@ -474,9 +410,12 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     return P <= 64 && c.TX * P <= c.NT;
 }
 
+// Candidates: y/z lines only in the XCD-aware order (the plain order reads
+// the z pass's material lines once per XCD; the time difference is noise,
+// the traffic is not); x lines in both orders.
 static std::vector<KCfg> cfg_candidates(const fdtd_plan_s* p, int axis) {
     std::vector<KCfg> out;
-    for (int remap = 1; remap >= 0; --remap) {
+    for (int remap = 1; remap >= (axis == 0 ? 0 : 1); --remap) {
         if (axis == 0) {
             for (int M : {8, 16})
                 for (int wpb : {4, 2, 1}) {
@@ -486,10 +425,6 @@ static std::vector<KCfg> cfg_candidates(const fdtd_plan_s* p, int axis) {
         } else if (p->d.dtype == FDTD_F32) {
             for (const auto& v : kYzF32) {
                 KCfg c{v[0], v[1], v[2], 0, remap};
-                if (cfg_valid(p, axis, c)) out.push_back(c);
-            }
-            for (const auto& v : kYzPipeF32) {
-                KCfg c{v[0], v[1], v[2], 0, remap, 1};
                 if (cfg_valid(p, axis, c)) out.push_back(c);
             }
         } else {
@@ -564,7 +499,7 @@ static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
 }
 
 // Text cache of tuned configurations: one line per key
-//   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>", "cfg": [[M,TX,NT,wpb,remap,pipe],[...],[...]]}
+//   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>", "cfg": [[M,TX,NT,wpb,remap],[...],[...]]}
 static std::string tune_key(const fdtd_plan_s* p) {
     char b[160];
     std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme, p->d.form);
@@ -580,11 +515,9 @@ static bool tune_cache_lookup(fdtd_plan_s* p, const char* path) {
     while (std::fgets(line, sizeof(line), f)) {
         char k[160];
         KCfg c[3];
-        if (std::sscanf(line,
-                        " {\"key\": \"%159[^\"]\", \"cfg\": [[%d,%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d,%d]]}",
-                        k, &c[0].M, &c[0].TX, &c[0].NT, &c[0].wpb, &c[0].remap, &c[0].pipe, &c[1].M, &c[1].TX,
-                        &c[1].NT, &c[1].wpb, &c[1].remap, &c[1].pipe, &c[2].M, &c[2].TX, &c[2].NT, &c[2].wpb,
-                        &c[2].remap, &c[2].pipe) != 19)
+        if (std::sscanf(line, " {\"key\": \"%159[^\"]\", \"cfg\": [[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d]]}", k,
+                        &c[0].M, &c[0].TX, &c[0].NT, &c[0].wpb, &c[0].remap, &c[1].M, &c[1].TX, &c[1].NT, &c[1].wpb,
+                        &c[1].remap, &c[2].M, &c[2].TX, &c[2].NT, &c[2].wpb, &c[2].remap) != 16)
             continue;
         if (key != k) continue;
         if (cfg_valid(p, 0, c[0]) && cfg_valid(p, 1, c[1]) && cfg_valid(p, 2, c[2])) {
@@ -600,9 +533,9 @@ static void tune_cache_store(const fdtd_plan_s* p, const char* path) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;
     const KCfg* c = p->cfg;
-    std::fprintf(f, "{\"key\": \"%s\", \"cfg\": [[%d,%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d,%d]]}\n",
-                 tune_key(p).c_str(), c[0].M, c[0].TX, c[0].NT, c[0].wpb, c[0].remap, c[0].pipe, c[1].M, c[1].TX,
-                 c[1].NT, c[1].wpb, c[1].remap, c[1].pipe, c[2].M, c[2].TX, c[2].NT, c[2].wpb, c[2].remap, c[2].pipe);
+    std::fprintf(f, "{\"key\": \"%s\", \"cfg\": [[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d],[%d,%d,%d,%d,%d]]}\n",
+                 tune_key(p).c_str(), c[0].M, c[0].TX, c[0].NT, c[0].wpb, c[0].remap, c[1].M, c[1].TX, c[1].NT,
+                 c[1].wpb, c[1].remap, c[2].M, c[2].TX, c[2].NT, c[2].wpb, c[2].remap);
     std::fclose(f);
 }
 
@@ -913,7 +846,6 @@ static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
 }
 
 static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
-    if (c.pipe) return false;   // the batched kernels take work items, not persistent tiles
     int Pmax = 1;
     for (const fdtd_plan_s* g : p->batch->subs) {
         if (!cfg_valid(g, axis, c)) return false;
@@ -1271,7 +1203,6 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     p->d.eps_r = nullptr;
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
-    if (hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) p->ncu = 1;
     p->esz = d->dtype == FDTD_F64 ? 8 : 4;
     Dims& dm = p->dims;
     dm.nx = d->nx; dm.ny = d->ny; dm.nz = d->nz;
@@ -1431,14 +1362,13 @@ fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* 
     c->tile_x = axis == 0 ? 0 : k.TX;
     c->block_threads = axis == 0 ? 64 * k.wpb : k.NT;
     c->remap = k.remap;
-    c->pipeline = k.pipe;
     return FDTD_OK;
 }
 
 fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_config* c) {
     if (!plan_ok(p) || axis < 0 || axis > 2 || !c) return FDTD_EINVAL;
     KCfg k{c->chunk, axis == 0 ? 0 : c->tile_x, axis == 0 ? 0 : c->block_threads,
-           axis == 0 ? c->block_threads / 64 : 0, c->remap, c->pipeline};
+           axis == 0 ? c->block_threads / 64 : 0, c->remap};
     if (axis == 0 && c->block_threads % 64 != 0) return FDTD_EINVAL;
     if (p->batch) {
         if (!batch_cfg_valid(p, axis, k)) return FDTD_EINVAL;

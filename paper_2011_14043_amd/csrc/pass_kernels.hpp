@@ -33,6 +33,8 @@
 // instructions, and loads past the end of an array return 0.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
+
 #include "line_solver.hpp"
 
 namespace fdtd {
@@ -150,11 +152,11 @@ __device__ __forceinline__ void st_chunk(Rsrc r, int vo, const T (&v)[M]) {
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Material table: eps_r of each material index, copied to LDS once per block.
-__device__ __forceinline__ void load_mat_table(float* tab, const float* src, int nmat) {
-    for (int k = threadIdx.x; k < 256; k += blockDim.x) tab[k] = k < nmat ? src[k] : 1.0f;
-    __syncthreads();
-}
+// Per-slot coefficients of the scaled system: c multiplies U_e on the right
+// side (2 sigma for FUND, sigma for the original forms), d = 2 + sigma is the
+// diagonal.
+template <typename S>
+struct SlotCoef { S c, d; };
 // M consecutive material bytes at byte offset vo (8-byte aligned).
 template <int M>
 __device__ __forceinline__ void ld_bytes(Rsrc r, int vo, unsigned (&id)[M]) {
@@ -181,32 +183,57 @@ __device__ __forceinline__ S make_sigma(double Ks, float eps) {
     if constexpr (sizeof(S) == 4) return (2.0f + float(Ks) * eps) - 2.0f;
     else return Ks * double(eps);
 }
+template <typename S, int MODE>
+__device__ __forceinline__ SlotCoef<S> coef_of(double Ks, float eps) {
+    const S sig = make_sigma<S>(Ks, eps);
+    return SlotCoef<S>{(MODE == FUND) ? sig + sig : sig, S(2) + sig};
+}
+// Material-index variants keep a per-material table in LDS, filled once per
+// block.  FP32 solves store the coefficients themselves (one LDS read per
+// slot, no per-slot arithmetic); FP64 solves store eps_r and form the
+// coefficients per slot, which costs less than 16-byte table reads.
+template <typename S>
+using CoefTab = typename std::conditional<sizeof(S) == 4, SlotCoef<float>, float>::type;
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ void load_coef_table(CoefTab<S>* tab, const PassArgs<T, S>& a) {
+    for (int k = threadIdx.x; k < 256; k += blockDim.x) {
+        const float e = k < a.nmat ? a.mat_eps[k] : 1.0f;
+        if constexpr (sizeof(S) == 4) tab[k] = coef_of<S, MODE>(a.Ks, e);
+        else tab[k] = e;
+    }
+    __syncthreads();
+}
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ SlotCoef<S> coef_from_tab(const PassArgs<T, S>& a, const CoefTab<S>* tab, unsigned id) {
+    if constexpr (sizeof(S) == 4) return tab[id];
+    else return coef_of<S, MODE>(a.Ks, tab[id]);
+}
 
 // rhs and diagonal of one slot; x2 = CONV_ADI cross term (scaled)
 template <typename T, typename S, int MODE>
-__device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, float eps, S ue, S uh, S uh_m, S ue_m, S ue_p,
+__device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, SlotCoef<S> sc, S ue, S uh, S uh_m, S ue_m, S ue_p,
                                          S x2, S& dg, S& r) {
-    const S sig = make_sigma<S>(a.Ks, eps);
-    dg = S(2) + sig;
+    dg = sc.d;
     const S dh = uh - uh_m;
     S hterm = dh * a.kap_hi;
     if constexpr (sizeof(S) == 4) hterm = __builtin_fmaf(dh, a.kap_lo, hterm);
     if constexpr (MODE == FUND) {
-        r = (sig + sig) * ue + hterm;
+        r = sc.c * ue + hterm;
     } else if constexpr (MODE == CONV_LOD) {
-        r = sig * ue + hterm + ((ue_p + ue_m) - S(2) * ue);
+        r = sc.c * ue + hterm + ((ue_p + ue_m) - S(2) * ue);
     } else {
-        r = sig * ue + hterm + x2;
+        r = sc.c * ue + hterm + x2;
     }
 }
 
 // Source term at slot si of this chunk (rhs: 2 sigma pre or sigma pre).
+// sigma is recovered from the diagonal: dg - 2 is exact.
 template <typename T, typename S, int MODE, int M>
-__device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, const float (&ep)[M], S (&r)[M]) {
+__device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, const S (&dg)[M], S (&r)[M]) {
     const S pre = a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const S sig = make_sigma<S>(a.Ks, ep[i]);
+        const S sig = dg[i] - S(2);
         const S coef = (MODE == FUND) ? sig + sig : sig;
         r[i] += (i == si) ? coef * pre : S(0);
     }
@@ -219,9 +246,9 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 // FULL: P*M == n_w (no slot beyond the line).
 // ---------------------------------------------------------------------------
 // Body of one block of x-line work: block `blk` of the pass described by `a`
-// (lines blk * waves * 64/P ...); mtab = the material table in LDS (MAT).
+// (lines blk * waves * 64/P ...); ctab = the per-material coefficients in LDS (MAT).
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
-__device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const float* mtab) {
+__device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const CoefTab<S>* ctab) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
     const int P = a.P;
@@ -245,13 +272,13 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const Rsrc rP = make_rsrc(a.eps, wbase, a.comp, 4);
 
     S ue[M], uh[M];
-    float ep[M];
+    SlotCoef<S> sc[M];
     {
         T te[M], th[M];
         if (!FULL && j0 >= n) {
             // chunk past the end of its line (power-of-two padding): no loads
 #pragma unroll
-            for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); ep[i] = 1.0f; }
+            for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); sc[i] = SlotCoef<S>{S(0), S(2)}; }
         } else {
             ld_chunk<T, M>(rE, vo, te);
             ld_chunk<T, M>(rH, vo, th);
@@ -259,9 +286,12 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
                 unsigned id[M];
                 ld_bytes<M>(make_rsrc(a.mat, wbase, a.comp, 1), lel, id);
 #pragma unroll
-                for (int i = 0; i < M; ++i) ep[i] = mtab[id[i]];
+                for (int i = 0; i < M; ++i) sc[i] = coef_from_tab<T, S, MODE>(a, ctab, id[i]);
             } else {
+                float ep[M];
                 ld_chunk<float, M>(rP, vo_e, ep);
+#pragma unroll
+                for (int i = 0; i < M; ++i) sc[i] = coef_of<S, MODE>(a.Ks, ep[i]);
             }
         }
 #pragma unroll
@@ -269,7 +299,6 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
             const bool in = FULL || j0 + i < n;
             ue[i] = in ? S(te[i]) : S(0);
             uh[i] = in ? S(th[i]) : S(0);
-            ep[i] = in ? ep[i] : 1.0f;
         }
     }
     const bool first = j0 == 0;
@@ -311,7 +340,7 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        slot_rhs<T, S, MODE>(a, ep[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        slot_rhs<T, S, MODE>(a, sc[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
         if (!FULL) {
             const bool out = j0 + i >= n;
             dg[i] = out ? Big<S>::v : dg[i];
@@ -324,7 +353,7 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, ep, r);
+    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
     Chunk<S, M> c;
     chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
 
@@ -366,9 +395,9 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
 
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
-    __shared__ float mtab[MAT ? 256 : 1];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
-    pass_x_body<T, S, M, MODE, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), mtab);
+    __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
+    if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
+    pass_x_body<T, S, M, MODE, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), ctab);
 }
 
 // ---------------------------------------------------------------------------
@@ -383,7 +412,7 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // stores nothing but takes part in the barriers), LDS area sm of
 // 9 P (TX+1) elements.  TX * P must be a multiple of 64 (whole waves).
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
-__device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const float* mtab,
+__device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const CoefTab<S>* ctab,
                                              bool valid) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
@@ -414,20 +443,21 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     const Rsrc rP = make_rsrc(a.eps, wbase, a.comp, 4);
 
     S ue[M], uh[M], x2[M];
-    float ep[M];
+    unsigned id[M];      // MAT: material index per slot
+    float epf[M];        // else: eps_r per slot
     const Rsrc rM = make_rsrc(a.mat, wbase, a.comp, 1);
     T te[M], th[M];
     if (!FULL && j0 >= n) {
         // chunk past the end of its line (power-of-two padding): no loads
 #pragma unroll
-        for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); ep[i] = 1.0f; }
+        for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); id[i] = 0u; epf[i] = 1.0f; }
     } else {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             te[i] = Buf<T>::ld(rE, vo, i * swb);
             th[i] = Buf<T>::ld(rH, vo, i * swb);
-            if constexpr (MAT) ep[i] = mtab[__builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0)];
-            else ep[i] = Buf<float>::ld(rP, vo_e, i * swf);
+            if constexpr (MAT) id[i] = __builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0);
+            else epf[i] = Buf<float>::ld(rP, vo_e, i * swf);
         }
     }
 #pragma unroll
@@ -435,7 +465,6 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
         const bool in = FULL || j0 + i < n;
         ue[i] = in ? S(te[i]) : S(0);
         uh[i] = in ? S(th[i]) : S(0);
-        ep[i] = in ? ep[i] : 1.0f;
     }
     const bool first = (p == 0);
     const bool beyond = j0 > n;                   // chunk entirely past the far wall
@@ -473,7 +502,8 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        slot_rhs<T, S, MODE>(a, ep[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        const SlotCoef<S> sci = MAT ? coef_from_tab<T, S, MODE>(a, ctab, id[i]) : coef_of<S, MODE>(a.Ks, epf[i]);
+        slot_rhs<T, S, MODE>(a, sci, ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
         if (!FULL) {
             const bool out = j0 + i >= n;
             dg[i] = out ? Big<S>::v : dg[i];
@@ -485,7 +515,7 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, ep, r);
+    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
     Chunk<S, M> c;
     chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
 
@@ -529,168 +559,6 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     }
 }
 
-// Persistent, software-pipelined y/z pass (modes FUND and CONV_LOD).  A
-// block runs tiles w = blockIdx.x, blockIdx.x + gridDim.x, ... of the pass.
-// The loads of tile w+gridDim.x are issued right after tile w's chunk
-// elimination, into the registers its inputs no longer need, so they are in
-// flight during tile w's separator solve, finish and stores.  With one
-// 1024-thread block per CU this overlaps the CU's loads with its arithmetic,
-// which separate blocks cannot.  LDS per block: 9 P (TX+1) elements; the
-// values of the next chunk that the finish step needs are read before the
-// second barrier, so the next tile may rewrite the separator rows after it.
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
-__global__ void __launch_bounds__(NT) pass_yz_pipe_kernel(PassArgs<T, S> a) {
-    static_assert(MODE != CONV_ADI, "the cross-term arrays do not fit the pipelined register budget");
-    constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
-    constexpr int ES = (int)sizeof(T);
-    constexpr int CPW = 64 / TX;                  // chunks per wave
-    constexpr int LD = TX + 1;
-    __shared__ float mtab[MAT ? 256 : 1];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
-    extern __shared__ unsigned char smem_raw[];
-    S* sm = reinterpret_cast<S*>(smem_raw);
-    const int P = a.P;
-    const int t = threadIdx.x;
-    const int tx = t % TX, p = t / TX;
-    S* ep_ = sm;                                 // [8][P][LD]
-    S* sb_ = sm + 8 * P * LD;                    // [P][LD]
-    auto EP = [&](int k, int pp, int xx) -> S& { return ep_[(k * P + pp) * LD + xx]; };
-    auto SB = [&](int pp, int xx) -> S& { return sb_[pp * LD + xx]; };
-    const int wave = wave_uniform(t >> 6);
-    const int pw0 = wave * CPW;
-    const int n = a.n_w;
-    const int j0 = p * M;
-    const long long sw = a.sw;
-    const int swb = (int)(sw * ES), swf = (int)(sw * 4);
-    const int lel = tx + (p - pw0) * M * (int)sw;
-    const int vo = lel * ES, vo_e = lel * 4;
-    const bool first = (p == 0);
-    const bool beyond = j0 > n;
-    const bool skip = !FULL && j0 >= n;          // chunk past the end of its line: no loads
-    const int pl = t % P, xl = t / P;            // separator solve: line xl, chunk pl
-    const bool hn = p + 1 < P;
-    const int pn = hn ? p + 1 : p;
-    const int G = (int)gridDim.x;
-
-    auto tile_of = [&](int w) { return a.remap ? xcd_remap(w, a.nblk) : w; };
-    auto wbase_of = [&](int blk) {
-        return (long long)((blk % a.ntx) * TX) * a.sa + (long long)(a.b_lo + blk / a.ntx) * a.sb +
-               (long long)pw0 * M * sw;
-    };
-    // raw inputs of the tile in flight
-    T te[M], th[M], hp, epv, env;
-    float fe[M];
-    unsigned id[M];
-    auto issue = [&](int blk) {
-        const long long wb = wbase_of(blk);
-        const Rsrc rE = make_rsrc(a.Ein, wb, a.comp, ES), rH = make_rsrc(a.Hin, wb, a.comp, ES);
-        if (skip) {
-#pragma unroll
-            for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); fe[i] = 1.0f; id[i] = 0u; }
-        } else {
-            const Rsrc rM = make_rsrc(a.mat, wb, a.comp, 1), rP = make_rsrc(a.eps, wb, a.comp, 4);
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                te[i] = Buf<T>::ld(rE, vo, i * swb);
-                th[i] = Buf<T>::ld(rH, vo, i * swb);
-                if constexpr (MAT) id[i] = __builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0);
-                else fe[i] = Buf<float>::ld(rP, vo_e, i * swf);
-            }
-        }
-        const Rsrc rHm = make_rsrc(a.Hin, wb - sw, a.comp, ES);
-        hp = (first || beyond) ? T(0) : Buf<T>::ld(rHm, vo, 0);
-        if constexpr (MODE == CONV_LOD) {
-            const Rsrc rEm = make_rsrc(a.Ein, wb - sw, a.comp, ES);
-            epv = (first || beyond) ? T(0) : Buf<T>::ld(rEm, vo, 0);
-            env = (j0 + M <= n) ? Buf<T>::ld(rE, vo, M * swb) : T(0);
-        }
-    };
-
-    int w = blockIdx.x;
-    if (w < a.nblk) issue(tile_of(w));
-    for (; w < a.nblk; w += G) {               // uniform over the block
-        const int blk = tile_of(w);
-        const int tile0 = (blk % a.ntx) * TX;
-        const int ib = a.b_lo + blk / a.ntx;
-        const int ia = tile0 + tx;
-        const bool live = ia >= a.a_lo && ia < a.a_lo + a.na;
-        const long long wbase = wbase_of(blk);
-        S ue[M], uh[M];
-        float ep[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            const bool in = FULL || j0 + i < n;
-            float f;
-            if constexpr (MAT) f = mtab[id[i]];
-            else f = fe[i];
-            ue[i] = in ? S(te[i]) : S(0);
-            uh[i] = in ? S(th[i]) : S(0);
-            ep[i] = in ? f : 1.0f;
-        }
-        const S uh_prev = S(hp);
-        const S ue_prev = (MODE == CONV_LOD) ? S(epv) : S(0);
-        const S ue_next = (MODE == CONV_LOD) ? S(env) : S(0);
-        S dg[M], r[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            const S um = (i == 0) ? uh_prev : uh[i - 1];
-            const S em = (i == 0) ? ue_prev : ue[i - 1];
-            const S ex = (i == M - 1) ? ue_next : ue[i + 1];
-            slot_rhs<T, S, MODE>(a, ep[i], ue[i], uh[i], um, em, ex, S(0), dg[i], r[i]);
-            if (!FULL) {
-                const bool out = j0 + i >= n;
-                dg[i] = out ? Big<S>::v : dg[i];
-                r[i] = out ? S(0) : r[i];
-            }
-        }
-        dg[0] = first ? Big<S>::v : dg[0];
-        r[0] = first ? S(0) : r[0];
-        const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
-        const bool src_here = si >= 0 && si < M;
-        const bool src_wave = __ballot(src_here) != 0;
-        if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, ep, r);
-        Chunk<S, M> c;
-        chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
-
-        EP(0, p, tx) = c.a0; EP(1, p, tx) = c.g0; EP(2, p, tx) = c.y0;
-        EP(3, p, tx) = c.aL; EP(4, p, tx) = c.gL; EP(5, p, tx) = c.yL;
-        EP(6, p, tx) = c.dgS; EP(7, p, tx) = c.rS;
-        __syncthreads();
-        if (w + G < a.nblk) issue(tile_of(w + G));     // next tile's loads fly from here on
-        {
-            const bool hq = pl + 1 < P;
-            const int pq = hq ? pl + 1 : pl;
-            Row<S> rw = separator_row<S>(EP(3, pl, xl), EP(4, pl, xl), EP(5, pl, xl), EP(6, pl, xl), EP(7, pl, xl),
-                                         hq ? EP(0, pq, xl) : S(0), hq ? EP(1, pq, xl) : S(0),
-                                         hq ? EP(2, pq, xl) : S(0));
-            SB(pl, xl) = pcr_wave<S>(rw, pl, P);
-        }
-        const S a0n = EP(0, pn, tx), g0n = EP(1, pn, tx), y0n = EP(2, pn, tx);
-        __syncthreads();
-        const S Sl = SB(p, tx);
-        const S Sp = first ? S(0) : SB(p - 1, tx);
-        const S Sn = hn ? SB(pn, tx) : S(0);
-        const S xn = hn ? y0n + a0n * Sl + g0n * Sn : S(0);
-        S eo[M], ho[M];
-        chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
-        eo[0] = first ? S(0) : eo[0];
-        if (MODE == FUND && __builtin_expect(src_wave, 0)) {
-#pragma unroll
-            for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
-        }
-        if (live) {
-            const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                if (FULL || j0 + i < n) {
-                    Buf<T>::st(T(eo[i]), wE, vo, i * swb);
-                    Buf<T>::st(T(ho[i]), wH, vo, i * swb);
-                }
-            }
-        }
-    }
-}
-
 // Waves per SIMD the register allocation must allow: FP32 solves with 8-slot
 // chunks (modes without the cross-term arrays) fit in 64 VGPRs, so two
 // 1024-thread blocks share a CU and one block's loads overlap the other's LDS
@@ -702,11 +570,11 @@ struct YzOcc {
 
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
 __global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT>::v)) pass_yz_kernel(PassArgs<T, S> a) {
-    __shared__ float mtab[MAT ? 256 : 1];
-    if constexpr (MAT) load_mat_table(mtab, a.mat_eps, a.nmat);
+    __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
+    if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     extern __shared__ unsigned char smem_raw[];
     pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
-                                                   threadIdx.x, reinterpret_cast<S*>(smem_raw), mtab, true);
+                                                   threadIdx.x, reinterpret_cast<S*>(smem_raw), ctab, true);
 }
 
 }  // namespace fdtd
