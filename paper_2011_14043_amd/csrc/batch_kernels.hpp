@@ -21,9 +21,10 @@ __global__ void __launch_bounds__(256) pass_x_batch_kernel(const PassArgs<T, S>*
 }
 
 // Batched y/z lines: block b runs work item items[remap(b)] = (entry e of
-// tab, item index q).  The block has blockDim.x = TX * Pmax threads; entry e has P <=
-// Pmax chunks per line, so the block splits into Pmax/P sub-blocks of TX * P
-// threads, which run the virtual blocks q * (Pmax/P) + sub of that entry.
+// tab, item index q).  The block has blockDim.x = TX * Pmax threads; entry e
+// has P <= Pmax chunks per line, so the block splits into floor(Pmax/P)
+// sub-blocks of TX * P threads, which run the virtual blocks
+// q * floor(Pmax/P) + sub of that entry; leftover threads idle.
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool MAT>
 __global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>* tab, const int2* items) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
@@ -32,11 +33,14 @@ __global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>*
     const PassArgs<T, S> a = tab[it.x];
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     const int sub_n = TX * a.P;
-    const int spb = blockDim.x / sub_n;
-    const int sub = threadIdx.x / sub_n;
-    const int vb = it.y * spb + sub;
+    const int spb = blockDim.x / sub_n;          // whole sub-blocks per block
+    const int sub = threadIdx.x / sub_n;         // sub == spb: leftover threads (Pmax not a multiple of P)
+    const bool partial = sub >= spb;
+    const int vb = it.y * spb + (partial ? 0 : sub);
+    // LDS holds ceil(Pmax / P) sub-block areas (the launch sizes it so), so the
+    // leftover threads have an area of their own; they never store.
     S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * 9 * a.P * (TX + 1);
-    const bool valid = vb < a.nblk;
+    const bool valid = !partial && vb < a.nblk;
     pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, ctab, valid);
 }
 

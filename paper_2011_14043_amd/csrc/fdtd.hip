@@ -58,7 +58,7 @@ static const SchemeDef kSchemes[4] = {
 struct KCfg { int M, TX, NT, wpb, remap; };
 
 // Instantiated y/z-line variants {M, TX, NT} by solve precision.
-static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}};
+static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}, {8, 32, 512}};
 static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
 
 struct Timing {
@@ -79,6 +79,7 @@ struct BatchPass {
     void* items = nullptr;    // device int2[nitems]
     int nitems = 0;
     int Pmax = 1;             // y/z lines: largest chunk count (block = TX * Pmax)
+    size_t lds = 0;           // y/z lines: dynamic LDS per block
 };
 struct Batch {
     std::vector<fdtd_plan_s*> subs;
@@ -361,7 +362,8 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         launch_yz_mode<T, S, MM, TT, NN>(mode, sh.full, sh.mat, sh.grid, sh.block, sh.lds, p->stream, a);     \
     } else
         if constexpr (sizeof(S) == 4) {
-            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) return FDTD_EUNSUPPORTED;
+            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) CASE_YZ(8, 32, 512)
+            return FDTD_EUNSUPPORTED;
         } else {
             CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) CASE_YZ(8, 16, 1024) return FDTD_EUNSUPPORTED;
         }
@@ -838,8 +840,10 @@ static void batch_clear(Batch* b) {
     b->passes.clear();
 }
 
-// Chunks per line of a grid in a batched pass (y/z: at least 64/TX, so that a
-// sub-block of TX * P threads is whole waves).
+// Chunks per line of a grid in a batched pass: a power of two (the separator
+// solve runs over segments of P lanes), for y/z lines at least 64/TX so that a
+// sub-block of TX * P threads is whole waves.  (Chunk counts rounded only to
+// a multiple of 64/TX, with a serial separator solve, were measured slower.)
 static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
     const int P = next_pow2((axis_cells(g->dims, axis) + c.M - 1) / c.M);
     return axis == 0 ? P : std::max(P, 64 / c.TX);
@@ -889,13 +893,16 @@ static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const 
         Pmax = std::max(Pmax, tab[g].P);
     }
     std::vector<int2> items;
+    int lds_rows = 0;   // y/z: sub-block areas x chunks, the most any grid needs
     for (int g = 0; g < n; ++g) {
         const int per = (w == 0) ? 1 : Pmax / tab[g].P;   // virtual blocks per block
         const int nit = (tab[g].nblk + per - 1) / per;
         for (int q = 0; q < nit; ++q) items.push_back(make_int2(g, q));
+        if (w != 0) lds_rows = std::max(lds_rows, ((Pmax + tab[g].P - 1) / tab[g].P) * tab[g].P);
     }
     BatchPass bp;
     bp.op = op; bp.k = k; bp.frac = frac; bp.Pmax = Pmax;
+    bp.lds = (size_t)9 * lds_rows * (cf.TX + 1) * sizeof(S);
     bp.nitems = (int)items.size();
     HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * n));
     hipError_t e = hipMalloc(&bp.items, sizeof(int2) * items.size());
@@ -931,7 +938,7 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
     } else {
         const int M = cf.M, TX = cf.TX, NT = cf.NT;
         const dim3 block(TX * bp.Pmax);
-        const size_t lds = (size_t)9 * bp.Pmax * (TX + 1) * sizeof(S);
+        const size_t lds = bp.lds;
 #define CASE_YZB(MM, TT, NN)                                                                                  \
     if (M == MM && TX == TT && NT == NN) {                                                                    \
         if (mat)                                                                                              \
@@ -940,7 +947,8 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
             hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, FUND, TT, NN, false>), grid, block, lds, st, tab, items); \
     } else
         if constexpr (sizeof(S) == 4) {
-            CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) return FDTD_EUNSUPPORTED;
+            CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) CASE_YZB(8, 32, 512)
+            return FDTD_EUNSUPPORTED;
         } else {
             CASE_YZB(16, 16, 512) CASE_YZB(8, 8, 512) CASE_YZB(8, 16, 1024) return FDTD_EUNSUPPORTED;
         }

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-YZ_F32 = [(16, 32, 1024), (16, 16, 512), (8, 16, 1024), (32, 16, 512)]
+YZ_F32 = [(16, 32, 1024), (16, 16, 512), (8, 16, 1024), (32, 16, 512), (8, 32, 512)]
 X_CFG = [(8, 256), (8, 64), (16, 128)]
 
 
