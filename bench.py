@@ -258,7 +258,7 @@ def main():
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU slab decomposition is a design, not built", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")

@@ -45,7 +45,7 @@ typedef enum {
     FDTD_EINVAL = -1,        /* bad argument (NULL, sizes, time step, cell index ...) */
     FDTD_ENOMEM = -2,        /* device allocation failed                             */
     FDTD_EDEVICE = -3,       /* HIP runtime error                                    */
-    FDTD_EUNSUPPORTED = -4,  /* valid request this build does not implement          */
+    FDTD_EUNSUPPORTED = -4,  /* valid request the library does not implement         */
     FDTD_ENONFINITE = -5     /* NaN/Inf found in the energy after stepping           */
 } fdtd_status;
 

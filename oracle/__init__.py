@@ -30,8 +30,8 @@ Stable Implicit FDTD Methods", arXiv 2011.14043):
                       that the paper omits (Sec. II opening);
 * ``run``          -- one entry point ``run(...)`` over schemes and forms.
 
-Parity status of every function is listed in the design doc; the pins live in
-``tests/test_oracle_*.py``.
+Every function is pinned by tests in ``tests/test_oracle_*.py`` against
+closed forms, brute-force dense solves or finite differences.
 """
 from .yee import (EPS0, MU0, C0, Grid, COMPONENTS, dynamic_mask, energy,
                   apply_operator, cfl_dt)

@@ -16,7 +16,7 @@ pairs, each pair along one axis w with a sign s:
     A: (Ex, Hz, y, +1), (Ey, Hx, z, +1), (Ez, Hy, x, +1)
     B: (Ex, Hy, z, -1), (Ey, Hz, x, -1), (Ez, Hx, y, -1)
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 * PEC on all six faces: tangential E on a wall is 0; normal H on a wall is
   static (its driving differences are tangential E on that wall).
 * eps and mu at staggered nodes: the component stored at node index [k, j, i]

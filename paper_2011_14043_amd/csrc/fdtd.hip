@@ -1177,7 +1177,7 @@ const char* fdtd_strerror(fdtd_status s) {
         case FDTD_EINVAL: return "invalid argument";
         case FDTD_ENOMEM: return "device out of memory";
         case FDTD_EDEVICE: return "HIP runtime error";
-        case FDTD_EUNSUPPORTED: return "not supported by this build";
+        case FDTD_EUNSUPPORTED: return "not supported by this library";
         case FDTD_ENONFINITE: return "non-finite energy after stepping";
     }
     return "unknown status";

@@ -36,7 +36,7 @@ def test_binding_names_match_header():
 
 
 def test_strerror(L):
-    for code, name in ((0, b"ok"), (-1, b"invalid argument"), (-4, b"not supported by this build")):
+    for code, name in ((0, b"ok"), (-1, b"invalid argument"), (-4, b"not supported by this library")):
         assert L.fdtd_strerror(code) == name
 
 

@@ -231,7 +231,7 @@ def test_adi_dispersion_closed_form(cfl, mnp):
     assert np.all(re >= cosw - 1e-12)
 
 
-def test_dispersion_worked_example_config1():
+def test_dispersion_worked_example_24cube():
     """24^3 cavity, 1 mm, CFL 4: ADI frequency of the (1,1,0) mode vs the Yee
     semi-discrete and the analytic resonance."""
     n, h = 24, 1e-3
