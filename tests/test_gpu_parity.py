@@ -135,6 +135,37 @@ def test_anisotropic_long_lines(scheme, form):
     assert oracle.yee.weighted_rel_l2(got2, ref2, g2) < 1e-11
 
 
+@pytest.fixture(scope="module")
+def max_line_refs():
+    """Lines of the longest length a plan accepts along each axis: 1024 cells
+    for FP32 fields, 512 for FP64; CFL 8, random boxes, a source."""
+    out = {}
+    for prec, nmax in (("f32", 1024), ("f64", 512)):
+        for axis in range(3):
+            dims = [11, 9, 10]
+            dims[axis] = nmax
+            nx, ny, nz = dims
+            h = 1e-3
+            dt = W.yee_dt(h, h, h, 8.0)
+            eps = W.random_box_eps(nx, ny, nz, seed=20 + axis, nboxes=8)
+            u0 = W.random_fields(nx, ny, nz, seed=30 + axis)
+            src = OSource(*W.interior_cell(nx, ny, nz, seed=40 + axis, margin=2), amp=1e12, t0=2 * dt, tau=2 * dt,
+                          f0=1 / (10 * dt))
+            g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+            out[(prec, axis)] = (dims, dt, h, eps, u0, src, g, oracle.run("adi", "fundamental", g, u0, 5, src)[0])
+    return out
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_maximum_line_length(max_line_refs, prec, axis):
+    (nx, ny, nz), dt, h, eps, u0, src, g, ref = max_line_refs[(prec, axis)]
+    print(f"[case] max line length {prec} {nx}x{ny}x{nz}", flush=True)
+    got, _ = gpu_run("adi", "fundamental", prec, nx, ny, nz, dt, h, eps, u0, 5, src)
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    assert err < (2e-5 if prec == "f32" else 1e-11), err
+
+
 @pytest.mark.parametrize("dims", [(2, 2, 2), (2, 3, 4), (5, 2, 3), (64, 2, 2)])
 def test_degenerate_small_grids(dims):
     nx, ny, nz = dims
