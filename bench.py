@@ -105,7 +105,7 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, t
     H = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
     src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
-                eps_r=torch.from_numpy(eps))
+                eps_r=torch.from_numpy(eps), refine=prec == "f32r")
     if tune:
         plan.autotune(tune_reps)
     cfg = [plan.kernel_config(ax) for ax in range(3)]
@@ -288,7 +288,8 @@ def main():
         extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
         extras["adjoint_gradient"] = run_adjoint()
     if args.variants != "none":
-        todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32s64"), ("adi", "conventional", "f32s64"),
+        todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32r"), ("adi", "fundamental", "f32s64"),
+                ("adi", "conventional", "f32s64"),
                 ("adi", "fundamental", "f64"), ("adi", "conventional", "f64"),
                 ("lod1", "fundamental", "f32"), ("ss2", "fundamental", "f32"), ("lod2", "fundamental", "f32"),
                 ("lod1", "conventional", "f32"), ("ss2", "conventional", "f32"), ("lod2", "conventional", "f32")]

@@ -59,10 +59,11 @@ class Plan:
     """One simulation plan (fdtd_plan).  Not thread-safe."""
 
     def __init__(self, nx, ny, nz, dt, dx, dy, dz, scheme="adi", form="fundamental",
-                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None):
+                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None, refine=False):
         """dtype: field storage (float32/float64); solve_dtype: arithmetic of the
         line solves (defaults to dtype; float64 with float32 fields selects
-        FDTD_F32_F64SOLVE)."""
+        FDTD_F32_F64SOLVE); refine: FP32 solves refined once (FDTD_F32_REFINE,
+        float32 fields and solves, fundamental forms)."""
         import torch
         L = _lib.lib()
         self.dtype = dtype if dtype is not None else torch.float32
@@ -71,7 +72,10 @@ class Plan:
         solve = solve_dtype if solve_dtype is not None else self.dtype
         if self.dtype == torch.float64 and solve != torch.float64:
             raise ValueError("float64 fields need float64 solves")
-        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else 0)
+        if refine and (self.dtype != torch.float32 or solve != torch.float32):
+            raise ValueError("refine applies to float32 fields with float32 solves")
+        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else (3 if refine else 0))
+        self.refine = bool(refine)
         self.shape = (nz + 1, ny + 1, nx + 1)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         eps_ptr = None

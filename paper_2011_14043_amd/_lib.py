@@ -16,7 +16,7 @@ STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ENOMEM", -3: "FDTD_EDEVICE"
           -4: "FDTD_EUNSUPPORTED", -5: "FDTD_ENONFINITE"}
 SCHEMES = {"adi": 0, "lod1": 1, "ss1": 1, "ss2": 2, "lod2": 3}
 FORMS = {"fundamental": 0, "conventional": 1}
-DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2}
+DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2, "f32_refine": 3}
 
 EXPORTS = ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
            "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",

@@ -116,6 +116,7 @@ struct fdtd_plan_s {
     fdtd::Timing tm;
     fdtd::KCfg cfg[3];        // per line axis x, y, z
     int tuned = 0;
+    int refine = 0;           // FDTD_F32_REFINE: fundamental passes refine each solve once
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
     int fam_n[2] = {0, 0};
@@ -164,11 +165,18 @@ static void launch_x(bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const 
         else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, false>), g, b, 0, st, a);
     }
 }
+// Refined solves are built for FP32: x lines with 8-slot chunks, y/z lines
+// with 8- or 16-slot chunks.
+template <typename S, int M> struct HasRefX { static constexpr bool v = sizeof(S) == 4 && M == 8; };
+template <typename S, int M> struct HasRefYZ { static constexpr bool v = sizeof(S) == 4 && (M == 8 || M == 16); };
 template <typename T, typename S, int M>
-static void launch_x_mode(int mode, bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+static bool launch_x_mode(int mode, bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
     if (mode == FUND) launch_x<T, S, M, FUND>(full, mat, g, b, st, a);
     else if (mode == CONV_LOD) launch_x<T, S, M, CONV_LOD>(full, mat, g, b, st, a);
-    else launch_x<T, S, M, CONV_ADI>(full, mat, g, b, st, a);
+    else if (mode == CONV_ADI) launch_x<T, S, M, CONV_ADI>(full, mat, g, b, st, a);
+    else if constexpr (HasRefX<S, M>::v) launch_x<T, S, M, FUND_REF>(full, mat, g, b, st, a);
+    else return false;
+    return true;
 }
 template <typename T, typename S, int M, int TX, int NT, int MODE>
 static void launch_yz(bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
@@ -181,11 +189,14 @@ static void launch_yz(bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream
     }
 }
 template <typename T, typename S, int M, int TX, int NT>
-static void launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st,
+static bool launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st,
                            const PassArgs<T, S>& a) {
     if (mode == FUND) launch_yz<T, S, M, TX, NT, FUND>(full, mat, g, b, lds, st, a);
     else if (mode == CONV_LOD) launch_yz<T, S, M, TX, NT, CONV_LOD>(full, mat, g, b, lds, st, a);
-    else launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
+    else if (mode == CONV_ADI) launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
+    else if constexpr (HasRefYZ<S, M>::v) launch_yz<T, S, M, TX, NT, FUND_REF>(full, mat, g, b, lds, st, a);
+    else return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -352,14 +363,17 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         HIPCHK(hipEventRecord(e0, p->stream));
     }
     const KCfg& cf = p->cfg[sh.w];
+    const int kmode = (mode == FUND && p->refine) ? FUND_REF : mode;
+    bool built = true;
     if (sh.w == 0) {
-        if (cf.M == 8) launch_x_mode<T, S, 8>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
-        else launch_x_mode<T, S, 16>(mode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+        if (cf.M == 8) built = launch_x_mode<T, S, 8>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+        else built = launch_x_mode<T, S, 16>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
     } else {
         const int M = cf.M, TX = cf.TX, NT = cf.NT;
+        const size_t lds = kmode == FUND_REF ? sh.lds / 9 * 13 : sh.lds;   // refined: second exchange areas
 #define CASE_YZ(MM, TT, NN)                                                                                    \
     if (M == MM && TX == TT && NT == NN) {                                                                     \
-        launch_yz_mode<T, S, MM, TT, NN>(mode, sh.full, sh.mat, sh.grid, sh.block, sh.lds, p->stream, a);     \
+        built = launch_yz_mode<T, S, MM, TT, NN>(kmode, sh.full, sh.mat, sh.grid, sh.block, lds, p->stream, a); \
     } else
         if constexpr (sizeof(S) == 4) {
             CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) CASE_YZ(8, 32, 512)
@@ -369,6 +383,7 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
         }
 #undef CASE_YZ
     }
+    if (!built) return FDTD_EUNSUPPORTED;
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(e1, p->stream));
     return FDTD_OK;
@@ -392,6 +407,7 @@ static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& 
 static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     const int n = axis_cells(p->dims, axis);
     if (c.remap != 0 && c.remap != 1) return false;
+    if (p->refine && (axis == 0 ? c.M != 8 : c.M > 16)) return false;   // refined solves built
     if (axis == 0) {
         if (c.M != 8 && c.M != 16) return false;
         if (c.wpb < 1 || c.wpb > 4) return false;
@@ -446,7 +462,8 @@ static void default_cfg(fdtd_plan_s* p) {
         if (axis == 0) {
             pref = {{8, 0, 0, 4, 1}, {16, 0, 0, 4, 1}};
         } else if (p->d.dtype == FDTD_F32) {
-            pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {8, 16, 1024, 0, 1}};
+            pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {8, 16, 1024, 0, 1},
+                    {8, 32, 512, 0, 1}};
         } else {
             pref = {{16, 16, 512, 0, 1}, {8, 8, 512, 0, 1}};
         }
@@ -1190,12 +1207,15 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!(d->dt > 0) || !(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return FDTD_EINVAL;
     if (!std::isfinite(d->dt) || !std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz))
         return FDTD_EINVAL;
-    if (d->scheme < 0 || d->scheme > 3 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 2)
+    if (d->scheme < 0 || d->scheme > 3 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
         return FDTD_EINVAL;
     if (d->boundary != 0) return FDTD_EUNSUPPORTED;
     if (d->mu_r != nullptr) return FDTD_EUNSUPPORTED;
+    const bool refine = d->dtype == FDTD_F32_REFINE;
+    if (refine && d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
     const int nmax = std::max(d->nx, std::max(d->ny, d->nz));
-    if (nmax > (d->dtype == FDTD_F32 ? 1024 : 512)) return FDTD_EUNSUPPORTED;   // register budget
+    // register budget (refined solves: 8-slot chunks on at most 64 lanes)
+    if (nmax > (d->dtype == FDTD_F32 ? 1024 : 512)) return FDTD_EUNSUPPORTED;
     const long long ncells = (long long)d->nx * d->ny * d->nz;
     std::vector<float> eps_host;
     if (d->eps_r) {
@@ -1209,6 +1229,10 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!p) return FDTD_ENOMEM;
     p->d = *d;
     p->d.eps_r = nullptr;
+    if (refine) {
+        p->refine = 1;
+        p->d.dtype = FDTD_F32;   // FP32 storage and arithmetic; only the fundamental passes differ
+    }
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
     p->esz = d->dtype == FDTD_F64 ? 8 : 4;
@@ -1432,10 +1456,10 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     *out = nullptr;
     for (int g = 0; g < n; ++g) {
         if (d[g].scheme != d[0].scheme || d[g].form != d[0].form || d[g].dtype != d[0].dtype) return FDTD_EINVAL;
-        if (d[g].scheme < 0 || d[g].scheme > 3 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 2)
+        if (d[g].scheme < 0 || d[g].scheme > 3 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
             return FDTD_EINVAL;
     }
-    if (d[0].form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    if (d[0].form != FDTD_FUNDAMENTAL || d[0].dtype == FDTD_F32_REFINE) return FDTD_EUNSUPPORTED;
     fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
     if (!p) return FDTD_ENOMEM;
     p->batch = new (std::nothrow) Batch();

@@ -153,4 +153,69 @@ __device__ __forceinline__ void chunk_finish(const Chunk<T, M>& c, T Sp, T S, T 
     ho[M - 1] = c.Z[M - 1] + q * ((xn - S) + T(CH) * (uen - c.W[M - 1]));
 }
 
+// ---------------------------------------------------------------------------
+// Refined solves.  The coefficients of the elimination (pivots, influence
+// vectors, the separator system) depend only on the medium, so in FP32 their
+// rounding is the same at every time step: a fixed perturbation of the
+// operator, whose phase error grows linearly with the step count.  One step of
+// iterative refinement in working precision -- the residual rho = r - T V,
+// then a second solve T dV = rho with the same factors -- takes that bias to
+// second order; what is left is rounding that changes from step to step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// A refined chunk keeps only the inverse pivots g of its interior rows.  With
+// p_k = g_0 ... g_k (p_{-1} = 1), the values the separator rows need follow
+// from forward sweeps alone:  alpha_{M-2} = gamma_0 = p_{M-2},
+// gamma_{M-2} = g_{M-2},  alpha_0 = sum_k p_{k-1} p_k,  y_{M-2} = d_{M-2} and
+// y_0 = sum_k p_{k-1} d_k  (d: the forward-swept right side), since
+// alpha_i = p_i + g_i alpha_{i+1} and y_i = d_i + g_i y_{i+1}.
+
+// Forward sweep of the interior rows 0..M-2 in place (d holds the right side
+// on entry): d_i <- (d_i + d_{i-1}) g_i.  Returns y_0.
+template <typename T, int M>
+__device__ __forceinline__ T rsweep(const T (&g)[M - 1], T (&d)[M]) {
+    d[0] = d[0] * g[0];
+    T p = g[0], y0 = d[0];
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+        d[i] = (d[i] + d[i - 1]) * g[i];
+        y0 = fused(p, d[i], y0);
+        p = p * g[i];
+    }
+    return y0;
+}
+
+// alpha_0 and p_{M-2} of the interior rows.
+template <typename T, int M>
+__device__ __forceinline__ void rinfluence(const T (&g)[M - 1], T& a0, T& pL) {
+    T p = g[0], a = g[0];
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+        const T pn = p * g[i];
+        a = fused(p, pn, a);
+        p = pn;
+    }
+    a0 = a;
+    pL = p;
+}
+
+// Slot values from the forward-swept d once the separators S_{l-1} (Sp) and
+// S_l (S) are known, in place: the interior rows see Sp in row 0 and S in row
+// M-2, i.e. d_k + Sp p_k, then the backward sweep; V[M-1] = S.
+template <typename T, int M>
+__device__ __forceinline__ void rvalues(const T (&g)[M - 1], T (&V)[M], T Sp, T S) {
+    T p = g[0];
+    V[0] = fused(Sp, p, V[0]);
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+        p = p * g[i];
+        V[i] = fused(Sp, p, V[i]);
+    }
+    V[M - 1] = S;
+#pragma unroll
+    for (int i = M - 2; i >= 0; --i) V[i] = fused(g[i], V[i + 1], V[i]);
+}
+
 }  // namespace fdtd

@@ -39,7 +39,10 @@
 
 namespace fdtd {
 
-enum Mode { FUND = 0, CONV_LOD = 1, CONV_ADI = 2 };
+// FUND_REF: the fundamental update with one step of iterative refinement of
+// every tridiagonal solve (FP32 solves without their fixed rounding bias).
+enum Mode { FUND = 0, CONV_LOD = 1, CONV_ADI = 2, FUND_REF = 3 };
+template <int MODE> struct IsFund { static constexpr bool v = MODE == FUND || MODE == FUND_REF; };
 
 template <typename T, typename S>
 struct PassArgs {
@@ -82,7 +85,7 @@ __device__ __forceinline__ int xcd_remap(int L, int G) {
     return c * per + (c < rem ? c : rem) + q;
 }
 
-template <int MODE> struct ModeCE { static constexpr int v = (MODE == FUND) ? -1 : 0; };
+template <int MODE> struct ModeCE { static constexpr int v = IsFund<MODE>::v ? -1 : 0; };
 template <int MODE> struct ModeCH { static constexpr int v = (MODE == CONV_LOD) ? 1 : 0; };
 
 // ---------------------------------------------------------------------------
@@ -183,10 +186,13 @@ __device__ __forceinline__ S make_sigma(double Ks, float eps) {
     if constexpr (sizeof(S) == 4) return (2.0f + float(Ks) * eps) - 2.0f;
     else return Ks * double(eps);
 }
+// Refined solves take sigma as it is: the rounded diagonal only shapes the
+// factors, and the residual of the refinement step is formed with sigma itself
+// (rhs c = 2 sigma exactly), so no fixed perturbation of the medium remains.
 template <typename S, int MODE>
 __device__ __forceinline__ SlotCoef<S> coef_of(double Ks, float eps) {
-    const S sig = make_sigma<S>(Ks, eps);
-    return SlotCoef<S>{(MODE == FUND) ? sig + sig : sig, S(2) + sig};
+    const S sig = (MODE == FUND_REF) ? S(Ks * double(eps)) : make_sigma<S>(Ks, eps);
+    return SlotCoef<S>{IsFund<MODE>::v ? sig + sig : sig, S(2) + sig};
 }
 // Material-index variants keep a per-material table in LDS, filled once per
 // block.  FP32 solves store the coefficients themselves (one LDS read per
@@ -217,7 +223,7 @@ __device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, SlotCoef<S> sc
     const S dh = uh - uh_m;
     S hterm = dh * a.kap_hi;
     if constexpr (sizeof(S) == 4) hterm = __builtin_fmaf(dh, a.kap_lo, hterm);
-    if constexpr (MODE == FUND) {
+    if constexpr (IsFund<MODE>::v) {
         r = sc.c * ue + hterm;
     } else if constexpr (MODE == CONV_LOD) {
         r = sc.c * ue + hterm + ((ue_p + ue_m) - S(2) * ue);
@@ -234,7 +240,7 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const S sig = dg[i] - S(2);
-        const S coef = (MODE == FUND) ? sig + sig : sig;
+        const S coef = IsFund<MODE>::v ? sig + sig : sig;
         r[i] += (i == si) ? coef * pre : S(0);
     }
 }
@@ -353,24 +359,87 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
-    Chunk<S, M> c;
-    chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
-
-    // separator system across the P lanes of the line (all lanes shuffle)
+    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    // separator system across the P lanes of the line (all lanes shuffle):
+    // own last interior slot (aL, gL, yL), separator row (dgS, rS), and the
+    // next chunk's first slot (a0n, g0n, y0; zero past the line).  Returns
+    // S_l, S_{l-1} and the next chunk's first value.
     const bool has_next = ls + 1 < P;
-    const S a0n_r = __shfl_down(c.a0, 1, P), g0n_r = __shfl_down(c.g0, 1, P), y0n_r = __shfl_down(c.y0, 1, P);
-    const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0), y0n = has_next ? y0n_r : S(0);
-    const S Sl = pcr_wave<S>(separator_row<S>(c.aL, c.gL, c.yL, c.dgS, c.rS, a0n, g0n, y0n), ls, P);
-    const S Sp_r = __shfl_up(Sl, 1, P), Sn_r = __shfl_down(Sl, 1, P);
-    const S Sp = (ls > 0) ? Sp_r : S(0);
-    const S Sn = has_next ? Sn_r : S(0);
-    const S xn = y0n + a0n * Sl + g0n * Sn;
+    auto separators = [&](S aL, S gL, S yL, S dgS, S rS, S a0n, S g0n, S y0, S& Sl, S& Sp, S& xn) {
+        const S y0n_r = __shfl_down(y0, 1, P);
+        const S y0n = has_next ? y0n_r : S(0);
+        Sl = pcr_wave<S>(separator_row<S>(aL, gL, yL, dgS, rS, a0n, g0n, y0n), ls, P);
+        const S Sp_r = __shfl_up(Sl, 1, P), Sn_r = __shfl_down(Sl, 1, P);
+        Sp = (ls > 0) ? Sp_r : S(0);
+        const S Sn = has_next ? Sn_r : S(0);
+        xn = y0n + a0n * Sl + g0n * Sn;
+    };
 
     S eo[M], ho[M];
-    chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    if constexpr (MODE == FUND_REF) {
+        // refined solve: first solve, residual with the unrounded sigma, and
+        // a correction solve with the same pivots (right sides recomputed
+        // from the fields instead of kept in registers)
+        unsigned fixed = first ? 1u : 0u;   // rows with no unknown: the wall, slots past the line
+        if (!FULL) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) fixed |= (j0 + i >= n) ? (1u << i) : 0u;
+        }
+        const S pre = src_wave ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
+        auto rhs = [&](int i) -> S {
+            const S dh = uh[i] - ((i == 0) ? uh_m_eff : uh[i - 1]);
+            S rr = fused(sc[i].c, ue[i], fused(dh, a.kap_lo, dh * a.kap_hi));
+            rr = (src_here && i == si) ? fused(sc[i].c, pre, rr) : rr;
+            return ((fixed >> i) & 1u) ? S(0) : rr;
+        };
+        S g[M - 1], d[M];
+#pragma unroll
+        for (int i = 0; i < M - 1; ++i) {
+            const S dgi = ((fixed >> i) & 1u) ? Big<S>::v : sc[i].d;
+            g[i] = recip(i == 0 ? dgi : dgi - g[i - 1]);
+            d[i] = rhs(i);
+        }
+        const S y0 = rsweep<S, M>(g, d);
+        S a0, pL;
+        rinfluence<S, M>(g, a0, pL);
+        const S dgS = ((fixed >> (M - 1)) & 1u) ? Big<S>::v : sc[M - 1].d;
+        const S a0n_r = __shfl_down(a0, 1, P), g0n_r = __shfl_down(pL, 1, P);
+        const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0);
+        S Sl, Sp, xn;
+        separators(pL, g[M - 2], d[M - 2], dgS, rhs(M - 1), a0n, g0n, y0, Sl, Sp, xn);
+        rvalues<S, M>(g, d, Sp, Sl);
+        S rho[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const S vm = (i == 0) ? Sp : d[i - 1];
+            const S vp = (i == M - 1) ? xn : d[i + 1];
+            const S res = fused(S(-0.5) * sc[i].c, d[i], rhs(i)) + ((vm - d[i]) + (vp - d[i]));
+            rho[i] = ((fixed >> i) & 1u) ? S(0) : res;
+            eo[i] = d[i] - ue[i];
+            ho[i] = fused(a.q, vp - d[i], uh[i]);
+        }
+        const S rS = rho[M - 1];
+        const S y0c = rsweep<S, M>(g, rho);
+        S dSl, dSp, dxn;
+        separators(pL, g[M - 2], rho[M - 2], dgS, rS, a0n, g0n, y0c, dSl, dSp, dxn);
+        rvalues<S, M>(g, rho, dSp, dSl);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const S dn = (i == M - 1) ? dxn : rho[i + 1];
+            eo[i] += rho[i];
+            ho[i] = fused(a.q, dn - rho[i], ho[i]);
+        }
+    } else {
+        Chunk<S, M> c;
+        chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
+        const S a0n_r = __shfl_down(c.a0, 1, P), g0n_r = __shfl_down(c.g0, 1, P);
+        const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0);
+        S Sl, Sp, xn;
+        separators(c.aL, c.gL, c.yL, c.dgS, c.rS, a0n, g0n, c.y0, Sl, Sp, xn);
+        chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    }
     eo[0] = first ? S(0) : eo[0];
-    if (MODE == FUND && __builtin_expect(src_wave, 0)) {
+    if (IsFund<MODE>::v && __builtin_expect(src_wave, 0)) {
 #pragma unroll
         for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
     }
@@ -410,7 +479,9 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // Body of one (virtual) block of TX * P threads: thread t, block index blk of
 // the pass (blk < a.nblk when valid; an invalid block computes nothing and
 // stores nothing but takes part in the barriers), LDS area sm of
-// 9 P (TX+1) elements.  TX * P must be a multiple of 64 (whole waves).
+// 9 P (TX+1) elements (13 P (TX+1) for refined solves, whose second
+// separator exchange has areas of its own).  TX * P must be a multiple of 64
+// (whole waves).
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
 __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const CoefTab<S>* ctab,
                                              bool valid) {
@@ -424,6 +495,14 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     S* sb_ = sm + 8 * P * LD;                    // [P][LD]
     auto EP = [&](int k, int pp, int xx) -> S& { return ep_[(k * P + pp) * LD + xx]; };
     auto SB = [&](int pp, int xx) -> S& { return sb_[pp * LD + xx]; };
+    // refined solves, second exchange: y_0, y_{M-2}, rS in [3][P][LD], S in [P][LD]
+    S* ep2_ = sm + 9 * P * LD;
+    S* sb2_ = sm + 12 * P * LD;
+    auto EPs = [&](int set, int k, int pp, int xx) -> S& {
+        if (set && (k == 2 || k == 5 || k == 7)) return ep2_[((k == 2 ? 0 : (k == 5 ? 1 : 2)) * P + pp) * LD + xx];
+        return EP(k, pp, xx);
+    };
+    auto SBs = [&](int set, int pp, int xx) -> S& { return set ? sb2_[pp * LD + xx] : SB(pp, xx); };
 
     const int tile0 = (blk % a.ntx) * TX;
     const int ib = a.b_lo + blk / a.ntx;
@@ -515,36 +594,130 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (__builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
-    Chunk<S, M> c;
-    chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
-
-    EP(0, p, tx) = c.a0; EP(1, p, tx) = c.g0; EP(2, p, tx) = c.y0;
-    EP(3, p, tx) = c.aL; EP(4, p, tx) = c.gL; EP(5, p, tx) = c.yL;
-    EP(6, p, tx) = c.dgS; EP(7, p, tx) = c.rS;
-    __syncthreads();
-    {
-        // re-index: line = t / P, chunk = t % P (P consecutive lanes per line)
-        const int pl = t % P, xl = t / P;
-        const bool hn = pl + 1 < P;
-        const int pn = hn ? pl + 1 : pl;
-        Row<S> w = separator_row<S>(EP(3, pl, xl), EP(4, pl, xl), EP(5, pl, xl), EP(6, pl, xl), EP(7, pl, xl),
-                                    hn ? EP(0, pn, xl) : S(0), hn ? EP(1, pn, xl) : S(0), hn ? EP(2, pn, xl) : S(0));
-        const S Sv = pcr_wave<S>(w, pl, P);
-        SB(pl, xl) = Sv;
-    }
-    __syncthreads();
-    const S Sl = SB(p, tx);
-    const S Sp = first ? S(0) : SB(p - 1, tx);
+    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    // Separator system: every chunk's end values go through LDS (slots
+    // 0-2: first interior slot alpha, gamma, y; 3-5: last interior slot;
+    // 6, 7: separator diagonal and right side), the P chunks of a line are
+    // reduced on P consecutive lanes, and S returns through LDS.
+    auto separators = [&](int set) {
+        __syncthreads();
+        {
+            // re-index: line = t / P, chunk = t % P (P consecutive lanes per line)
+            const int pl = t % P, xl = t / P;
+            const bool hn = pl + 1 < P;
+            const int pn = hn ? pl + 1 : pl;
+            Row<S> w = separator_row<S>(EPs(set, 3, pl, xl), EPs(set, 4, pl, xl), EPs(set, 5, pl, xl),
+                                        EPs(set, 6, pl, xl), EPs(set, 7, pl, xl), hn ? EPs(set, 0, pn, xl) : S(0),
+                                        hn ? EPs(set, 1, pn, xl) : S(0), hn ? EPs(set, 2, pn, xl) : S(0));
+            const S Sv = pcr_wave<S>(w, pl, P);
+            SBs(set, pl, xl) = Sv;
+        }
+        __syncthreads();
+    };
     const bool hn = p + 1 < P;
     const int pn = hn ? p + 1 : p;
-    const S Sn = hn ? SB(pn, tx) : S(0);
-    const S xn = hn ? EP(2, pn, tx) + EP(0, pn, tx) * Sl + EP(1, pn, tx) * Sn : S(0);
+    // S_l, S_{l-1} and the next chunk's first value, after separators(set)
+    auto read_separators = [&](int set, S& Sl, S& Sp, S& xn) {
+        Sl = SBs(set, p, tx);
+        Sp = first ? S(0) : SBs(set, p - 1, tx);
+        const S Sn = hn ? SBs(set, pn, tx) : S(0);
+        xn = hn ? EPs(set, 2, pn, tx) + EPs(set, 0, pn, tx) * Sl + EPs(set, 1, pn, tx) * Sn : S(0);
+    };
 
     S eo[M], ho[M];
-    chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    if constexpr (MODE == FUND_REF) {
+        // refined solve (see the x lines); material indices packed 4 per word
+        unsigned fixed = first ? 1u : 0u;   // rows with no unknown: the wall, slots past the line
+        if (!FULL) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) fixed |= (j0 + i >= n) ? (1u << i) : 0u;
+        }
+        unsigned idp[(M + 3) / 4];
+        if constexpr (MAT) {
+#pragma unroll
+            for (int k = 0; k < (M + 3) / 4; ++k) {
+                unsigned w = 0;
+#pragma unroll
+                for (int e = 0; e < 4 && 4 * k + e < M; ++e) w |= id[4 * k + e] << (8 * e);
+                idp[k] = w;
+            }
+        }
+        auto coef = [&](int i) -> SlotCoef<S> {
+            if constexpr (MAT) return coef_from_tab<T, S, MODE>(a, ctab, (idp[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+            else return coef_of<S, MODE>(a.Ks, epf[i]);
+        };
+        const S pre = src_wave ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
+        auto rhs = [&](int i, S c) -> S {
+            const S dh = uh[i] - ((i == 0) ? uh_m_eff : uh[i - 1]);
+            S rr = fused(c, ue[i], fused(dh, a.kap_lo, dh * a.kap_hi));
+            rr = (src_here && i == si) ? fused(c, pre, rr) : rr;
+            return ((fixed >> i) & 1u) ? S(0) : rr;
+        };
+        S g[M - 1], d[M];
+#pragma unroll
+        for (int i = 0; i < M - 1; ++i) {
+            const SlotCoef<S> sci = coef(i);
+            const S dgi = ((fixed >> i) & 1u) ? Big<S>::v : sci.d;
+            g[i] = recip(i == 0 ? dgi : dgi - g[i - 1]);
+            d[i] = rhs(i, sci.c);
+        }
+        const S y0 = rsweep<S, M>(g, d);
+        S a0, pL;
+        rinfluence<S, M>(g, a0, pL);
+        const SlotCoef<S> scS = coef(M - 1);
+        EP(0, p, tx) = a0; EP(1, p, tx) = pL; EP(2, p, tx) = y0;
+        EP(3, p, tx) = pL; EP(4, p, tx) = g[M - 2]; EP(5, p, tx) = d[M - 2];
+        EP(6, p, tx) = ((fixed >> (M - 1)) & 1u) ? Big<S>::v : scS.d;
+        EP(7, p, tx) = rhs(M - 1, scS.c);
+        separators(0);
+        S Sl, Sp, xn;
+        read_separators(0, Sl, Sp, xn);
+        rvalues<S, M>(g, d, Sp, Sl);
+        // the right sides are formed again from the fields (an opaque copy,
+        // so that the first ones are not kept live across the barriers)
+#pragma unroll
+        for (int i = 0; i < M; ++i) asm volatile("" : "+v"(uh[i]));
+        S rho[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const SlotCoef<S> sci = coef(i);
+            const S vm = (i == 0) ? Sp : d[i - 1];
+            const S vp = (i == M - 1) ? xn : d[i + 1];
+            const S res = fused(S(-0.5) * sci.c, d[i], rhs(i, sci.c)) + ((vm - d[i]) + (vp - d[i]));
+            rho[i] = ((fixed >> i) & 1u) ? S(0) : res;
+            eo[i] = d[i] - ue[i];
+            ho[i] = fused(a.q, vp - d[i], uh[i]);
+        }
+        // keep the compiler from re-deriving the first outputs after the
+        // barriers below (that would hold V and the fields live instead)
+#pragma unroll
+        for (int i = 0; i < M; ++i) asm volatile("" : "+v"(eo[i]), "+v"(ho[i]), "+v"(rho[i]));
+        const S rS = rho[M - 1];
+        const S y0c = rsweep<S, M>(g, rho);
+        EPs(1, 2, p, tx) = y0c; EPs(1, 5, p, tx) = rho[M - 2]; EPs(1, 7, p, tx) = rS;
+        separators(1);
+        S dSl, dSp, dxn;
+        read_separators(1, dSl, dSp, dxn);
+        rvalues<S, M>(g, rho, dSp, dSl);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const S dn = (i == M - 1) ? dxn : rho[i + 1];
+            eo[i] += rho[i];
+            ho[i] = fused(a.q, dn - rho[i], ho[i]);
+        }
+    } else {
+        Chunk<S, M> c;
+        chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
+        EP(0, p, tx) = c.a0; EP(1, p, tx) = c.g0; EP(2, p, tx) = c.y0;
+        EP(3, p, tx) = c.aL; EP(4, p, tx) = c.gL; EP(5, p, tx) = c.yL;
+        EP(6, p, tx) = c.dgS; EP(7, p, tx) = c.rS;
+        separators(0);
+        S Sl, Sp, xn;
+        read_separators(0, Sl, Sp, xn);
+        chunk_finish<S, M, CE, CH>(c, Sp, Sl, xn, ue_next, a.q, eo, ho);
+    }
     eo[0] = first ? S(0) : eo[0];
-    if (MODE == FUND && __builtin_expect(src_wave, 0)) {
+    if (IsFund<MODE>::v && __builtin_expect(src_wave, 0)) {
 #pragma unroll
         for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
     }
@@ -565,7 +738,7 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
 // phase.
 template <typename S, int M, int MODE, int NT>
 struct YzOcc {
-    static constexpr int v = (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI) ? 8 : 1;
+    static constexpr int v = (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI && MODE != FUND_REF) ? 8 : 1;
 };
 
 template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>

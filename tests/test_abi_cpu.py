@@ -53,6 +53,7 @@ def _desc(**kw):
     (dict(dx=0.0), -1), (dict(dt=float("nan")), -1), (dict(dz=float("inf")), -1),
     (dict(scheme=4), -1), (dict(form=2), -1), (dict(dtype=7), -1),
     (dict(boundary=1), -4), (dict(mu_r=12345), -4), (dict(nx=2000), -4), (dict(nz=600, dtype=1), -4),
+    (dict(dtype=4), -1), (dict(dtype=3, form=1), -4), (dict(dtype=3, ny=600), -4),
 ])
 def test_plan_rejects_invalid(L, kw, status):
     d = _desc(**kw)

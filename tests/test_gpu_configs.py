@@ -29,12 +29,12 @@ def case(request):
     return dict(nx=nx, ny=ny, nz=nz, h=h, dt=dt, eps=eps, u0=u0, src=src, g=g, refs=refs)
 
 
-def _run(c, scheme, form, cfg_yz, cfg_x):
+def _run(c, scheme, form, cfg_yz, cfg_x, refine=False):
     from paper_2011_14043_amd import FdtdError, Plan, Source
     E = [torch.tensor(a, dtype=torch.float32, device=DEV) for a in c["u0"][:3]]
     H = [torch.tensor(a, dtype=torch.float32, device=DEV) for a in c["u0"][3:]]
     plan = Plan(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["h"], c["h"], scheme=scheme, form=form,
-                dtype=torch.float32, eps_r=torch.tensor(c["eps"]))
+                dtype=torch.float32, eps_r=torch.tensor(c["eps"]), refine=refine)
     try:
         M, TX, NT = cfg_yz
         for ax in (1, 2):
@@ -67,3 +67,30 @@ def test_x_variants(case, cfg_x):
     assert got is not None
     err = oracle.yee.weighted_rel_l2(got, case["refs"][("adi", "fundamental")], case["g"])
     assert err <= 2e-5, err
+
+
+@pytest.mark.parametrize("scheme", ["adi", "ss2"])
+@pytest.mark.parametrize("cfg_yz", [(8, 16, 1024), (8, 32, 512), (16, 32, 1024), (16, 16, 512)],
+                         ids=lambda v: "yz%d-%d-%d" % v)
+@pytest.mark.parametrize("wpb", [4, 1])
+def test_refined_variants(case, scheme, cfg_yz, wpb):
+    """Refined FP32 solves in every launch shape built for them (x lines:
+    8-slot chunks; y/z lines: 8 or 16); other chunk lengths are rejected."""
+    from paper_2011_14043_amd import FdtdError, Plan
+    print(f"[case] refined {case['nx']}x{case['ny']}x{case['nz']} {scheme} yz={cfg_yz} wpb={wpb}", flush=True)
+    got = _run(case, scheme, "fundamental", cfg_yz, (8, 64 * wpb), refine=True)
+    if got is None:
+        pytest.skip("variant does not fit this grid")
+    ref = case["refs"][(scheme, "fundamental")] if scheme == "adi" else \
+        oracle.run(scheme, "fundamental", case["g"], case["u0"], 6, case["src"])[0]
+    err = oracle.yee.weighted_rel_l2(got, ref, case["g"])
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-5, err
+    plan = Plan(case["nx"], case["ny"], case["nz"], case["dt"], case["h"], case["h"], case["h"], refine=True)
+    try:
+        with pytest.raises(FdtdError):
+            plan.set_kernel_config(1, chunk=32, tile_x=16, block_threads=512, remap=1)
+        with pytest.raises(FdtdError):
+            plan.set_kernel_config(0, chunk=16, block_threads=256, remap=1)
+    finally:
+        plan.close()

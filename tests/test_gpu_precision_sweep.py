@@ -1,14 +1,16 @@
 """Precision sweep: 128^3 cells, random-box eps_r (32 boxes), N(0,1) fields,
 CFL number 10, 1000 steps, every fundamental scheme, FP64 / FP32-storage with
-FP64 solves / pure FP32 on the GPU against the FP64 oracle (fixtures written
-by tests/golden/make_precision_sweep.py, which calls only the oracle).
+FP64 solves / pure FP32 / pure FP32 with refined solves on the GPU against the
+FP64 oracle (fixtures written by tests/golden/make_precision_sweep.py, which
+calls only the oracle).
 
 Reported at steps 100, 500, 1000: the energy-weighted relative L2 error over
 4096 seeded samples per component, and the relative error of the field's
-energy norm.  Bars: FP64 1e-10; FP32 storage with FP64 solves 1e-4 (the
-accuracy target for FP32 fields after 1000 steps); pure FP32 arithmetic 1e-3,
-limited by the coherent rounding of the tridiagonal pivots at sigma =
-eps mu dw^2 / theta^2 << 1."""
+energy norm.  Bars: FP64 1e-10; FP32 storage with FP64 solves 1e-4 and pure
+FP32 with one refinement step per solve 1e-4 (the accuracy target for FP32
+fields after 1000 steps); plain FP32 arithmetic 1e-3, limited by the coherent
+rounding of the tridiagonal factors at sigma = eps mu dw^2 / theta^2 << 1,
+which is the same at every step."""
 import os
 
 import numpy as np
@@ -24,8 +26,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 DEV = "cuda:0"
 PREC = {"f64": (torch.float64, torch.float64), "f32s64": (torch.float32, torch.float64),
-        "f32": (torch.float32, torch.float32)}
-BAR = {"f64": 1e-10, "f32s64": 1e-4, "f32": 1e-3}
+        "f32": (torch.float32, torch.float32), "f32r": (torch.float32, torch.float32)}
+BAR = {"f64": 1e-10, "f32s64": 1e-4, "f32": 1e-3, "f32r": 1e-4}
 
 
 def _golden(scheme):
@@ -45,7 +47,7 @@ def setup():
     return dict(n=n, h=h, dt=dt, eps=eps, u0=u0, g=g)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
 def test_precision_sweep(setup, scheme, prec):
     from paper_2011_14043_amd import Plan
@@ -58,7 +60,7 @@ def test_precision_sweep(setup, scheme, prec):
     E = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][:3]]
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][3:]]
     plan = Plan(n, n, n, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve,
-                eps_r=torch.tensor(c["eps"]))
+                eps_r=torch.tensor(c["eps"]), refine=prec == "f32r")
     done = 0
     errs, nerrs = [], []
     for m, step in enumerate(ref["steps"]):
