@@ -56,10 +56,10 @@ typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
  * but forms every right-hand side, tridiagonal solve and update in FP64
  * registers, rounding once per stored value.  FDTD_F32_REFINE is FDTD_F32
  * with one step of iterative refinement of every tridiagonal solve (the
- * residual r - T V and a second solve with the same factors, all in FP32),
- * which removes the fixed rounding bias of the FP32 factors; fundamental
- * forms only (else FDTD_EUNSUPPORTED), nx, ny, nz <= 512, single-grid
- * plans only (fdtd_plan_batch returns FDTD_EUNSUPPORTED). */
+ * residual r - T V formed with the unrounded sigma, and a second solve with
+ * the same factors, all in FP32), which removes the fixed rounding bias of
+ * the FP32 factors and of 2 + sigma; fundamental forms only (else
+ * FDTD_EUNSUPPORTED), nx, ny, nz <= 512. */
 typedef enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_F32_F64SOLVE = 2, FDTD_F32_REFINE = 3 } fdtd_dtype;
 
 typedef struct {

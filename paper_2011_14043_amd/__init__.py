@@ -209,7 +209,7 @@ class BatchPlan(Plan):
     fundamental forms).  grids: list of (nx, ny, nz, eps_r or None)."""
 
     def __init__(self, grids, dt, dx, dy, dz, scheme="adi", dtype=None, stream=None, device=None,
-                 solve_dtype=None):
+                 solve_dtype=None, refine=False):
         import torch
         L = _lib.lib()
         self.dtype = dtype if dtype is not None else torch.float32
@@ -218,7 +218,9 @@ class BatchPlan(Plan):
         solve = solve_dtype if solve_dtype is not None else self.dtype
         if self.dtype == torch.float64 and solve != torch.float64:
             raise ValueError("float64 fields need float64 solves")
-        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else 0)
+        if refine and (self.dtype != torch.float32 or solve != torch.float32):
+            raise ValueError("refine applies to float32 fields with float32 solves")
+        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else (3 if refine else 0))
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.shapes = []
         keep = []

@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(NT) pass_yz_batch_kernel(const PassArgs<T, S>*
     const int vb = it.y * spb + (partial ? 0 : sub);
     // LDS holds ceil(Pmax / P) sub-block areas (the launch sizes it so), so the
     // leftover threads have an area of their own; they never store.
-    S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * 9 * a.P * (TX + 1);
+    constexpr int ROWS = (MODE == FUND_REF) ? 13 : 9;   // rows of P (TX + 1) per area
+    S* sm = reinterpret_cast<S*>(smem_raw) + (size_t)sub * ROWS * a.P * (TX + 1);
     const bool valid = !partial && vb < a.nblk;
     pass_yz_body<T, S, M, MODE, TX, NT, false, MAT>(a, valid ? vb : 0, threadIdx.x - sub * sub_n, sm, ctab, valid);
 }

@@ -867,6 +867,9 @@ static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
 }
 
 static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
+    // refined batched passes: 8-slot chunks (the 16-slot y/z variant does not fit
+    // its registers with the batch addressing)
+    if (p->refine && c.M != 8) return false;
     int Pmax = 1;
     for (const fdtd_plan_s* g : p->batch->subs) {
         if (!cfg_valid(g, axis, c)) return false;
@@ -919,7 +922,7 @@ static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const 
     }
     BatchPass bp;
     bp.op = op; bp.k = k; bp.frac = frac; bp.Pmax = Pmax;
-    bp.lds = (size_t)9 * lds_rows * (cf.TX + 1) * sizeof(S);
+    bp.lds = (size_t)(p->refine ? 13 : 9) * lds_rows * (cf.TX + 1) * sizeof(S);
     bp.nitems = (int)items.size();
     HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * n));
     hipError_t e = hipMalloc(&bp.items, sizeof(int2) * items.size());
@@ -935,8 +938,8 @@ static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const 
     return FDTD_OK;
 }
 
-template <typename T, typename S>
-static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
+template <typename T, typename S, int MODE>
+static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
     const int w = kPairs[bp.op][bp.k].w;
     const KCfg& cf = p->cfg[w];
     const bool mat = p->batch->mat;
@@ -946,11 +949,13 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
     if (w == 0) {
         const dim3 block(64 * cf.wpb);
         if (cf.M == 8) {
-            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, FUND, true>), grid, block, 0, st, tab, items);
-            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, FUND, false>), grid, block, 0, st, tab, items);
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, false>), grid, block, 0, st, tab, items);
+        } else if constexpr (MODE != FUND_REF) {
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, false>), grid, block, 0, st, tab, items);
         } else {
-            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, FUND, true>), grid, block, 0, st, tab, items);
-            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, FUND, false>), grid, block, 0, st, tab, items);
+            return FDTD_EUNSUPPORTED;
         }
     } else {
         const int M = cf.M, TX = cf.TX, NT = cf.NT;
@@ -958,10 +963,14 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
         const size_t lds = bp.lds;
 #define CASE_YZB(MM, TT, NN)                                                                                  \
     if (M == MM && TX == TT && NT == NN) {                                                                    \
-        if (mat)                                                                                              \
-            hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, FUND, TT, NN, true>), grid, block, lds, st, tab, items); \
-        else                                                                                                  \
-            hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, FUND, TT, NN, false>), grid, block, lds, st, tab, items); \
+        if constexpr (MODE != FUND_REF || MM == 8) {                                                          \
+            if (mat)                                                                                          \
+                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, items); \
+            else                                                                                              \
+                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, false>), grid, block, lds, st, tab, items); \
+        } else {                                                                                              \
+            return FDTD_EUNSUPPORTED;                                                                         \
+        }                                                                                                     \
     } else
         if constexpr (sizeof(S) == 4) {
             CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) CASE_YZB(8, 32, 512)
@@ -973,6 +982,13 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
     }
     HIPCHK(hipGetLastError());
     return FDTD_OK;
+}
+template <typename T, typename S>
+static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
+    if constexpr (sizeof(S) == 4) {
+        if (p->refine) return batch_launch_mode<T, S, FUND_REF>(p, bp, st);
+    }
+    return batch_launch_mode<T, S, FUND>(p, bp, st);
 }
 
 // One sub-step (operator op, theta = frac * dt) of every grid: three launches.
@@ -1459,7 +1475,7 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
         if (d[g].scheme < 0 || d[g].scheme > 3 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
             return FDTD_EINVAL;
     }
-    if (d[0].form != FDTD_FUNDAMENTAL || d[0].dtype == FDTD_F32_REFINE) return FDTD_EUNSUPPORTED;
+    if (d[0].form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
     fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
     if (!p) return FDTD_ENOMEM;
     p->batch = new (std::nothrow) Batch();
@@ -1469,6 +1485,10 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     }
     p->d = d[0];
     p->d.eps_r = nullptr;
+    if (d[0].dtype == FDTD_F32_REFINE) {
+        p->refine = 1;
+        p->d.dtype = FDTD_F32;
+    }
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
     p->esz = d[0].dtype == FDTD_F64 ? 8 : 4;

@@ -13,8 +13,8 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
-        "f32s64": (torch.float32, torch.float64)}
-TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
+        "f32s64": (torch.float32, torch.float64), "f32r": (torch.float32, torch.float32)}
+TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6, "f32r": 1e-5}
 
 
 def _fields(u0, dtype):
@@ -46,7 +46,7 @@ def small_refs():
     return dict(h=h, dt=dt, grids=grids, refs=refs)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
 def test_batch_vs_oracle_small(small_refs, scheme, prec):
     from paper_2011_14043_amd import BatchPlan
@@ -54,7 +54,7 @@ def test_batch_vs_oracle_small(small_refs, scheme, prec):
     dtype, solve = PREC[prec]
     print(f"[case] batch 5 grids {scheme}/{prec}", flush=True)
     plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in c["grids"]], c["dt"], c["h"],
-                     c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve)
+                     c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve, refine=prec == "f32r")
     fields = [_fields(u0, dtype) for (*_, u0) in c["grids"]]
     plan.run(fields, 10)
     torch.cuda.synchronize()
@@ -110,6 +110,9 @@ def test_batch_invalid():
     d[1].scheme = 1
     assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # mixed schemes
     d[1].scheme = 0
+    d[1].dtype = 3
+    assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # mixed precisions
+    d[1].dtype = 0
     d[1].nx = 1
     assert L.fdtd_plan_batch(d, 2, None, ctypes.byref(hnd)) == -1       # invalid grid
     assert L.fdtd_plan_batch(d, 0, None, ctypes.byref(hnd)) == -1
@@ -148,7 +151,7 @@ def cavities_single_f64(cavities):
     return out
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32s64", 2e-5), ("f32", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32s64", 2e-5), ("f32", 1e-4), ("f32r", 2e-5)])
 def test_64_cavities_vs_single_grid(cavities, cavities_single_f64, prec, tol):
     from paper_2011_14043_amd import BatchPlan
     h = 1e-3
@@ -156,7 +159,7 @@ def test_64_cavities_vs_single_grid(cavities, cavities_single_f64, prec, tol):
     dtype, solve = PREC[prec]
     print(f"[case] 64 cavities U[16,96], 500 steps, {prec}", flush=True)
     plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in cavities], dt, h, h, h,
-                     scheme="adi", dtype=dtype, solve_dtype=solve)
+                     scheme="adi", dtype=dtype, solve_dtype=solve, refine=prec == "f32r")
     plan.autotune(2)
     fields = [_fields(u0, dtype) for (*_, u0) in cavities]
     plan.run(fields, 500)
@@ -220,8 +223,9 @@ def test_graph_replays_match_eager_single_grids(small_refs):
         p.close()
 
 
+@pytest.mark.parametrize("refine", [False, True], ids=["f32", "f32r"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1"])
-def test_batch_bitwise_equals_single_grids(scheme):
+def test_batch_bitwise_equals_single_grids(scheme, refine):
     """Grids whose chunk counts are the same powers of two in both paths run
     the same arithmetic: the batch (graph replays, one launch per pass over
     all grids) equals the single-grid plans (eager) bit for bit."""
@@ -236,14 +240,14 @@ def test_batch_bitwise_equals_single_grids(scheme):
             p.set_kernel_config(ax, chunk=8, tile_x=16, block_threads=1024, remap=1)
 
     bp = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in grids], dt, h, h, h,
-                   scheme=scheme, dtype=torch.float32)
+                   scheme=scheme, dtype=torch.float32, refine=refine)
     configure(bp)
     fb = [_fields(u0, torch.float32) for (*_, u0) in grids]
     bp.run(fb, 6)
     torch.cuda.synchronize()
     bp.close()
     for (nx, ny, nz, eps, u0), (Eb, Hb) in zip(grids, fb):
-        p = Plan(nx, ny, nz, dt, h, h, h, scheme=scheme, dtype=torch.float32, eps_r=torch.tensor(eps))
+        p = Plan(nx, ny, nz, dt, h, h, h, scheme=scheme, dtype=torch.float32, eps_r=torch.tensor(eps), refine=refine)
         configure(p)
         E, H = _fields(u0, torch.float32)
         p.run(E, H, 6)
