@@ -13,14 +13,14 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
-        "f32s64": (torch.float32, torch.float64)}
+        "f32s64": (torch.float32, torch.float64), "f32r": (torch.float32, torch.float32)}
 
 
 def _plan(nx, ny, nz, dt, h, eps, prec, scheme="adi", form="fundamental"):
     from paper_2011_14043_amd import Plan
     dtype, solve = PREC[prec]
     return Plan(nx, ny, nz, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
-                eps_r=torch.tensor(np.asarray(eps, dtype=np.float32)))
+                eps_r=torch.tensor(np.asarray(eps, dtype=np.float32)), refine=prec == "f32r")
 
 
 def _fields(u0, prec):
@@ -51,10 +51,10 @@ def _tiny(seed, probe_at_source=False):
 
 # FP64 path: the same arithmetic up to rounding order; FP32 paths: rounding of
 # the stored fields and solves over 2 x 10 sub-steps (forward and adjoint).
-GRAD_TOL = {"f64": 1e-9, "f32s64": 2e-5, "f32": 2e-4}
+GRAD_TOL = {"f64": 1e-9, "f32s64": 2e-5, "f32": 2e-4, "f32r": 2e-4}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
 @pytest.mark.parametrize("seed,at_src", [(0, False), (1, True)])
 def test_gradient_vs_oracle_tiny(prec, seed, at_src):
     c = _tiny(seed, at_src)
@@ -186,7 +186,7 @@ def design_fd(design):
     return np.array(fd)
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 2e-5), ("f32s64", 1e-3), ("f32", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("f64", 2e-5), ("f32s64", 1e-3), ("f32", 1e-3), ("f32r", 1e-3)])
 def test_design_gradient_vs_central_fd(design, design_fd, prec, tol):
     d = design
     print(f"[case] adjoint 128x128x64 design box, 500 steps, {prec}", flush=True)
