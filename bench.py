@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources whose hash is recorded and the profiled y/z
 # configuration; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "d402bdb016f40571",
+    "kernel_hash": "aeb04688a3ef57bf",
     "config": [16, 32, 1024, 1],                             # chunk, tile_x, block_threads, remap (y and z)
-    "fetch_kib": {"y": 596547.8, "z": 596904.4},
+    "fetch_kib": {"y": 596655.0, "z": 596906.2},
     "write_kib": {"y": 1047552.0, "z": 1047552.0},
     "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
