@@ -188,9 +188,10 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
  * fdtd_plan; sizes, dt, dx, dy, dz and eps_r may differ; scheme, form and
  * dtype must be equal, else FDTD_EINVAL).  Every line pass of a sub-step
  * runs as ONE launch over all grids: the plan keeps a device table of the
- * grids' pass arguments and a work list of (grid, block) items, and one time
- * step of the main iteration is captured once as a HIP graph (on a private
- * stream) and replayed on `hip_stream`.  Per-grid state and eps_r as in
+ * grids' pass arguments and a work list of (grid, block) items, and eight time
+ * steps of the main iteration are captured once as a HIP graph (on a private
+ * stream) and replayed on `hip_stream` (remaining steps are launched
+ * directly).  Per-grid state and eps_r as in
  * fdtd_plan.  fdtd_autotune, fdtd_get/set_kernel_config (a configuration
  * must fit every grid), fdtd_set_timing/fdtd_last_timing (main_ms only) and
  * fdtd_destroy accept a batch plan; fdtd_run, fdtd_step and fdtd_grad_eps

@@ -1023,7 +1023,13 @@ static fdtd_status batch_tables(fdtd_plan_s* p) {
     return FDTD_OK;
 }
 
-// Capture one time step of the main iteration (all sub-steps) as a graph.
+// Time steps per captured graph.  A graph launch costs tens of microseconds
+// of host time and separates consecutive replays on the device, so one graph
+// holds several steps; a run replays it floor(steps / kGraphSteps) times and
+// launches the remaining steps directly.
+constexpr int kGraphSteps = 8;
+
+// Capture kGraphSteps time steps of the main iteration (all sub-steps) as a graph.
 template <typename T, typename S>
 static fdtd_status batch_graph(fdtd_plan_s* p) {
     Batch* b = p->batch;
@@ -1038,7 +1044,8 @@ static fdtd_status batch_graph(fdtd_plan_s* p) {
         fdtd_status s2 = batch_pass<T, S>(p, op, k, frac, &bp);
         return s2 == FDTD_OK ? batch_launch<T, S>(p, *bp, str) : s2;
     };
-    for (int u = 0; u < sd.nsub && st == FDTD_OK; ++u) {
+    for (int v = 0; v < kGraphSteps * sd.nsub && st == FDTD_OK; ++v) {
+        const int u = v % sd.nsub;
         const int op = sd.sub[u].op;
         const double frac = sd.sub[u].theta_frac;
         if (hipEventRecord(b->ev[0], b->cap) != hipSuccess || hipStreamWaitEvent(b->fork[0], b->ev[0], 0) != hipSuccess ||
@@ -1095,7 +1102,8 @@ static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H
         st = batch_substep<T, S>(p, 1, 0.25, p->stream);
         if (st != FDTD_OK) return st;
     }
-    const int ngraph = nsteps > 0 ? (adi ? nsteps - 1 : nsteps) : 0;
+    const int nmain = nsteps > 0 ? (adi ? nsteps - 1 : nsteps) : 0;   // steps of the plain main iteration
+    const int ngraph = nmain / kGraphSteps;
     if (ngraph > 0) {
         st = batch_graph<T, S>(p);
         if (st != FDTD_OK) return st;
@@ -1109,6 +1117,14 @@ static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H
     }
     HIPCHK(hipEventRecord(tm.main0, p->stream));
     for (int m = 0; m < ngraph; ++m) HIPCHK(hipGraphLaunch(b->exec, p->stream));
+    {
+        const SchemeDef& sd = kSchemes[d.scheme];
+        for (int m = ngraph * kGraphSteps; m < nmain; ++m)
+            for (int u = 0; u < sd.nsub; ++u) {
+                st = batch_substep<T, S>(p, sd.sub[u].op, sd.sub[u].theta_frac, p->stream);
+                if (st != FDTD_OK) return st;
+            }
+    }
     if (adi && nsteps > 0) {
         // last step: the state before the B sub-step is kept for the output
         st = batch_substep<T, S>(p, 0, 0.5, p->stream);

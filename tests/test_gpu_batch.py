@@ -198,22 +198,26 @@ def test_64_cavities_smallest_vs_oracle(cavities):
         assert err <= 1e-10
 
 
-def test_graph_replays_match_eager_single_grids(small_refs):
-    """LOD1 has no special last step, so every one-step batch call replays the
-    captured graph once between eager input/output kernels.  After each call
-    (synchronized) the batch equals the single-grid plans stepped eagerly."""
+@pytest.mark.parametrize("scheme", ["lod1", "adi"])
+def test_graph_replays_match_eager_single_grids(small_refs, scheme):
+    """A batch run replays the captured eight-step graph floor(steps / 8) times
+    (ADI: of steps - 1, the last step being special) and launches the rest
+    directly.  Calls of 9 steps (LOD1: one replay and one direct step; ADI:
+    one replay and the last step), with eager input/output kernels and a
+    synchronization between them: after each call the batch equals the
+    single-grid plans stepped eagerly."""
     from paper_2011_14043_amd import BatchPlan, Plan
     c = small_refs
     grids = [(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in c["grids"]]
-    bp = BatchPlan(grids, c["dt"], c["h"], c["h"], c["h"], scheme="lod1", dtype=torch.float64)
+    bp = BatchPlan(grids, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=torch.float64)
     fb = [_fields(u0, torch.float64) for (*_, u0) in c["grids"]]
-    singles = [Plan(nx, ny, nz, c["dt"], c["h"], c["h"], c["h"], scheme="lod1", dtype=torch.float64, eps_r=e)
+    singles = [Plan(nx, ny, nz, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=torch.float64, eps_r=e)
                for (nx, ny, nz, e) in grids]
     fs = [_fields(u0, torch.float64) for (*_, u0) in c["grids"]]
     for call in range(4):
-        bp.run(fb, 1)
+        bp.run(fb, 9)
         for p, (E, H) in zip(singles, fs):
-            p.run(E, H, 1)
+            p.run(E, H, 9)
         torch.cuda.synchronize()
         for (E1, H1), (E2, H2) in zip(fb, fs):
             for a, b in zip(E1 + H1, E2 + H2):
