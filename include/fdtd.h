@@ -191,7 +191,12 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
  * grids' pass arguments and a work list of (grid, block) items, and eight time
  * steps of the main iteration are captured once as a HIP graph (on a private
  * stream) and replayed on `hip_stream` (remaining steps are launched
- * directly).  Per-grid state and eps_r as in
+ * directly).  When the fields and media of all grids exceed 128 MiB, the
+ * grids are split into groups of consecutive grids of about equal size
+ * (each below that bound when possible), and fdtd_run_batch steps one group
+ * through all `nsteps` before the next, so that a group's arrays stay in the
+ * 256 MB on-die cache between passes; each group is then batched as above.
+ * Per-grid state and eps_r as in
  * fdtd_plan.  fdtd_autotune, fdtd_get/set_kernel_config (a configuration
  * must fit every grid), fdtd_set_timing/fdtd_last_timing (main_ms only) and
  * fdtd_destroy accept a batch plan; fdtd_run, fdtd_step and fdtd_grad_eps
