@@ -144,7 +144,9 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, t
 def run_batch(steps, warmup, prec="f32"):
     """64 independent PEC cavities, sizes U[16, 96] per axis (seed 4), random-box
     eps_r and N(0,1) fields per cavity, fundamental ADI, CFL 5: one launch per
-    line pass over all cavities, one captured graph per step."""
+    line pass over the cavities of a group (groups that fit the MALL), captured
+    graphs of eight steps.  Beside it, the same cavities stepped one after the
+    other through single-grid plans."""
     import numpy as np
     import torch
     import workloads as W
@@ -177,8 +179,27 @@ def run_batch(steps, warmup, prec="f32"):
     cells = int(sum(np.prod(sz) for sz in sizes))
     ms = (t1 - t0) * 1e3 / steps
     main_ms = tm["main_ms"] / steps
+    # the same cavities one after the other, each its own (autotuned) single-grid plan
+    from paper_2011_14043_amd import Plan
+    singles = []
+    for (nx, ny, nz, eps) in grids:
+        sp = Plan(nx, ny, nz, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve, eps_r=eps)
+        sp.autotune(1)
+        singles.append(sp)
+    for sp, (E, H) in zip(singles, fields):
+        sp.run(E, H, warmup)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for sp, (E, H) in zip(singles, fields):
+        sp.run(E, H, steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for sp in singles:
+        sp.close()
+    seq_ms = (t3 - t2) * 1e3 / steps
     out = dict(workload="64 cavities U[16,96]^3, fundamental ADI, CFL 5", prec=prec, cells=cells, steps=steps,
                ms_per_step=ms, mcells_per_s=cells / (ms * 1e-3) / 1e6, main_ms_per_step=main_ms,
+               sequential_single_ms_per_step=seq_ms, sequential_single_mcells_per_s=cells / (seq_ms * 1e-3) / 1e6,
                hbm_frac_alg=6 * cells * bytes_per_node(prec) / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                kernel_config=cfg, finite=finite)
     log(json.dumps(out))
