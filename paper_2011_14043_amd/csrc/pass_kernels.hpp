@@ -279,6 +279,7 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
 
     S ue[M], uh[M];
     SlotCoef<S> sc[M];
+    unsigned idp[(M + 3) / 4] = {};   // refined solves: material indices, 4 per word
     {
         T te[M], th[M];
         if (!FULL && j0 >= n) {
@@ -293,6 +294,8 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
                 ld_bytes<M>(make_rsrc(a.mat, wbase, a.comp, 1), lel, id);
 #pragma unroll
                 for (int i = 0; i < M; ++i) sc[i] = coef_from_tab<T, S, MODE>(a, ctab, id[i]);
+#pragma unroll
+                for (int i = 0; i < M; ++i) idp[i >> 2] |= id[i] << (8 * (i & 3));
             } else {
                 float ep[M];
                 ld_chunk<float, M>(rP, vo_e, ep);
@@ -386,38 +389,55 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
             for (int i = 0; i < M; ++i) fixed |= (j0 + i >= n) ? (1u << i) : 0u;
         }
         const S pre = src_wave ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
-        auto rhs = [&](int i) -> S {
+        // coefficients: from the LDS table again (material index) rather than kept
+        auto coef = [&](int i) -> SlotCoef<S> {
+            if constexpr (MAT) {
+                if (!FULL && j0 >= n) return SlotCoef<S>{S(0), S(2)};
+                return coef_from_tab<T, S, MODE>(a, ctab, (idp[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+            } else {
+                return sc[i];
+            }
+        };
+        auto rhs = [&](int i, S c) -> S {
             const S dh = uh[i] - ((i == 0) ? uh_m_eff : uh[i - 1]);
-            S rr = fused(sc[i].c, ue[i], fused(dh, a.kap_lo, dh * a.kap_hi));
-            rr = (src_here && i == si) ? fused(sc[i].c, pre, rr) : rr;
+            S rr = fused(c, ue[i], fused(dh, a.kap_lo, dh * a.kap_hi));
+            rr = (src_here && i == si) ? fused(c, pre, rr) : rr;
             return ((fixed >> i) & 1u) ? S(0) : rr;
         };
         S g[M - 1], d[M];
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) {
-            const S dgi = ((fixed >> i) & 1u) ? Big<S>::v : sc[i].d;
+            const SlotCoef<S> sci = coef(i);
+            const S dgi = ((fixed >> i) & 1u) ? Big<S>::v : sci.d;
             g[i] = recip(i == 0 ? dgi : dgi - g[i - 1]);
-            d[i] = rhs(i);
+            d[i] = rhs(i, sci.c);
         }
         const S y0 = rsweep<S, M>(g, d);
         S a0, pL;
         rinfluence<S, M>(g, a0, pL);
-        const S dgS = ((fixed >> (M - 1)) & 1u) ? Big<S>::v : sc[M - 1].d;
+        const SlotCoef<S> scS = coef(M - 1);
+        const S dgS = ((fixed >> (M - 1)) & 1u) ? Big<S>::v : scS.d;
         const S a0n_r = __shfl_down(a0, 1, P), g0n_r = __shfl_down(pL, 1, P);
         const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0);
         S Sl, Sp, xn;
-        separators(pL, g[M - 2], d[M - 2], dgS, rhs(M - 1), a0n, g0n, y0, Sl, Sp, xn);
+        separators(pL, g[M - 2], d[M - 2], dgS, rhs(M - 1, scS.c), a0n, g0n, y0, Sl, Sp, xn);
         rvalues<S, M>(g, d, Sp, Sl);
+#pragma unroll
+        for (int i = 0; i < M; ++i) asm volatile("" : "+v"(uh[i]));
         S rho[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) {
+            const SlotCoef<S> sci = coef(i);
             const S vm = (i == 0) ? Sp : d[i - 1];
             const S vp = (i == M - 1) ? xn : d[i + 1];
-            const S res = fused(S(-0.5) * sc[i].c, d[i], rhs(i)) + ((vm - d[i]) + (vp - d[i]));
+            const S res = fused(S(-0.5) * sci.c, d[i], rhs(i, sci.c)) + ((vm - d[i]) + (vp - d[i]));
             rho[i] = ((fixed >> i) & 1u) ? S(0) : res;
             eo[i] = d[i] - ue[i];
             ho[i] = fused(a.q, vp - d[i], uh[i]);
         }
+        // first outputs and the residual are final here (see the y/z lines)
+#pragma unroll
+        for (int i = 0; i < M; ++i) asm volatile("" : "+v"(eo[i]), "+v"(ho[i]), "+v"(rho[i]));
         const S rS = rho[M - 1];
         const S y0c = rsweep<S, M>(g, rho);
         S dSl, dSp, dxn;
