@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources whose hash is recorded and the profiled y/z
 # configuration; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "aeb04688a3ef57bf",
+    "kernel_hash": "f287126b152eafc0",
     "config": [16, 32, 1024, 1],                             # chunk, tile_x, block_threads, remap (y and z)
-    "fetch_kib": {"y": 596655.0, "z": 596906.2},
+    "fetch_kib": {"y": 596607.8, "z": 596817.0},
     "write_kib": {"y": 1047552.0, "z": 1047552.0},
     "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
@@ -308,6 +308,10 @@ def main():
     if not args.no_extras:
         extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
         extras["adjoint_gradient"] = run_adjoint()
+        # the smaller size of the same workload (256^3), plain and refined FP32
+        in256 = make_inputs(256)
+        extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256)
+                                             for prec in ("f32", "f32r")]
     if args.variants != "none":
         todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32r"), ("adi", "fundamental", "f32s64"),
                 ("adi", "conventional", "f32s64"),
