@@ -13,6 +13,15 @@ struct Dims {
     long long cplane, ccomp;     // caller: plane pitch, component size (nx+1)(ny+1)(nz+1)
 };
 
+// Node (i, j, k) of flat node index idx (x fastest).  Node counts stay below
+// 2^32 (at most 1025^3), so 32-bit division suffices.
+struct Node { int i, j, k; };
+__device__ __forceinline__ Node node_of(unsigned idx, const Dims& d) {
+    const unsigned nx1 = unsigned(d.nx + 1), ny1 = unsigned(d.ny + 1);
+    const unsigned t = idx / nx1;
+    return Node{int(idx - t * nx1), int(t % ny1), int(t / ny1)};
+}
+
 // Is component c (0..5 = Ex Ey Ez Hx Hy Hz) dynamic / inside the box at node (i, j, k)?
 __device__ __forceinline__ bool is_dynamic(int c, int i, int j, int k, const Dims& d) {
     switch (c) {
@@ -48,25 +57,25 @@ __device__ __forceinline__ T phys(const FieldPtrs<T>& f, int c, int i, int j, in
     return ok ? f.c[c][(long long)k * d.cplane + (long long)j * (d.nx + 1) + i] : T(0);
 }
 
+struct AuxCoef {
+    double eps0, mu0;
+    double rmu0, rdx, rdy, rdz;   // 1/mu0, 1/dx, 1/dy, 1/dz (formed on the host)
+    double link;                  // ADI: dt/4 (state = 1/2 u + dt/4 B u); 0 for a plain copy
+};
+
 // (B u)_c at a node, operator B of eq. (AMat) with Yee central differences.
-// inv_eps = 1/(eps0 eps_r) at the node; inv_mu = 1/mu0.
+// inv_eps = 1/(eps0 eps_r) at the node.
 template <typename T, typename F>
-__device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, double inv_eps, double inv_mu,
-                                          double dx, double dy, double dz) {
+__device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, double inv_eps, const AuxCoef& q) {
     switch (c) {
-        case 0: return -inv_eps * (double(get(4, i, j, k)) - double(get(4, i, j, k - 1))) / dz;   // -dHy/dz
-        case 1: return -inv_eps * (double(get(5, i, j, k)) - double(get(5, i - 1, j, k))) / dx;   // -dHz/dx
-        case 2: return -inv_eps * (double(get(3, i, j, k)) - double(get(3, i, j - 1, k))) / dy;   // -dHx/dy
-        case 3: return -inv_mu * (double(get(2, i, j + 1, k)) - double(get(2, i, j, k))) / dy;    // -dEz/dy
-        case 4: return -inv_mu * (double(get(0, i, j, k + 1)) - double(get(0, i, j, k))) / dz;    // -dEx/dz
-        default: return -inv_mu * (double(get(1, i + 1, j, k)) - double(get(1, i, j, k))) / dx;   // -dEy/dx
+        case 0: return -inv_eps * (double(get(4, i, j, k)) - double(get(4, i, j, k - 1))) * q.rdz;   // -dHy/dz
+        case 1: return -inv_eps * (double(get(5, i, j, k)) - double(get(5, i - 1, j, k))) * q.rdx;   // -dHz/dx
+        case 2: return -inv_eps * (double(get(3, i, j, k)) - double(get(3, i, j - 1, k))) * q.rdy;   // -dHx/dy
+        case 3: return -q.rmu0 * (double(get(2, i, j + 1, k)) - double(get(2, i, j, k))) * q.rdy;    // -dEz/dy
+        case 4: return -q.rmu0 * (double(get(0, i, j, k + 1)) - double(get(0, i, j, k))) * q.rdz;    // -dEx/dz
+        default: return -q.rmu0 * (double(get(1, i + 1, j, k)) - double(get(1, i, j, k))) * q.rdx;   // -dEy/dx
     }
 }
-
-struct AuxCoef {
-    double eps0, mu0, dx, dy, dz;
-    double link;   // ADI: dt/4 (state = 1/2 u + dt/4 B u); 0 for a plain copy
-};
 
 // Input processing: caller fields -> state.  link != 0: the ADI/LOD1 link
 // U = (1/2 I + dt/4 B) u (Sec. II-E); else U = u.  Non-dynamic E -> 0.
@@ -75,20 +84,18 @@ __global__ void load_state_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* 
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     if (idx >= nn) return;
-    const int i = int(idx % (d.nx + 1));
-    const int j = int((idx / (d.nx + 1)) % (d.ny + 1));
-    const int k = int(idx / ((long long)(d.nx + 1) * (d.ny + 1)));
+    const Node nd = node_of(unsigned(idx), d);
+    const int i = nd.i, j = nd.j, k = nd.k;
     const long long so = (long long)k * d.plane + (long long)j * d.px + i;
     auto get = [&](int c, int ii, int jj, int kk) { return phys<T>(f, c, ii, jj, kk, d); };
     const double inv_eps = 1.0 / (k_.eps0 * double(eps[so]));
-    const double inv_mu = 1.0 / k_.mu0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         const double u = double(get(c, i, j, k));
         double v = u;
         if (k_.link != 0.0) {
             const bool dyn = is_dynamic(c, i, j, k, d);
-            const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, inv_mu, k_.dx, k_.dy, k_.dz) : 0.0;
+            const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, k_) : 0.0;
             v = 0.5 * u + k_.link * bu;
         }
         s.c[c][so] = T(v);
@@ -105,9 +112,8 @@ __global__ void store_state_kernel(FieldPtrs<T> s, FieldPtrs<T> s_old, FieldPtrs
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     if (idx >= nn) return;
-    const int i = int(idx % (d.nx + 1));
-    const int j = int((idx / (d.nx + 1)) % (d.ny + 1));
-    const int k = int(idx / ((long long)(d.nx + 1) * (d.ny + 1)));
+    const Node nd = node_of(unsigned(idx), d);
+    const int i = nd.i, j = nd.j, k = nd.k;
     const long long so = (long long)k * d.plane + (long long)j * d.px + i;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -133,9 +139,8 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
     double acc = 0.0;
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
          idx += (long long)gridDim.x * blockDim.x) {
-        const int i = int(idx % (d.nx + 1));
-        const int j = int((idx / (d.nx + 1)) % (d.ny + 1));
-        const int k = int(idx / ((long long)(d.nx + 1) * (d.ny + 1)));
+        const Node nd = node_of(unsigned(idx), d);
+        const int i = nd.i, j = nd.j, k = nd.k;
         const long long so = (long long)k * d.plane + (long long)j * d.px + i;
         const double ew = k_.eps0 * double(eps[so]);
         if (k_.link == 0.0) {
@@ -149,12 +154,12 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
                 if (ii < 0 || jj < 0 || kk < 0 || ii > d.nx || jj > d.ny || kk > d.nz) return T(0);
                 return s.c[c][(long long)kk * d.plane + (long long)jj * d.px + ii];
             };
-            const double inv_eps = 1.0 / ew, inv_mu = 1.0 / k_.mu0;
+            const double inv_eps = 1.0 / ew;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const double u = double(get(c, i, j, k));
                 const bool dyn = is_dynamic(c, i, j, k, d);
-                const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, inv_mu, k_.dx, k_.dy, k_.dz) : 0.0;
+                const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, k_) : 0.0;
                 const double v = 0.5 * u + k_.link * bu;
                 acc += (c < 3 ? ew : k_.mu0) * v * v;
             }

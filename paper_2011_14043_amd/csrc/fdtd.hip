@@ -234,6 +234,11 @@ static Inject source_inject(const fdtd_plan_s* p, const fdtd_source* src, double
     return in;
 }
 
+// Coefficients of the input/output and energy kernels (reciprocals formed here).
+static AuxCoef aux_coef(const fdtd_desc& d, double link) {
+    return AuxCoef{kEps0, kMu0, 1.0 / kMu0, 1.0 / d.dx, 1.0 / d.dy, 1.0 / d.dz, link};
+}
+
 template <typename T>
 static T* set_ptr(fdtd_plan_s* p, int set) {
     return reinterpret_cast<T*>(p->state) + (size_t)set * 6 * p->dims.comp;
@@ -584,7 +589,7 @@ static FieldPtrsW<T> state_ptrs_w(fdtd_plan_s* p, int set) {
 
 template <typename T>
 static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst) {
-    AuxCoef k{kEps0, kMu0, p->d.dx, p->d.dy, p->d.dz, 0.0};
+    AuxCoef k = aux_coef(p->d, 0.0);
     if (p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL) k.link = 0.25 * p->d.dt;
     hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
                        state_ptrs<T>(p, set), p->eps, p->dims, k, p->partial);
@@ -620,7 +625,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
         p->energy_cap = nrec;
     }
     // input processing
-    AuxCoef kin{kEps0, kMu0, d.dx, d.dy, d.dz, (adi && !conv) ? 0.25 * d.dt : 0.0};
+    const AuxCoef kin = aux_coef(d, (adi && !conv) ? 0.25 * d.dt : 0.0);
     hipLaunchKernelGGL((load_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
                        p->eps, dm, kin);
     HIPCHK(hipGetLastError());
@@ -771,7 +776,7 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
     } while (0)
 
     // forward sweep: J, checkpoints every K steps
-    AuxCoef kin{kEps0, kMu0, d.dx, d.dy, d.dz, 0.25 * d.dt};
+    const AuxCoef kin = aux_coef(d, 0.25 * d.dt);
     hipLaunchKernelGGL((load_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
                        p->eps, dm, kin);
     HIPCHK(hipGetLastError());
@@ -1105,7 +1110,7 @@ static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H
         fdtd_plan_s* sub = b->subs[g];
         const Dims& dm = sub->dims;
         const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
-        AuxCoef kin{kEps0, kMu0, sub->d.dx, sub->d.dy, sub->d.dz, adi ? 0.25 * sub->d.dt : 0.0};
+        const AuxCoef kin = aux_coef(sub->d, adi ? 0.25 * sub->d.dt : 0.0);
         hipLaunchKernelGGL((load_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
                            caller(g), state_ptrs_w<T>(sub, 0), sub->eps, dm, kin);
         HIPCHK(hipGetLastError());

@@ -32,6 +32,17 @@ template <typename T> struct Big;
 template <> struct Big<float> { static constexpr float v = 1.2676506e30f; };   // 2^100
 template <> struct Big<double> { static constexpr double v = 1.2676506002282294e30; };
 
+// a * b + c with one rounding.  Written out where the result must not depend
+// on which multiply-adds the compiler chooses to fuse (that choice can differ
+// between kernels that inline the same code).
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a * b rounded once and never fused into a later addition (an FMA with a zero
+// addend): a product that several expressions use then rounds the same way in
+// every kernel, whichever uses the compiler would otherwise have fused.
+__device__ __forceinline__ float sealed_mul(float a, float b) { return __builtin_fmaf(a, b, 0.0f); }
+__device__ __forceinline__ double sealed_mul(double a, double b) { return __builtin_fma(a, b, 0.0); }
+
 // Reciprocal of a positive normal number (pivots, diagonals): the hardware
 // estimate refined by Newton-Raphson steps r <- r + r (1 - x r), one for FP32
 // and two for FP64 (each step squares the relative error), which ends within
@@ -131,11 +142,13 @@ __device__ __forceinline__ T pcr_wave(Row<T> w, int ls, int P) {
         Row<T> n;
         n.A = hm ? -k1 * Am : T(0);
         n.C = hp ? -k2 * Cp : T(0);
-        n.B = w.B - (hm ? k1 * Cm : T(0)) - (hp ? k2 * Ap : T(0));
-        n.D = w.D - (hm ? k1 * Dm : T(0)) - (hp ? k2 * Dp : T(0));
+        const T b1 = hm ? fused(-k1, Cm, w.B) : w.B;
+        const T d1 = hm ? fused(-k1, Dm, w.D) : w.D;
+        n.B = hp ? fused(-k2, Ap, b1) : b1;
+        n.D = hp ? fused(-k2, Dp, d1) : d1;
         w = n;
     }
-    return w.D * recip(w.B);
+    return sealed_mul(w.D, recip(w.B));
 }
 
 // Final values of one chunk given S_{l-1} (Sp), S_l (S) and the first slot of
@@ -162,9 +175,6 @@ __device__ __forceinline__ void chunk_finish(const Chunk<T, M>& c, T Sp, T S, T 
 // then a second solve T dV = rho with the same factors -- takes that bias to
 // second order; what is left is rounding that changes from step to step.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
 // A refined chunk keeps only the inverse pivots g of its interior rows.  With
 // p_k = g_0 ... g_k (p_{-1} = 1), the values the separator rows need follow
 // from forward sweeps alone:  alpha_{M-2} = gamma_0 = p_{M-2},
@@ -176,11 +186,11 @@ __device__ __forceinline__ double fused(double a, double b, double c) { return _
 // on entry): d_i <- (d_i + d_{i-1}) g_i.  Returns y_0.
 template <typename T, int M>
 __device__ __forceinline__ T rsweep(const T (&g)[M - 1], T (&d)[M]) {
-    d[0] = d[0] * g[0];
+    d[0] = sealed_mul(d[0], g[0]);
     T p = g[0], y0 = d[0];
 #pragma unroll
     for (int i = 1; i < M - 1; ++i) {
-        d[i] = (d[i] + d[i - 1]) * g[i];
+        d[i] = sealed_mul(d[i] + d[i - 1], g[i]);
         y0 = fused(p, d[i], y0);
         p = p * g[i];
     }

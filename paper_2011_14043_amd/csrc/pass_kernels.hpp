@@ -375,7 +375,7 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
         const S Sp_r = __shfl_up(Sl, 1, P), Sn_r = __shfl_down(Sl, 1, P);
         Sp = (ls > 0) ? Sp_r : S(0);
         const S Sn = has_next ? Sn_r : S(0);
-        xn = y0n + a0n * Sl + g0n * Sn;
+        xn = fused(g0n, Sn, fused(a0n, Sl, y0n));
     };
 
     S eo[M], ho[M];
@@ -641,7 +641,7 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
         Sl = SBs(set, p, tx);
         Sp = first ? S(0) : SBs(set, p - 1, tx);
         const S Sn = hn ? SBs(set, pn, tx) : S(0);
-        xn = hn ? EPs(set, 2, pn, tx) + EPs(set, 0, pn, tx) * Sl + EPs(set, 1, pn, tx) * Sn : S(0);
+        xn = hn ? fused(EPs(set, 1, pn, tx), Sn, fused(EPs(set, 0, pn, tx), Sl, EPs(set, 2, pn, tx))) : S(0);
     };
 
     S eo[M], ho[M];
