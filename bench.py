@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources whose hash is recorded and the profiled y/z
 # configuration; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "f287126b152eafc0",
+    "kernel_hash": "d82b047710e89874",
     "config": [16, 32, 1024, 1],                             # chunk, tile_x, block_threads, remap (y and z)
-    "fetch_kib": {"y": 596607.8, "z": 596817.0},
+    "fetch_kib": {"y": 596611.0, "z": 596813.5},
     "write_kib": {"y": 1047552.0, "z": 1047552.0},
     "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
