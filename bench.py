@@ -93,7 +93,13 @@ def pass_nodes(n):
     return n * (n - 1) * n
 
 
-def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=True, tune=True, tune_reps=5):
+# HIP events bracket every line pass of every TIMING_EVERY-th step of a timed
+# run (each event pair costs a few microseconds between launches; on every
+# step they slow the 512^3 step by 1.5 %).
+TIMING_EVERY = 8
+
+
+def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5):
     import torch
     from paper_2011_14043_amd import Plan, Source
     h, dt, eps, ci = inputs

@@ -122,11 +122,14 @@ fdtd_status fdtd_set_step(fdtd_plan_t p, long long n);
 /* Timing of the most recent fdtd_run (synchronizes the plan's stream).
  * main_ms: milliseconds between HIP events recorded on the plan's stream
  * around the main iterations (input/output processing excluded).
- * If per-launch timing was enabled with fdtd_set_timing(p, 1) before the run,
- * HIP events bracket every line pass on the plan's stream and
- * pass_ms_avg[f] / pass_launches[f] give the mean duration [ms] and count of
- * the launches of family f (0 = y/z-line passes, 1 = x-line passes);
- * otherwise both are 0.  Either output pointer may be NULL (arrays of 2). */
+ * fdtd_set_timing(p, k), k >= 1, before the run: HIP events bracket every
+ * line pass of every k-th main-iteration step (steps 0, k, 2k, ...; k = 1:
+ * every step) on the plan's stream, and pass_ms_avg[f] / pass_launches[f]
+ * give the mean duration [ms] and count of the bracketed launches of family
+ * f (0 = y/z-line passes, 1 = x-line passes); k = 0 (the default): no
+ * per-launch events, both are 0.  k < 0: FDTD_EINVAL.  Either output pointer
+ * may be NULL (arrays of 2).  Each event pair adds a few microseconds between
+ * launches. */
 fdtd_status fdtd_set_timing(fdtd_plan_t p, int per_launch);
 fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* pass_ms_avg, int* pass_launches);
 

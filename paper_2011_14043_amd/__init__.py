@@ -125,8 +125,11 @@ class Plan:
     def set_step(self, n: int):
         _lib.check(_lib.lib().fdtd_set_step(self._h, int(n)), "fdtd_set_step")
 
-    def set_timing(self, per_launch: bool):
-        _lib.check(_lib.lib().fdtd_set_timing(self._h, 1 if per_launch else 0), "fdtd_set_timing")
+    def set_timing(self, per_launch):
+        """per_launch: False/0 off, True/1 every step, k >= 1 every k-th step
+        (HIP events around each line pass of those steps)."""
+        k = int(per_launch) if not isinstance(per_launch, bool) else (1 if per_launch else 0)
+        _lib.check(_lib.lib().fdtd_set_timing(self._h, k), "fdtd_set_timing")
 
     def last_timing(self):
         """{'main_ms', 'yz_ms_avg', 'x_ms_avg', 'yz_launches', 'x_launches'}."""

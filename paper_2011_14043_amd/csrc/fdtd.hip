@@ -62,7 +62,7 @@ static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {3
 static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
 
 struct Timing {
-    bool per_launch = false;
+    int per_launch = 0;           // 0: off; k >= 1: every launch of every k-th main-loop step
     hipEvent_t main0 = nullptr, main1 = nullptr;
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<int> fam;         // family of each pair (0 = yz lines, 1 = x lines)
@@ -663,7 +663,8 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
                                       hipMemcpyDeviceToDevice, p->stream));
             }
             const Inject inj = source_inject(p, src, g, mode);
-            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, tm.per_launch);
+            const bool timed = tm.per_launch > 0 && n % tm.per_launch == 0;
+            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, timed);
             if (st != FDTD_OK) return st;
             if (ss.op == 1) last_b_g = g;
         }
@@ -1391,10 +1392,10 @@ fdtd_status fdtd_set_step(fdtd_plan_t p, long long n) {
 }
 
 fdtd_status fdtd_set_timing(fdtd_plan_t p, int per_launch) {
-    if (!plan_ok(p)) return FDTD_EINVAL;
-    p->tm.per_launch = per_launch != 0;
+    if (!plan_ok(p) || per_launch < 0) return FDTD_EINVAL;
+    p->tm.per_launch = per_launch;
     if (p->batch)
-        for (fdtd_plan_s* c : p->batch->groups) c->tm.per_launch = per_launch != 0;
+        for (fdtd_plan_s* c : p->batch->groups) c->tm.per_launch = per_launch;
     return FDTD_OK;
 }
 

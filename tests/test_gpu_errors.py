@@ -1,5 +1,6 @@
-"""Error paths that need a plan on the device: non-finite fields are reported
-after stepping (FDTD_ENONFINITE), and the plan stays usable afterwards."""
+"""Paths that need a plan on the device: non-finite fields are reported after
+stepping (FDTD_ENONFINITE) and the plan stays usable afterwards; sampled
+per-launch timing."""
 import numpy as np
 import pytest
 
@@ -29,3 +30,34 @@ def test_nonfinite_fields_reported(dtype):
     tr = plan.run(E, H, 2, energy_every=1)
     plan.close()
     assert np.all(np.isfinite(tr))
+
+
+@pytest.mark.parametrize("every,steps", [(1, 5), (4, 9), (8, 3)])
+def test_sampled_launch_timing(every, steps):
+    """fdtd_set_timing(p, k) brackets the line passes of main-iteration steps
+    0, k, 2k, ...: ADI has 4 y/z and 2 x passes per step; a timed run does not
+    change the fields; k < 0 is rejected."""
+    from paper_2011_14043_amd import FdtdError, Plan
+    nx, ny, nz, h = 20, 18, 16, 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    u0 = W.random_fields(nx, ny, nz, seed=2)
+    fields = lambda: ([torch.tensor(a, dtype=torch.float32, device=DEV) for a in u0[:3]],
+                      [torch.tensor(a, dtype=torch.float32, device=DEV) for a in u0[3:]])
+    plan = Plan(nx, ny, nz, dt, h, h, h)
+    E0, H0 = fields()
+    plan.run(E0, H0, steps)
+    plan.set_timing(every)
+    E, H = fields()
+    plan.run(E, H, steps)
+    tm = plan.last_timing()
+    timed = len(range(0, steps, every))
+    assert tm["yz_launches"] == 4 * timed and tm["x_launches"] == 2 * timed
+    assert tm["yz_ms_avg"] > 0 and tm["x_ms_avg"] > 0 and tm["main_ms"] > 0
+    for a, b in zip(E + H, E0 + H0):
+        assert torch.equal(a, b)
+    plan.set_timing(0)
+    plan.run(E, H, 1)
+    assert plan.last_timing()["yz_launches"] == 0
+    with pytest.raises(FdtdError):
+        plan.set_timing(-1)
+    plan.close()
