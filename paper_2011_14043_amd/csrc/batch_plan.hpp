@@ -1,0 +1,392 @@
+// batch_plan.hpp -- batch plans: pass tables and work lists, launches, captured step
+// graphs, groups sized to the MALL, batch autotuning
+//
+// Part of the single translation unit of libfdtd.so: included by fdtd.hip
+// after the kernel headers and the headers before it in fdtd.hip.
+#pragma once
+
+namespace fdtd {
+
+// ---------------------------------------------------------------------------
+// batch plans
+// ---------------------------------------------------------------------------
+static void batch_clear(Batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (BatchPass& bp : b->passes) {
+        if (bp.tab) (void)hipFree(bp.tab);
+        if (bp.items) (void)hipFree(bp.items);
+    }
+    b->passes.clear();
+}
+
+// Chunks per line of a grid in a batched pass: a power of two (the separator
+// solve runs over segments of P lanes), for y/z lines at least 64/TX so that a
+// sub-block of TX * P threads is whole waves.  (Chunk counts rounded only to
+// a multiple of 64/TX, with a serial separator solve, were measured slower.)
+static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
+    const int P = next_pow2((axis_cells(g->dims, axis) + c.M - 1) / c.M);
+    return axis == 0 ? P : std::max(P, 64 / c.TX);
+}
+
+static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
+    // refined batched passes: 8-slot chunks (the 16-slot y/z variant does not fit
+    // its registers with the batch addressing)
+    if (p->refine && c.M != 8) return false;
+    int Pmax = 1;
+    for (const fdtd_plan_s* g : p->batch->subs) {
+        if (!cfg_valid(g, axis, c)) return false;
+        Pmax = std::max(Pmax, batch_P(g, axis, c));
+    }
+    if (Pmax > 64) return false;
+    return axis == 0 || c.TX * Pmax <= c.NT;
+}
+
+static void batch_default_cfg(fdtd_plan_s* p) {
+    for (int axis = 0; axis < 3; ++axis) {
+        std::vector<KCfg> pref;
+        if (axis == 0) pref = {{8, 0, 0, 4, 0}, {16, 0, 0, 4, 0}};
+        else if (p->d.dtype == FDTD_F32) pref = {{8, 16, 1024, 0, 0}, {16, 32, 1024, 0, 0}, {16, 16, 512, 0, 0}, {32, 16, 512, 0, 0}};
+        else pref = {{8, 8, 512, 0, 0}, {16, 16, 512, 0, 0}};
+        for (const KCfg& c : pref)
+            if (batch_cfg_valid(p, axis, c)) { p->cfg[axis] = c; break; }
+    }
+}
+
+// The table of pass (op, k) with theta = frac * dt for every grid (built on
+// first use with the current kernel configuration).
+template <typename T, typename S>
+static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const BatchPass** out) {
+    Batch* b = p->batch;
+    for (const BatchPass& bp : b->passes)
+        if (bp.op == op && bp.k == k && bp.frac == frac) { *out = &bp; return FDTD_OK; }
+    const int w = kPairs[op][k].w;
+    const KCfg& cf = p->cfg[w];
+    const int n = (int)b->subs.size();
+    std::vector<PassArgs<T, S>> tab(n);
+    int Pmax = 1;
+    for (int g = 0; g < n; ++g) {
+        fdtd_plan_s* sub = b->subs[g];
+        sub->cfg[w] = cf;
+        PassShape sh;
+        build_pass<T, S>(sub, op, k, frac * sub->d.dt, FUND, set_ptr<T>(sub, 0), set_ptr<T>(sub, 0), nullptr,
+                         tab[g], sh);
+        tab[g].P = batch_P(sub, w, cf);
+        tab[g].remap = 0;
+        Pmax = std::max(Pmax, tab[g].P);
+    }
+    std::vector<int2> items;
+    int lds_rows = 0;   // y/z: sub-block areas x chunks, the most any grid needs
+    for (int g = 0; g < n; ++g) {
+        const int per = (w == 0) ? 1 : Pmax / tab[g].P;   // virtual blocks per block
+        const int nit = (tab[g].nblk + per - 1) / per;
+        for (int q = 0; q < nit; ++q) items.push_back(make_int2(g, q));
+        if (w != 0) lds_rows = std::max(lds_rows, ((Pmax + tab[g].P - 1) / tab[g].P) * tab[g].P);
+    }
+    BatchPass bp;
+    bp.op = op; bp.k = k; bp.frac = frac; bp.Pmax = Pmax;
+    bp.lds = (size_t)(p->refine ? 13 : 9) * lds_rows * (cf.TX + 1) * sizeof(S);
+    bp.nitems = (int)items.size();
+    HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * n));
+    hipError_t e = hipMalloc(&bp.items, sizeof(int2) * items.size());
+    if (e == hipSuccess) e = hipMemcpy(bp.tab, tab.data(), sizeof(PassArgs<T, S>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bp.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(bp.tab);
+        if (bp.items) (void)hipFree(bp.items);
+        return from_hip(e);
+    }
+    b->passes.push_back(bp);
+    *out = &b->passes.back();
+    return FDTD_OK;
+}
+
+template <typename T, typename S, int MODE>
+static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
+    const int w = kPairs[bp.op][bp.k].w;
+    const KCfg& cf = p->cfg[w];
+    const bool mat = p->batch->mat;
+    const auto* tab = static_cast<const PassArgs<T, S>*>(bp.tab);
+    const auto* items = static_cast<const int2*>(bp.items);
+    const dim3 grid((unsigned)bp.nitems);
+    if (w == 0) {
+        const dim3 block(64 * cf.wpb);
+        if (cf.M == 8) {
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, false>), grid, block, 0, st, tab, items);
+        } else if constexpr (MODE != FUND_REF) {
+            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, true>), grid, block, 0, st, tab, items);
+            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, false>), grid, block, 0, st, tab, items);
+        } else {
+            return FDTD_EUNSUPPORTED;
+        }
+    } else {
+        const int M = cf.M, TX = cf.TX, NT = cf.NT;
+        const dim3 block(TX * bp.Pmax);
+        const size_t lds = bp.lds;
+#define CASE_YZB(MM, TT, NN)                                                                                  \
+    if (M == MM && TX == TT && NT == NN) {                                                                    \
+        if constexpr (MODE != FUND_REF || MM == 8) {                                                          \
+            if (mat)                                                                                          \
+                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, items); \
+            else                                                                                              \
+                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, false>), grid, block, lds, st, tab, items); \
+        } else {                                                                                              \
+            return FDTD_EUNSUPPORTED;                                                                         \
+        }                                                                                                     \
+    } else
+        if constexpr (sizeof(S) == 4) {
+            CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) CASE_YZB(8, 32, 512)
+            return FDTD_EUNSUPPORTED;
+        } else {
+            CASE_YZB(16, 16, 512) CASE_YZB(8, 8, 512) CASE_YZB(8, 16, 1024) return FDTD_EUNSUPPORTED;
+        }
+#undef CASE_YZB
+    }
+    HIPCHK(hipGetLastError());
+    return FDTD_OK;
+}
+template <typename T, typename S>
+static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
+    if constexpr (sizeof(S) == 4) {
+        if (p->refine) return batch_launch_mode<T, S, FUND_REF>(p, bp, st);
+    }
+    return batch_launch_mode<T, S, FUND>(p, bp, st);
+}
+
+// One sub-step (operator op, theta = frac * dt) of every grid: three launches.
+template <typename T, typename S>
+static fdtd_status batch_substep(fdtd_plan_s* p, int op, double frac, hipStream_t st) {
+    for (int k = 0; k < 3; ++k) {
+        const BatchPass* bp = nullptr;
+        fdtd_status s = batch_pass<T, S>(p, op, k, frac, &bp);
+        if (s != FDTD_OK) return s;
+        s = batch_launch<T, S>(p, *bp, st);
+        if (s != FDTD_OK) return s;
+    }
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status batch_tables(fdtd_plan_s* p) {
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    for (int u = 0; u < sd.nsub; ++u)
+        for (int k = 0; k < 3; ++k) {
+            const BatchPass* bp = nullptr;
+            fdtd_status s = batch_pass<T, S>(p, sd.sub[u].op, k, sd.sub[u].theta_frac, &bp);
+            if (s != FDTD_OK) return s;
+        }
+    if (p->d.scheme == FDTD_LOD2)
+        for (double f : {0.25, -0.25})
+            for (int k = 0; k < 3; ++k) {
+                const BatchPass* bp = nullptr;
+                fdtd_status s = batch_pass<T, S>(p, 1, k, f, &bp);
+                if (s != FDTD_OK) return s;
+            }
+    return FDTD_OK;
+}
+
+// Time steps per captured graph.  A graph launch costs tens of microseconds
+// of host time and separates consecutive replays on the device, so one graph
+// holds several steps; a run replays it floor(steps / kGraphSteps) times and
+// launches the remaining steps directly.
+constexpr int kGraphSteps = 8;
+
+// Per-step working set (fields and medium) above which a batch is stepped in
+// groups.  A group runs all its steps before the next one starts, so its
+// arrays stay in the 256 MB MALL (AMD Infinity Cache) from pass to pass
+// instead of cycling through it: 21 of the 64 test cavities (130 MB) step at
+// 38 G cell-updates/s, all 64 (308 MB) at 31.
+constexpr size_t kGroupBytes = size_t(128) << 20;
+
+// Capture kGraphSteps time steps of the main iteration (all sub-steps) as a graph.
+template <typename T, typename S>
+static fdtd_status batch_graph(fdtd_plan_s* p) {
+    Batch* b = p->batch;
+    if (b->exec) return FDTD_OK;
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    // The three pair passes of a sub-step update disjoint arrays: capture them
+    // as parallel branches (fork on events, join before the next sub-step).
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    fdtd_status st = FDTD_OK;
+    auto branch = [&](int k, hipStream_t str, int op, double frac) -> fdtd_status {
+        const BatchPass* bp = nullptr;
+        fdtd_status s2 = batch_pass<T, S>(p, op, k, frac, &bp);
+        return s2 == FDTD_OK ? batch_launch<T, S>(p, *bp, str) : s2;
+    };
+    for (int v = 0; v < kGraphSteps * sd.nsub && st == FDTD_OK; ++v) {
+        const int u = v % sd.nsub;
+        const int op = sd.sub[u].op;
+        const double frac = sd.sub[u].theta_frac;
+        if (hipEventRecord(b->ev[0], b->cap) != hipSuccess || hipStreamWaitEvent(b->fork[0], b->ev[0], 0) != hipSuccess ||
+            hipStreamWaitEvent(b->fork[1], b->ev[0], 0) != hipSuccess) {
+            st = FDTD_EDEVICE;
+            break;
+        }
+        st = branch(0, b->cap, op, frac);
+        if (st == FDTD_OK) st = branch(1, b->fork[0], op, frac);
+        if (st == FDTD_OK) st = branch(2, b->fork[1], op, frac);
+        if (st == FDTD_OK &&
+            (hipEventRecord(b->ev[1], b->fork[0]) != hipSuccess || hipEventRecord(b->ev[2], b->fork[1]) != hipSuccess ||
+             hipStreamWaitEvent(b->cap, b->ev[1], 0) != hipSuccess || hipStreamWaitEvent(b->cap, b->ev[2], 0) != hipSuccess))
+            st = FDTD_EDEVICE;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != FDTD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(e);
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H, int nsteps) {
+    Batch* b = p->batch;
+    const fdtd_desc& d = p->d;
+    const bool adi = d.scheme == FDTD_ADI;
+    const int n = (int)b->subs.size();
+    auto caller = [&](int g) {
+        FieldPtrs<T> f;
+        for (int c = 0; c < 3; ++c) {
+            f.c[c] = static_cast<const T*>(E[3 * g + c]);
+            f.c[3 + c] = static_cast<const T*>(H[3 * g + c]);
+        }
+        return f;
+    };
+    fdtd_status st = batch_tables<T, S>(p);
+    if (st != FDTD_OK) return st;
+    for (int g = 0; g < n; ++g) {
+        fdtd_plan_s* sub = b->subs[g];
+        const Dims& dm = sub->dims;
+        const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+        const AuxCoef kin = aux_coef(sub->d, adi ? 0.25 * sub->d.dt : 0.0);
+        hipLaunchKernelGGL((load_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
+                           caller(g), state_ptrs_w<T>(sub, 0), sub->eps, dm, kin);
+        HIPCHK(hipGetLastError());
+    }
+    if (d.scheme == FDTD_LOD2) {
+        st = batch_substep<T, S>(p, 1, 0.25, p->stream);
+        if (st != FDTD_OK) return st;
+    }
+    const int nmain = nsteps > 0 ? (adi ? nsteps - 1 : nsteps) : 0;   // steps of the plain main iteration
+    const int ngraph = nmain / kGraphSteps;
+    if (ngraph > 0) {
+        st = batch_graph<T, S>(p);
+        if (st != FDTD_OK) return st;
+    }
+    Timing& tm = p->tm;
+    tm.used = 0;
+    tm.fam.clear();
+    if (!tm.main0) {
+        HIPCHK(hipEventCreate(&tm.main0));
+        HIPCHK(hipEventCreate(&tm.main1));
+    }
+    HIPCHK(hipEventRecord(tm.main0, p->stream));
+    for (int m = 0; m < ngraph; ++m) HIPCHK(hipGraphLaunch(b->exec, p->stream));
+    {
+        const SchemeDef& sd = kSchemes[d.scheme];
+        for (int m = ngraph * kGraphSteps; m < nmain; ++m)
+            for (int u = 0; u < sd.nsub; ++u) {
+                st = batch_substep<T, S>(p, sd.sub[u].op, sd.sub[u].theta_frac, p->stream);
+                if (st != FDTD_OK) return st;
+            }
+    }
+    if (adi && nsteps > 0) {
+        // last step: the state before the B sub-step is kept for the output
+        st = batch_substep<T, S>(p, 0, 0.5, p->stream);
+        if (st != FDTD_OK) return st;
+        for (fdtd_plan_s* sub : b->subs)
+            HIPCHK(hipMemcpyAsync(sub->snap, sub->state, sizeof(T) * sub->dims.comp * 6, hipMemcpyDeviceToDevice,
+                                  p->stream));
+        st = batch_substep<T, S>(p, 1, 0.5, p->stream);
+        if (st != FDTD_OK) return st;
+    }
+    HIPCHK(hipEventRecord(tm.main1, p->stream));
+    if (nsteps > 0) {
+        if (d.scheme == FDTD_LOD2) {
+            st = batch_substep<T, S>(p, 1, -0.25, p->stream);
+            if (st != FDTD_OK) return st;
+        }
+        for (int g = 0; g < n; ++g) {
+            fdtd_plan_s* sub = b->subs[g];
+            const Dims& dm = sub->dims;
+            const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
+            FieldPtrsW<T> out;
+            for (int c = 0; c < 3; ++c) {
+                out.c[c] = static_cast<T*>(E[3 * g + c]);
+                out.c[3 + c] = static_cast<T*>(H[3 * g + c]);
+            }
+            FieldPtrs<T> old;
+            for (int c = 0; c < 6; ++c)
+                old.c[c] = reinterpret_cast<const T*>(adi ? sub->snap : sub->state) + (size_t)c * dm.comp;
+            hipLaunchKernelGGL((store_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
+                               state_ptrs<T>(sub, 0), old, out, dm, adi ? 1 : 0, -1LL, 0.0);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    p->step += nsteps;
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status batch_autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
+    Batch* b = p->batch;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    fdtd_status st = FDTD_OK;
+    for (int axis = 0; axis < 3 && st == FDTD_OK; ++axis) {
+        int k = 0;
+        while (kPairs[0][k].w != axis) ++k;
+        std::vector<KCfg> cand;
+        if (axis == 0) {
+            for (int M : {8, 16})
+                for (int wpb : {4, 2, 1}) cand.push_back(KCfg{M, 0, 0, wpb, 0});
+        } else if (p->d.dtype == FDTD_F32) {
+            for (const auto& v : kYzF32) cand.push_back(KCfg{v[0], v[1], v[2], 0, 0});
+        } else {
+            for (const auto& v : kYzF64) cand.push_back(KCfg{v[0], v[1], v[2], 0, 0});
+        }
+        KCfg best = p->cfg[axis];
+        float tbest = 1e30f;
+        for (const KCfg& c : cand) {
+            if (!batch_cfg_valid(p, axis, c)) continue;
+            p->cfg[axis] = c;
+            batch_clear(b);
+            const BatchPass* bp = nullptr;
+            st = batch_pass<T, S>(p, 0, k, 0.5, &bp);
+            if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, p->stream);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e0, p->stream) != hipSuccess) { st = FDTD_EDEVICE; break; }
+            for (int r = 0; r < reps && st == FDTD_OK; ++r) st = batch_launch<T, S>(p, *bp, p->stream);
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = FDTD_EDEVICE;
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < tbest) { tbest = ms; best = c; }
+        }
+        p->cfg[axis] = best;
+        if (best_ms) best_ms[axis] = tbest / reps;
+    }
+    batch_clear(b);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == FDTD_OK) p->tuned = 1;
+    return st;
+}
+
+// Wrap single-grid plans (their ownership passes to the result; on failure
+// they are destroyed) into one batch plan.
+static fdtd_status batch_from_subs(const fdtd_desc& d0, const std::vector<fdtd_plan_s*>& subs, void* hip_stream,
+                                   fdtd_plan_s** out);
+
+}  // namespace fdtd

@@ -1,0 +1,264 @@
+// pass_launch.hpp -- one line pass: kernel variant dispatch, source injection, pass
+// arguments, launch and sub-step
+//
+// Part of the single translation unit of libfdtd.so: included by fdtd.hip
+// after the kernel headers and the headers before it in fdtd.hip.
+#pragma once
+
+namespace fdtd {
+
+// ---------------------------------------------------------------------------
+// kernel launch helpers (variants: full lines, material-index eps_r)
+// ---------------------------------------------------------------------------
+template <typename T, typename S, int M, int MODE>
+static void launch_x(bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+    if (full) {
+        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, false>), g, b, 0, st, a);
+    } else {
+        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, false>), g, b, 0, st, a);
+    }
+}
+// Refined solves are built for FP32: x lines with 8-slot chunks, y/z lines
+// with 8- or 16-slot chunks.
+template <typename S, int M> struct HasRefX { static constexpr bool v = sizeof(S) == 4 && M == 8; };
+template <typename S, int M> struct HasRefYZ { static constexpr bool v = sizeof(S) == 4 && (M == 8 || M == 16); };
+template <typename T, typename S, int M>
+static bool launch_x_mode(int mode, bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+    if (mode == FUND) launch_x<T, S, M, FUND>(full, mat, g, b, st, a);
+    else if (mode == CONV_LOD) launch_x<T, S, M, CONV_LOD>(full, mat, g, b, st, a);
+    else if (mode == CONV_ADI) launch_x<T, S, M, CONV_ADI>(full, mat, g, b, st, a);
+    else if constexpr (HasRefX<S, M>::v) launch_x<T, S, M, FUND_REF>(full, mat, g, b, st, a);
+    else return false;
+    return true;
+}
+template <typename T, typename S, int M, int TX, int NT, int MODE>
+static void launch_yz(bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
+    if (full) {
+        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, false>), g, b, lds, st, a);
+    } else {
+        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, false>), g, b, lds, st, a);
+    }
+}
+template <typename T, typename S, int M, int TX, int NT>
+static bool launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                           const PassArgs<T, S>& a) {
+    if (mode == FUND) launch_yz<T, S, M, TX, NT, FUND>(full, mat, g, b, lds, st, a);
+    else if (mode == CONV_LOD) launch_yz<T, S, M, TX, NT, CONV_LOD>(full, mat, g, b, lds, st, a);
+    else if (mode == CONV_ADI) launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
+    else if constexpr (HasRefYZ<S, M>::v) launch_yz<T, S, M, TX, NT, FUND_REF>(full, mat, g, b, lds, st, a);
+    else return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// one line pass
+// ---------------------------------------------------------------------------
+// Right-hand-side injection of one sub-step at the E samples stored at node
+// (i, j, k): component c (bit c of mask) gets `pre` added to its state before
+// the solve (FUND; the conventional forms add it to the right-hand side) and
+// `post` subtracted from the FUND output.  pre_dev (device, 3 doubles),
+// if set, supplies the pre values instead.
+struct Inject {
+    int i = 0, j = 0, k = 0;
+    unsigned mask = 0;
+    double pre[3] = {0, 0, 0}, post[3] = {0, 0, 0};
+    const double* pre_dev = nullptr;
+};
+
+// The physical source of a sub-step with source term g (fdtd_source).
+static Inject source_inject(const fdtd_plan_s* p, const fdtd_source* src, double g, int mode) {
+    Inject in;
+    if (!src || g == 0.0) return in;
+    in.i = src->i; in.j = src->j; in.k = src->k;
+    in.mask = 4u;   // Ez
+    if (mode == FUND) {
+        in.pre[2] = 0.5 * g;
+        in.post[2] = (p->d.scheme == FDTD_ADI) ? 0.5 * g : 0.0;
+    } else {
+        in.pre[2] = g;
+    }
+    return in;
+}
+
+// Coefficients of the input/output and energy kernels (reciprocals formed here).
+static AuxCoef aux_coef(const fdtd_desc& d, double link) {
+    return AuxCoef{kEps0, kMu0, 1.0 / kMu0, 1.0 / d.dx, 1.0 / d.dy, 1.0 / d.dz, link};
+}
+
+template <typename T>
+static T* set_ptr(fdtd_plan_s* p, int set) {
+    return reinterpret_cast<T*>(p->state) + (size_t)set * 6 * p->dims.comp;
+}
+
+// Launch shape of one pass.
+struct PassShape {
+    int w = 0;            // line axis
+    dim3 grid, block;
+    size_t lds = 0;
+    bool full = false;    // every line fills its P*M slots exactly
+    bool mat = false;     // material-index variant
+};
+
+// Arguments and launch shape of the pass of pair k of operator op (half-span
+// theta, mode) from state set `set_in` to `set_out` of plan p, with the plan's
+// kernel configuration for the line axis.
+template <typename T, typename S>
+static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
+                       const Inject* inj, PassArgs<T, S>& a, PassShape& sh) {
+    const PairDef& pd = kPairs[op][k];
+    const Dims& d = p->dims;
+    std::memset(&a, 0, sizeof(a));
+    const size_t cs = (size_t)d.comp;
+    a.Ein = set_in + pd.ce * cs;
+    a.Hin = set_in + pd.ch * cs;
+    a.Eout = set_out + pd.ce * cs;
+    a.Hout = set_out + pd.ch * cs;
+    a.eps = p->eps;
+    a.mat = p->mat;
+    a.mat_eps = p->mat_eps;
+    a.nmat = p->nmat;
+    sh.mat = p->mat != nullptr;
+    sh.w = pd.w;
+    a.sw = axis_stride(d, pd.w);
+    a.n_w = axis_cells(d, pd.w);
+    const double h = axis_h(p->d, pd.w);
+    const double mu = kMu0;
+    const double s = double(pd.s);
+    a.Ks = kEps0 * mu * h * h / (theta * theta);
+    const double qd = s * theta / (mu * h);
+    double kap = (mode == CONV_ADI) ? s * mu * h / theta : 2.0 * s * mu * h / theta;
+    a.q = S(qd);
+    a.kap_hi = S(kap);
+    a.kap_lo = (sizeof(S) == 4) ? S(kap - double(S(kap))) : S(0);
+    if (mode == CONV_ADI) {
+        // Y = the other operator; H2 = partner of E in Y, E3 = partner of H in Y
+        const int yo = 1 - op;
+        int h2 = -1, e3 = -1;
+        for (int m = 0; m < 3; ++m) {
+            if (kPairs[yo][m].ce == pd.ce) h2 = kPairs[yo][m].ch;
+            if (kPairs[yo][m].ch == pd.ch) e3 = kPairs[yo][m].ce;
+        }
+        const double sy = (op == 0) ? -1.0 : 1.0;
+        const double ht = axis_h(p->d, pd.t), he = axis_h(p->d, pd.e);
+        a.H2 = set_in + h2 * cs;
+        a.E3 = set_in + e3 * cs;
+        a.s_t = axis_stride(d, pd.t);
+        a.s_e = axis_stride(d, pd.e);
+        a.cH2 = S(sy * h * h * mu / (ht * theta));
+        a.hE3 = S(sy * theta / (mu * he));
+    }
+    a.comp = d.comp;
+    a.src_a = a.src_b = a.src_j = -1;
+    int src_idx[3] = {0, 0, 0};
+    const bool has_src = inj && ((inj->mask >> pd.ce) & 1u);
+    if (has_src) {
+        src_idx[0] = inj->i; src_idx[1] = inj->j; src_idx[2] = inj->k;
+        a.src_pre = S(inj->pre[pd.ce]);
+        a.src_post = S(inj->post[pd.ce]);
+        a.src_pre_dev = inj->pre_dev ? inj->pre_dev + pd.ce : nullptr;
+    }
+    const int ne = axis_cells(d, pd.e), nt = axis_cells(d, pd.t);
+    const KCfg& cf = p->cfg[pd.w];
+    a.remap = cf.remap;
+    if (pd.w == 0) {
+        // x lines: a = y (fast), b = z (slow), so that line order is memory
+        // order and every line of a wave lies after the wave's first line.
+        // The e axis starts at 0, the t axis at 1 (t = 0 is a PEC wall plane).
+        a.sa = axis_stride(d, 1);
+        a.sb = axis_stride(d, 2);
+        if (pd.e == 1) { a.a_lo = 0; a.na = d.ny; a.b_lo = 1; a.nb = d.nz - 1; }
+        else { a.a_lo = 1; a.na = d.ny - 1; a.b_lo = 0; a.nb = d.nz; }
+        if (has_src) { a.src_a = src_idx[1]; a.src_b = src_idx[2]; a.src_j = src_idx[0]; }
+        const int M = cf.M;
+        a.P = next_pow2((a.n_w + M - 1) / M);
+        const long long nlines = (long long)a.na * a.nb;
+        const long long lines_per_block = (long long)cf.wpb * (64 / a.P);
+        a.nblk = (int)((nlines + lines_per_block - 1) / lines_per_block);
+        sh.grid = dim3((unsigned)a.nblk);
+        sh.block = dim3(64 * cf.wpb);
+        sh.lds = 0;
+    } else {
+        // y/z lines: a = x axis (lanes), b = the other transverse axis
+        const int other = (pd.e == 0) ? pd.t : pd.e;
+        a.sa = 1;
+        a.sb = axis_stride(d, other);
+        if (pd.e == 0) { a.a_lo = 0; a.na = d.nx; a.b_lo = 1; a.nb = nt - 1; }
+        else { a.a_lo = 1; a.na = d.nx - 1; a.b_lo = 0; a.nb = ne; }
+        if (has_src) { a.src_a = src_idx[0]; a.src_b = src_idx[other]; a.src_j = src_idx[pd.w]; }
+        const int M = cf.M, TX = cf.TX;
+        a.P = next_pow2((a.n_w + M - 1) / M);
+        a.ntx = (a.a_lo + a.na + TX - 1) / TX;
+        a.nblk = a.ntx * a.nb;
+        sh.block = dim3(TX * a.P);
+        sh.grid = dim3((unsigned)a.nblk);
+        sh.lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
+    }
+    sh.full = a.P * cf.M == a.n_w;
+}
+
+template <typename T, typename S>
+static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
+                               const Inject* inj, bool timed) {
+    PassArgs<T, S> a;
+    PassShape sh;
+    build_pass<T, S>(p, op, k, theta, mode, set_in, set_out, inj, a, sh);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        Timing& tm = p->tm;
+        if (tm.used + 2 > tm.ev.size()) {
+            for (int m = 0; m < 64; ++m) {
+                hipEvent_t ev;
+                HIPCHK(hipEventCreate(&ev));
+                tm.ev.push_back(ev);
+            }
+        }
+        e0 = tm.ev[tm.used];
+        e1 = tm.ev[tm.used + 1];
+        tm.fam.push_back(sh.w == 0 ? 1 : 0);
+        tm.used += 2;
+        HIPCHK(hipEventRecord(e0, p->stream));
+    }
+    const KCfg& cf = p->cfg[sh.w];
+    const int kmode = (mode == FUND && p->refine) ? FUND_REF : mode;
+    bool built = true;
+    if (sh.w == 0) {
+        if (cf.M == 8) built = launch_x_mode<T, S, 8>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+        else built = launch_x_mode<T, S, 16>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+    } else {
+        const int M = cf.M, TX = cf.TX, NT = cf.NT;
+        const size_t lds = kmode == FUND_REF ? sh.lds / 9 * 13 : sh.lds;   // refined: second exchange areas
+#define CASE_YZ(MM, TT, NN)                                                                                    \
+    if (M == MM && TX == TT && NT == NN) {                                                                     \
+        built = launch_yz_mode<T, S, MM, TT, NN>(kmode, sh.full, sh.mat, sh.grid, sh.block, lds, p->stream, a); \
+    } else
+        if constexpr (sizeof(S) == 4) {
+            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) CASE_YZ(8, 32, 512)
+            return FDTD_EUNSUPPORTED;
+        } else {
+            CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) CASE_YZ(8, 16, 1024) return FDTD_EUNSUPPORTED;
+        }
+#undef CASE_YZ
+    }
+    if (!built) return FDTD_EUNSUPPORTED;
+    HIPCHK(hipGetLastError());
+    if (timed) HIPCHK(hipEventRecord(e1, p->stream));
+    return FDTD_OK;
+}
+
+template <typename T, typename S>
+static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& cur, const Inject* inj,
+                           bool timed) {
+    const int out = (mode == CONV_ADI) ? 1 - cur : cur;
+    for (int k = 0; k < 3; ++k) {
+        fdtd_status st = launch_pass<T, S>(p, op, k, theta, mode, set_ptr<T>(p, cur), set_ptr<T>(p, out), inj, timed);
+        if (st != FDTD_OK) return st;
+    }
+    cur = out;
+    return FDTD_OK;
+}
+
+}  // namespace fdtd

@@ -1,0 +1,136 @@
+// plan_state.hpp -- plan state: physical constants, scheme tables, kernel configurations, batch
+// bookkeeping and the plan object
+//
+// Part of the single translation unit of libfdtd.so: included by fdtd.hip
+// after the kernel headers and the headers before it in fdtd.hip.
+#pragma once
+
+namespace fdtd {
+
+static constexpr double kEps0 = 8.8541878128e-12;
+static constexpr double kMu0 = 1.25663706212e-6;
+
+// Pairs of eq. (AMat): E component, H component, line axis, e axis, t axis, sign.
+// Components 0..5 = Ex Ey Ez Hx Hy Hz; axes 0..2 = x y z.
+struct PairDef { int ce, ch, w, e, t, s; };
+static const PairDef kPairs[2][3] = {
+    {{0, 5, 1, 0, 2, +1}, {1, 3, 2, 1, 0, +1}, {2, 4, 0, 2, 1, +1}},   // A
+    {{0, 4, 2, 0, 1, -1}, {1, 5, 0, 1, 2, -1}, {2, 3, 1, 2, 0, -1}},   // B
+};
+
+struct SubStep { int op; double theta_frac; double t_frac; };
+struct SchemeDef { int nsub; SubStep sub[3]; };
+static const SchemeDef kSchemes[4] = {
+    {2, {{0, 0.5, 0.25}, {1, 0.5, 0.75}, {0, 0, 0}}},          // ADI
+    {2, {{0, 0.5, 0.25}, {1, 0.5, 0.75}, {0, 0, 0}}},          // LOD1
+    {3, {{0, 0.25, 0.125}, {1, 0.5, 0.5}, {0, 0.25, 0.875}}},  // SS2
+    {2, {{0, 0.5, 0.5}, {1, 0.5, 1.0}, {0, 0, 0}}},            // LOD2
+};
+
+// Kernel configuration of the passes along one line axis.
+//   x lines: M (slots per lane), wpb (waves per block), remap
+//   y/z lines: M (slots per thread), TX (x positions per block),
+//              NT (block-size bound of the instantiation), remap
+struct KCfg { int M, TX, NT, wpb, remap; };
+
+// Instantiated y/z-line variants {M, TX, NT} by solve precision.
+static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}, {8, 32, 512}};
+static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
+
+struct Timing {
+    int per_launch = 0;           // 0: off; k >= 1: every launch of every k-th main-loop step
+    hipEvent_t main0 = nullptr, main1 = nullptr;
+    std::vector<hipEvent_t> ev;   // pairs
+    std::vector<int> fam;         // family of each pair (0 = yz lines, 1 = x lines)
+    size_t used = 0;
+};
+
+// Batch plans (fdtd_plan_batch): one pass of every grid of the batch per
+// launch.  For each (operator, pair, theta) the batch keeps a device table of
+// the grids' pass arguments and a work list of (grid, block) items.
+struct BatchPass {
+    int op = 0, k = 0;
+    double frac = 0.0;        // theta = frac * dt of each grid
+    void* tab = nullptr;      // device PassArgs<T, S>[ngrids]
+    void* items = nullptr;    // device int2[nitems]
+    int nitems = 0;
+    int Pmax = 1;             // y/z lines: largest chunk count (block = TX * Pmax)
+    size_t lds = 0;           // y/z lines: dynamic LDS per block
+};
+struct Batch {
+    std::vector<fdtd_plan_s*> subs;
+    bool mat = false;         // every grid has a material index
+    std::vector<BatchPass> passes;
+    hipStream_t cap = nullptr;        // private stream for graph capture
+    hipStream_t fork[2] = {nullptr, nullptr};   // capture branches: the three pair passes of a
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // sub-step are independent and run side by side
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;    // time steps of the main iteration
+    // A batch larger than kGroupBytes is split into groups of consecutive
+    // grids, each a batch plan of its own (it owns its grids); the plan then
+    // only delegates, and a run steps one group after the other.
+    std::vector<fdtd_plan_s*> groups;
+    std::vector<int> first;           // first grid of each group
+};
+
+}  // namespace fdtd
+
+struct fdtd_plan_s {
+    fdtd_desc d;
+    hipStream_t stream;
+    int device;
+    fdtd::Dims dims;
+    size_t esz;
+    void* state = nullptr;    // 6 (or 12 for original ADI) arrays, padded layout
+    void* snap = nullptr;     // ADI: state before the last B sub-step
+    float* eps = nullptr;     // node layout, padded
+    unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
+    float* mat_eps = nullptr;       // eps_r per material
+    int nmat = 0;
+    double* partial = nullptr;
+    int npartial = 0;
+    double* energy_dev = nullptr;
+    int energy_cap = 0;
+    void* gbuf = nullptr;     // adjoint: checkpoints, records, adjoint state (grown on demand)
+    size_t gcap = 0;
+    long long step = 0;
+    fdtd::Timing tm;
+    fdtd::KCfg cfg[3];        // per line axis x, y, z
+    int tuned = 0;
+    int refine = 0;           // FDTD_F32_REFINE: fundamental passes refine each solve once
+    double last_main_ms = 0.0;
+    double fam_ms[2] = {0, 0};
+    int fam_n[2] = {0, 0};
+    fdtd::Batch* batch = nullptr;   // batch plan: the grids and their tables
+    unsigned magic = 0xFD7DFD7Du;
+};
+
+namespace fdtd {
+
+static fdtd_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return FDTD_OK;
+    if (e == hipErrorOutOfMemory) return FDTD_ENOMEM;
+    return FDTD_EDEVICE;
+}
+#define HIPCHK(x)                                       \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return from_hip(e_);      \
+    } while (0)
+
+static int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+template <typename T>
+static T* comp_ptr(fdtd_plan_s* p, int set, int c) {
+    return reinterpret_cast<T*>(p->state) + (size_t)(set * 6 + c) * p->dims.comp;
+}
+
+static long long axis_stride(const Dims& d, int ax) { return ax == 0 ? 1 : (ax == 1 ? d.px : d.plane); }
+static int axis_cells(const Dims& d, int ax) { return ax == 0 ? d.nx : (ax == 1 ? d.ny : d.nz); }
+static double axis_h(const fdtd_desc& d, int ax) { return ax == 0 ? d.dx : (ax == 1 ? d.dy : d.dz); }
+
+}  // namespace fdtd
