@@ -10,6 +10,8 @@
  *   SS2   -- Sec. II-C, eq. (orgSS2)  / fundamental (fastSS2)
  *   LOD2  -- Sec. II-D, eq. (orgLOD2) / fundamental (fastLOD2), with the
  *            input/output processing (orgLOD2i/o), (fastLOD2i/o)
+ *   D'Yakonov, Douglas-Gunn -- Sec. II-E, eqs. (orgDY) / (fastDY) and the
+ *            delta formulation / (fastDGo), fundamental form only
  * using the operators A, B of eq. (AMat) with b = dt/(2 eps), d = dt/(2 mu)
  * (eq. (bd)) and second-order central differences on Yee cells (Sec. III).
  * "Fundamental" runs the matrix-operator-free right-hand sides of Sec. III;
@@ -49,7 +51,22 @@ typedef enum {
     FDTD_ENONFINITE = -5     /* NaN/Inf found in the energy after stepping           */
 } fdtd_status;
 
-typedef enum { FDTD_ADI = 0, FDTD_LOD1 = 1 /* == SS1 */, FDTD_SS2 = 2, FDTD_LOD2 = 3 } fdtd_scheme;
+/* FDTD_DYAKONOV and FDTD_DOUGLAS_GUNN (Sec. II-E) take the fundamental form
+ * only (else FDTD_EUNSUPPORTED) and no source (fdtd_run, fdtd_step and
+ * fdtd_grad_eps return FDTD_EUNSUPPORTED for a non-NULL `src`: the paper
+ * gives these splittings without a nonhomogeneous term).  Their fundamental
+ * forms are the iteration of (fasterADI) with other variables: (fastDY) is
+ * it with u in place of u~ = 2u and the input v^{-1/2} = (1/2 I - dt/4 B) u^0,
+ * and (fastDGo) reads the delta formulation's increments off u~.  Both give
+ * the Peaceman-Rachford fields u^n, and the ADI plan already iterates in the
+ * variables of (fastDY) (state v^n = (1/2 I + dt/4 B) u^n, field
+ * u^{n+1} = v^{n+1/2} + v^{n+1}), so these plans run the fundamental ADI
+ * passes, input and output processing unchanged: same fields, energy trace,
+ * kernels and cost.  Batches accept them too. */
+typedef enum {
+    FDTD_ADI = 0, FDTD_LOD1 = 1 /* == SS1 */, FDTD_SS2 = 2, FDTD_LOD2 = 3,
+    FDTD_DYAKONOV = 4, FDTD_DOUGLAS_GUNN = 5
+} fdtd_scheme;
 typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
 /* Precision: FDTD_F32 keeps fields in FP32 and solves in FP32; FDTD_F64 uses
  * FP64 for both; FDTD_F32_F64SOLVE keeps fields in FP32 (FP32 HBM traffic)
@@ -156,8 +173,8 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
  * per axis (0 when taken from the cache).  Synchronizes the stream. */
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms);
 
-/* Gradient of a probe objective with respect to eps_r (fundamental ADI
- * plans only, else FDTD_EUNSUPPORTED).
+/* Gradient of a probe objective with respect to eps_r (fundamental ADI,
+ * D'Yakonov and Douglas-Gunn plans only, else FDTD_EUNSUPPORTED).
  *   J = dt * sum_{n=1..nsteps} (Ex^2 + Ey^2 + Ez^2)(u^n) at the E samples stored
  *   at the probe node (probe_i, probe_j, probe_k), 1 <= probe_* < n_*,
  * where u^n are the fields fdtd_run would return after n steps from the

@@ -15,7 +15,8 @@ Stable Implicit FDTD Methods", arXiv 2011.14043):
 * ``tridiag``      -- the Thomas algorithm (Sec. IV, tridiagonal solving);
 * ``conventional`` -- the original splitting formulae: ADI eq. (clsADI), LOD1/SS1
                       eq. (orgLOD), SS2 eq. (orgSS2), LOD2 eq. (orgLOD2) with
-                      (orgLOD2i)/(orgLOD2o); each implicit stage solved by
+                      (orgLOD2i)/(orgLOD2o), D'Yakonov (orgDY), Douglas-Gunn
+                      in delta form (Sec. II-E); each implicit stage solved by
                       eliminating H (a tridiagonal E system per grid line);
 * ``fundamental``  -- the fundamental schemes in the paper's component form:
                       ADI Sec. III-A eqs. (fasterADIaa)-(fasterADIddh) with
@@ -23,6 +24,8 @@ Stable Implicit FDTD Methods", arXiv 2011.14043):
                       Sec. III-B eqs. (fastLOD2aa)-(fastLOD2dd) with
                       (fastestLOD2ex1/2), (fastLOD2i), (fastLOD2o); LOD1 (fastLOD)
                       and SS2 (fastSS2) by the same component pattern;
+                      D'Yakonov (fastDY) and Douglas-Gunn ((fasterADI) with
+                      the increments of (fastDGo)) of Sec. II-E;
 * ``dense``        -- a dense-matrix version of every scheme for tiny grids,
                       with A and B assembled node by node from Maxwell's curl
                       equations (independent of ``yee``);
@@ -36,7 +39,7 @@ closed forms, brute-force dense solves or finite differences.
 from .yee import (EPS0, MU0, C0, Grid, COMPONENTS, dynamic_mask, energy,
                   apply_operator, cfl_dt)
 from .tridiag import thomas
-from .run import run, SCHEMES, FORMS
+from .run import run, SCHEMES, FORMS, SPLITTINGS
 
 __all__ = ["EPS0", "MU0", "C0", "Grid", "COMPONENTS", "dynamic_mask", "energy",
-           "apply_operator", "cfl_dt", "thomas", "run", "SCHEMES", "FORMS"]
+           "apply_operator", "cfl_dt", "thomas", "run", "SCHEMES", "FORMS", "SPLITTINGS"]

@@ -71,3 +71,27 @@ def invariant(scheme: str, u, g: Grid) -> float:
         bu = apply_operator("B", u, g)
         return energy([0.5 * a + 0.25 * g.dt * b for a, b in zip(u, bu)], g)
     return energy(u, g)
+
+
+def splitting_step(scheme: str, u, g: Grid):
+    """One step of the original D'Yakonov (orgDY) or delta-formulation
+    Douglas-Gunn splitting of Sec. II-E, operators applied as written:
+      "dy":  (I - dt/2 A) u* = (I + dt/2 A)(I + dt/2 B) u^n ;  (I - dt/2 B) u^{n+1} = u*
+      "dg":  (I - dt/2 A) du* = dt (A + B) u^n ;  (I - dt/2 B) du = du* ;  u^{n+1} = u^n + du
+    """
+    h = 0.5 * g.dt
+    if scheme == "dy":
+        bu = apply_operator("B", u, g)
+        w = [a + h * b for a, b in zip(u, bu)]
+        aw = apply_operator("A", w, g)
+        f = [a + h * b for a, b in zip(w, aw)]
+        ustar = solve_implicit("A", PAIRS["A"], f, h, g)
+        return solve_implicit("B", PAIRS["B"], ustar, h, g)
+    if scheme == "dg":
+        au = apply_operator("A", u, g)
+        bu = apply_operator("B", u, g)
+        f = [g.dt * (a + b) for a, b in zip(au, bu)]
+        dstar = solve_implicit("A", PAIRS["A"], f, h, g)
+        du = solve_implicit("B", PAIRS["B"], dstar, h, g)
+        return [a + b for a, b in zip(u, du)]
+    raise ValueError(scheme)

@@ -187,3 +187,78 @@ def run_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int, so
         v = np.linalg.solve(0.5 * I + dt / 8 * ds.B, u)
         u = v - u
     return u, trace
+
+
+# ----------------------------------------------------------------------------
+# further splittings of Sec. II-E: D'Yakonov and Douglas-Gunn (no sources)
+# ----------------------------------------------------------------------------
+
+def run_splitting_original(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int):
+    """Original splitting formulae of Sec. II-E on matrices.
+
+    "dy", eq. (orgDY):  (I - dt/2 A) u* = (I + dt/2 A)(I + dt/2 B) u^n ,
+                        (I - dt/2 B) u^{n+1} = u* ;
+    "dg", the delta formulation (before (fastDGo)):
+                        (I - dt/2 A) du* = dt (A + B) u^n ,
+                        (I - dt/2 B) du = du* ,   u^{n+1} = u^n + du .
+    Returns (u^steps, per-step intermediates): u* for "dy", (du*, du) for "dg".
+    """
+    I, h = np.eye(ds.n), 0.5 * ds.g.dt
+    x = x0.copy()
+    mids = []
+    for _ in range(steps):
+        if scheme == "dy":
+            ustar = np.linalg.solve(I - h * ds.A, (I + h * ds.A) @ ((I + h * ds.B) @ x))
+            x = np.linalg.solve(I - h * ds.B, ustar)
+            mids.append(ustar)
+        elif scheme == "dg":
+            dstar = np.linalg.solve(I - h * ds.A, ds.g.dt * ((ds.A + ds.B) @ x))
+            du = np.linalg.solve(I - h * ds.B, dstar)
+            x = x + du
+            mids.append((dstar, du))
+        else:
+            raise ValueError(scheme)
+    return x, mids
+
+
+def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int):
+    """Fundamental forms of the same splittings (Sec. II-E).
+
+    "dy", eq. (fastDY) with its input v^{-1/2} = (1/2 I - dt/4 B) u^0:
+        v^n = u^n - v^{n-1/2};  (1/2 I - dt/4 A) u^{n+1/2} = v^n;
+        v^{n+1/2} = u^{n+1/2} - v^n;  (1/2 I - dt/4 B) u^{n+1} = v^{n+1/2};
+      intermediate u* = 2 v^{n+1/2}.
+    "dg", the ADI iteration (fasterADI) with (fastADIi) and (uTldCol), and the
+      increments of (fastDGo): du* = u~^{n+1/2} - u~^n, du = (u~^{n+1} - u~^n)/2,
+      accumulated as u^{n+1} = u^n + du.
+    Returns the same as ``run_splitting_original``.
+    """
+    g, I = ds.g, np.eye(ds.n)
+    q = 0.25 * g.dt
+    mids = []
+    if scheme == "dy":
+        v = (0.5 * I - q * ds.B) @ x0            # v^{-1/2}
+        u = x0.copy()
+        for _ in range(steps):
+            v = u - v                            # v^n
+            uh = np.linalg.solve(0.5 * I - q * ds.A, v)
+            v = uh - v                           # v^{n+1/2}
+            u = np.linalg.solve(0.5 * I - q * ds.B, v)
+            mids.append(2.0 * v)
+        return u, mids
+    if scheme == "dg":
+        v = (I - 0.5 * g.dt * ds.B) @ x0         # v^{-1/2}, (fastADIi)
+        ut = 2.0 * x0                            # u~^0, (uTldCol)
+        u = x0.copy()
+        for _ in range(steps):
+            v = ut - v
+            uth = np.linalg.solve(0.5 * I - q * ds.A, v)
+            dstar = uth - ut
+            v = uth - v
+            utn = np.linalg.solve(0.5 * I - q * ds.B, v)
+            du = 0.5 * (utn - ut)
+            u = u + du
+            ut = utn
+            mids.append((dstar, du))
+        return u, mids
+    raise ValueError(scheme)

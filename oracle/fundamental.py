@@ -38,7 +38,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .implicit import line_operator_solve
+from .implicit import line_operator_solve, solve_implicit
 from .yee import CIDX, PAIRS, Grid, apply_operator, diff_to_half, diff_to_integer, dynamic_mask, energy
 
 E_COMPS = ("Ex", "Ey", "Ez")
@@ -164,3 +164,54 @@ class FundamentalADI:
         equal to W((I + dt/2 B) u^n)/4."""
         v = [self.Et[c] - self.e[c] for c in E_COMPS] + [self.h[c] for c in H_COMPS]
         return 0.25 * energy(v, self.g)
+
+
+# ----------------------------------------------------------------------------
+# D'Yakonov and Douglas-Gunn in fundamental form (Sec. II-E), no sources
+# ----------------------------------------------------------------------------
+
+def solve_half(op: str, r, theta: float, g: Grid):
+    """y with (1/2 I - theta/2 X) y = r for all six components, i.e. the stage
+    (I - theta X) y = 2 r (static normal H keeps 2 r, wall E stays 0)."""
+    return solve_implicit(op, PAIRS[op], [2.0 * a for a in r], theta, g)
+
+
+def dyakonov(u0, g: Grid, steps: int, record=None):
+    """Eq. (fastDY) with input v^{-1/2} = (1/2 I - dt/4 B) u^0; returns u^steps.
+    `record(n, u)` is called with u^n for n = 0..steps when given."""
+    half = 0.5 * g.dt
+    bu = apply_operator("B", u0, g)
+    v = [0.5 * a - 0.5 * half * b for a, b in zip(u0, bu)]   # v^{-1/2}
+    u = [np.array(a, copy=True) for a in u0]
+    if record:
+        record(0, u)
+    for n in range(steps):
+        v = [a - b for a, b in zip(u, v)]                     # v^n = u^n - v^{n-1/2}
+        uh = solve_half("A", v, half, g)                      # u^{n+1/2}
+        v = [a - b for a, b in zip(uh, v)]                    # v^{n+1/2}
+        u = solve_half("B", v, half, g)                       # u^{n+1}
+        if record:
+            record(n + 1, u)
+    return u
+
+
+def douglas_gunn(u0, g: Grid, steps: int, record=None):
+    """The ADI iteration (fasterADI) from (fastADIi), (uTldCol), with the field
+    advanced by the increment of (fastDGo): u^{n+1} = u^n + (u~^{n+1} - u~^n)/2."""
+    half = 0.5 * g.dt
+    bu = apply_operator("B", u0, g)
+    v = [a - half * b for a, b in zip(u0, bu)]                # v^{-1/2}
+    ut = [2.0 * a for a in u0]                                # u~^0
+    u = [np.array(a, copy=True) for a in u0]
+    if record:
+        record(0, u)
+    for n in range(steps):
+        v = [a - b for a, b in zip(ut, v)]
+        uth = solve_half("A", v, half, g)                     # u~^{n+1/2}
+        v = [a - b for a, b in zip(uth, v)]
+        utn = solve_half("B", v, half, g)                     # u~^{n+1}
+        u = [a + 0.5 * (b - c) for a, b, c in zip(u, utn, ut)]
+        ut = utn
+        if record:
+            record(n + 1, u)
+    return u

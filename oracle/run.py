@@ -13,6 +13,8 @@ from .yee import Grid, clean
 
 SCHEMES = ("adi", "lod1", "ss2", "lod2")
 FORMS = ("fundamental", "conventional")
+# D'Yakonov and Douglas-Gunn splittings of Sec. II-E (no nonhomogeneous terms)
+SPLITTINGS = ("dy", "dg")
 
 
 def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
@@ -23,7 +25,7 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
     (see ``conventional.invariant``) at steps 0, e, 2e, ... (e = energy_every;
     empty if 0).  Tangential E on the walls is treated as 0 on input.
     """
-    if scheme not in SCHEMES or form not in FORMS:
+    if (scheme not in SCHEMES and scheme not in SPLITTINGS) or form not in FORMS:
         raise ValueError((scheme, form))
     u = clean(fields, g)
     trace = []
@@ -31,6 +33,24 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
     def record(n, value_fn):
         if energy_every and n % energy_every == 0:
             trace.append(value_fn())
+
+    if scheme in SPLITTINGS:
+        # both splittings give the ADI fields u^n; their invariant is ADI's,
+        # W((1/2 I + dt/4 B) u^n)
+        if source is not None:
+            raise ValueError("the D'Yakonov and Douglas-Gunn splittings take no source")
+
+        def rec(n, un):
+            record(n, lambda: conventional.invariant("adi", un, g))
+
+        if form == "conventional":
+            rec(0, u)
+            for n in range(steps):
+                u = conventional.splitting_step(scheme, u, g)
+                rec(n + 1, u)
+            return u, trace
+        run_f = fundamental.dyakonov if scheme == "dy" else fundamental.douglas_gunn
+        return run_f(u, g, steps, rec), trace
 
     if form == "conventional":
         u = conventional.input_processing(scheme, u, g)

@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 FDTD_OK = 0
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ENOMEM", -3: "FDTD_EDEVICE",
           -4: "FDTD_EUNSUPPORTED", -5: "FDTD_ENONFINITE"}
-SCHEMES = {"adi": 0, "lod1": 1, "ss1": 1, "ss2": 2, "lod2": 3}
+SCHEMES = {"adi": 0, "lod1": 1, "ss1": 1, "ss2": 2, "lod2": 3,
+           "dyakonov": 4, "dy": 4, "douglas_gunn": 5, "dg": 5}
 FORMS = {"fundamental": 0, "conventional": 1}
 DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2, "f32_refine": 3}
 

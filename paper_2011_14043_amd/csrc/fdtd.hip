@@ -62,8 +62,18 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!(d->dt > 0) || !(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return FDTD_EINVAL;
     if (!std::isfinite(d->dt) || !std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz))
         return FDTD_EINVAL;
-    if (d->scheme < 0 || d->scheme > 3 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
+    if (d->scheme < 0 || d->scheme > 5 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
         return FDTD_EINVAL;
+    // D'Yakonov and Douglas-Gunn: the fundamental ADI iteration (Sec. II-E)
+    fdtd_desc as_adi;
+    int splitting = 0;
+    if (d->scheme == FDTD_DYAKONOV || d->scheme == FDTD_DOUGLAS_GUNN) {
+        if (d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+        splitting = d->scheme;
+        as_adi = *d;
+        as_adi.scheme = FDTD_ADI;
+        d = &as_adi;
+    }
     if (d->boundary != 0) return FDTD_EUNSUPPORTED;
     if (d->mu_r != nullptr) return FDTD_EUNSUPPORTED;
     const bool refine = d->dtype == FDTD_F32_REFINE;
@@ -84,6 +94,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!p) return FDTD_ENOMEM;
     p->d = *d;
     p->d.eps_r = nullptr;
+    p->splitting = splitting;
     if (refine) {
         p->refine = 1;
         p->d.dtype = FDTD_F32;   // FP32 storage and arithmetic; only the fundamental passes differ
@@ -164,6 +175,7 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
     for (int c = 0; c < 3; ++c)
         if (!E[c] || !H[c]) return FDTD_EINVAL;
     if (energy && energy_every < 1) return FDTD_EINVAL;
+    if (src && p->splitting) return FDTD_EUNSUPPORTED;
     if (src) {
         if (src->i < 1 || src->i >= p->d.nx || src->j < 1 || src->j >= p->d.ny || src->k < 0 || src->k >= p->d.nz)
             return FDTD_EINVAL;
@@ -316,6 +328,7 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
     const fdtd_desc& d = p->d;
     if (probe_i < 1 || probe_i >= d.nx || probe_j < 1 || probe_j >= d.ny || probe_k < 1 || probe_k >= d.nz)
         return FDTD_EINVAL;
+    if (src && p->splitting) return FDTD_EUNSUPPORTED;
     if (src) {
         if (src->i < 1 || src->i >= d.nx || src->j < 1 || src->j >= d.ny || src->k < 0 || src->k >= d.nz)
             return FDTD_EINVAL;
@@ -350,10 +363,17 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     *out = nullptr;
     for (int g = 0; g < n; ++g) {
         if (d[g].scheme != d[0].scheme || d[g].form != d[0].form || d[g].dtype != d[0].dtype) return FDTD_EINVAL;
-        if (d[g].scheme < 0 || d[g].scheme > 3 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
+        if (d[g].scheme < 0 || d[g].scheme > 5 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
             return FDTD_EINVAL;
     }
     if (d[0].form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    // D'Yakonov and Douglas-Gunn batches step as ADI (no sources in a batch)
+    std::vector<fdtd_desc> as_adi;
+    if (d[0].scheme == FDTD_DYAKONOV || d[0].scheme == FDTD_DOUGLAS_GUNN) {
+        as_adi.assign(d, d + n);
+        for (fdtd_desc& x : as_adi) x.scheme = FDTD_ADI;
+        d = as_adi.data();
+    }
     std::vector<fdtd_plan_s*> subs;
     fdtd_status st = FDTD_OK;
     for (int g = 0; g < n && st == FDTD_OK; ++g) {

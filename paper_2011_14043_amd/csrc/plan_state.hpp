@@ -85,6 +85,7 @@ struct fdtd_plan_s {
     void* snap = nullptr;     // ADI: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
+    int splitting = 0;        // FDTD_DYAKONOV / FDTD_DOUGLAS_GUNN as requested (the plan runs as ADI)
     float* mat_eps = nullptr;       // eps_r per material
     int nmat = 0;
     double* partial = nullptr;

@@ -1,0 +1,96 @@
+"""GPU parity of the D'Yakonov and Douglas-Gunn scheme ids (Sec. II-E)
+against the oracle's own forms of those splittings, which the CPU pins tie to
+the original formulae (orgDY), the delta formulation and Peaceman-Rachford."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.source import Source as OSource
+
+from .test_gpu_parity import PREC, TOL, gpu_run
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def case():
+    """37 x 45 x 70 cells (ragged tiles), CFL 10, random boxes and fields."""
+    nx, ny, nz, h = 37, 45, 70, 1e-3
+    dt = W.yee_dt(h, h, h, 10.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=12, nboxes=8)
+    u0 = W.random_fields(nx, ny, nz, seed=13)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    refs = {s: oracle.run(s, "fundamental", g, u0, 12, None, 3) for s in oracle.SPLITTINGS}
+    return dict(nx=nx, ny=ny, nz=nz, h=h, dt=dt, eps=eps, u0=u0, g=g, refs=refs)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s64", "f32r"])
+@pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
+def test_splitting_parity(case, scheme, dtype):
+    c = case
+    key = "dy" if scheme == "dyakonov" else "dg"
+    print(f"[case] 37x45x70 {scheme}/{dtype}", flush=True)
+    got, tr = gpu_run(scheme, "fundamental", dtype, c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"],
+                      c["u0"], 12, None, 3)
+    ref, tr_ref = c["refs"][key]
+    err = oracle.yee.weighted_rel_l2(got, ref, c["g"])
+    terr = np.max(np.abs(np.array(tr) - np.array(tr_ref)) / np.abs(np.array(tr_ref)))
+    print(f"  rel-L2 {err:.3e}  energy {terr:.3e}")
+    assert err < TOL[dtype]
+    assert terr < 10 * TOL[dtype]
+
+
+@pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
+def test_splitting_runs_the_adi_passes(case, scheme):
+    """Same kernels, input and output processing as fundamental ADI: the
+    fields agree bit for bit."""
+    c = case
+    args = (c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], c["u0"], 7)
+    a, _ = gpu_run("adi", "fundamental", "f32", *args)
+    b, _ = gpu_run(scheme, "fundamental", "f32", *args)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
+def test_splitting_rejects_source_and_conventional_form(scheme):
+    from paper_2011_14043_amd import Plan, Source
+    n, h = 16, 1e-3
+    dt = W.yee_dt(h, h, h, 4.0)
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        Plan(n, n, n, dt, h, h, h, scheme=scheme, form="conventional")
+    plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, dtype=torch.float32)
+    E = [torch.zeros(n + 1, n + 1, n + 1, device=DEV) for _ in range(3)]
+    H = [torch.zeros(n + 1, n + 1, n + 1, device=DEV) for _ in range(3)]
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        plan.run(E, H, 2, source=Source(8, 8, 8, f0=1e10, tau=1e-10, t0=4e-10, amp=1.0))
+    plan.run(E, H, 2)
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_dyakonov_batch_equals_adi_batch():
+    from paper_2011_14043_amd import BatchPlan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    shapes = [(16, 18, 17), (21, 16, 25), (17, 23, 16)]
+    grids, fields0 = [], []
+    for g, (nx, ny, nz) in enumerate(shapes):
+        grids.append((nx, ny, nz, torch.tensor(W.random_box_eps(nx, ny, nz, seed=50 + g, nboxes=4))))
+        fields0.append(W.random_fields(nx, ny, nz, seed=60 + g))
+    out = {}
+    for scheme in ("adi", "dyakonov"):
+        print(f"[case] batch of 3 grids {scheme}", flush=True)
+        plan = BatchPlan(grids, dt, h, h, h, scheme=scheme, dtype=torch.float32)
+        f = [([torch.tensor(a, dtype=torch.float32, device=DEV) for a in u0[:3]],
+              [torch.tensor(a, dtype=torch.float32, device=DEV) for a in u0[3:]]) for u0 in fields0]
+        plan.run(f, 10)
+        torch.cuda.synchronize()
+        plan.close()
+        out[scheme] = [t.cpu() for E, H in f for t in E + H]
+    for x, y in zip(out["adi"], out["dyakonov"]):
+        assert torch.equal(x, y)

@@ -6,7 +6,8 @@
   and the closed-form ADI dispersion relation;
 * invariants: skew-adjointness of A and B, exact energy conservation of the
   Cayley sub-steps, the fundamental == original equivalence (Sec. II-A
-  closing paragraph, Sec. II-B construction), the ADI <-> LOD link (Sec. II-E);
+  closing paragraph, Sec. II-B construction), the ADI <-> LOD link (Sec. II-E),
+  the D'Yakonov and Douglas-Gunn splittings against Peaceman-Rachford (Sec. II-E);
 * the temporal orders of Table I (2, 1, 2, 2).
 """
 import math
@@ -187,6 +188,94 @@ def test_adi_lod_link():
         U = Unew
         adi.step()
         assert yee.weighted_rel_l2(V, adi.fields(), g) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# D'Yakonov and Douglas-Gunn splittings (Sec. II-E)
+# --------------------------------------------------------------------------
+
+def _wrel(ds, a, b):
+    scale = np.sqrt(ds.w)
+    return np.linalg.norm((a - b) * scale) / np.linalg.norm(b * scale)
+
+
+@pytest.mark.parametrize("scheme", oracle.SPLITTINGS)
+@pytest.mark.parametrize("cfl", [2.0, 20.0])
+def test_dense_splitting_original_equals_peaceman_rachford(scheme, cfl):
+    """(orgDY) and the delta formulation give the Peaceman-Rachford fields of
+    (clsADI): (I - dt/2 A)^-1 and (I + dt/2 A) commute, and the delta form is
+    the same product written for the increment.  A wrong sign or a dropped
+    operator in either formula breaks the equality."""
+    g = small_grid(seed=21, cfl=cfl)
+    ds = dense.DenseSystem(g)
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 22))
+    x_pr, _ = dense.run_original(ds, "adi", x0, 12)
+    x, mids = dense.run_splitting_original(ds, scheme, x0, 12)
+    assert len(mids) == 12
+    assert _wrel(ds, x, x_pr) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", oracle.SPLITTINGS)
+def test_dense_splitting_fundamental_equals_original(scheme):
+    """(fastDY) with its input reproduces (orgDY) step by step, including the
+    intermediate u* = 2 v^{n+1/2}; (fasterADI) with the increments of (fastDGo)
+    reproduces the delta formulation's du* and du at every step."""
+    g = small_grid(seed=23, cfl=12.0)
+    ds = dense.DenseSystem(g)
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 24))
+    xo, mo = dense.run_splitting_original(ds, scheme, x0, 10)
+    xf, mf = dense.run_splitting_fundamental(ds, scheme, x0, 10)
+    assert _wrel(ds, xf, xo) < 1e-12
+    for a, b in zip(mf, mo):
+        if scheme == "dy":
+            assert _wrel(ds, a, b) < 1e-12
+        else:
+            assert _wrel(ds, a[0], b[0]) < 1e-11 and _wrel(ds, a[1], b[1]) < 1e-11
+
+
+def test_dyakonov_intermediate_is_original_adi_auxiliary():
+    """u* of (orgDY) equals (I + dt/2 A) u^{n+1/2} of the original ADI
+    (orgADIc), and differs from u^{n+1/2} itself."""
+    g = small_grid(seed=25, cfl=6.0)
+    ds = dense.DenseSystem(g)
+    I, h = np.eye(ds.n), 0.5 * g.dt
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 26))
+    _, mids = dense.run_splitting_original(ds, "dy", x0, 1)
+    u_half = np.linalg.solve(I - h * ds.A, (I + h * ds.B) @ x0)
+    assert _wrel(ds, mids[0], (I + h * ds.A) @ u_half) < 1e-12
+    assert _wrel(ds, mids[0], u_half) > 1e-3
+
+
+@pytest.mark.parametrize("scheme", oracle.SPLITTINGS)
+@pytest.mark.parametrize("form", oracle.FORMS)
+def test_splitting_component_form_matches_dense(scheme, form):
+    g = small_grid(seed=27, cfl=8.0)
+    ds = dense.DenseSystem(g)
+    u0 = W.random_fields(g.nx, g.ny, g.nz, 28)
+    x_ref, _ = dense.run_splitting_original(ds, scheme, ds.to_vec(u0), 9)
+    u, _ = oracle.run(scheme, form, g, u0, 9)
+    assert _wrel(ds, ds.to_vec(u), x_ref) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", oracle.SPLITTINGS)
+def test_splitting_fields_equal_adi_larger_grid(scheme):
+    nx, ny, nz = 12, 10, 11
+    eps = W.random_box_eps(nx, ny, nz, seed=2, nboxes=8)
+    g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, 10.0), eps)
+    u0 = W.random_fields(nx, ny, nz, 3)
+    ua, ta = oracle.run("adi", "conventional", g, u0, 25, None, 1)
+    for form in oracle.FORMS:
+        u, t = oracle.run(scheme, form, g, u0, 25, None, 1)
+        assert yee.weighted_rel_l2(u, ua, g) < 1e-12
+        assert np.allclose(t, ta, rtol=1e-12)
+        assert np.abs(np.array(t) - t[0]).max() / t[0] < 1e-12   # conserved
+
+
+def test_splittings_take_no_source():
+    g = small_grid(seed=29)
+    u0 = W.random_fields(g.nx, g.ny, g.nz, 30)
+    with pytest.raises(ValueError):
+        oracle.run("dy", "fundamental", g, u0, 2, _src(g))
 
 
 # --------------------------------------------------------------------------
