@@ -29,6 +29,8 @@ Stable Implicit FDTD Methods", arXiv 2011.14043):
 * ``dense``        -- a dense-matrix version of every scheme for tiny grids,
                       with A and B assembled node by node from Maxwell's curl
                       equations (independent of ``yee``);
+* ``crank_nicolson`` -- Crank-Nicolson without factorization, original and
+                      fundamental forms (Sec. II-E), sparse direct solves;
 * ``source``       -- the point-source convention for the nonhomogeneous terms
                       that the paper omits (Sec. II opening);
 * ``run``          -- one entry point ``run(...)`` over schemes and forms.
@@ -39,7 +41,8 @@ closed forms, brute-force dense solves or finite differences.
 from .yee import (EPS0, MU0, C0, Grid, COMPONENTS, dynamic_mask, energy,
                   apply_operator, cfl_dt)
 from .tridiag import thomas
-from .run import run, SCHEMES, FORMS, SPLITTINGS
+from .run import run, SCHEMES, FORMS, SPLITTINGS, UNFACTORIZED
 
 __all__ = ["EPS0", "MU0", "C0", "Grid", "COMPONENTS", "dynamic_mask", "energy",
-           "apply_operator", "cfl_dt", "thomas", "run", "SCHEMES", "FORMS", "SPLITTINGS"]
+           "apply_operator", "cfl_dt", "thomas", "run", "SCHEMES", "FORMS", "SPLITTINGS",
+           "UNFACTORIZED"]

@@ -20,7 +20,7 @@ from .yee import COMPONENTS, CIDX, EPS0, MU0, Grid, dynamic_mask
 
 
 class DenseSystem:
-    def __init__(self, g: Grid):
+    def __init__(self, g: Grid, sparse: bool = False):
         self.g = g
         self.index = {}
         self.nodes = []
@@ -30,9 +30,16 @@ class DenseSystem:
                 self.index[(c, int(k), int(j), int(i))] = len(self.nodes)
                 self.nodes.append((c, int(k), int(j), int(i)))
         self.n = len(self.nodes)
-        self.A = np.zeros((self.n, self.n))
-        self.B = np.zeros((self.n, self.n))
+        if sparse:   # same assembly into (row, col, value) lists (larger grids)
+            self.A, self.B = [], []
+        else:
+            self.A = np.zeros((self.n, self.n))
+            self.B = np.zeros((self.n, self.n))
         self._assemble()
+        if sparse:
+            from scipy.sparse import csr_matrix
+            self.A, self.B = ([csr_matrix((np.array([t[2] for t in M]), ([t[0] for t in M], [t[1] for t in M])),
+                                          shape=(self.n, self.n)) for M in (self.A, self.B)])
         self.w = np.array([self._material(c, k, j, i) for c, k, j, i in self.nodes])
 
     def _material(self, c, k, j, i):
@@ -48,7 +55,10 @@ class DenseSystem:
             # only wall E (which is 0) may be referenced outside the dynamic set
             assert comp[0] == "E", (comp, k, j, i)
             return
-        M[row, col] += val
+        if isinstance(M, list):
+            M.append((row, col, val))   # duplicates are summed by csr_matrix
+        else:
+            M[row, col] += val
 
     def _assemble(self):
         g = self.g

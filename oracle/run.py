@@ -8,13 +8,15 @@ iteration state.
 """
 from __future__ import annotations
 
-from . import conventional, fundamental
+from . import conventional, crank_nicolson, fundamental
 from .yee import Grid, clean
 
 SCHEMES = ("adi", "lod1", "ss2", "lod2")
 FORMS = ("fundamental", "conventional")
 # D'Yakonov and Douglas-Gunn splittings of Sec. II-E (no nonhomogeneous terms)
 SPLITTINGS = ("dy", "dg")
+# Crank-Nicolson without factorization (Sec. II-E), a global sparse solve per step
+UNFACTORIZED = ("cn",)
 
 
 def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
@@ -25,8 +27,12 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
     (see ``conventional.invariant``) at steps 0, e, 2e, ... (e = energy_every;
     empty if 0).  Tangential E on the walls is treated as 0 on input.
     """
-    if (scheme not in SCHEMES and scheme not in SPLITTINGS) or form not in FORMS:
+    if (scheme not in SCHEMES + SPLITTINGS + UNFACTORIZED) or form not in FORMS:
         raise ValueError((scheme, form))
+    if scheme == "cn":
+        if source is not None:
+            raise ValueError("Crank-Nicolson takes no source")
+        return crank_nicolson.run_fields(g, fields, steps, form, energy_every)
     u = clean(fields, g)
     trace = []
 

@@ -142,3 +142,12 @@ def adi_dispersion_cos(nx, ny, nz, dx, dy, dz, m, n, p, dt, c=C0):
     s = [c * dt / 2 * Kw for Kw in K]
     cw = [(1 - x * x) / (1 + x * x) for x in s]
     return (cw[0] * cw[1] + cw[1] * cw[2] + cw[2] * cw[0] - 1) / 2
+
+
+def cn_phase(nx, ny, nz, dx, dy, dz, m, n, p, dt, c=C0):
+    """Phase per step of Crank-Nicolson on mode (m, n, p): the Cayley factor of
+    dt (A + B)/2 maps the eigenvalues +-i w of A + B, w = c |K| (the Yee
+    frequency), to e^{+-i phi} with phi = 2 atan(w dt / 2)."""
+    _, K = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p)
+    w = c * math.sqrt(sum(k * k for k in K))
+    return 2.0 * math.atan(0.5 * w * dt)

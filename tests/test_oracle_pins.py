@@ -7,7 +7,8 @@
 * invariants: skew-adjointness of A and B, exact energy conservation of the
   Cayley sub-steps, the fundamental == original equivalence (Sec. II-A
   closing paragraph, Sec. II-B construction), the ADI <-> LOD link (Sec. II-E),
-  the D'Yakonov and Douglas-Gunn splittings against Peaceman-Rachford (Sec. II-E);
+  the D'Yakonov and Douglas-Gunn splittings against Peaceman-Rachford (Sec. II-E),
+  Crank-Nicolson (fundamental == classical, the closed-form Cayley phase);
 * the temporal orders of Table I (2, 1, 2, 2).
 """
 import math
@@ -276,6 +277,84 @@ def test_splittings_take_no_source():
     u0 = W.random_fields(g.nx, g.ny, g.nz, 30)
     with pytest.raises(ValueError):
         oracle.run("dy", "fundamental", g, u0, 2, _src(g))
+
+
+# --------------------------------------------------------------------------
+# Crank-Nicolson without factorization (Sec. II-E)
+# --------------------------------------------------------------------------
+
+def test_sparse_assembly_equals_dense():
+    g = small_grid(seed=31, cfl=8.0)
+    d, s_ = dense.DenseSystem(g), dense.DenseSystem(g, sparse=True)
+    assert np.array_equal(d.A, s_.A.toarray()) and np.array_equal(d.B, s_.B.toarray())
+
+
+@pytest.mark.parametrize("cfl", [2.0, 20.0])
+def test_cn_fundamental_equals_original_dense(cfl):
+    """[1/2 I - dt/4 (A+B)] v = u, u' = v - u against the classical form, both
+    written here with dense solves on the assembled matrices."""
+    from oracle import crank_nicolson as cn
+    g = small_grid(seed=33, cfl=cfl)
+    ds = dense.DenseSystem(g)
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 34))
+    I, K = np.eye(ds.n), ds.A + ds.B
+    x_ref = x0.copy()
+    for _ in range(8):
+        x_ref = np.linalg.solve(I - 0.5 * g.dt * K, (I + 0.5 * g.dt * K) @ x_ref)
+    xs = dense.DenseSystem(g, sparse=True)
+    for form in oracle.FORMS:
+        x, tr = cn.run(xs, x0, 8, form)
+        assert _wrel(ds, x, x_ref) < 1e-12
+        assert np.abs(np.array(tr) / tr[0] - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize("mnp", [(1, 1, 1), (2, 1, 3)])
+@pytest.mark.parametrize("cfl", [1.0, 8.0])
+def test_cn_cavity_mode_closed_form_phase(mnp, cfl):
+    """On a PEC cavity mode the oracle's step is the 6x6 Cayley factor of
+    dt (A + B)/2, whose rotation angle is 2 atan(w dt / 2) with w the Yee
+    frequency (closed form, not from the oracle)."""
+    nx, ny, nz, dx, dy, dz = 10, 8, 9, 1e-3, 1.1e-3, 0.9e-3
+    dt = yee.cfl_dt(dx, dy, dz, cfl)
+    g = yee.Grid(nx, ny, nz, dx, dy, dz, dt)
+    a = np.random.default_rng(6).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, dx, dy, dz, *mnp)
+    C = an.cayley(A6 + B6, 0.5 * dt)
+    ang = np.sort(np.abs(np.angle(np.linalg.eigvals(C))))
+    phi = an.cn_phase(nx, ny, nz, dx, dy, dz, *mnp, dt)
+    assert np.allclose(ang, [0, 0, phi, phi, phi, phi], atol=1e-10)
+    N = 12
+    u0 = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, a)
+    ref = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, np.linalg.matrix_power(C, N) @ a)
+    for form in oracle.FORMS:
+        u, _ = oracle.run("cn", form, g, u0, N)
+        assert yee.weighted_rel_l2(u, ref, g) < 1e-12
+
+
+def test_cn_temporal_order_two():
+    nx, ny, nz, h = 8, 7, 6, 1e-3
+    a = np.random.default_rng(7).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, h, h, h, 1, 1, 1)
+    T = 40 * yee.cfl_dt(h, h, h, 1.0)
+    ref = an.exact(A6, B6, T) @ a
+    w = np.r_[[an.EPS0] * 3, [an.MU0] * 3]
+    errs = []
+    for N in (640, 1280, 2560):
+        x = np.linalg.matrix_power(an.cayley(A6 + B6, 0.5 * T / N), N) @ a
+        errs.append(math.sqrt(np.sum(w * (x - ref) ** 2) / np.sum(w * ref ** 2)))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(s_ - 2) < 0.1 for s_ in slopes), (errs, slopes)
+
+
+def test_cn_energy_conserved_and_no_source():
+    nx, ny, nz = 9, 8, 7
+    eps = W.random_box_eps(nx, ny, nz, seed=9, nboxes=6)
+    g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, 20.0), eps)
+    u0 = W.random_fields(nx, ny, nz, 10)
+    _, tr = oracle.run("cn", "fundamental", g, u0, 30, None, 1)
+    assert len(tr) == 31 and np.abs(np.array(tr) / tr[0] - 1).max() < 1e-12
+    with pytest.raises(ValueError):
+        oracle.run("cn", "fundamental", g, u0, 2, _src(g))
 
 
 # --------------------------------------------------------------------------
