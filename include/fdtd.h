@@ -48,7 +48,9 @@ typedef enum {
     FDTD_ENOMEM = -2,        /* device allocation failed                             */
     FDTD_EDEVICE = -3,       /* HIP runtime error                                    */
     FDTD_EUNSUPPORTED = -4,  /* valid request the library does not implement         */
-    FDTD_ENONFINITE = -5     /* NaN/Inf found in the energy after stepping           */
+    FDTD_ENONFINITE = -5,    /* NaN/Inf found in the energy after stepping           */
+    FDTD_ENOTCONVERGED = -6  /* an iterative solve stopped at its iteration limit    */
+                             /* above its tolerance (Crank-Nicolson plans)           */
 } fdtd_status;
 
 /* FDTD_DYAKONOV and FDTD_DOUGLAS_GUNN (Sec. II-E) take the fundamental form
@@ -63,9 +65,21 @@ typedef enum {
  * u^{n+1} = v^{n+1/2} + v^{n+1}), so these plans run the fundamental ADI
  * passes, input and output processing unchanged: same fields, energy trace,
  * kernels and cost.  Batches accept them too. */
+/* FDTD_CRANK_NICOLSON (Sec. II-E, closing part) is the unfactorized scheme in
+ * its fundamental form, [1/2 I - dt/4 (A + B)] u^{n+1/2} = u^n,
+ * u^{n+1} = u^{n+1/2} - u^n: one global sparse system per step instead of line
+ * solves.  With theta = dt/2 the H rows are eliminated, leaving for E the
+ * symmetric positive definite system eps v + theta^2 C_H(mu^-1 C_E(v)) =
+ * 2 eps u_E + 2 theta C_H(u_H) (C_E, C_H the discrete curls), which each step
+ * solves by conjugate gradients with the diagonal as preconditioner, started
+ * from v = 2 u_E, to the relative residual of fdtd_set_cg.  Fundamental form
+ * and FDTD_F64 only, no source (else FDTD_EUNSUPPORTED); no batches, adjoint
+ * or kernel configuration (no line passes).  fdtd_run returns
+ * FDTD_ENOTCONVERGED, with every step done, if some step ended at the
+ * iteration limit above the tolerance. */
 typedef enum {
     FDTD_ADI = 0, FDTD_LOD1 = 1 /* == SS1 */, FDTD_SS2 = 2, FDTD_LOD2 = 3,
-    FDTD_DYAKONOV = 4, FDTD_DOUGLAS_GUNN = 5
+    FDTD_DYAKONOV = 4, FDTD_DOUGLAS_GUNN = 5, FDTD_CRANK_NICOLSON = 6
 } fdtd_scheme;
 typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
 /* Precision: FDTD_F32 keeps fields in FP32 and solves in FP32; FDTD_F64 uses
@@ -202,6 +216,16 @@ fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms);
 fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int nsteps,
                           const fdtd_source* src, int probe_i, int probe_j, int probe_k,
                           const int* design_box, int ckpt_every, double* J_out, double* grad_out);
+
+/* Conjugate-gradient controls of a Crank-Nicolson plan (else
+ * FDTD_EUNSUPPORTED): stop when |r| <= tol |b| (0 < tol < 1, checked every
+ * fourth iteration) or after maxit >= 1 iterations.  Defaults 1e-12, 500. */
+fdtd_status fdtd_set_cg(fdtd_plan_t p, double tol, int maxit);
+
+/* Conjugate-gradient iterations summed over the steps of the last fdtd_run of
+ * a Crank-Nicolson plan, and the largest final |r| / |b| among those steps
+ * (host pointers, either may be NULL). */
+fdtd_status fdtd_last_cg(fdtd_plan_t p, long long* iterations, double* rel_residual);
 
 /* Batch of independent grids stepped together (fundamental forms only, else
  * FDTD_EUNSUPPORTED).  d[0..n-1] describe the grids (each validated as by

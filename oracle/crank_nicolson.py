@@ -23,7 +23,7 @@ import scipy.sparse as sp
 from scipy.sparse.linalg import splu
 
 from .dense import DenseSystem
-from .yee import Grid, clean
+from .yee import Grid, clean, energy
 
 
 def run(ds: DenseSystem, x0: np.ndarray, steps: int, form: str = "fundamental"):
@@ -55,6 +55,10 @@ def run_fields(g: Grid, fields, steps: int, form: str = "fundamental", energy_ev
     normal H passed through); trace at steps 0, e, 2e, ... (e = energy_every)."""
     u = clean(fields, g)
     ds = DenseSystem(g, sparse=True)
-    x, tr = run(ds, ds.to_vec(u), steps, form)
-    trace = tr[::energy_every] if energy_every else []
+    x0 = ds.to_vec(u)
+    x, tr = run(ds, x0, steps, form)
+    # the trace is W over all samples: the static normal H on the walls, which
+    # the dynamic-node vector leaves out, adds a constant
+    static = energy(u, g) - ds.energy(x0)
+    trace = [t + static for t in tr[::energy_every]] if energy_every else []
     return ds.from_vec(x, u), trace

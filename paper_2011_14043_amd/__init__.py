@@ -140,6 +140,17 @@ class Plan:
         return {"main_ms": main.value, "yz_ms_avg": avg[0], "x_ms_avg": avg[1],
                 "yz_launches": cnt[0], "x_launches": cnt[1]}
 
+    def set_cg(self, tol: float = 1e-12, maxit: int = 500):
+        """Conjugate-gradient controls of a Crank-Nicolson plan."""
+        _lib.check(_lib.lib().fdtd_set_cg(self._h, float(tol), int(maxit)), "fdtd_set_cg")
+
+    def last_cg(self):
+        """{'iterations': CG iterations of the last run, 'rel_residual': largest final |r|/|b|}."""
+        it = ctypes.c_longlong()
+        rel = ctypes.c_double()
+        _lib.check(_lib.lib().fdtd_last_cg(self._h, ctypes.byref(it), ctypes.byref(rel)), "fdtd_last_cg")
+        return {"iterations": it.value, "rel_residual": rel.value}
+
     def kernel_config(self, axis: int) -> dict:
         """Kernel configuration of the passes along axis 0 (x), 1 (y), 2 (z)."""
         c = _lib.FdtdKernelConfig()

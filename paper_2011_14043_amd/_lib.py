@@ -13,15 +13,16 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 FDTD_OK = 0
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ENOMEM", -3: "FDTD_EDEVICE",
-          -4: "FDTD_EUNSUPPORTED", -5: "FDTD_ENONFINITE"}
+          -4: "FDTD_EUNSUPPORTED", -5: "FDTD_ENONFINITE", -6: "FDTD_ENOTCONVERGED"}
 SCHEMES = {"adi": 0, "lod1": 1, "ss1": 1, "ss2": 2, "lod2": 3,
-           "dyakonov": 4, "dy": 4, "douglas_gunn": 5, "dg": 5}
+           "dyakonov": 4, "dy": 4, "douglas_gunn": 5, "dg": 5, "crank_nicolson": 6, "cn": 6}
 FORMS = {"fundamental": 0, "conventional": 1}
 DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2, "f32_refine": 3}
 
 EXPORTS = ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
            "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-           "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_destroy", "fdtd_strerror")
+           "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_set_cg", "fdtd_last_cg",
+           "fdtd_destroy", "fdtd_strerror")
 
 
 class FdtdDesc(ctypes.Structure):
@@ -78,12 +79,15 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     L.fdtd_plan_batch.argtypes = [ctypes.POINTER(FdtdDesc), ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.fdtd_run_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int]
+    L.fdtd_set_cg.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+    L.fdtd_last_cg.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.fdtd_destroy.argtypes = [vp]
     L.fdtd_strerror.argtypes = [ctypes.c_int]
     L.fdtd_strerror.restype = ctypes.c_char_p
     for name in ("fdtd_plan", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
                  "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-                 "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_destroy"):
+                 "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_set_cg", "fdtd_last_cg",
+                 "fdtd_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

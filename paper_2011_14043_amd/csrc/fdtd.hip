@@ -29,6 +29,7 @@
 #include "adjoint_kernels.hpp"
 #include "aux_kernels.hpp"
 #include "batch_kernels.hpp"
+#include "cn_kernels.hpp"
 #include "pass_kernels.hpp"
 #include "plan_state.hpp"
 #include "pass_launch.hpp"
@@ -36,6 +37,7 @@
 #include "run_loop.hpp"
 #include "adjoint_grad.hpp"
 #include "batch_plan.hpp"
+#include "cn_solver.hpp"
 
 using namespace fdtd;
 
@@ -51,6 +53,7 @@ const char* fdtd_strerror(fdtd_status s) {
         case FDTD_EDEVICE: return "HIP runtime error";
         case FDTD_EUNSUPPORTED: return "not supported by this library";
         case FDTD_ENONFINITE: return "non-finite energy after stepping";
+        case FDTD_ENOTCONVERGED: return "iterative solve not converged";
     }
     return "unknown status";
 }
@@ -62,8 +65,10 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!(d->dt > 0) || !(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return FDTD_EINVAL;
     if (!std::isfinite(d->dt) || !std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz))
         return FDTD_EINVAL;
-    if (d->scheme < 0 || d->scheme > 5 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
+    if (d->scheme < 0 || d->scheme > 6 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
         return FDTD_EINVAL;
+    const bool cn = d->scheme == FDTD_CRANK_NICOLSON;
+    if (cn && (d->form != FDTD_FUNDAMENTAL || d->dtype != FDTD_F64)) return FDTD_EUNSUPPORTED;
     // D'Yakonov and Douglas-Gunn: the fundamental ADI iteration (Sec. II-E)
     fdtd_desc as_adi;
     int splitting = 0;
@@ -118,6 +123,9 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
         if (p->partial) (void)hipFree(p->partial);
         if (p->mat) (void)hipFree(p->mat);
         if (p->mat_eps) (void)hipFree(p->mat_eps);
+        if (p->cg) (void)hipFree(p->cg);
+        if (p->cg_partial) (void)hipFree(p->cg_partial);
+        if (p->cg_scal) (void)hipFree(p->cg_scal);
         delete p;
         return st;
     };
@@ -165,6 +173,14 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     default_cfg(p);
     p->npartial = 1024;
     if ((e = hipMalloc(&p->partial, sizeof(double) * p->npartial)) != hipSuccess) return fail(from_hip(e));
+    if (cn) {
+        const size_t bytes = sizeof(double) * 15 * (size_t)dm.comp;
+        if ((e = hipMalloc(&p->cg, bytes)) != hipSuccess) return fail(from_hip(e));
+        if ((e = hipMemset(p->cg, 0, bytes)) != hipSuccess) return fail(from_hip(e));
+        if ((e = hipMalloc(&p->cg_partial, sizeof(double) * 3 * kCnBlocks)) != hipSuccess) return fail(from_hip(e));
+        if ((e = hipMalloc(&p->cg_scal, sizeof(double) * kCnScalars)) != hipSuccess) return fail(from_hip(e));
+        if ((e = hipMemset(p->cg_scal, 0, sizeof(double) * kCnScalars)) != hipSuccess) return fail(from_hip(e));
+    }
     *out = p;
     return FDTD_OK;
 }
@@ -175,7 +191,7 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
     for (int c = 0; c < 3; ++c)
         if (!E[c] || !H[c]) return FDTD_EINVAL;
     if (energy && energy_every < 1) return FDTD_EINVAL;
-    if (src && p->splitting) return FDTD_EUNSUPPORTED;
+    if (src && (p->splitting || p->cg)) return FDTD_EUNSUPPORTED;
     if (src) {
         if (src->i < 1 || src->i >= p->d.nx || src->j < 1 || src->j >= p->d.ny || src->k < 0 || src->k >= p->d.nz)
             return FDTD_EINVAL;
@@ -186,7 +202,8 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
     (void)hipGetDevice(&dev_now);
     if (dev_now != p->device) (void)hipSetDevice(p->device);
     fdtd_status st;
-    if (p->d.dtype == FDTD_F32) st = run_impl<float, float>(p, E, H, nsteps, src, energy, energy_every);
+    if (p->cg) st = cn_run_impl(p, E, H, nsteps, energy, energy_every);
+    else if (p->d.dtype == FDTD_F32) st = run_impl<float, float>(p, E, H, nsteps, src, energy, energy_every);
     else if (p->d.dtype == FDTD_F64) st = run_impl<double, double>(p, E, H, nsteps, src, energy, energy_every);
     else st = run_impl<float, double>(p, E, H, nsteps, src, energy, energy_every);
     if (dev_now != p->device) (void)hipSetDevice(dev_now);
@@ -249,6 +266,7 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* fam_ms_avg,
 
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
     if (!plan_ok(p) || reps < 1) return FDTD_EINVAL;
+    if (p->cg) return FDTD_EUNSUPPORTED;   // Crank-Nicolson: no line passes
     if (p->batch && !p->batch->groups.empty()) {
         // each group tunes for its own grids; best_ms: one pass over all groups
         double tot[3] = {0, 0, 0};
@@ -288,6 +306,7 @@ fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
 
 fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* c) {
     if (!plan_ok(p) || axis < 0 || axis > 2 || !c) return FDTD_EINVAL;
+    if (p->cg) return FDTD_EUNSUPPORTED;
     const KCfg& k = p->cfg[axis];
     c->chunk = k.M;
     c->tile_x = axis == 0 ? 0 : k.TX;
@@ -298,6 +317,7 @@ fdtd_status fdtd_get_kernel_config(fdtd_plan_t p, int axis, fdtd_kernel_config* 
 
 fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_config* c) {
     if (!plan_ok(p) || axis < 0 || axis > 2 || !c) return FDTD_EINVAL;
+    if (p->cg) return FDTD_EUNSUPPORTED;
     KCfg k{c->chunk, axis == 0 ? 0 : c->tile_x, axis == 0 ? 0 : c->block_threads,
            axis == 0 ? c->block_threads / 64 : 0, c->remap};
     if (axis == 0 && c->block_threads % 64 != 0) return FDTD_EINVAL;
@@ -363,10 +383,10 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     *out = nullptr;
     for (int g = 0; g < n; ++g) {
         if (d[g].scheme != d[0].scheme || d[g].form != d[0].form || d[g].dtype != d[0].dtype) return FDTD_EINVAL;
-        if (d[g].scheme < 0 || d[g].scheme > 5 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
+        if (d[g].scheme < 0 || d[g].scheme > 6 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
             return FDTD_EINVAL;
     }
-    if (d[0].form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    if (d[0].form != FDTD_FUNDAMENTAL || d[0].scheme == FDTD_CRANK_NICOLSON) return FDTD_EUNSUPPORTED;
     // D'Yakonov and Douglas-Gunn batches step as ADI (no sources in a batch)
     std::vector<fdtd_desc> as_adi;
     if (d[0].scheme == FDTD_DYAKONOV || d[0].scheme == FDTD_DOUGLAS_GUNN) {
@@ -473,6 +493,22 @@ fdtd_status fdtd_run_batch(fdtd_plan_t p, void* const* E, void* const* H, int ns
     return st;
 }
 
+fdtd_status fdtd_set_cg(fdtd_plan_t p, double tol, int maxit) {
+    if (!plan_ok(p) || !(tol > 0.0 && tol < 1.0) || maxit < 1) return FDTD_EINVAL;
+    if (!p->cg) return FDTD_EUNSUPPORTED;
+    p->cg_tol = tol;
+    p->cg_maxit = maxit;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_last_cg(fdtd_plan_t p, long long* iterations, double* rel_residual) {
+    if (!plan_ok(p)) return FDTD_EINVAL;
+    if (!p->cg) return FDTD_EUNSUPPORTED;
+    if (iterations) *iterations = p->cg_iters;
+    if (rel_residual) *rel_residual = p->cg_rel;
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (!plan_ok(p)) return FDTD_EINVAL;
     (void)hipStreamSynchronize(p->stream);
@@ -496,6 +532,9 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->mat) (void)hipFree(p->mat);
     if (p->mat_eps) (void)hipFree(p->mat_eps);
     if (p->gbuf) (void)hipFree(p->gbuf);
+    if (p->cg) (void)hipFree(p->cg);
+    if (p->cg_partial) (void)hipFree(p->cg_partial);
+    if (p->cg_scal) (void)hipFree(p->cg_scal);
     for (hipEvent_t e : p->tm.ev) (void)hipEventDestroy(e);
     if (p->tm.main0) (void)hipEventDestroy(p->tm.main0);
     if (p->tm.main1) (void)hipEventDestroy(p->tm.main1);

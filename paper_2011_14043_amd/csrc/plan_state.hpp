@@ -86,6 +86,15 @@ struct fdtd_plan_s {
     float* eps = nullptr;     // node layout, padded
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     int splitting = 0;        // FDTD_DYAKONOV / FDTD_DOUGLAS_GUNN as requested (the plan runs as ADI)
+    // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
+    // 3 x 1024 partial sums, scalars; CG controls and the last run's statistics
+    double* cg = nullptr;
+    double* cg_partial = nullptr;
+    double* cg_scal = nullptr;
+    double cg_tol = 1e-12;
+    int cg_maxit = 500;
+    long long cg_iters = 0;
+    double cg_rel = 0.0;
     float* mat_eps = nullptr;       // eps_r per material
     int nmat = 0;
     double* partial = nullptr;

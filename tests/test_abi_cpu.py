@@ -51,8 +51,9 @@ def _desc(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=1), -1), (dict(ny=0), -1), (dict(nz=-3), -1), (dict(dt=0.0), -1), (dict(dt=-1e-12), -1),
     (dict(dx=0.0), -1), (dict(dt=float("nan")), -1), (dict(dz=float("inf")), -1),
-    (dict(scheme=6), -1), (dict(scheme=-1), -1), (dict(form=2), -1), (dict(dtype=7), -1),
-    (dict(scheme=4, form=1), -4), (dict(scheme=5, form=1), -4),
+    (dict(scheme=8), -1), (dict(scheme=-1), -1), (dict(form=2), -1), (dict(dtype=7), -1),
+    (dict(scheme=4, form=1), -4), (dict(scheme=5, form=1), -4), (dict(scheme=7), -1),
+    (dict(scheme=6), -4), (dict(scheme=6, dtype=1, form=1), -4), (dict(scheme=6, dtype=3), -4),
     (dict(boundary=1), -4), (dict(mu_r=12345), -4), (dict(nx=2000), -4), (dict(nz=600, dtype=1), -4),
     (dict(dtype=4), -1), (dict(dtype=3, form=1), -4), (dict(dtype=3, ny=600), -4),
 ])
@@ -72,6 +73,8 @@ def test_null_arguments(L):
     assert L.fdtd_set_step(None, 0) == -1
     assert L.fdtd_destroy(None) == -1
     assert L.fdtd_last_timing(None, None, None, None) == -1
+    assert L.fdtd_set_cg(None, 1e-10, 10) == -1
+    assert L.fdtd_last_cg(None, None, None) == -1
 
 
 def test_forced_allocation_failure(L, monkeypatch):

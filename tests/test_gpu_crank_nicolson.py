@@ -1,0 +1,115 @@
+"""GPU parity of the Crank-Nicolson plans (Sec. II-E, unfactorized scheme in
+fundamental form, conjugate gradients per step) against the oracle's sparse
+direct solves and the closed-form Cayley amplification of cavity modes."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from . import _analytic as an
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _plan(nx, ny, nz, dt, h, eps=None, **kw):
+    from paper_2011_14043_amd import Plan
+    hx, hy, hz = h if isinstance(h, tuple) else (h, h, h)
+    return Plan(nx, ny, nz, dt, hx, hy, hz, scheme="crank_nicolson", dtype=torch.float64,
+                eps_r=None if eps is None else torch.tensor(eps), **kw)
+
+
+def _run(plan, u0, steps, every=0):
+    E = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[3:]]
+    tr = plan.run(E, H, steps, energy_every=every)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in E + H], tr
+
+
+@pytest.mark.parametrize("cfl", [2.0, 8.0])
+def test_cn_parity_random_media(cfl):
+    nx, ny, nz, h = 14, 12, 13, 1e-3
+    dt = W.yee_dt(h, h, h, cfl)
+    eps = W.random_box_eps(nx, ny, nz, seed=70, nboxes=6)
+    u0 = W.random_fields(nx, ny, nz, seed=71)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    print(f"[case] CN 14x12x13 CFL {cfl}", flush=True)
+    ref, tr_ref = oracle.run("cn", "fundamental", g, u0, 6, None, 1)
+    plan = _plan(nx, ny, nz, dt, h, eps)
+    plan.set_cg(1e-13, 2000)
+    got, tr = _run(plan, u0, 6, 1)
+    st = plan.last_cg()
+    plan.close()
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    print(f"  rel-L2 {err:.3e}  iterations {st['iterations']}  residual {st['rel_residual']:.2e}")
+    assert err < 1e-10
+    assert np.allclose(tr, tr_ref, rtol=1e-10)
+    assert st["rel_residual"] <= 1e-13 and st["iterations"] > 0
+
+
+def test_cn_cavity_mode_closed_form():
+    """A PEC cavity mode advanced by the closed-form 6x6 Cayley factor of
+    dt (A + B)/2 (anisotropic cells, CFL 6, 10 steps)."""
+    nx, ny, nz, dx, dy, dz = 24, 20, 22, 1e-3, 1.1e-3, 0.9e-3
+    mnp = (2, 3, 1)
+    dt = W.yee_dt(dx, dy, dz, 6.0)
+    a = np.random.default_rng(8).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(nx, ny, nz, dx, dy, dz, *mnp)
+    C = an.cayley(A6 + B6, 0.5 * dt)
+    u0 = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, a)
+    ref = an.mode_fields(nx, ny, nz, dx, dy, dz, *mnp, np.linalg.matrix_power(C, 10) @ a)
+    print("[case] CN cavity mode 24x20x22", flush=True)
+    plan = _plan(nx, ny, nz, dt, (dx, dy, dz))
+    got, _ = _run(plan, u0, 10)
+    plan.close()
+    g = oracle.Grid(nx, ny, nz, dx, dy, dz, dt)
+    assert oracle.yee.weighted_rel_l2(got, ref, g) < 1e-10
+
+
+def test_cn_zero_fields_and_zero_steps():
+    n, h = 10, 1e-3
+    dt = W.yee_dt(h, h, h, 4.0)
+    plan = _plan(n, n, n, dt, h)
+    z = [np.zeros((n + 1, n + 1, n + 1)) for _ in range(6)]
+    got, _ = _run(plan, z, 3)
+    assert all(np.all(a == 0.0) for a in got)
+    u0 = W.random_fields(n, n, n, seed=72)
+    got, _ = _run(plan, u0, 0)
+    for a, b in zip(got, u0):
+        assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_cn_iteration_limit_and_rejections():
+    from paper_2011_14043_amd import Plan, Source
+    n, h = 12, 1e-3
+    dt = W.yee_dt(h, h, h, 8.0)
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        Plan(n, n, n, dt, h, h, h, scheme="crank_nicolson", form="conventional", dtype=torch.float64)
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        Plan(n, n, n, dt, h, h, h, scheme="crank_nicolson", dtype=torch.float32)
+    plan = _plan(n, n, n, dt, h)
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        plan.set_cg(0.0, 10)
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        plan.autotune(1)
+    u0 = W.random_fields(n, n, n, seed=73)
+    E = [torch.tensor(a, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, device=DEV) for a in u0[3:]]
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        plan.run(E, H, 1, source=Source(6, 6, 6, f0=1e10, tau=1e-10, t0=4e-10, amp=1.0))
+    plan.set_cg(1e-14, 2)
+    with pytest.raises(RuntimeError, match="ENOTCONVERGED"):
+        plan.run(E, H, 2)
+    torch.cuda.synchronize()
+    st = plan.last_cg()
+    assert st["iterations"] == 4 and st["rel_residual"] > 1e-14
+    plan.close()
+    other = Plan(n, n, n, dt, h, h, h, scheme="adi", dtype=torch.float64)
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        other.set_cg(1e-10, 10)
+    other.close()

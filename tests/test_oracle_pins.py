@@ -351,8 +351,9 @@ def test_cn_energy_conserved_and_no_source():
     eps = W.random_box_eps(nx, ny, nz, seed=9, nboxes=6)
     g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, 20.0), eps)
     u0 = W.random_fields(nx, ny, nz, 10)
-    _, tr = oracle.run("cn", "fundamental", g, u0, 30, None, 1)
+    u, tr = oracle.run("cn", "fundamental", g, u0, 30, None, 1)
     assert len(tr) == 31 and np.abs(np.array(tr) / tr[0] - 1).max() < 1e-12
+    assert abs(tr[-1] / yee.energy(u, g) - 1) < 1e-13   # W over all samples
     with pytest.raises(ValueError):
         oracle.run("cn", "fundamental", g, u0, 2, _src(g))
 
