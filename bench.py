@@ -259,6 +259,54 @@ def run_adjoint(prec="f32", steps=500, ckpt=50):
     return out
 
 
+def run_cn(n=256, steps=10, tol=1e-12):
+    """Crank-Nicolson without factorization (FP64, one CG solve per step)
+    against fundamental ADI (FP64) on the same n^3 random-box medium at CFL 5,
+    from the same seeded N(0,1) fields (Crank-Nicolson takes no source)."""
+    import torch
+    from paper_2011_14043_amd import Plan
+    h, dt, eps, _ = make_inputs(n)
+    dev = torch.device("cuda", 0)
+    shape = (n + 1, n + 1, n + 1)
+    out = dict(workload=f"{n}^3 random-box eps_r, CFL 5, N(0,1) initial fields, no source", prec="f64", steps=steps,
+               cg_tol=tol)
+    for scheme in ("crank_nicolson", "adi"):
+        gen = torch.Generator(device=dev).manual_seed(11)
+        E = [torch.empty(shape, dtype=torch.float64, device=dev).normal_(generator=gen) for _ in range(3)]
+        H = [torch.empty(shape, dtype=torch.float64, device=dev).normal_(generator=gen) for _ in range(3)]
+        plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, dtype=torch.float64, eps_r=torch.from_numpy(eps))
+        if scheme == "adi":
+            plan.autotune(3)
+        else:
+            plan.set_cg(tol, 5000)
+        plan.run(E, H, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(E, H, steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        key = "cn" if scheme == "crank_nicolson" else "adi"
+        out[f"{key}_ms_per_step"] = ms
+        out[f"{key}_mcells_per_s"] = n ** 3 / (ms * 1e-3) / 1e6
+        if scheme == "crank_nicolson":
+            st = plan.last_cg()
+            it = st["iterations"] / steps
+            out["cg_iterations_per_step"] = it
+            out["cg_rel_residual_max"] = st["rel_residual"]
+            # algorithmic bytes of one CG iteration: 348 B per node in FP64
+            # (curl: p -> w; apply: p, w, eps -> q; update: x, p, r, q, eps -> x, r;
+            # direction: r, p, eps -> p), kernels over all (n+1)^3 nodes
+            out["cg_iteration_gbs"] = 348 * (n + 1) ** 3 * it / (ms * 1e-3) / 1e9
+        finite = all(bool(torch.isfinite(t).all()) for t in E + H)
+        out[f"{key}_finite"] = finite
+        plan.close()
+        del E, H
+        torch.cuda.empty_cache()
+    out["cn_over_adi"] = out["cn_ms_per_step"] / out["adi_ms_per_step"]
+    log(json.dumps(out))
+    return out
+
+
 def cpu_baseline(n=256, steps=3):
     """The FP64 oracle (fundamental ADI) on the host, single thread, on a
     bounded sample of the same workload (n^3 cells, `steps` steps)."""
@@ -289,7 +337,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-cavity and adjoint lines")
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["batch", "adjoint", "cn"], default=None,
                     help="run only the batched-cavity or the adjoint measurement and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
@@ -315,6 +363,9 @@ def main():
     if args.only == "adjoint":
         print(json.dumps(run_adjoint()), flush=True)
         return
+    if args.only == "cn":
+        print(json.dumps(run_cn()), flush=True)
+        return
     n = args.n
     inputs = make_inputs(n)
     log(f"[bench] {n}^3, {args.steps} steps, warmup {args.warmup}")
@@ -324,6 +375,7 @@ def main():
     if not args.no_extras:
         extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
         extras["adjoint_gradient"] = run_adjoint()
+        extras["crank_nicolson_256cube"] = run_cn()
         # the smaller size of the same workload (256^3), plain and refined FP32
         in256 = make_inputs(256)
         extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256)
