@@ -55,43 +55,82 @@ static void batch_default_cfg(fdtd_plan_s* p) {
     }
 }
 
-// The table of pass (op, k) with theta = frac * dt for every grid (built on
-// first use with the current kernel configuration).
+// y and z lines share a kernel; their passes can run as one launch when the
+// two axes have the same configuration.
+static bool yz_same_cfg(const fdtd_plan_s* p) {
+    return p->cfg[1].M == p->cfg[2].M && p->cfg[1].TX == p->cfg[2].TX && p->cfg[1].NT == p->cfg[2].NT;
+}
+
+// Launches of one sub-step with operator op: the x-line pair alone, the y- and
+// z-line pairs together when they share a configuration (else one each).
+static int substep_masks(const fdtd_plan_s* p, int op, int (&masks)[3]) {
+    int yz = 0, n = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (kPairs[op][k].w == 0) masks[n++] = 1 << k;
+        else yz |= 1 << k;
+    }
+    if (yz_same_cfg(p)) {
+        masks[n++] = yz;
+    } else {
+        for (int k = 0; k < 3; ++k)
+            if (yz & (1 << k)) masks[n++] = 1 << k;
+    }
+    return n;
+}
+
+// The table of the passes (op, k in mask) with theta = frac * dt for every grid
+// (built on first use with the current kernel configuration).  Entry
+// j * ngrids + g is the j-th pair of the mask on grid g; a work item (entry,
+// block) names one block of one of them.
 template <typename T, typename S>
-static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const BatchPass** out) {
+static fdtd_status batch_pass(fdtd_plan_s* p, int op, int mask, double frac, const BatchPass** out) {
     Batch* b = p->batch;
     for (const BatchPass& bp : b->passes)
-        if (bp.op == op && bp.k == k && bp.frac == frac) { *out = &bp; return FDTD_OK; }
-    const int w = kPairs[op][k].w;
+        if (bp.op == op && bp.mask == mask && bp.frac == frac) { *out = &bp; return FDTD_OK; }
+    int ks[3], nk = 0;
+    for (int k = 0; k < 3; ++k)
+        if (mask & (1 << k)) ks[nk++] = k;
+    if (nk == 0) return FDTD_EINVAL;
+    const int w = kPairs[op][ks[0]].w;
     const KCfg& cf = p->cfg[w];
+    for (int j = 1; j < nk; ++j) {   // one launch needs one kernel configuration
+        const KCfg& c2 = p->cfg[kPairs[op][ks[j]].w];
+        if ((w == 0) != (kPairs[op][ks[j]].w == 0) || c2.M != cf.M || c2.TX != cf.TX || c2.NT != cf.NT)
+            return FDTD_EINVAL;
+    }
     const int n = (int)b->subs.size();
-    std::vector<PassArgs<T, S>> tab(n);
+    const int ne = n * nk;
+    std::vector<PassArgs<T, S>> tab(ne);
     int Pmax = 1;
-    for (int g = 0; g < n; ++g) {
-        fdtd_plan_s* sub = b->subs[g];
-        sub->cfg[w] = cf;
-        PassShape sh;
-        build_pass<T, S>(sub, op, k, frac * sub->d.dt, FUND, set_ptr<T>(sub, 0), set_ptr<T>(sub, 0), nullptr,
-                         tab[g], sh);
-        tab[g].P = batch_P(sub, w, cf);
-        tab[g].remap = 0;
-        Pmax = std::max(Pmax, tab[g].P);
+    for (int j = 0; j < nk; ++j) {
+        const int wj = kPairs[op][ks[j]].w;
+        for (int g = 0; g < n; ++g) {
+            fdtd_plan_s* sub = b->subs[g];
+            PassArgs<T, S>& a = tab[j * n + g];
+            sub->cfg[wj] = p->cfg[wj];
+            PassShape sh;
+            build_pass<T, S>(sub, op, ks[j], frac * sub->d.dt, FUND, set_ptr<T>(sub, 0), set_ptr<T>(sub, 0), nullptr,
+                             a, sh);
+            a.P = batch_P(sub, wj, p->cfg[wj]);
+            a.remap = 0;
+            Pmax = std::max(Pmax, a.P);
+        }
     }
     std::vector<int2> items;
-    int lds_rows = 0;   // y/z: sub-block areas x chunks, the most any grid needs
-    for (int g = 0; g < n; ++g) {
-        const int per = (w == 0) ? 1 : Pmax / tab[g].P;   // virtual blocks per block
-        const int nit = (tab[g].nblk + per - 1) / per;
-        for (int q = 0; q < nit; ++q) items.push_back(make_int2(g, q));
-        if (w != 0) lds_rows = std::max(lds_rows, ((Pmax + tab[g].P - 1) / tab[g].P) * tab[g].P);
+    int lds_rows = 0;   // y/z: sub-block areas x chunks, the most any entry needs
+    for (int e = 0; e < ne; ++e) {
+        const int per = (w == 0) ? 1 : Pmax / tab[e].P;   // virtual blocks per block
+        const int nit = (tab[e].nblk + per - 1) / per;
+        for (int q = 0; q < nit; ++q) items.push_back(make_int2(e, q));
+        if (w != 0) lds_rows = std::max(lds_rows, ((Pmax + tab[e].P - 1) / tab[e].P) * tab[e].P);
     }
     BatchPass bp;
-    bp.op = op; bp.k = k; bp.frac = frac; bp.Pmax = Pmax;
+    bp.op = op; bp.mask = mask; bp.w = w; bp.frac = frac; bp.Pmax = Pmax;
     bp.lds = (size_t)(p->refine ? 13 : 9) * lds_rows * (cf.TX + 1) * sizeof(S);
     bp.nitems = (int)items.size();
-    HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * n));
+    HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * ne));
     hipError_t e = hipMalloc(&bp.items, sizeof(int2) * items.size());
-    if (e == hipSuccess) e = hipMemcpy(bp.tab, tab.data(), sizeof(PassArgs<T, S>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bp.tab, tab.data(), sizeof(PassArgs<T, S>) * ne, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(bp.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(bp.tab);
@@ -105,7 +144,7 @@ static fdtd_status batch_pass(fdtd_plan_s* p, int op, int k, double frac, const 
 
 template <typename T, typename S, int MODE>
 static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
-    const int w = kPairs[bp.op][bp.k].w;
+    const int w = bp.w;
     const KCfg& cf = p->cfg[w];
     const bool mat = p->batch->mat;
     const auto* tab = static_cast<const PassArgs<T, S>*>(bp.tab);
@@ -156,12 +195,14 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
     return batch_launch_mode<T, S, FUND>(p, bp, st);
 }
 
-// One sub-step (operator op, theta = frac * dt) of every grid: three launches.
+// One sub-step (operator op, theta = frac * dt) of every grid: two or three launches.
 template <typename T, typename S>
 static fdtd_status batch_substep(fdtd_plan_s* p, int op, double frac, hipStream_t st) {
-    for (int k = 0; k < 3; ++k) {
+    int masks[3];
+    const int nl = substep_masks(p, op, masks);
+    for (int l = 0; l < nl; ++l) {
         const BatchPass* bp = nullptr;
-        fdtd_status s = batch_pass<T, S>(p, op, k, frac, &bp);
+        fdtd_status s = batch_pass<T, S>(p, op, masks[l], frac, &bp);
         if (s != FDTD_OK) return s;
         s = batch_launch<T, S>(p, *bp, st);
         if (s != FDTD_OK) return s;
@@ -172,19 +213,24 @@ static fdtd_status batch_substep(fdtd_plan_s* p, int op, double frac, hipStream_
 template <typename T, typename S>
 static fdtd_status batch_tables(fdtd_plan_s* p) {
     const SchemeDef& sd = kSchemes[p->d.scheme];
-    for (int u = 0; u < sd.nsub; ++u)
-        for (int k = 0; k < 3; ++k) {
+    int masks[3];
+    for (int u = 0; u < sd.nsub; ++u) {
+        const int nl = substep_masks(p, sd.sub[u].op, masks);
+        for (int l = 0; l < nl; ++l) {
             const BatchPass* bp = nullptr;
-            fdtd_status s = batch_pass<T, S>(p, sd.sub[u].op, k, sd.sub[u].theta_frac, &bp);
+            fdtd_status s = batch_pass<T, S>(p, sd.sub[u].op, masks[l], sd.sub[u].theta_frac, &bp);
             if (s != FDTD_OK) return s;
         }
+    }
     if (p->d.scheme == FDTD_LOD2)
-        for (double f : {0.25, -0.25})
-            for (int k = 0; k < 3; ++k) {
+        for (double f : {0.25, -0.25}) {
+            const int nl = substep_masks(p, 1, masks);
+            for (int l = 0; l < nl; ++l) {
                 const BatchPass* bp = nullptr;
-                fdtd_status s = batch_pass<T, S>(p, 1, k, f, &bp);
+                fdtd_status s = batch_pass<T, S>(p, 1, masks[l], f, &bp);
                 if (s != FDTD_OK) return s;
             }
+        }
     return FDTD_OK;
 }
 
@@ -207,31 +253,28 @@ static fdtd_status batch_graph(fdtd_plan_s* p) {
     Batch* b = p->batch;
     if (b->exec) return FDTD_OK;
     const SchemeDef& sd = kSchemes[p->d.scheme];
-    // The three pair passes of a sub-step update disjoint arrays: capture them
-    // as parallel branches (fork on events, join before the next sub-step).
+    // The launches of a sub-step update disjoint arrays: capture them as
+    // parallel branches (fork on events, join before the next sub-step).
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     fdtd_status st = FDTD_OK;
-    auto branch = [&](int k, hipStream_t str, int op, double frac) -> fdtd_status {
-        const BatchPass* bp = nullptr;
-        fdtd_status s2 = batch_pass<T, S>(p, op, k, frac, &bp);
-        return s2 == FDTD_OK ? batch_launch<T, S>(p, *bp, str) : s2;
-    };
+    hipStream_t br[3] = {b->cap, b->fork[0], b->fork[1]};
     for (int v = 0; v < kGraphSteps * sd.nsub && st == FDTD_OK; ++v) {
         const int u = v % sd.nsub;
         const int op = sd.sub[u].op;
         const double frac = sd.sub[u].theta_frac;
-        if (hipEventRecord(b->ev[0], b->cap) != hipSuccess || hipStreamWaitEvent(b->fork[0], b->ev[0], 0) != hipSuccess ||
-            hipStreamWaitEvent(b->fork[1], b->ev[0], 0) != hipSuccess) {
-            st = FDTD_EDEVICE;
-            break;
+        int masks[3];
+        const int nl = substep_masks(p, op, masks);
+        if (hipEventRecord(b->ev[0], b->cap) != hipSuccess) { st = FDTD_EDEVICE; break; }
+        for (int l = 1; l < nl && st == FDTD_OK; ++l)
+            if (hipStreamWaitEvent(br[l], b->ev[0], 0) != hipSuccess) st = FDTD_EDEVICE;
+        for (int l = 0; l < nl && st == FDTD_OK; ++l) {
+            const BatchPass* bp = nullptr;
+            st = batch_pass<T, S>(p, op, masks[l], frac, &bp);
+            if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, br[l]);
         }
-        st = branch(0, b->cap, op, frac);
-        if (st == FDTD_OK) st = branch(1, b->fork[0], op, frac);
-        if (st == FDTD_OK) st = branch(2, b->fork[1], op, frac);
-        if (st == FDTD_OK &&
-            (hipEventRecord(b->ev[1], b->fork[0]) != hipSuccess || hipEventRecord(b->ev[2], b->fork[1]) != hipSuccess ||
-             hipStreamWaitEvent(b->cap, b->ev[1], 0) != hipSuccess || hipStreamWaitEvent(b->cap, b->ev[2], 0) != hipSuccess))
-            st = FDTD_EDEVICE;
+        for (int l = 1; l < nl && st == FDTD_OK; ++l)
+            if (hipEventRecord(b->ev[l], br[l]) != hipSuccess || hipStreamWaitEvent(b->cap, b->ev[l], 0) != hipSuccess)
+                st = FDTD_EDEVICE;
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);
@@ -360,7 +403,7 @@ static fdtd_status batch_autotune_impl(fdtd_plan_s* p, int reps, double* best_ms
             p->cfg[axis] = c;
             batch_clear(b);
             const BatchPass* bp = nullptr;
-            st = batch_pass<T, S>(p, 0, k, 0.5, &bp);
+            st = batch_pass<T, S>(p, 0, 1 << k, 0.5, &bp);
             if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, p->stream);
             if (st != FDTD_OK) break;
             if (hipEventRecord(e0, p->stream) != hipSuccess) { st = FDTD_EDEVICE; break; }

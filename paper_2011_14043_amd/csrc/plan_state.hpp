@@ -49,9 +49,12 @@ struct Timing {
 // launch.  For each (operator, pair, theta) the batch keeps a device table of
 // the grids' pass arguments and a work list of (grid, block) items.
 struct BatchPass {
-    int op = 0, k = 0;
+    int op = 0;
+    int mask = 0;             // pairs k of operator op in this launch (bit k); all on one axis
+                              // family with one kernel configuration (x, or y and z)
+    int w = 0;                // line axis of the first pair (selects the configuration)
     double frac = 0.0;        // theta = frac * dt of each grid
-    void* tab = nullptr;      // device PassArgs<T, S>[ngrids]
+    void* tab = nullptr;      // device PassArgs<T, S>[ngrids x pairs in mask], pair-major
     void* items = nullptr;    // device int2[nitems]
     int nitems = 0;
     int Pmax = 1;             // y/z lines: largest chunk count (block = TX * Pmax)
