@@ -113,3 +113,26 @@ def test_cn_iteration_limit_and_rejections():
     with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
         other.set_cg(1e-10, 10)
     other.close()
+
+
+def test_cn_cavity_mode_256cube_bench_size():
+    """The configuration the bench times (256^3, CFL 5, default CG tolerance):
+    a cavity mode after 3 steps against the closed-form Cayley amplification."""
+    n, h = 256, 1e-3
+    mnp = (3, 2, 5)
+    dt = W.yee_dt(h, h, h, 5.0)
+    a = np.random.default_rng(9).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(n, n, n, h, h, h, *mnp)
+    C = an.cayley(A6 + B6, 0.5 * dt)
+    u0 = an.mode_fields(n, n, n, h, h, h, *mnp, a)
+    print("[case] CN cavity mode 256^3", flush=True)
+    plan = _plan(n, n, n, dt, h)
+    got, _ = _run(plan, u0, 3)
+    st = plan.last_cg()
+    plan.close()
+    del u0
+    ref = an.mode_fields(n, n, n, h, h, h, *mnp, np.linalg.matrix_power(C, 3) @ a)
+    g = oracle.Grid(n, n, n, h, h, h, dt)
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    print(f"  rel-L2 {err:.3e}  iterations {st['iterations']}")
+    assert err < 1e-9
