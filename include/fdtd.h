@@ -230,9 +230,11 @@ fdtd_status fdtd_last_cg(fdtd_plan_t p, long long* iterations, double* rel_resid
 /* Batch of independent grids stepped together (fundamental forms only, else
  * FDTD_EUNSUPPORTED).  d[0..n-1] describe the grids (each validated as by
  * fdtd_plan; sizes, dt, dx, dy, dz and eps_r may differ; scheme, form and
- * dtype must be equal, else FDTD_EINVAL).  Every line pass of a sub-step
- * runs as ONE launch over all grids: the plan keeps a device table of the
- * grids' pass arguments and a work list of (grid, block) items, and eight time
+ * dtype must be equal, else FDTD_EINVAL; Crank-Nicolson: FDTD_EUNSUPPORTED).
+ * Every line pass of a sub-step runs as ONE launch over all grids, and the
+ * y- and z-line passes share that launch when their kernel configurations
+ * agree: the plan keeps a device table of the grids' pass arguments and a
+ * work list of (table entry, block) items, and eight time
  * steps of the main iteration are captured once as a HIP graph (on a private
  * stream) and replayed on `hip_stream` (remaining steps are launched
  * directly).  When the fields and media of all grids exceed 128 MiB, the

@@ -65,8 +65,8 @@ struct Batch {
     bool mat = false;         // every grid has a material index
     std::vector<BatchPass> passes;
     hipStream_t cap = nullptr;        // private stream for graph capture
-    hipStream_t fork[2] = {nullptr, nullptr};   // capture branches: the three pair passes of a
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // sub-step are independent and run side by side
+    hipStream_t fork[2] = {nullptr, nullptr};   // capture branches: the launches of a sub-step
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // are independent and run side by side
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;    // time steps of the main iteration
     // A batch larger than kGroupBytes is split into groups of consecutive
