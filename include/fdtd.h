@@ -76,7 +76,9 @@ typedef enum {
  * and FDTD_F64 only, no source (else FDTD_EUNSUPPORTED); no batches, adjoint
  * or kernel configuration (no line passes).  fdtd_run returns
  * FDTD_ENOTCONVERGED, with every step done, if some step ended at the
- * iteration limit above the tolerance. */
+ * iteration limit above the tolerance.  A Crank-Nicolson run synchronizes
+ * the plan's stream: the host reads the residual every fourth iteration.
+ * The plan holds 15 more FP64 arrays of the state's size (CG work vectors). */
 typedef enum {
     FDTD_ADI = 0, FDTD_LOD1 = 1 /* == SS1 */, FDTD_SS2 = 2, FDTD_LOD2 = 3,
     FDTD_DYAKONOV = 4, FDTD_DOUGLAS_GUNN = 5, FDTD_CRANK_NICOLSON = 6
