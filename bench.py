@@ -314,17 +314,59 @@ def cpu_baseline(n=256, steps=3):
     import oracle
     import workloads as W
     from oracle.source import Source as OSource
+    from threadpoolctl import threadpool_limits
     h, dt, eps, ci = make_inputs(n)
     g = oracle.Grid(n, n, n, h, h, h, dt, eps)
     u0 = W.zero_fields(n, n, n)
     src = OSource(*ci)
-    t0 = time.perf_counter()
-    oracle.run("adi", "fundamental", g, u0, steps, src)
-    t1 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.run("adi", "fundamental", g, u0, steps, src)
+        t1 = time.perf_counter()
     rate = n ** 3 * steps / (t1 - t0) / 1e6
     return {"value": rate, "unit": "Mcell/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 NumPy oracle, fundamental ADI, {n}^3 cells of the same random-box/source "
-                      f"workload, {steps} step(s), single thread ({t1 - t0:.1f} s)"}
+                      f"workload, {steps} step(s), single thread ({t1 - t0:.1f} s)",
+            "host": host_info()}
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
+def cpu_schemes(n=96, steps=2):
+    """The FP64 oracle, single thread, per scheme and form on n^3 cells of the
+    random-box workload with its source (the D'Yakonov and Douglas-Gunn
+    splittings from N(0,1) fields, without source); Mcell/s."""
+    import oracle
+    import workloads as W
+    from oracle.source import Source as OSource
+    from threadpoolctl import threadpool_limits
+    h, dt, eps, ci = make_inputs(n)
+    g = oracle.Grid(n, n, n, h, h, h, dt, eps)
+    rows = []
+    with threadpool_limits(limits=1):
+        for scheme in oracle.SCHEMES + oracle.SPLITTINGS:
+            for form in oracle.FORMS:
+                split = scheme in oracle.SPLITTINGS
+                u0 = W.random_fields(n, n, n, seed=3) if split else W.zero_fields(n, n, n)
+                t0 = time.perf_counter()
+                oracle.run(scheme, form, g, u0, steps, None if split else OSource(*ci))
+                t1 = time.perf_counter()
+                rows.append({"scheme": scheme, "form": form, "mcells_per_s": n ** 3 * steps / (t1 - t0) / 1e6,
+                             "seconds": t1 - t0})
+                log(json.dumps(rows[-1]))
+    return {"workload": f"{n}^3 random-box eps_r, CFL 5, {steps} steps, FP64 NumPy oracle, single thread",
+            "host": host_info(), "rows": rows}
 
 
 def main():
@@ -339,6 +381,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--only", choices=["batch", "adjoint", "cn"], default=None,
                     help="run only the batched-cavity or the adjoint measurement and print its JSON")
+    ap.add_argument("--cpu-schemes", action="store_true",
+                    help="only time the FP64 oracle per scheme and form on the host (no GPU) and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -347,6 +391,9 @@ def main():
               "the multi-GPU slab decomposition is a design, not built", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
+    if args.cpu_schemes:
+        print(json.dumps(cpu_schemes()), flush=True)
+        return
     import torch
     if args.copy_probe:
         nel = args.copy_probe * (1 << 20) // 4
