@@ -293,10 +293,10 @@ def run_cn(n=256, steps=10, tol=1e-12):
             it = st["iterations"] / steps
             out["cg_iterations_per_step"] = it
             out["cg_rel_residual_max"] = st["rel_residual"]
-            # algorithmic bytes of one CG iteration: 348 B per node in FP64
-            # (curl: p -> w; apply: p, w, eps -> q; update: x, p, r, q, eps -> x, r;
-            # direction: r, p, eps -> p), kernels over all (n+1)^3 nodes
-            out["cg_iteration_gbs"] = 348 * (n + 1) ** 3 * it / (ms * 1e-3) / 1e9
+            # algorithmic bytes of one CG iteration: 276 B per node in FP64
+            # (apply: p, eps -> q; update: x, p, r, q, eps -> x, r; direction:
+            # r, p, eps -> p), kernels over all (n+1)^3 nodes
+            out["cg_iteration_gbs"] = 276 * (n + 1) ** 3 * it / (ms * 1e-3) / 1e9
         finite = all(bool(torch.isfinite(t).all()) for t in E + H)
         out[f"{key}_finite"] = finite
         plan.close()

@@ -13,6 +13,9 @@
 // C_E(u_E)), so no product with S is needed to start.  Finally
 //     u_E^{n+1} = v_E - u_E^n ,   u_H^{n+1} = u_H^n - theta mu^-1 C_E(v_E).
 //
+// The product S p evaluates the curls of p at the H samples inside the kernel
+// that forms S p, so an iteration moves p, q, x, r and eps_r only.
+//
 // Every kernel walks the nodes with a grid-stride loop over a fixed grid of
 // kCnBlocks blocks, so the dot products (per-block partials, then one fixed-
 // order tree per sum) are deterministic.  Non-dynamic E samples of the work
@@ -40,7 +43,7 @@ struct CnArgs {
     double* r[3];               // residual
     double* p[3];               // search direction
     double* q[3];               // S p
-    double* w[3];               // mu^-1 C_E(p) at the H samples (work)
+    double* w[3];               // u_H - theta mu^-1 C_E(u_E) at the H samples (start of a step)
     double* partial;            // 3 x kCnBlocks
     double* scal;               // kCnScalars
 };
@@ -139,21 +142,13 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_e_kernel(CnArgs a) {
     block_partials<3>(acc, a.partial);
 }
 
-// w = mu^-1 C_E(p) at the dynamic H samples.
-__global__ void __launch_bounds__(kCnThreads) cn_curl_kernel(CnArgs a) {
-    const double* e[3] = {a.p[0], a.p[1], a.p[2]};
-    CN_NODES(a) {
-        const Node nd = node_of(unsigned(idx), a.d);
-        const long long so = (long long)nd.k * a.d.plane + (long long)nd.j * a.d.px + nd.i;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            a.w[c][so] = is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d) ? a.rmu0 * curl_e(e, c, so, a) : 0.0;
-    }
-}
-
-// q = S p = eps p + theta^2 C_H(w); sum p.q.
+// q = S p = eps p + theta^2 C_H(mu^-1 C_E(p)); sum p.q.  The H values come from
+// the curls of p at the four H samples around each E sample, formed here (the
+// stencil reads of p hit the caches), so no H-side vector goes through HBM.
 __global__ void __launch_bounds__(kCnThreads) cn_apply_kernel(CnArgs a) {
-    const double* w[3] = {a.w[0], a.w[1], a.w[2]};
+    const double* e[3] = {a.p[0], a.p[1], a.p[2]};
+    const long long sy = a.d.px, sz = a.d.plane;
+    const double t2m = a.theta * a.theta * a.rmu0;
     double acc[1] = {0.0};
     CN_NODES(a) {
         const Node nd = node_of(unsigned(idx), a.d);
@@ -163,8 +158,19 @@ __global__ void __launch_bounds__(kCnThreads) cn_apply_kernel(CnArgs a) {
         for (int c = 0; c < 3; ++c) {
             double qv = 0.0;
             if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) {
+                // the four H samples around a dynamic E sample are dynamic
+                double ch;
+                if (c == 0)
+                    ch = (curl_e(e, 2, so, a) - curl_e(e, 2, so - sy, a)) * a.rdy -
+                         (curl_e(e, 1, so, a) - curl_e(e, 1, so - sz, a)) * a.rdz;
+                else if (c == 1)
+                    ch = (curl_e(e, 0, so, a) - curl_e(e, 0, so - sz, a)) * a.rdz -
+                         (curl_e(e, 2, so, a) - curl_e(e, 2, so - 1, a)) * a.rdx;
+                else
+                    ch = (curl_e(e, 1, so, a) - curl_e(e, 1, so - 1, a)) * a.rdx -
+                         (curl_e(e, 0, so, a) - curl_e(e, 0, so - sy, a)) * a.rdy;
                 const double pv = a.p[c][so];
-                qv = eps * pv + a.theta * a.theta * curl_h(w, c, so, a);
+                qv = eps * pv + t2m * ch;
                 acc[0] += pv * qv;
             }
             a.q[c][so] = qv;

@@ -57,7 +57,6 @@ static fdtd_status cn_step(fdtd_plan_s* p, const CnArgs& a, long long* iters, do
     *rel = 0.0;
     while (it < p->cg_maxit) {
         if (it > 0) CN_LAUNCH(cn_direction_kernel, a, it & 1);
-        CN_LAUNCH(cn_curl_kernel, a);
         CN_LAUNCH(cn_apply_kernel, a);
         if ((st = cn_reduce(p, 1, CnSlots{{kPq, 0, 0}})) != FDTD_OK) return st;
         CN_LAUNCH(cn_update_kernel, a, it & 1);
