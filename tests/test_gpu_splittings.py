@@ -94,3 +94,29 @@ def test_dyakonov_batch_equals_adi_batch():
         out[scheme] = [t.cpu() for E, H in f for t in E + H]
     for x, y in zip(out["adi"], out["dyakonov"]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
+def test_splitting_gradient_equals_adi(scheme):
+    """The adjoint gradient of a splitting plan (no source) is ADI's, bit for
+    bit; with a source the call is rejected."""
+    from paper_2011_14043_amd import Plan, Source
+    nx, ny, nz, h = 24, 20, 18, 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    eps = torch.tensor(W.random_box_eps(nx, ny, nz, seed=80, nboxes=6))
+    u0 = W.random_fields(nx, ny, nz, seed=81)
+    E = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[3:]]
+    box = (6, 14, 5, 12, 6, 10)
+    out = {}
+    for s in ("adi", scheme):
+        print(f"[case] gradient 24x20x18 {s}", flush=True)
+        plan = Plan(nx, ny, nz, dt, h, h, h, scheme=s, dtype=torch.float64, eps_r=eps)
+        out[s] = plan.grad_eps(E, H, 30, (12, 10, 12), design_box=box, ckpt_every=7)
+        if s != "adi":
+            with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+                plan.grad_eps(E, H, 5, (12, 10, 12), Source(4, 4, 4, f0=1e10, tau=1e-10, t0=4e-10, amp=1.0))
+        torch.cuda.synchronize()
+        plan.close()
+    assert out["adi"][0] == out[scheme][0]
+    assert torch.equal(out["adi"][1], out[scheme][1])
