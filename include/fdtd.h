@@ -219,6 +219,20 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
                           const fdtd_source* src, int probe_i, int probe_j, int probe_k,
                           const int* design_box, int ckpt_every, double* J_out, double* grad_out);
 
+/* FP64 distance of two field sets on a single-grid plan's grid (else
+ * FDTD_EINVAL for a batch plan):
+ *   out[0] = sum eps |Ea - Eb|^2 + mu |Ha - Hb|^2,  out[1] = sum eps |Eb|^2 + mu |Hb|^2
+ * over the samples inside each component's extent, eps = eps0 eps_r of the
+ * sample's owning cell (as in the energy trace), mu = mu0; so
+ * sqrt(out[0] / out[1]) is the energy-weighted relative L2 distance of Ea, Ha
+ * from Eb, Hb.  Ea, Ha, Eb, Hb: device arrays in the caller's field layout and
+ * the plan's element type (read only); out: host array of 2.  Two-stage
+ * reduction in a fixed order (deterministic); synchronizes the plan's stream;
+ * FDTD_ENONFINITE if a sum is not finite.  The first call allocates 16 KB of
+ * device memory kept by the plan. */
+fdtd_status fdtd_diff_norm(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
+                           void* const Hb[3], double* out);
+
 /* Conjugate-gradient controls of a Crank-Nicolson plan (else
  * FDTD_EUNSUPPORTED): stop when |r| <= tol |b| (0 < tol < 1, checked every
  * fourth iteration) or after maxit >= 1 iterations.  Defaults 1e-12, 500. */

@@ -140,6 +140,17 @@ class Plan:
         return {"main_ms": main.value, "yz_ms_avg": avg[0], "x_ms_avg": avg[1],
                 "yz_launches": cnt[0], "x_launches": cnt[1]}
 
+    def diff_norm(self, Ea, Ha, Eb, Hb):
+        """(sum eps|Ea-Eb|^2 + mu|Ha-Hb|^2, sum eps|Eb|^2 + mu|Hb|^2) in FP64 on the
+        device; sqrt of their ratio is the energy-weighted relative L2 distance."""
+        out = (ctypes.c_double * 2)()
+        _lib.check(_lib.lib().fdtd_diff_norm(self._h, _ptrs(Ea, self.dtype, self.shape, self.device),
+                                             _ptrs(Ha, self.dtype, self.shape, self.device),
+                                             _ptrs(Eb, self.dtype, self.shape, self.device),
+                                             _ptrs(Hb, self.dtype, self.shape, self.device), out),
+                   "fdtd_diff_norm")
+        return out[0], out[1]
+
     def set_cg(self, tol: float = 1e-12, maxit: int = 500):
         """Conjugate-gradient controls of a Crank-Nicolson plan."""
         _lib.check(_lib.lib().fdtd_set_cg(self._h, float(tol), int(maxit)), "fdtd_set_cg")

@@ -174,6 +174,48 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Weighted squared distance of two field sets in the caller's layout, FP64,
+// first stage: per block, sum eps |E_a - E_b|^2 + mu |H_a - H_b|^2 and
+// sum eps |E_b|^2 + mu |H_b|^2 over the samples inside each component's
+// extent (eps of the sample's owning node), into partial[b] and
+// partial[gridDim.x + b] (fixed order => deterministic).
+template <typename T>
+__global__ void __launch_bounds__(256) diff_partial_kernel(FieldPtrs<T> fa, FieldPtrs<T> fb, const float* eps, Dims d,
+                                                           AuxCoef k_, double* partial) {
+    __shared__ double red[2][256];
+    const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
+    double num = 0.0, den = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const Node nd = node_of(unsigned(idx), d);
+        const long long so = (long long)nd.k * d.plane + (long long)nd.j * d.px + nd.i;
+        const double ew = k_.eps0 * double(eps[so]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            if (!in_extent(c, nd.i, nd.j, nd.k, d)) continue;
+            const double w = c < 3 ? ew : k_.mu0;
+            const double vb = double(fb.c[c][idx]);
+            const double dv = double(fa.c[c][idx]) - vb;
+            num += w * dv * dv;
+            den += w * vb * vb;
+        }
+    }
+    red[0][threadIdx.x] = num;
+    red[1][threadIdx.x] = den;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s2];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0][0];
+        partial[gridDim.x + blockIdx.x] = red[1][0];
+    }
+}
+
 // Second stage: one thread sums the partials in index order.
 __global__ void energy_final_kernel(const double* partial, int n, double* out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -493,6 +493,48 @@ fdtd_status fdtd_run_batch(fdtd_plan_t p, void* const* E, void* const* H, int ns
     return st;
 }
 
+fdtd_status fdtd_diff_norm(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
+                           void* const Hb[3], double* out) {
+    if (!plan_ok(p) || p->batch || !Ea || !Ha || !Eb || !Hb || !out) return FDTD_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!Ea[c] || !Ha[c] || !Eb[c] || !Hb[c]) return FDTD_EINVAL;
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    auto body = [&]() -> fdtd_status {
+        const int nb = p->npartial;
+        if (!p->diff_dev) HIPCHK(hipMalloc(&p->diff_dev, sizeof(double) * (2 * nb + 2)));
+        const AuxCoef k = aux_coef(p->d, 0.0);
+        auto launch = [&](auto tag) -> fdtd_status {
+            using T = decltype(tag);
+            FieldPtrs<T> fa, fb;
+            for (int c = 0; c < 3; ++c) {
+                fa.c[c] = static_cast<const T*>(Ea[c]);
+                fa.c[3 + c] = static_cast<const T*>(Ha[c]);
+                fb.c[c] = static_cast<const T*>(Eb[c]);
+                fb.c[3 + c] = static_cast<const T*>(Hb[c]);
+            }
+            hipLaunchKernelGGL((diff_partial_kernel<T>), dim3(nb), dim3(256), 0, p->stream, fa, fb, p->eps, p->dims, k,
+                               p->diff_dev);
+            HIPCHK(hipGetLastError());
+            return FDTD_OK;
+        };
+        const fdtd_status st = p->d.dtype == FDTD_F64 ? launch(double()) : launch(float());
+        if (st != FDTD_OK) return st;
+        for (int m = 0; m < 2; ++m) {
+            hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, p->diff_dev + m * nb, nb,
+                               p->diff_dev + 2 * nb + m);
+            HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipMemcpyAsync(out, p->diff_dev + 2 * nb, sizeof(double) * 2, hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        return std::isfinite(out[0]) && std::isfinite(out[1]) ? FDTD_OK : FDTD_ENONFINITE;
+    };
+    const fdtd_status st = body();
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    return st;
+}
+
 fdtd_status fdtd_set_cg(fdtd_plan_t p, double tol, int maxit) {
     if (!plan_ok(p) || !(tol > 0.0 && tol < 1.0) || maxit < 1) return FDTD_EINVAL;
     if (!p->cg) return FDTD_EUNSUPPORTED;
@@ -535,6 +577,7 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->cg) (void)hipFree(p->cg);
     if (p->cg_partial) (void)hipFree(p->cg_partial);
     if (p->cg_scal) (void)hipFree(p->cg_scal);
+    if (p->diff_dev) (void)hipFree(p->diff_dev);
     for (hipEvent_t e : p->tm.ev) (void)hipEventDestroy(e);
     if (p->tm.main0) (void)hipEventDestroy(p->tm.main0);
     if (p->tm.main1) (void)hipEventDestroy(p->tm.main1);

@@ -104,6 +104,7 @@ struct fdtd_plan_s {
     int npartial = 0;
     double* energy_dev = nullptr;
     int energy_cap = 0;
+    double* diff_dev = nullptr;   // fdtd_diff_norm: 2 x npartial partials and 2 results (on first use)
     void* gbuf = nullptr;     // adjoint: checkpoints, records, adjoint state (grown on demand)
     size_t gcap = 0;
     long long step = 0;

@@ -74,6 +74,7 @@ def test_null_arguments(L):
     assert L.fdtd_destroy(None) == -1
     assert L.fdtd_last_timing(None, None, None, None) == -1
     assert L.fdtd_set_cg(None, 1e-10, 10) == -1
+    assert L.fdtd_diff_norm(None, None, None, None, None, None) == -1
     assert L.fdtd_last_cg(None, None, None) == -1
 
 

@@ -61,3 +61,33 @@ def test_sampled_launch_timing(every, steps):
     with pytest.raises(FdtdError):
         plan.set_timing(-1)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_diff_norm_matches_host_sum(dtype):
+    """fdtd_diff_norm against the energy-weighted sums formed on the host from
+    the same values (eps of the owning cell, in-extent samples only)."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2011_14043_amd import Plan
+    nx, ny, nz, h = 37, 21, 30, 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    eps = W.random_box_eps(nx, ny, nz, seed=90, nboxes=6)
+    a, b = W.random_fields(nx, ny, nz, seed=91), W.random_fields(nx, ny, nz, seed=92)
+    plan = Plan(nx, ny, nz, dt, h, h, h, dtype=tdt, eps_r=torch.tensor(eps))
+    dev = [torch.tensor(x, dtype=tdt, device="cuda") for x in a + b]
+    num, den = plan.diff_norm(dev[0:3], dev[3:6], dev[6:9], dev[9:12])
+    plan.close()
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    av = [x.double().cpu().numpy() for x in dev[0:6]]
+    bv = [x.double().cpu().numpy() for x in dev[6:12]]
+    ref_num = oracle.energy([x - y for x, y in zip(av, bv)], g)
+    ref_den = oracle.energy(bv, g)
+    assert abs(num / ref_num - 1) < 1e-12 and abs(den / ref_den - 1) < 1e-12
+    p2 = Plan(nx, ny, nz, dt, h, h, h, dtype=tdt)
+    same = p2.diff_norm(dev[0:3], dev[3:6], dev[0:3], dev[3:6])
+    p2.close()
+    assert same[0] == 0.0 and same[1] > 0.0
