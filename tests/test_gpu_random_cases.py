@@ -1,0 +1,58 @@
+"""Seeded random cases against the oracle: grid sizes from 2 to 40 cells per
+axis (degenerate, ragged and multi-chunk lines), every scheme and form, all
+precisions, CFL 0.5 to 20, random boxes of eps_r, with and without a source,
+anisotropic cells.  Each case prints its parameters before it runs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.source import Source as OSource
+
+from .test_gpu_parity import REFINED, TOL, gpu_run
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["adi", "lod1", "ss2", "lod2", "dyakonov", "douglas_gunn"]
+ORACLE_NAME = {"dyakonov": "dy", "douglas_gunn": "dg"}
+
+
+def _case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    nx, ny, nz = (int(v) for v in rng.integers(2, 41, 3))
+    scheme = SCHEMES[int(rng.integers(len(SCHEMES)))]
+    split = scheme in ORACLE_NAME
+    form = "fundamental" if split else ["fundamental", "conventional"][int(rng.integers(2))]
+    dtype = ["f64", "f32", "f32s64", "f32r"][int(rng.integers(4))]
+    if dtype in REFINED and form == "conventional":
+        dtype = "f32"
+    cfl = float(np.exp(rng.uniform(np.log(0.5), np.log(20.0))))
+    h = tuple(float(v) for v in rng.uniform(0.7e-3, 1.4e-3, 3))
+    steps = int(rng.integers(1, 9))
+    use_src = (not split) and bool(rng.integers(2)) and nx >= 3 and ny >= 3
+    return nx, ny, nz, scheme, form, dtype, cfl, h, steps, use_src
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_case(seed):
+    nx, ny, nz, scheme, form, dtype, cfl, h, steps, use_src = _case(seed)
+    print(f"[case] seed {seed}: {nx}x{ny}x{nz} {scheme}/{form}/{dtype} CFL {cfl:.2f} h {h} "
+          f"steps {steps} source {use_src}", flush=True)
+    dt = W.yee_dt(*h, cfl)
+    eps = W.random_box_eps(nx, ny, nz, seed=2000 + seed, nboxes=4)
+    u0 = W.random_fields(nx, ny, nz, seed=3000 + seed)
+    src = None
+    if use_src:
+        rng = np.random.default_rng(4000 + seed)
+        i, j = int(rng.integers(1, nx)), int(rng.integers(1, ny))
+        k = int(rng.integers(0, nz))
+        src = OSource(i, j, k, amp=1e12, t0=2 * dt, tau=3 * dt, f0=1 / (10 * dt))
+    g = oracle.Grid(nx, ny, nz, *h, dt, eps)
+    ref, tr_ref = oracle.run(ORACLE_NAME.get(scheme, scheme), form, g, u0, steps, src, 1)
+    got, tr = gpu_run(scheme, form, dtype, nx, ny, nz, dt, h, eps, u0, steps, src, 1)
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    terr = np.max(np.abs(np.array(tr) - np.array(tr_ref)) / np.abs(np.array(tr_ref)))
+    print(f"  rel-L2 {err:.3e}  energy {terr:.3e}", flush=True)
+    assert err < TOL[dtype]
+    assert terr < 10 * TOL[dtype]
