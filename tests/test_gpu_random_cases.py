@@ -56,3 +56,75 @@ def test_random_case(seed):
     print(f"  rel-L2 {err:.3e}  energy {terr:.3e}", flush=True)
     assert err < TOL[dtype]
     assert terr < 10 * TOL[dtype]
+
+
+def _batch_case(seed):
+    rng = np.random.default_rng(5000 + seed)
+    ng = int(rng.integers(2, 7))
+    sizes = [tuple(int(v) for v in rng.integers(2, 41, 3)) for _ in range(ng)]
+    scheme = ["adi", "lod1", "ss2", "lod2", "dyakonov"][int(rng.integers(5))]
+    dtype = ["f64", "f32", "f32s64", "f32r"][int(rng.integers(4))]
+    cfl = float(np.exp(rng.uniform(np.log(0.5), np.log(20.0))))
+    steps = int(rng.integers(1, 20))
+    return sizes, scheme, dtype, cfl, steps
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_batch_case(seed):
+    """Batches of 2 to 6 random grids, every fundamental scheme, all
+    precisions, 1 to 19 steps (graph replays from 9 steps on)."""
+    from paper_2011_14043_amd import BatchPlan
+    from .test_gpu_parity import PREC
+    sizes, scheme, dtype, cfl, steps = _batch_case(seed)
+    print(f"[case] batch seed {seed}: {sizes} {scheme}/{dtype} CFL {cfl:.2f} steps {steps}", flush=True)
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, cfl)
+    tdt, solve = PREC[dtype]
+    grids, fields, refs = [], [], []
+    for g, (nx, ny, nz) in enumerate(sizes):
+        eps = W.random_box_eps(nx, ny, nz, seed=6000 + 10 * seed + g, nboxes=4)
+        u0 = W.random_fields(nx, ny, nz, seed=7000 + 10 * seed + g)
+        grids.append((nx, ny, nz, torch.tensor(eps)))
+        fields.append(([torch.tensor(a, dtype=tdt, device="cuda") for a in u0[:3]],
+                       [torch.tensor(a, dtype=tdt, device="cuda") for a in u0[3:]]))
+        gr = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+        refs.append((gr, oracle.run(ORACLE_NAME.get(scheme, scheme), "fundamental", gr, u0, steps)[0]))
+    plan = BatchPlan(grids, dt, h, h, h, scheme=scheme, dtype=tdt, solve_dtype=solve, refine=dtype in REFINED)
+    plan.run(fields, steps)
+    torch.cuda.synchronize()
+    plan.close()
+    for (E, H), (gr, ref) in zip(fields, refs):
+        got = [t.double().cpu().numpy() for t in E + H]
+        err = oracle.yee.weighted_rel_l2(got, ref, gr)
+        print(f"  {gr.nx}x{gr.ny}x{gr.nz}: rel-L2 {err:.3e}", flush=True)
+        assert err < 2 * TOL[dtype]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_crank_nicolson_case(seed):
+    """Crank-Nicolson (FP64) on random grids of 2 to 16 cells per axis,
+    anisotropic cells, CFL 0.5 to 20, 1 to 4 steps, against sparse direct solves."""
+    from paper_2011_14043_amd import Plan
+    rng = np.random.default_rng(8000 + seed)
+    nx, ny, nz = (int(v) for v in rng.integers(2, 17, 3))
+    cfl = float(np.exp(rng.uniform(np.log(0.5), np.log(20.0))))
+    h = tuple(float(v) for v in rng.uniform(0.7e-3, 1.4e-3, 3))
+    steps = int(rng.integers(1, 5))
+    print(f"[case] CN seed {seed}: {nx}x{ny}x{nz} CFL {cfl:.2f} h {h} steps {steps}", flush=True)
+    dt = W.yee_dt(*h, cfl)
+    eps = W.random_box_eps(nx, ny, nz, seed=9000 + seed, nboxes=4)
+    u0 = W.random_fields(nx, ny, nz, seed=9100 + seed)
+    g = oracle.Grid(nx, ny, nz, *h, dt, eps)
+    ref, tr_ref = oracle.run("cn", "fundamental", g, u0, steps, None, 1)
+    plan = Plan(nx, ny, nz, dt, *h, scheme="crank_nicolson", dtype=torch.float64, eps_r=torch.tensor(eps))
+    plan.set_cg(1e-13, 5000)
+    E = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in u0[:3]]
+    H = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in u0[3:]]
+    tr = plan.run(E, H, steps, energy_every=1)
+    torch.cuda.synchronize()
+    plan.close()
+    got = [t.cpu().numpy() for t in E + H]
+    err = oracle.yee.weighted_rel_l2(got, ref, g)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert np.allclose(tr, tr_ref, rtol=1e-10)
