@@ -15,8 +15,24 @@ HIPCC_FLAGS = [
 ]
 
 
+ROOT = os.path.dirname(HERE)
+C_CHECK_SRC = os.path.join(ROOT, "tests", "c_abi", "fdtd_abi_check.c")
+C_CHECK_BIN = os.path.join(ROOT, "tests", "c_abi", "fdtd_abi_check")
+
+
+def c_check_cmd(out: str) -> list[str]:
+    """gcc command that builds the plain-C program of tests/c_abi against the
+    library and the HIP runtime's C API (C11, warnings as errors)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+            "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(ROOT, "include"), C_CHECK_SRC, "-o", out,
+            "-L" + HERE, "-lfdtd", "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-lm",
+            "-Wl,-rpath,$ORIGIN/../../paper_2011_14043_amd", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+
+
 def build(verbose: bool = False) -> str:
-    """Compile libfdtd.so in-tree; returns its path.  Raises on failure."""
+    """Compile libfdtd.so in-tree, then the plain-C check program that links
+    it; returns the library's path.  Raises on failure."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, SRC]
@@ -26,6 +42,12 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, LIB)
+    cmd = c_check_cmd(C_CHECK_BIN)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + res.stdout + res.stderr)
+    if verbose:
+        print(" ".join(cmd))
     return LIB
 
 

@@ -83,3 +83,16 @@ def test_forced_allocation_failure(L, monkeypatch):
     h = ctypes.c_void_p()
     assert L.fdtd_plan(ctypes.byref(_desc()), None, ctypes.byref(h)) == -2
     assert not h.value
+
+
+def test_header_is_c_and_c_program_builds(tmp_path):
+    """include/fdtd.h compiles as C99, and the plain-C check program compiles
+    and links against the library with warnings as errors."""
+    import subprocess
+    from paper_2011_14043_amd import _build
+    hdr = os.path.join(ROOT, "include", "fdtd.h")
+    res = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", "c", hdr],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    res = subprocess.run(_build.c_check_cmd(str(tmp_path / "check")), capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
