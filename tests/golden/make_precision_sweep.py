@@ -1,6 +1,6 @@
 """Write tests/golden/precision_sweep_<scheme>.npz: FP64 oracle reference for
 the precision sweep (128^3 cells, 1 mm, random-box eps_r (32 boxes, seed 2),
-N(0,1) fields (seed 3), CFL number 10, no source, 1000 steps).
+N(0,1) fields (seed 3), CFL number 10 (or the one given), no source, 1000 steps).
 
 Stored (calls only oracle/ and workloads/):
   steps            [100, 500, 1000]
@@ -9,7 +9,8 @@ Stored (calls only oracle/ and workloads/):
   norm2            (3,) energy-weighted squared norm of the whole field
   trace            invariant energy every 10 steps (101 values)
 
-Usage: python tests/golden/make_precision_sweep.py <scheme> [n] [steps]
+Usage: python tests/golden/make_precision_sweep.py <scheme> [n] [steps] [cfl]
+(cfl other than 10 writes precision_sweep_<scheme>_cfl<cfl>.npz)
 """
 import os
 import sys
@@ -30,8 +31,9 @@ def main():
     scheme = sys.argv[1]
     n = int(sys.argv[2]) if len(sys.argv) > 2 else 128
     steps = int(sys.argv[3]) if len(sys.argv) > 3 else 1000
+    cfl = float(sys.argv[4]) if len(sys.argv) > 4 else 10.0
     h = 1e-3
-    dt = W.yee_dt(h, h, h, 10.0)
+    dt = W.yee_dt(h, h, h, cfl)
     eps = W.random_box_eps(n, n, n, seed=2, nboxes=32)
     u0 = W.random_fields(n, n, n, seed=3)
     g = oracle.Grid(n, n, n, h, h, h, dt, eps)
@@ -72,9 +74,10 @@ def main():
                 out = fundamental.lod2_output(u, g) if scheme == "lod2" else u
                 record(out, marks.index(s))
             print(scheme, s, flush=True) if s % 50 == 0 else None
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"precision_sweep_{scheme}.npz")
+    tag = "" if cfl == 10.0 else f"_cfl{cfl:g}"
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"precision_sweep_{scheme}{tag}.npz")
     np.savez_compressed(out, steps=np.array(marks), norm2=norm2, trace=np.array(trace),
-                        n=n, cfl=10.0, **{f"idx_{c}": idx[c] for c in yee.COMPONENTS},
+                        n=n, cfl=cfl, **{f"idx_{c}": idx[c] for c in yee.COMPONENTS},
                         **{f"val_{c}": vals[c] for c in yee.COMPONENTS})
     print("wrote", out)
 

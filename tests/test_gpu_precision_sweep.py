@@ -10,7 +10,8 @@ energy norm.  Bars: FP64 1e-10; FP32 storage with FP64 solves 1e-4 and pure
 FP32 with one refinement step per solve 1e-4 (the accuracy target for FP32
 fields after 1000 steps); plain FP32 arithmetic 1e-3, limited by the coherent
 rounding of the tridiagonal factors at sigma = eps mu dw^2 / theta^2 << 1,
-which is the same at every step."""
+which is the same at every step.  ADI is also swept at CFL 5, the CFL number
+of the 512^3 workload (fixture precision_sweep_adi_cfl5.npz)."""
 import os
 
 import numpy as np
@@ -28,6 +29,7 @@ DEV = "cuda:0"
 PREC = {"f64": (torch.float64, torch.float64), "f32s64": (torch.float32, torch.float64),
         "f32": (torch.float32, torch.float32), "f32r": (torch.float32, torch.float32)}
 BAR = {"f64": 1e-10, "f32s64": 1e-4, "f32": 1e-3, "f32r": 1e-4}
+BAR_CFL5 = {"f32s64": 1e-4, "f32": 1e-4, "f32r": 1e-4}
 
 
 def _golden(scheme):
@@ -47,16 +49,11 @@ def setup():
     return dict(n=n, h=h, dt=dt, eps=eps, u0=u0, g=g)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
-@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
-def test_precision_sweep(setup, scheme, prec):
+def _sweep(c, ref, scheme, prec):
     from paper_2011_14043_amd import Plan
-    ref = _golden(scheme)
-    c = setup
     n = c["n"]
     assert int(ref["n"]) == n
     dtype, solve = PREC[prec]
-    print(f"[case] precision sweep 128^3 CFL10 {scheme}/{prec}", flush=True)
     E = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][:3]]
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][3:]]
     plan = Plan(n, n, n, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve,
@@ -82,5 +79,33 @@ def test_precision_sweep(setup, scheme, prec):
         nerrs.append(nerr)
         print(f"  step {int(step):5d}: sampled rel-L2 {err:.3e}  energy-norm rel {nerr:.3e}", flush=True)
     plan.close()
+    return errs, nerrs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_precision_sweep(setup, scheme, prec):
+    ref = _golden(scheme)
+    print(f"[case] precision sweep 128^3 CFL10 {scheme}/{prec}", flush=True)
+    errs, nerrs = _sweep(setup, ref, scheme, prec)
     assert errs[-1] <= BAR[prec], errs
     assert nerrs[-1] <= BAR[prec], nerrs
+
+
+@pytest.fixture(scope="module")
+def setup_cfl5(setup):
+    c = dict(setup)
+    c["dt"] = W.yee_dt(c["h"], c["h"], c["h"], 5.0)
+    c["g"] = oracle.Grid(c["n"], c["n"], c["n"], c["h"], c["h"], c["h"], c["dt"], c["eps"])
+    return c
+
+
+@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r"])
+def test_precision_adi_cfl5(setup_cfl5, prec):
+    """The same sweep for ADI at CFL 5, the CFL number of the 512^3 workload."""
+    ref = _golden("adi_cfl5")
+    assert float(ref["cfl"]) == 5.0
+    print(f"[case] precision sweep 128^3 CFL5 adi/{prec}", flush=True)
+    errs, nerrs = _sweep(setup_cfl5, ref, "adi", prec)
+    assert errs[-1] <= BAR_CFL5[prec], errs
+    assert nerrs[-1] <= BAR_CFL5[prec], nerrs
