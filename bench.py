@@ -427,6 +427,17 @@ def main():
         in256 = make_inputs(256)
         extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256)
                                              for prec in ("f32", "f32r")]
+        # the other CFL numbers of the 512^3 workload: the passes have no
+        # data-dependent control flow, so the step time should not move
+        import workloads as W
+        h0, _, eps0, ci0 = inputs
+        cfl_rows = []
+        for cfl in (1.0, 10.0):
+            r = run_variant(n, "adi", "fundamental", "f32", max(10, args.steps // 4), 2,
+                            (h0, W.yee_dt(h0, h0, h0, cfl), eps0, ci0))
+            r["cfl"] = cfl
+            cfl_rows.append(r)
+        extras["adi_fundamental_512cube_cfl_1_and_10"] = cfl_rows
     if args.variants != "none":
         todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32r"), ("adi", "fundamental", "f32s64"),
                 ("adi", "conventional", "f32s64"),
