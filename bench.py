@@ -444,7 +444,9 @@ def main():
                 ("adi", "fundamental", "f64"), ("adi", "conventional", "f64"),
                 ("lod1", "fundamental", "f32"), ("ss2", "fundamental", "f32"), ("lod2", "fundamental", "f32"),
                 ("lod1", "conventional", "f32"), ("ss2", "conventional", "f32"), ("lod2", "conventional", "f32"),
-                ("dyakonov", "fundamental", "f32"), ("douglas_gunn", "fundamental", "f32")]
+                ("dyakonov", "fundamental", "f32"), ("douglas_gunn", "fundamental", "f32"),
+                ("lod1", "fundamental", "f64"), ("ss2", "fundamental", "f64"), ("lod2", "fundamental", "f64"),
+                ("lod1", "conventional", "f64"), ("ss2", "conventional", "f64"), ("lod2", "conventional", "f64")]
         if args.variants != "all":
             todo = [tuple(v.split("/")) for v in args.variants.split(",")]
         vsteps = max(10, args.steps // 4)
