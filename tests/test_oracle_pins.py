@@ -331,6 +331,35 @@ def test_cn_cavity_mode_closed_form_phase(mnp, cfl):
         assert yee.weighted_rel_l2(u, ref, g) < 1e-12
 
 
+def test_cn_schur_complement_is_spd_and_equivalent():
+    """The E-side reduction the library solves by CG: with theta = dt/2 and
+    (A + B) = [[0, eps^-1 K], [-mu^-1 K^T, 0]] on the dynamic samples, the
+    matrix S = eps + theta^2 K mu^-1 K^T is symmetric positive definite, and
+    S v_E = 2 eps u_E + 2 theta K u_H with v_H = 2 u_H - theta mu^-1 K^T v_E
+    solves [1/2 I - dt/4 (A + B)] v = u."""
+    g = small_grid(seed=35, cfl=9.0)
+    ds = dense.DenseSystem(g)
+    X = ds.A + ds.B
+    ie = np.array([c[0] == "E" for c, *_ in ds.nodes])
+    ih = ~ie
+    eps, mu = ds.w[ie], ds.w[ih]
+    K = eps[:, None] * X[np.ix_(ie, ih)]          # eps^-1 K is the E-H block
+    KT = -mu[:, None] * X[np.ix_(ih, ie)]         # -mu^-1 K^T is the H-E block
+    assert np.allclose(K.T, KT, atol=1e-12 * np.abs(K).max())
+    th = 0.5 * g.dt
+    S = np.diag(eps) + th * th * K @ (KT / mu[:, None])
+    assert np.allclose(S, S.T, rtol=0, atol=1e-12 * np.abs(S).max())
+    assert np.linalg.eigvalsh(S).min() > 0
+    u = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 36))
+    uE, uH = u[ie], u[ih]
+    vE = np.linalg.solve(S, 2 * eps * uE + 2 * th * K @ uH)
+    vH = 2 * uH - th * (KT @ vE) / mu
+    v = np.zeros_like(u)
+    v[ie], v[ih] = vE, vH
+    v_ref = np.linalg.solve(0.5 * np.eye(ds.n) - 0.25 * g.dt * X, u)
+    assert _wrel(ds, v, v_ref) < 1e-12
+
+
 def test_cn_temporal_order_two():
     nx, ny, nz, h = 8, 7, 6, 1e-3
     a = np.random.default_rng(7).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
