@@ -231,7 +231,7 @@ def run_splitting_original(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: 
     return x, mids
 
 
-def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int):
+def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, steps: int, source=None):
     """Fundamental forms of the same splittings (Sec. II-E).
 
     "dy", eq. (fastDY) with its input v^{-1/2} = (1/2 I - dt/4 B) u^0:
@@ -241,6 +241,9 @@ def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, step
     "dg", the ADI iteration (fasterADI) with (fastADIi) and (uTldCol), and the
       increments of (fastDGo): du* = u~^{n+1/2} - u~^n, du = (u~^{n+1} - u~^n)/2,
       accumulated as u^{n+1} = u^n + du.
+    A source enters as in ADI (the convention of ``source``): the term g of each
+    sub-step is added to the auxiliary subtraction, as g in the u~ scaling of
+    (fasterADI) and as g/2 in the unscaled variables of (fastDY).
     Returns the same as ``run_splitting_original``.
     """
     g, I = ds.g, np.eye(ds.n)
@@ -249,10 +252,12 @@ def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, step
     if scheme == "dy":
         v = (0.5 * I - q * ds.B) @ x0            # v^{-1/2}
         u = x0.copy()
-        for _ in range(steps):
-            v = u - v                            # v^n
+        for n in range(steps):
+            gA = ds.src_vec(source, source.g(0.5 * g.dt, (n + 0.25) * g.dt)) if source else 0.0
+            gB = ds.src_vec(source, source.g(0.5 * g.dt, (n + 0.75) * g.dt)) if source else 0.0
+            v = u - v + 0.5 * gA                 # v^n
             uh = np.linalg.solve(0.5 * I - q * ds.A, v)
-            v = uh - v                           # v^{n+1/2}
+            v = uh - v + 0.5 * gB                # v^{n+1/2}
             u = np.linalg.solve(0.5 * I - q * ds.B, v)
             mids.append(2.0 * v)
         return u, mids
@@ -260,11 +265,13 @@ def run_splitting_fundamental(ds: DenseSystem, scheme: str, x0: np.ndarray, step
         v = (I - 0.5 * g.dt * ds.B) @ x0         # v^{-1/2}, (fastADIi)
         ut = 2.0 * x0                            # u~^0, (uTldCol)
         u = x0.copy()
-        for _ in range(steps):
-            v = ut - v
+        for n in range(steps):
+            gA = ds.src_vec(source, source.g(0.5 * g.dt, (n + 0.25) * g.dt)) if source else 0.0
+            gB = ds.src_vec(source, source.g(0.5 * g.dt, (n + 0.75) * g.dt)) if source else 0.0
+            v = ut - v + gA
             uth = np.linalg.solve(0.5 * I - q * ds.A, v)
             dstar = uth - ut
-            v = uth - v
+            v = uth - v + gB
             utn = np.linalg.solve(0.5 * I - q * ds.B, v)
             du = 0.5 * (utn - ut)
             u = u + du

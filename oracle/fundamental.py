@@ -176,9 +176,21 @@ def solve_half(op: str, r, theta: float, g: Grid):
     return solve_implicit(op, PAIRS[op], [2.0 * a for a in r], theta, g)
 
 
-def dyakonov(u0, g: Grid, steps: int, record=None):
+def _src_add(v, source, val):
+    """v with val added at the Ez sample of the source (a copy of that component)."""
+    if source is None or val == 0.0:
+        return v
+    v = list(v)
+    v[CIDX["Ez"]] = v[CIDX["Ez"]].copy()
+    v[CIDX["Ez"]][source.k, source.j, source.i] += val
+    return v
+
+
+def dyakonov(u0, g: Grid, steps: int, record=None, source=None):
     """Eq. (fastDY) with input v^{-1/2} = (1/2 I - dt/4 B) u^0; returns u^steps.
-    `record(n, u)` is called with u^n for n = 0..steps when given."""
+    `record(n, u)` is called with u^n for n = 0..steps when given.  A source
+    term g of a sub-step enters the auxiliary subtraction as g/2 (the ADI
+    convention in these unscaled variables)."""
     half = 0.5 * g.dt
     bu = apply_operator("B", u0, g)
     v = [0.5 * a - 0.5 * half * b for a, b in zip(u0, bu)]   # v^{-1/2}
@@ -186,18 +198,21 @@ def dyakonov(u0, g: Grid, steps: int, record=None):
     if record:
         record(0, u)
     for n in range(steps):
-        v = [a - b for a, b in zip(u, v)]                     # v^n = u^n - v^{n-1/2}
-        uh = solve_half("A", v, half, g)                      # u^{n+1/2}
-        v = [a - b for a, b in zip(uh, v)]                    # v^{n+1/2}
-        u = solve_half("B", v, half, g)                       # u^{n+1}
+        gA = source.g(half, (n + 0.25) * g.dt) if source is not None else 0.0
+        gB = source.g(half, (n + 0.75) * g.dt) if source is not None else 0.0
+        v = _src_add([a - b for a, b in zip(u, v)], source, 0.5 * gA)    # v^n = u^n - v^{n-1/2}
+        uh = solve_half("A", v, half, g)                                  # u^{n+1/2}
+        v = _src_add([a - b for a, b in zip(uh, v)], source, 0.5 * gB)   # v^{n+1/2}
+        u = solve_half("B", v, half, g)                                   # u^{n+1}
         if record:
             record(n + 1, u)
     return u
 
 
-def douglas_gunn(u0, g: Grid, steps: int, record=None):
+def douglas_gunn(u0, g: Grid, steps: int, record=None, source=None):
     """The ADI iteration (fasterADI) from (fastADIi), (uTldCol), with the field
-    advanced by the increment of (fastDGo): u^{n+1} = u^n + (u~^{n+1} - u~^n)/2."""
+    advanced by the increment of (fastDGo): u^{n+1} = u^n + (u~^{n+1} - u~^n)/2.
+    A source term g enters the auxiliary subtraction as in ADI."""
     half = 0.5 * g.dt
     bu = apply_operator("B", u0, g)
     v = [a - half * b for a, b in zip(u0, bu)]                # v^{-1/2}
@@ -206,9 +221,11 @@ def douglas_gunn(u0, g: Grid, steps: int, record=None):
     if record:
         record(0, u)
     for n in range(steps):
-        v = [a - b for a, b in zip(ut, v)]
+        gA = source.g(half, (n + 0.25) * g.dt) if source is not None else 0.0
+        gB = source.g(half, (n + 0.75) * g.dt) if source is not None else 0.0
+        v = _src_add([a - b for a, b in zip(ut, v)], source, gA)
         uth = solve_half("A", v, half, g)                     # u~^{n+1/2}
-        v = [a - b for a, b in zip(uth, v)]
+        v = _src_add([a - b for a, b in zip(uth, v)], source, gB)
         utn = solve_half("B", v, half, g)                     # u~^{n+1}
         u = [a + 0.5 * (b - c) for a, b, c in zip(u, utn, ut)]
         ut = utn

@@ -13,7 +13,8 @@ from .yee import Grid, clean
 
 SCHEMES = ("adi", "lod1", "ss2", "lod2")
 FORMS = ("fundamental", "conventional")
-# D'Yakonov and Douglas-Gunn splittings of Sec. II-E (no nonhomogeneous terms)
+# D'Yakonov and Douglas-Gunn splittings of Sec. II-E (their original forms
+# take no nonhomogeneous term; the fundamental forms take the ADI convention)
 SPLITTINGS = ("dy", "dg")
 # Crank-Nicolson without factorization (Sec. II-E), a global sparse solve per step
 UNFACTORIZED = ("cn",)
@@ -30,9 +31,7 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
     if (scheme not in SCHEMES + SPLITTINGS + UNFACTORIZED) or form not in FORMS:
         raise ValueError((scheme, form))
     if scheme == "cn":
-        if source is not None:
-            raise ValueError("Crank-Nicolson takes no source")
-        return crank_nicolson.run_fields(g, fields, steps, form, energy_every)
+        return crank_nicolson.run_fields(g, fields, steps, form, energy_every, source)
     u = clean(fields, g)
     trace = []
 
@@ -43,8 +42,8 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
     if scheme in SPLITTINGS:
         # both splittings give the ADI fields u^n; their invariant is ADI's,
         # W((1/2 I + dt/4 B) u^n)
-        if source is not None:
-            raise ValueError("the D'Yakonov and Douglas-Gunn splittings take no source")
+        if source is not None and form == "conventional":
+            raise ValueError("the original D'Yakonov and Douglas-Gunn splittings take no source")
 
         def rec(n, un):
             record(n, lambda: conventional.invariant("adi", un, g))
@@ -56,7 +55,7 @@ def run(scheme: str, form: str, g: Grid, fields, steps: int, source=None,
                 rec(n + 1, u)
             return u, trace
         run_f = fundamental.dyakonov if scheme == "dy" else fundamental.douglas_gunn
-        return run_f(u, g, steps, rec), trace
+        return run_f(u, g, steps, rec, source), trace
 
     if form == "conventional":
         u = conventional.input_processing(scheme, u, g)

@@ -272,11 +272,23 @@ def test_splitting_fields_equal_adi_larger_grid(scheme):
         assert np.abs(np.array(t) - t[0]).max() / t[0] < 1e-12   # conserved
 
 
-def test_splittings_take_no_source():
-    g = small_grid(seed=29)
+@pytest.mark.parametrize("scheme", oracle.SPLITTINGS)
+def test_splitting_with_source_equals_adi(scheme):
+    """With a source, the fundamental D'Yakonov and Douglas-Gunn forms (the
+    ADI convention: g in the auxiliary subtraction, g/2 in the unscaled
+    variables of (fastDY)) give the fields of the original ADI with the same
+    source, dense and component form; the original splittings take none."""
+    g = small_grid(seed=29, cfl=6.0)
+    ds = dense.DenseSystem(g)
     u0 = W.random_fields(g.nx, g.ny, g.nz, 30)
+    src = _src(g)
+    x_adi, _ = dense.run_original(ds, "adi", ds.to_vec(u0), 9, src)
+    x, _ = dense.run_splitting_fundamental(ds, scheme, ds.to_vec(u0), 9, src)
+    assert _wrel(ds, x, x_adi) < 1e-12
+    u, _ = oracle.run(scheme, "fundamental", g, u0, 9, src)
+    assert _wrel(ds, ds.to_vec(u), x_adi) < 1e-12
     with pytest.raises(ValueError):
-        oracle.run("dy", "fundamental", g, u0, 2, _src(g))
+        oracle.run(scheme, "conventional", g, u0, 2, src)
 
 
 # --------------------------------------------------------------------------
@@ -375,7 +387,7 @@ def test_cn_temporal_order_two():
     assert all(abs(s_ - 2) < 0.1 for s_ in slopes), (errs, slopes)
 
 
-def test_cn_energy_conserved_and_no_source():
+def test_cn_energy_conserved():
     nx, ny, nz = 9, 8, 7
     eps = W.random_box_eps(nx, ny, nz, seed=9, nboxes=6)
     g = yee.Grid(nx, ny, nz, 1e-3, 1e-3, 1e-3, yee.cfl_dt(1e-3, 1e-3, 1e-3, 20.0), eps)
@@ -383,8 +395,26 @@ def test_cn_energy_conserved_and_no_source():
     u, tr = oracle.run("cn", "fundamental", g, u0, 30, None, 1)
     assert len(tr) == 31 and np.abs(np.array(tr) / tr[0] - 1).max() < 1e-12
     assert abs(tr[-1] / yee.energy(u, g) - 1) < 1e-13   # W over all samples
-    with pytest.raises(ValueError):
-        oracle.run("cn", "fundamental", g, u0, 2, _src(g))
+
+
+def test_cn_with_source_fundamental_equals_classical():
+    """With a source (one term per step, at its middle): the fundamental form,
+    which adds g/2 to u^n, against the classical form with g on its right
+    side written here with dense solves."""
+    from oracle import crank_nicolson as cn
+    g = small_grid(seed=43, cfl=6.0)
+    ds = dense.DenseSystem(g)
+    x0 = ds.to_vec(W.random_fields(g.nx, g.ny, g.nz, 44))
+    src = _src(g)
+    I, K = np.eye(ds.n), ds.A + ds.B
+    x_ref = x0.copy()
+    for n in range(7):
+        gv = ds.src_vec(src, src.g(0.5 * g.dt, (n + 0.5) * g.dt))
+        x_ref = np.linalg.solve(I - 0.5 * g.dt * K, (I + 0.5 * g.dt * K) @ x_ref + gv)
+    xs = dense.DenseSystem(g, sparse=True)
+    for form in oracle.FORMS:
+        x, _ = cn.run(xs, x0, 7, form, src)
+        assert _wrel(ds, x, x_ref) < 1e-12
 
 
 # --------------------------------------------------------------------------
