@@ -99,9 +99,6 @@ def pass_nodes(n):
 TIMING_EVERY = 8
 
 
-SPLITTINGS = ("dyakonov", "douglas_gunn")
-
-
 def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5):
     import torch
     from paper_2011_14043_amd import Plan, Source
@@ -113,13 +110,6 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     E = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
     H = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
     src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
-    if scheme in SPLITTINGS:
-        # the D'Yakonov and Douglas-Gunn splittings take no source: seeded
-        # N(0,1) initial fields instead
-        gen = torch.Generator(device=dev).manual_seed(7)
-        for t in E + H:
-            t.normal_(generator=gen)
-        src = None
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.from_numpy(eps), refine=prec == "f32r")
     if tune:

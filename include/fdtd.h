@@ -54,9 +54,9 @@ typedef enum {
 } fdtd_status;
 
 /* FDTD_DYAKONOV and FDTD_DOUGLAS_GUNN (Sec. II-E) take the fundamental form
- * only (else FDTD_EUNSUPPORTED) and no source (fdtd_run, fdtd_step and
- * fdtd_grad_eps return FDTD_EUNSUPPORTED for a non-NULL `src`: the paper
- * gives these splittings without a nonhomogeneous term).  Their fundamental
+ * only (else FDTD_EUNSUPPORTED).  The paper gives these splittings without a
+ * nonhomogeneous term; a source follows the ADI convention (see
+ * fdtd_source).  Their fundamental
  * forms are the iteration of (fasterADI) with other variables: (fastDY) is
  * it with u in place of u~ = 2u and the input v^{-1/2} = (1/2 I - dt/4 B) u^0,
  * and (fastDGo) reads the delta formulation's increments off u~.  Both give
@@ -64,7 +64,7 @@ typedef enum {
  * variables of (fastDY) (state v^n = (1/2 I + dt/4 B) u^n, field
  * u^{n+1} = v^{n+1/2} + v^{n+1}), so these plans run the fundamental ADI
  * passes, input and output processing unchanged: same fields, energy trace,
- * kernels and cost.  Batches accept them too. */
+ * kernels and cost.  Batches and fdtd_grad_eps accept them too. */
 /* FDTD_CRANK_NICOLSON (Sec. II-E, closing part) is the unfactorized scheme in
  * its fundamental form, [1/2 I - dt/4 (A + B)] u^{n+1/2} = u^n,
  * u^{n+1} = u^{n+1/2} - u^n: one global sparse system per step instead of line
@@ -73,8 +73,9 @@ typedef enum {
  * 2 eps u_E + 2 theta C_H(u_H) (C_E, C_H the discrete curls), which each step
  * solves by conjugate gradients with the diagonal as preconditioner, started
  * from v = 2 u_E, to the relative residual of fdtd_set_cg.  Fundamental form
- * and FDTD_F64 only, no source (else FDTD_EUNSUPPORTED); no batches, adjoint
- * or kernel configuration (no line passes).  fdtd_run returns
+ * and FDTD_F64 only (else FDTD_EUNSUPPORTED); no batches, adjoint or kernel
+ * configuration (no line passes).  A source adds one term per step (see
+ * fdtd_source).  fdtd_run returns
  * FDTD_ENOTCONVERGED, with every step done, if some step ended at the
  * iteration limit above the tolerance.  A Crank-Nicolson run synchronizes
  * the plan's stream: the host reads the residual every fourth iteration.
@@ -118,8 +119,10 @@ typedef struct {
  * with the single entry  theta * amp * p(t_k)  at that Ez sample, where
  * p(t) = exp(-((t - t0)/tau)^2) sin(2 pi f0 (t - t0)) and t_k is the middle
  * of the sub-step's time interval (ADI, LOD1: n+1/4, n+3/4; SS2: n+1/8, n+1/2,
- * n+7/8; LOD2: n+1/2, n+1; times dt, n counted from the plan's step counter).
- * The fundamental forms add the same term so that both forms agree. */
+ * n+7/8; LOD2: n+1/2, n+1; Crank-Nicolson, one term per step with
+ * theta = dt/2: n+1/2; times dt, n counted from the plan's step counter).
+ * The fundamental forms add the same term so that both forms agree; the
+ * D'Yakonov and Douglas-Gunn plans take ADI's. */
 typedef struct { int i, j, k; double f0, tau, t0, amp; } fdtd_source;
 
 /* Create a plan: validates `d`, copies eps_r, allocates the internal state

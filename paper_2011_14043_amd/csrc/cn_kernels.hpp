@@ -46,6 +46,8 @@ struct CnArgs {
     double* w[3];               // u_H - theta mu^-1 C_E(u_E) at the H samples (start of a step)
     double* partial;            // 3 x kCnBlocks
     double* scal;               // kCnScalars
+    long long src_off;          // state offset of the source's Ez sample (< 0: none)
+    double src_g;               // its term g of this step: eps g joins b and r at that sample
 };
 
 // Curl of H at E sample c (0..2) of node offset so; caller checks the E sample is dynamic.
@@ -112,7 +114,8 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_h_kernel(CnArgs a) {
 }
 
 // x = 2 u_E, r = 2 theta C_H(w), p = r / diag(S); sums r.z, r.r and b.b with
-// b = 2 eps u_E + 2 theta C_H(u_H).
+// b = 2 eps u_E + 2 theta C_H(u_H).  A source term g (added as g/2 to u_E in
+// the fundamental form) adds eps g to b and r at its Ez sample.
 __global__ void __launch_bounds__(kCnThreads) cn_start_e_kernel(CnArgs a) {
     const double* w[3] = {a.w[0], a.w[1], a.w[2]};
     const double* h[3] = {a.u[3], a.u[4], a.u[5]};
@@ -126,10 +129,11 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_e_kernel(CnArgs a) {
             double xv = 0.0, rv = 0.0, pv = 0.0;
             if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) {
                 const double ue = a.u[c][so];
+                const double gs = (c == 2 && so == a.src_off) ? eps * a.src_g : 0.0;
                 xv = 2.0 * ue;
-                rv = 2.0 * a.theta * curl_h(w, c, so, a);
+                rv = 2.0 * a.theta * curl_h(w, c, so, a) + gs;
                 pv = rv / s_diag(c, eps, a);
-                const double bv = 2.0 * eps * ue + 2.0 * a.theta * curl_h(h, c, so, a);
+                const double bv = 2.0 * eps * ue + 2.0 * a.theta * curl_h(h, c, so, a) + gs;
                 acc[0] += rv * pv;
                 acc[1] += rv * rv;
                 acc[2] += bv * bv;

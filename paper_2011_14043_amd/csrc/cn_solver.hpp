@@ -30,6 +30,8 @@ static CnArgs cn_args(fdtd_plan_s* p) {
     }
     a.partial = p->cg_partial;
     a.scal = p->cg_scal;
+    a.src_off = -1;
+    a.src_g = 0.0;
     return a;
 }
 
@@ -77,8 +79,8 @@ static fdtd_status cn_step(fdtd_plan_s* p, const CnArgs& a, long long* iters, do
 
 #undef CN_LAUNCH
 
-static fdtd_status cn_run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], int nsteps, double* energy,
-                               int every) {
+static fdtd_status cn_run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], int nsteps,
+                               const fdtd_source* src, double* energy, int every) {
     const Dims& dm = p->dims;
     const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
     const unsigned gblocks = (unsigned)((nn + 255) / 256);
@@ -110,11 +112,14 @@ static fdtd_status cn_run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3
     HIPCHK(hipEventRecord(tm.main0, p->stream));
     fdtd_status st = FDTD_OK;
     if (energy && (st = energy_into<double>(p, 0, p->energy_dev)) != FDTD_OK) return st;
-    const CnArgs a = cn_args(p);
+    CnArgs a = cn_args(p);
+    if (src) a.src_off = (long long)src->k * dm.plane + (long long)src->j * dm.px + src->i;
     p->cg_iters = 0;
     p->cg_rel = 0.0;
     fdtd_status conv = FDTD_OK;
     for (int n = 0; n < nsteps; ++n) {
+        // one source term per step, at its middle (theta = dt / 2)
+        a.src_g = source_value(src, 0.5 * p->d.dt, (double(p->step + n) + 0.5) * p->d.dt);
         double rel = 0.0;
         st = cn_step(p, a, &p->cg_iters, &rel);
         p->cg_rel = std::max(p->cg_rel, rel);

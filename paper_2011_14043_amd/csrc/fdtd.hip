@@ -71,10 +71,8 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (cn && (d->form != FDTD_FUNDAMENTAL || d->dtype != FDTD_F64)) return FDTD_EUNSUPPORTED;
     // D'Yakonov and Douglas-Gunn: the fundamental ADI iteration (Sec. II-E)
     fdtd_desc as_adi;
-    int splitting = 0;
     if (d->scheme == FDTD_DYAKONOV || d->scheme == FDTD_DOUGLAS_GUNN) {
         if (d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
-        splitting = d->scheme;
         as_adi = *d;
         as_adi.scheme = FDTD_ADI;
         d = &as_adi;
@@ -99,7 +97,6 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!p) return FDTD_ENOMEM;
     p->d = *d;
     p->d.eps_r = nullptr;
-    p->splitting = splitting;
     if (refine) {
         p->refine = 1;
         p->d.dtype = FDTD_F32;   // FP32 storage and arithmetic; only the fundamental passes differ
@@ -191,7 +188,6 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
     for (int c = 0; c < 3; ++c)
         if (!E[c] || !H[c]) return FDTD_EINVAL;
     if (energy && energy_every < 1) return FDTD_EINVAL;
-    if (src && (p->splitting || p->cg)) return FDTD_EUNSUPPORTED;
     if (src) {
         if (src->i < 1 || src->i >= p->d.nx || src->j < 1 || src->j >= p->d.ny || src->k < 0 || src->k >= p->d.nz)
             return FDTD_EINVAL;
@@ -202,7 +198,7 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
     (void)hipGetDevice(&dev_now);
     if (dev_now != p->device) (void)hipSetDevice(p->device);
     fdtd_status st;
-    if (p->cg) st = cn_run_impl(p, E, H, nsteps, energy, energy_every);
+    if (p->cg) st = cn_run_impl(p, E, H, nsteps, src, energy, energy_every);
     else if (p->d.dtype == FDTD_F32) st = run_impl<float, float>(p, E, H, nsteps, src, energy, energy_every);
     else if (p->d.dtype == FDTD_F64) st = run_impl<double, double>(p, E, H, nsteps, src, energy, energy_every);
     else st = run_impl<float, double>(p, E, H, nsteps, src, energy, energy_every);
@@ -348,7 +344,6 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
     const fdtd_desc& d = p->d;
     if (probe_i < 1 || probe_i >= d.nx || probe_j < 1 || probe_j >= d.ny || probe_k < 1 || probe_k >= d.nz)
         return FDTD_EINVAL;
-    if (src && p->splitting) return FDTD_EUNSUPPORTED;
     if (src) {
         if (src->i < 1 || src->i >= d.nx || src->j < 1 || src->j >= d.ny || src->k < 0 || src->k >= d.nz)
             return FDTD_EINVAL;

@@ -88,7 +88,6 @@ struct fdtd_plan_s {
     void* snap = nullptr;     // ADI: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
-    int splitting = 0;        // FDTD_DYAKONOV / FDTD_DOUGLAS_GUNN as requested (the plan runs as ADI)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
     // 3 x 1024 partial sums, scalars; CG controls and the last run's statistics
     double* cg = nullptr;

@@ -1,6 +1,7 @@
 """GPU parity of the D'Yakonov and Douglas-Gunn scheme ids (Sec. II-E)
 against the oracle's own forms of those splittings, which the CPU pins tie to
-the original formulae (orgDY), the delta formulation and Peaceman-Rachford."""
+the original formulae (orgDY), the delta formulation and Peaceman-Rachford;
+with a source, the ADI convention."""
 import numpy as np
 import pytest
 
@@ -57,20 +58,33 @@ def test_splitting_runs_the_adi_passes(case, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
-def test_splitting_rejects_source_and_conventional_form(scheme):
-    from paper_2011_14043_amd import Plan, Source
+def test_splitting_rejects_conventional_form(scheme):
+    from paper_2011_14043_amd import Plan
     n, h = 16, 1e-3
     dt = W.yee_dt(h, h, h, 4.0)
     with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
         Plan(n, n, n, dt, h, h, h, scheme=scheme, form="conventional")
-    plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, dtype=torch.float32)
-    E = [torch.zeros(n + 1, n + 1, n + 1, device=DEV) for _ in range(3)]
-    H = [torch.zeros(n + 1, n + 1, n + 1, device=DEV) for _ in range(3)]
-    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
-        plan.run(E, H, 2, source=Source(8, 8, 8, f0=1e10, tau=1e-10, t0=4e-10, amp=1.0))
-    plan.run(E, H, 2)
-    torch.cuda.synchronize()
-    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
+def test_splitting_with_source(case, scheme, dtype):
+    """With a point source: against the oracle's fundamental form with the ADI
+    convention, and bit for bit against an ADI plan."""
+    c = case
+    key = "dy" if scheme == "dyakonov" else "dg"
+    ci = W.interior_cell(c["nx"], c["ny"], c["nz"], seed=14)
+    src = OSource(*ci, amp=1e12, t0=3 * c["dt"], tau=3 * c["dt"], f0=1 / (12 * c["dt"]))
+    print(f"[case] 37x45x70 {scheme}/{dtype} with source", flush=True)
+    ref, _ = oracle.run(key, "fundamental", c["g"], c["u0"], 12, src)
+    args = (c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["eps"], c["u0"], 12, src)
+    got, _ = gpu_run(scheme, "fundamental", dtype, *args)
+    err = oracle.yee.weighted_rel_l2(got, ref, c["g"])
+    print(f"  rel-L2 {err:.3e}")
+    assert err < TOL[dtype]
+    adi, _ = gpu_run("adi", "fundamental", dtype, *args)
+    for x, y in zip(adi, got):
+        assert np.array_equal(x, y)
 
 
 def test_dyakonov_batch_equals_adi_batch():
@@ -98,8 +112,8 @@ def test_dyakonov_batch_equals_adi_batch():
 
 @pytest.mark.parametrize("scheme", ["dyakonov", "douglas_gunn"])
 def test_splitting_gradient_equals_adi(scheme):
-    """The adjoint gradient of a splitting plan (no source) is ADI's, bit for
-    bit; with a source the call is rejected."""
+    """The adjoint gradient of a splitting plan is ADI's, bit for bit, with
+    and without a source."""
     from paper_2011_14043_amd import Plan, Source
     nx, ny, nz, h = 24, 20, 18, 1e-3
     dt = W.yee_dt(h, h, h, 5.0)
@@ -109,14 +123,14 @@ def test_splitting_gradient_equals_adi(scheme):
     H = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[3:]]
     box = (6, 14, 5, 12, 6, 10)
     out = {}
+    src = Source(5, 6, 4, f0=1 / (10 * dt), tau=3 * dt, t0=4 * dt, amp=1e12)
     for s in ("adi", scheme):
         print(f"[case] gradient 24x20x18 {s}", flush=True)
         plan = Plan(nx, ny, nz, dt, h, h, h, scheme=s, dtype=torch.float64, eps_r=eps)
-        out[s] = plan.grad_eps(E, H, 30, (12, 10, 12), design_box=box, ckpt_every=7)
-        if s != "adi":
-            with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
-                plan.grad_eps(E, H, 5, (12, 10, 12), Source(4, 4, 4, f0=1e10, tau=1e-10, t0=4e-10, amp=1.0))
+        out[s] = [plan.grad_eps(E, H, 30, (12, 10, 12), design_box=box, ckpt_every=7),
+                  plan.grad_eps(E, H, 30, (12, 10, 12), src, design_box=box, ckpt_every=7)]
         torch.cuda.synchronize()
         plan.close()
-    assert out["adi"][0] == out[scheme][0]
-    assert torch.equal(out["adi"][1], out[scheme][1])
+    for a, b in zip(out["adi"], out[scheme]):
+        assert a[0] == b[0]
+        assert torch.equal(a[1], b[1])
