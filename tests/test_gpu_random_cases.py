@@ -30,7 +30,7 @@ def _case(seed):
     cfl = float(np.exp(rng.uniform(np.log(0.5), np.log(20.0))))
     h = tuple(float(v) for v in rng.uniform(0.7e-3, 1.4e-3, 3))
     steps = int(rng.integers(1, 9))
-    use_src = (not split) and bool(rng.integers(2)) and nx >= 3 and ny >= 3
+    use_src = bool(rng.integers(2)) and nx >= 3 and ny >= 3
     return nx, ny, nz, scheme, form, dtype, cfl, h, steps, use_src
 
 
@@ -103,24 +103,32 @@ def test_random_batch_case(seed):
 @pytest.mark.parametrize("seed", range(6))
 def test_random_crank_nicolson_case(seed):
     """Crank-Nicolson (FP64) on random grids of 2 to 16 cells per axis,
-    anisotropic cells, CFL 0.5 to 20, 1 to 4 steps, against sparse direct solves."""
-    from paper_2011_14043_amd import Plan
+    anisotropic cells, CFL 0.5 to 20, 1 to 4 steps (a source in odd cases),
+    against sparse direct solves."""
+    from paper_2011_14043_amd import Plan, Source
     rng = np.random.default_rng(8000 + seed)
     nx, ny, nz = (int(v) for v in rng.integers(2, 17, 3))
     cfl = float(np.exp(rng.uniform(np.log(0.5), np.log(20.0))))
     h = tuple(float(v) for v in rng.uniform(0.7e-3, 1.4e-3, 3))
     steps = int(rng.integers(1, 5))
-    print(f"[case] CN seed {seed}: {nx}x{ny}x{nz} CFL {cfl:.2f} h {h} steps {steps}", flush=True)
+    print(f"[case] CN seed {seed}: {nx}x{ny}x{nz} CFL {cfl:.2f} h {h} steps {steps} source {seed % 2}",
+          flush=True)
     dt = W.yee_dt(*h, cfl)
     eps = W.random_box_eps(nx, ny, nz, seed=9000 + seed, nboxes=4)
     u0 = W.random_fields(nx, ny, nz, seed=9100 + seed)
     g = oracle.Grid(nx, ny, nz, *h, dt, eps)
-    ref, tr_ref = oracle.run("cn", "fundamental", g, u0, steps, None, 1)
+    osrc = None
+    if seed % 2 == 1 and nx >= 3 and ny >= 3:
+        osrc = OSource(int(rng.integers(1, nx)), int(rng.integers(1, ny)), int(rng.integers(0, nz)), amp=1e12,
+                       t0=dt, tau=2 * dt, f0=1 / (8 * dt))
+    ref, tr_ref = oracle.run("cn", "fundamental", g, u0, steps, osrc, 1)
     plan = Plan(nx, ny, nz, dt, *h, scheme="crank_nicolson", dtype=torch.float64, eps_r=torch.tensor(eps))
     plan.set_cg(1e-13, 5000)
     E = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in u0[:3]]
     H = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in u0[3:]]
-    tr = plan.run(E, H, steps, energy_every=1)
+    src = None if osrc is None else Source(osrc.i, osrc.j, osrc.k, f0=osrc.f0, tau=osrc.tau, t0=osrc.t0,
+                                           amp=osrc.amp)
+    tr = plan.run(E, H, steps, source=src, energy_every=1)
     torch.cuda.synchronize()
     plan.close()
     got = [t.cpu().numpy() for t in E + H]
