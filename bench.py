@@ -250,9 +250,9 @@ def run_adjoint(prec="f32", steps=500, ckpt=50):
 
 
 def run_cn(n=256, steps=10, tol=1e-12):
-    """Crank-Nicolson without factorization (FP64, one CG solve per step)
-    against fundamental ADI (FP64) on the same n^3 random-box medium at CFL 5,
-    from the same seeded N(0,1) fields (Crank-Nicolson takes no source)."""
+    """Crank-Nicolson without factorization (FP64, one CG solve per step), in
+    fundamental and classical form, against fundamental ADI (FP64) on the same
+    n^3 random-box medium at CFL 5, from the same seeded N(0,1) fields."""
     import torch
     from paper_2011_14043_amd import Plan
     h, dt, eps, _ = make_inputs(n)
@@ -260,11 +260,12 @@ def run_cn(n=256, steps=10, tol=1e-12):
     shape = (n + 1, n + 1, n + 1)
     out = dict(workload=f"{n}^3 random-box eps_r, CFL 5, N(0,1) initial fields, no source", prec="f64", steps=steps,
                cg_tol=tol)
-    for scheme in ("crank_nicolson", "adi"):
+    for scheme, form, key in (("crank_nicolson", "fundamental", "cn"), ("crank_nicolson", "conventional", "cn_conv"),
+                              ("adi", "fundamental", "adi")):
         gen = torch.Generator(device=dev).manual_seed(11)
         E = [torch.empty(shape, dtype=torch.float64, device=dev).normal_(generator=gen) for _ in range(3)]
         H = [torch.empty(shape, dtype=torch.float64, device=dev).normal_(generator=gen) for _ in range(3)]
-        plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, dtype=torch.float64, eps_r=torch.from_numpy(eps))
+        plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=torch.float64, eps_r=torch.from_numpy(eps))
         if scheme == "adi":
             plan.autotune(3)
         else:
@@ -275,24 +276,23 @@ def run_cn(n=256, steps=10, tol=1e-12):
         plan.run(E, H, steps)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        key = "cn" if scheme == "crank_nicolson" else "adi"
         out[f"{key}_ms_per_step"] = ms
         out[f"{key}_mcells_per_s"] = n ** 3 / (ms * 1e-3) / 1e6
         if scheme == "crank_nicolson":
             st = plan.last_cg()
             it = st["iterations"] / steps
-            out["cg_iterations_per_step"] = it
-            out["cg_rel_residual_max"] = st["rel_residual"]
+            out[f"{key}_cg_iterations_per_step"] = it
+            out[f"{key}_cg_rel_residual_max"] = st["rel_residual"]
             # algorithmic bytes of one CG iteration: 276 B per node in FP64
             # (apply: p, eps -> q; update: x, p, r, q, eps -> x, r; direction:
             # r, p, eps -> p), kernels over all (n+1)^3 nodes
-            out["cg_iteration_gbs"] = 276 * (n + 1) ** 3 * it / (ms * 1e-3) / 1e9
-        finite = all(bool(torch.isfinite(t).all()) for t in E + H)
-        out[f"{key}_finite"] = finite
+            out[f"{key}_cg_iteration_gbs"] = 276 * (n + 1) ** 3 * it / (ms * 1e-3) / 1e9
+        out[f"{key}_finite"] = all(bool(torch.isfinite(t).all()) for t in E + H)
         plan.close()
         del E, H
         torch.cuda.empty_cache()
     out["cn_over_adi"] = out["cn_ms_per_step"] / out["adi_ms_per_step"]
+    out["cn_conventional_over_fundamental"] = out["cn_conv_ms_per_step"] / out["cn_ms_per_step"]
     log(json.dumps(out))
     return out
 

@@ -72,8 +72,11 @@ typedef enum {
  * symmetric positive definite system eps v + theta^2 C_H(mu^-1 C_E(v)) =
  * 2 eps u_E + 2 theta C_H(u_H) (C_E, C_H the discrete curls), which each step
  * solves by conjugate gradients with the diagonal as preconditioner, started
- * from v = 2 u_E, to the relative residual of fdtd_set_cg.  Fundamental form
- * and FDTD_F64 only (else FDTD_EUNSUPPORTED); no batches, adjoint or kernel
+ * from v = 2 u_E, to the relative residual of fdtd_set_cg.  The conventional
+ * form is the classical [I - dt/2 (A + B)] u^{n+1} = [I + dt/2 (A + B)] u^n:
+ * its right side f is formed explicitly, and the same system
+ * S u_E^{n+1} = eps f_E + theta C_H(f_H) is solved from the guess u_E^n.
+ * FDTD_F64 only (else FDTD_EUNSUPPORTED); no batches, adjoint or kernel
  * configuration (no line passes).  A source adds one term per step (see
  * fdtd_source).  fdtd_run returns
  * FDTD_ENOTCONVERGED, with every step done, if some step ended at the

@@ -236,6 +236,97 @@ __global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(CnArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Classical form, [I - theta (A + B)] u^{n+1} = [I + theta (A + B)] u^n + g:
+// the right side f is formed explicitly, then the same elimination of H gives
+//     S u_E^{n+1} = eps f_E + theta C_H(f_H),   u_H^{n+1} = f_H - theta mu^-1 C_E(u_E^{n+1}),
+// solved from the guess u_E^{n+1} = u_E^n.
+// ---------------------------------------------------------------------------
+
+// f_E = u_E + theta eps^-1 C_H(u_H) (+ g at the source) into r; f_H =
+// u_H - theta mu^-1 C_E(u_E) into w (0 off the dynamic samples).
+__global__ void __launch_bounds__(kCnThreads) cn_conv_rhs_kernel(CnArgs a) {
+    const double* e[3] = {a.u[0], a.u[1], a.u[2]};
+    const double* h[3] = {a.u[3], a.u[4], a.u[5]};
+    CN_NODES(a) {
+        const Node nd = node_of(unsigned(idx), a.d);
+        const long long so = (long long)nd.k * a.d.plane + (long long)nd.j * a.d.px + nd.i;
+        const double eps = a.eps0 * double(a.eps[so]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double fe = 0.0;
+            if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) {
+                fe = a.u[c][so] + a.theta * curl_h(h, c, so, a) / eps;
+                if (c == 2 && so == a.src_off) fe += a.src_g;
+            }
+            a.r[c][so] = fe;
+            a.w[c][so] = is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d)
+                             ? a.u[3 + c][so] - a.theta * a.rmu0 * curl_e(e, c, so, a) : 0.0;
+        }
+    }
+}
+
+// b = eps f_E + theta C_H(f_H) into r (f_E is read at the own node only);
+// x = p = u_E; sum b.b.
+__global__ void __launch_bounds__(kCnThreads) cn_conv_start_kernel(CnArgs a) {
+    const double* w[3] = {a.w[0], a.w[1], a.w[2]};
+    double acc[1] = {0.0};
+    CN_NODES(a) {
+        const Node nd = node_of(unsigned(idx), a.d);
+        const long long so = (long long)nd.k * a.d.plane + (long long)nd.j * a.d.px + nd.i;
+        const double eps = a.eps0 * double(a.eps[so]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double bv = 0.0, xv = 0.0;
+            if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) {
+                bv = eps * a.r[c][so] + a.theta * curl_h(w, c, so, a);
+                xv = a.u[c][so];
+                acc[0] += bv * bv;
+            }
+            a.r[c][so] = bv;
+            a.x[c][so] = xv;
+            a.p[c][so] = xv;
+        }
+    }
+    block_partials<1>(acc, a.partial);
+}
+
+// r = b - S x (q holds S x), p = r / diag(S); sums r.z and r.r.
+__global__ void __launch_bounds__(kCnThreads) cn_conv_resid_kernel(CnArgs a) {
+    double acc[2] = {0.0, 0.0};
+    CN_NODES(a) {
+        const Node nd = node_of(unsigned(idx), a.d);
+        const long long so = (long long)nd.k * a.d.plane + (long long)nd.j * a.d.px + nd.i;
+        const double eps = a.eps0 * double(a.eps[so]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (!is_dynamic(c, nd.i, nd.j, nd.k, a.d)) continue;
+            const double rv = a.r[c][so] - a.q[c][so];
+            const double pv = rv / s_diag(c, eps, a);
+            a.r[c][so] = rv;
+            a.p[c][so] = pv;
+            acc[0] += rv * pv;
+            acc[1] += rv * rv;
+        }
+    }
+    block_partials<2>(acc, a.partial);
+}
+
+// u_E = x;  u_H = f_H - theta mu^-1 C_E(x)  (dynamic samples only).
+__global__ void __launch_bounds__(kCnThreads) cn_conv_finish_kernel(CnArgs a) {
+    const double* e[3] = {a.x[0], a.x[1], a.x[2]};
+    CN_NODES(a) {
+        const Node nd = node_of(unsigned(idx), a.d);
+        const long long so = (long long)nd.k * a.d.plane + (long long)nd.j * a.d.px + nd.i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) a.u[c][so] = a.x[c][so];
+            if (is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d))
+                a.u[3 + c][so] = a.w[c][so] - a.theta * a.rmu0 * curl_e(e, c, so, a);
+        }
+    }
+}
+
 // scal[slot[m]] = sum of the m-th partial array (block m, fixed-order tree).
 struct CnSlots { int s[3]; };
 __global__ void __launch_bounds__(kCnThreads) cn_reduce_kernel(const double* partial, double* scal, CnSlots slots) {

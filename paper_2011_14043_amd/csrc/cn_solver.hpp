@@ -50,9 +50,20 @@ static fdtd_status cn_reduce(fdtd_plan_s* p, int m, CnSlots s) {
 // One Crank-Nicolson step on the plan's state.  Adds the iterations to
 // *iters and returns the final relative residual |r| / |b| in *rel.
 static fdtd_status cn_step(fdtd_plan_s* p, const CnArgs& a, long long* iters, double* rel) {
-    CN_LAUNCH(cn_start_h_kernel, a);
-    CN_LAUNCH(cn_start_e_kernel, a);
-    fdtd_status st = cn_reduce(p, 3, CnSlots{{kRz0, kRr, kBb}});
+    const bool conv = p->d.form == FDTD_CONVENTIONAL;
+    fdtd_status st;
+    if (conv) {   // classical form: explicit right side, guess u_E, residual by one product
+        CN_LAUNCH(cn_conv_rhs_kernel, a);
+        CN_LAUNCH(cn_conv_start_kernel, a);
+        if ((st = cn_reduce(p, 1, CnSlots{{kBb, 0, 0}})) != FDTD_OK) return st;
+        CN_LAUNCH(cn_apply_kernel, a);
+        CN_LAUNCH(cn_conv_resid_kernel, a);
+        st = cn_reduce(p, 2, CnSlots{{kRz0, kRr, 0}});
+    } else {
+        CN_LAUNCH(cn_start_h_kernel, a);
+        CN_LAUNCH(cn_start_e_kernel, a);
+        st = cn_reduce(p, 3, CnSlots{{kRz0, kRr, kBb}});
+    }
     if (st != FDTD_OK) return st;
     double host[2] = {0.0, 0.0};   // r.r, b.b
     int it = 0;
@@ -73,7 +84,8 @@ static fdtd_status cn_step(fdtd_plan_s* p, const CnArgs& a, long long* iters, do
         }
     }
     *iters += it;
-    CN_LAUNCH(cn_finish_kernel, a);
+    if (conv) CN_LAUNCH(cn_conv_finish_kernel, a);
+    else CN_LAUNCH(cn_finish_kernel, a);
     return *rel <= p->cg_tol ? FDTD_OK : FDTD_ENOTCONVERGED;
 }
 

@@ -68,7 +68,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (d->scheme < 0 || d->scheme > 6 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
         return FDTD_EINVAL;
     const bool cn = d->scheme == FDTD_CRANK_NICOLSON;
-    if (cn && (d->form != FDTD_FUNDAMENTAL || d->dtype != FDTD_F64)) return FDTD_EUNSUPPORTED;
+    if (cn && d->dtype != FDTD_F64) return FDTD_EUNSUPPORTED;
     // D'Yakonov and Douglas-Gunn: the fundamental ADI iteration (Sec. II-E)
     fdtd_desc as_adi;
     if (d->scheme == FDTD_DYAKONOV || d->scheme == FDTD_DOUGLAS_GUNN) {

@@ -15,10 +15,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _plan(nx, ny, nz, dt, h, eps=None, **kw):
+def _plan(nx, ny, nz, dt, h, eps=None, form="fundamental", **kw):
     from paper_2011_14043_amd import Plan
     hx, hy, hz = h if isinstance(h, tuple) else (h, h, h)
-    return Plan(nx, ny, nz, dt, hx, hy, hz, scheme="crank_nicolson", dtype=torch.float64,
+    return Plan(nx, ny, nz, dt, hx, hy, hz, scheme="crank_nicolson", form=form, dtype=torch.float64,
                 eps_r=None if eps is None else torch.tensor(eps), **kw)
 
 
@@ -30,16 +30,17 @@ def _run(plan, u0, steps, every=0):
     return [t.cpu().numpy() for t in E + H], tr
 
 
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
 @pytest.mark.parametrize("cfl", [2.0, 8.0])
-def test_cn_parity_random_media(cfl):
+def test_cn_parity_random_media(cfl, form):
     nx, ny, nz, h = 14, 12, 13, 1e-3
     dt = W.yee_dt(h, h, h, cfl)
     eps = W.random_box_eps(nx, ny, nz, seed=70, nboxes=6)
     u0 = W.random_fields(nx, ny, nz, seed=71)
     g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
-    print(f"[case] CN 14x12x13 CFL {cfl}", flush=True)
-    ref, tr_ref = oracle.run("cn", "fundamental", g, u0, 6, None, 1)
-    plan = _plan(nx, ny, nz, dt, h, eps)
+    print(f"[case] CN 14x12x13 CFL {cfl} {form}", flush=True)
+    ref, tr_ref = oracle.run("cn", form, g, u0, 6, None, 1)
+    plan = _plan(nx, ny, nz, dt, h, eps, form)
     plan.set_cg(1e-13, 2000)
     got, tr = _run(plan, u0, 6, 1)
     st = plan.last_cg()
@@ -70,7 +71,8 @@ def test_cn_cavity_mode_closed_form():
     assert oracle.yee.weighted_rel_l2(got, ref, g) < 1e-10
 
 
-def test_cn_with_source():
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+def test_cn_with_source(form):
     """A point source, one term per step at its middle, from zero fields and
     from random ones, against the oracle's sparse direct solves."""
     from paper_2011_14043_amd import Source
@@ -81,9 +83,9 @@ def test_cn_with_source():
     g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
     osrc = OSource(6, 7, 5, amp=1e12, t0=2 * dt, tau=3 * dt, f0=1 / (10 * dt))
     for u0 in (W.zero_fields(nx, ny, nz), W.random_fields(nx, ny, nz, seed=75)):
-        print("[case] CN 13x14x12 with source", flush=True)
-        ref, tr_ref = oracle.run("cn", "fundamental", g, u0, 8, osrc, 1)
-        plan = _plan(nx, ny, nz, dt, h, eps)
+        print(f"[case] CN 13x14x12 with source, {form}", flush=True)
+        ref, tr_ref = oracle.run("cn", form, g, u0, 8, osrc, 1)
+        plan = _plan(nx, ny, nz, dt, h, eps, form)
         plan.set_cg(1e-13, 2000)
         E = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[:3]]
         H = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[3:]]
@@ -116,8 +118,6 @@ def test_cn_iteration_limit_and_rejections():
     from paper_2011_14043_amd import Plan, Source
     n, h = 12, 1e-3
     dt = W.yee_dt(h, h, h, 8.0)
-    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
-        Plan(n, n, n, dt, h, h, h, scheme="crank_nicolson", form="conventional", dtype=torch.float64)
     with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
         Plan(n, n, n, dt, h, h, h, scheme="crank_nicolson", dtype=torch.float32)
     plan = _plan(n, n, n, dt, h)
