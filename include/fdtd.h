@@ -175,7 +175,10 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* pass_ms_avg
 /* Kernel configuration of the line passes along one axis (0 = x, 1 = y, 2 = z):
  *   chunk          slots of a line held by one thread (8, 16 or 32)
  *   tile_x         y/z lines: consecutive x positions per block (8, 16, 32); 0 for x
- *   block_threads  x lines: threads per block (64, 128, 256);
+ *   block_threads  x lines: threads per block (64, 128, 256); for a batch
+ *                  plan also 0: the x lines run inside the y/z launch of their
+ *                  sub-step, in its blocks, when chunk is 8 and y and z share
+ *                  a configuration built for it; otherwise in blocks of 256;
  *                  y/z lines: block-size bound of the variant (256, 512, 1024)
  *   remap          1 = XCD-aware block order, 0 = plain order
  * Every configuration computes the same result up to rounding order.
@@ -190,7 +193,10 @@ fdtd_status fdtd_set_kernel_config(fdtd_plan_t p, int axis, const fdtd_kernel_co
  * internal state, whose contents it overwrites) and keeps the fastest.  If
  * the environment variable FDTD_TUNE_CACHE names a file, a cached choice for
  * the same (nx, ny, nz, dtype, scheme, form) is used instead of timing, and a
- * new choice is appended to the file (one JSON object per line).
+ * new choice is appended to the file (one JSON object per line).  A batch
+ * plan then also times a pair of sub-steps with the tuned configurations
+ * against one launch per sub-step (x lines fused, y and z both in the tuned
+ * y or z configuration) and keeps the faster; it uses no cache.
  * best_ms (host array of 3, may be NULL) receives the best mean launch time
  * per axis (0 when taken from the cache).  Synchronizes the stream. */
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms);
@@ -253,10 +259,11 @@ fdtd_status fdtd_last_cg(fdtd_plan_t p, long long* iterations, double* rel_resid
  * FDTD_EUNSUPPORTED).  d[0..n-1] describe the grids (each validated as by
  * fdtd_plan; sizes, dt, dx, dy, dz and eps_r may differ; scheme, form and
  * dtype must be equal, else FDTD_EINVAL; Crank-Nicolson: FDTD_EUNSUPPORTED).
- * Every line pass of a sub-step runs as ONE launch over all grids, and the
- * y- and z-line passes share that launch when their kernel configurations
- * agree: the plan keeps a device table of the grids' pass arguments and a
- * work list of (table entry, block) items, and eight time
+ * Every line pass of a sub-step runs as ONE launch over all grids; the y-
+ * and z-line passes share that launch when their kernel configurations
+ * agree, and by default (x block_threads 0) the x-line pass joins it, so a
+ * sub-step is one launch.  The plan keeps a device table of the grids' pass
+ * arguments and a work list of (table entry, block) items, and eight time
  * steps of the main iteration are captured once as a HIP graph (on a private
  * stream) and replayed on `hip_stream` (remaining steps are launched
  * directly).  When the fields and media of all grids exceed 128 MiB, the

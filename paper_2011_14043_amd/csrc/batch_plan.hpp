@@ -31,7 +31,18 @@ static int batch_P(const fdtd_plan_s* g, int axis, const KCfg& c) {
     return axis == 0 ? P : std::max(P, 64 / c.TX);
 }
 
-static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
+// x lines of a batch with no block size of their own (wpb = 0) run inside
+// the y/z launch of their sub-step, in blocks of its size (fused launch);
+// where that launch is not available they run alone in blocks of 4 waves.
+static KCfg x_alone_cfg(const fdtd_plan_s* p) {
+    KCfg c = p->cfg[0];
+    if (c.wpb == 0) c.wpb = 4;
+    return c;
+}
+
+static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c0) {
+    KCfg c = c0;
+    if (axis == 0 && c.wpb == 0) c.wpb = 4;
     // refined batched passes: 8-slot chunks (the 16-slot y/z variant does not fit
     // its registers with the batch addressing)
     if (p->refine && c.M != 8) return false;
@@ -47,7 +58,7 @@ static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
 static void batch_default_cfg(fdtd_plan_s* p) {
     for (int axis = 0; axis < 3; ++axis) {
         std::vector<KCfg> pref;
-        if (axis == 0) pref = {{8, 0, 0, 4, 0}, {16, 0, 0, 4, 0}};
+        if (axis == 0) pref = {{8, 0, 0, 0, 0}, {16, 0, 0, 4, 0}};   // 8-slot chunks fused where possible
         else if (p->d.dtype == FDTD_F32) pref = {{8, 16, 1024, 0, 0}, {16, 32, 1024, 0, 0}, {16, 16, 512, 0, 0}, {32, 16, 512, 0, 0}};
         else pref = {{8, 8, 512, 0, 0}, {16, 16, 512, 0, 0}};
         for (const KCfg& c : pref)
@@ -61,9 +72,38 @@ static bool yz_same_cfg(const fdtd_plan_s* p) {
     return p->cfg[1].M == p->cfg[2].M && p->cfg[1].TX == p->cfg[2].TX && p->cfg[1].NT == p->cfg[2].NT;
 }
 
-// Launches of one sub-step with operator op: the x-line pair alone, the y- and
-// z-line pairs together when they share a configuration (else one each).
+// Kernel configurations {M, TX, NT} of the y/z lines with a fused launch (x
+// lines with 8-slot chunks), by solve precision.
+static const int kSubF32[][3] = {{8, 16, 1024}, {8, 32, 512}, {16, 32, 1024}, {16, 16, 512}};
+static const int kSubF64[][3] = {{8, 8, 512}, {8, 16, 1024}, {16, 16, 512}};
+
+static bool same_kcfg(const KCfg& a, const KCfg& b) {
+    return a.M == b.M && a.TX == b.TX && a.NT == b.NT && a.wpb == b.wpb && a.remap == b.remap;
+}
+
+static bool fused_ok(const fdtd_plan_s* p) {
+    if (p->cfg[0].wpb != 0 || p->cfg[0].M != 8 || !yz_same_cfg(p)) return false;
+    const KCfg& c = p->cfg[1];
+    if (p->refine && c.M != 8) return false;
+    if (p->d.dtype == FDTD_F32) {
+        for (const auto& v : kSubF32)
+            if (v[0] == c.M && v[1] == c.TX && v[2] == c.NT) return true;
+    } else {
+        for (const auto& v : kSubF64)
+            if (v[0] == c.M && v[1] == c.TX && v[2] == c.NT) return true;
+    }
+    return false;
+}
+
+// Launches of one sub-step with operator op: all three pairs in one launch
+// when the x lines are fused (above); otherwise the x-line pair alone, and
+// the y- and z-line pairs together when they share a configuration (else one
+// each).
 static int substep_masks(const fdtd_plan_s* p, int op, int (&masks)[3]) {
+    if (fused_ok(p)) {
+        masks[0] = 7;
+        return 1;
+    }
     int yz = 0, n = 0;
     for (int k = 0; k < 3; ++k) {
         if (kPairs[op][k].w == 0) masks[n++] = 1 << k;
@@ -80,52 +120,74 @@ static int substep_masks(const fdtd_plan_s* p, int op, int (&masks)[3]) {
 
 // The table of the passes (op, k in mask) with theta = frac * dt for every grid
 // (built on first use with the current kernel configuration).  Entry
-// j * ngrids + g is the j-th pair of the mask on grid g; a work item (entry,
-// block) names one block of one of them.
+// j * ngrids + g is the j-th pair of the mask (y/z pairs first) on grid g; a
+// work item (entry, block) names one block of one of them.
 template <typename T, typename S>
 static fdtd_status batch_pass(fdtd_plan_s* p, int op, int mask, double frac, const BatchPass** out) {
     Batch* b = p->batch;
     for (const BatchPass& bp : b->passes)
         if (bp.op == op && bp.mask == mask && bp.frac == frac) { *out = &bp; return FDTD_OK; }
-    int ks[3], nk = 0;
-    for (int k = 0; k < 3; ++k)
-        if (mask & (1 << k)) ks[nk++] = k;
+    int ks[3], nk = 0, nyz = 0;
+    for (int x = 0; x < 2; ++x)
+        for (int k = 0; k < 3; ++k)
+            if ((mask & (1 << k)) && (kPairs[op][k].w == 0) == (x == 1)) ks[nk++] = k;
+    for (int j = 0; j < nk; ++j) nyz += kPairs[op][ks[j]].w != 0;
     if (nk == 0) return FDTD_EINVAL;
+    const bool fused = nyz > 0 && nyz < nk;
+    if (fused && (nk != 3 || !fused_ok(p))) return FDTD_EINVAL;
     const int w = kPairs[op][ks[0]].w;
-    const KCfg& cf = p->cfg[w];
-    for (int j = 1; j < nk; ++j) {   // one launch needs one kernel configuration
+    const KCfg cf = w == 0 ? x_alone_cfg(p) : p->cfg[w];
+    for (int j = 1; j < nyz; ++j) {   // one launch needs one y/z kernel configuration
         const KCfg& c2 = p->cfg[kPairs[op][ks[j]].w];
-        if ((w == 0) != (kPairs[op][ks[j]].w == 0) || c2.M != cf.M || c2.TX != cf.TX || c2.NT != cf.NT)
-            return FDTD_EINVAL;
+        if (c2.M != cf.M || c2.TX != cf.TX || c2.NT != cf.NT) return FDTD_EINVAL;
     }
+    if (nyz == 0 && nk > 1) return FDTD_EINVAL;
     const int n = (int)b->subs.size();
     const int ne = n * nk;
     std::vector<PassArgs<T, S>> tab(ne);
-    int Pmax = 1;
-    for (int j = 0; j < nk; ++j) {
+    int Pmax = 1;   // y/z entries: block = TX * Pmax threads
+    auto build = [&](int j, const KCfg& c) {
         const int wj = kPairs[op][ks[j]].w;
         for (int g = 0; g < n; ++g) {
             fdtd_plan_s* sub = b->subs[g];
             PassArgs<T, S>& a = tab[j * n + g];
-            sub->cfg[wj] = p->cfg[wj];
+            sub->cfg[wj] = c;
             PassShape sh;
             build_pass<T, S>(sub, op, ks[j], frac * sub->d.dt, FUND, set_ptr<T>(sub, 0), set_ptr<T>(sub, 0), nullptr,
                              a, sh);
-            a.P = batch_P(sub, wj, p->cfg[wj]);
+            a.P = batch_P(sub, wj, c);
             a.remap = 0;
-            Pmax = std::max(Pmax, a.P);
+            if (wj != 0) Pmax = std::max(Pmax, a.P);
         }
+    };
+    for (int j = 0; j < nyz; ++j) build(j, p->cfg[kPairs[op][ks[j]].w]);
+    const int threads = nyz > 0 ? cf.TX * Pmax : 64 * cf.wpb;
+    if (nyz < nk) {   // the x pair: blocks of `threads` threads
+        KCfg cx = x_alone_cfg(p);
+        cx.wpb = threads / 64;
+        build(nyz, cx);
     }
-    std::vector<int2> items;
+    std::vector<int2> iyz, ix;
     int lds_rows = 0;   // y/z: sub-block areas x chunks, the most any entry needs
     for (int e = 0; e < ne; ++e) {
-        const int per = (w == 0) ? 1 : Pmax / tab[e].P;   // virtual blocks per block
+        const bool yz = e < nyz * n;
+        const int per = yz ? Pmax / tab[e].P : 1;   // virtual blocks per block
         const int nit = (tab[e].nblk + per - 1) / per;
-        for (int q = 0; q < nit; ++q) items.push_back(make_int2(e, q));
-        if (w != 0) lds_rows = std::max(lds_rows, ((Pmax + tab[e].P - 1) / tab[e].P) * tab[e].P);
+        for (int q = 0; q < nit; ++q) (yz ? iyz : ix).push_back(make_int2(e, q));
+        if (yz) lds_rows = std::max(lds_rows, ((Pmax + tab[e].P - 1) / tab[e].P) * tab[e].P);
+    }
+    // Interleave the two kinds in proportion: each XCD runs a contiguous
+    // range of the list.
+    std::vector<int2> items;
+    items.reserve(iyz.size() + ix.size());
+    for (size_t u = 0, v = 0; u < iyz.size() || v < ix.size();) {
+        if (v >= ix.size() || (u < iyz.size() && u * ix.size() <= v * iyz.size())) items.push_back(iyz[u++]);
+        else items.push_back(ix[v++]);
     }
     BatchPass bp;
     bp.op = op; bp.mask = mask; bp.w = w; bp.frac = frac; bp.Pmax = Pmax;
+    bp.ex0 = fused ? nyz * n : -1;
+    bp.threads = threads;
     bp.lds = (size_t)(p->refine ? 13 : 9) * lds_rows * (cf.TX + 1) * sizeof(S);
     bp.nitems = (int)items.size();
     HIPCHK(hipMalloc(&bp.tab, sizeof(PassArgs<T, S>) * ne));
@@ -150,8 +212,34 @@ static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStr
     const auto* tab = static_cast<const PassArgs<T, S>*>(bp.tab);
     const auto* items = static_cast<const int2*>(bp.items);
     const dim3 grid((unsigned)bp.nitems);
-    if (w == 0) {
-        const dim3 block(64 * cf.wpb);
+    if (bp.ex0 >= 0) {
+        // fused sub-step: x lines with 8-slot chunks inside the y/z launch
+        const int M = cf.M, TX = cf.TX, NT = cf.NT, ex0 = bp.ex0;
+        const dim3 block(bp.threads);
+        const size_t lds = bp.lds;
+        if (p->cfg[0].M != 8) return FDTD_EINVAL;
+#define CASE_SUB(MM, TT, NN)                                                                                  \
+    if (M == MM && TX == TT && NN == NT) {                                                                    \
+        if constexpr (MODE != FUND_REF || MM == 8) {                                                          \
+            if (mat)                                                                                          \
+                hipLaunchKernelGGL((pass_sub_batch_kernel<T, S, 8, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, \
+                                   items, ex0);                                                               \
+            else                                                                                              \
+                hipLaunchKernelGGL((pass_sub_batch_kernel<T, S, 8, MM, MODE, TT, NN, false>), grid, block, lds, st, tab, \
+                                   items, ex0);                                                               \
+        } else {                                                                                              \
+            return FDTD_EUNSUPPORTED;                                                                         \
+        }                                                                                                     \
+    } else
+        if constexpr (sizeof(S) == 4) {
+            CASE_SUB(8, 16, 1024) CASE_SUB(8, 32, 512) CASE_SUB(16, 32, 1024) CASE_SUB(16, 16, 512)
+            return FDTD_EUNSUPPORTED;
+        } else {
+            CASE_SUB(8, 8, 512) CASE_SUB(8, 16, 1024) CASE_SUB(16, 16, 512) return FDTD_EUNSUPPORTED;
+        }
+#undef CASE_SUB
+    } else if (w == 0) {
+        const dim3 block(bp.threads);
         if (cf.M == 8) {
             if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, true>), grid, block, 0, st, tab, items);
             else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, false>), grid, block, 0, st, tab, items);
@@ -163,7 +251,7 @@ static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStr
         }
     } else {
         const int M = cf.M, TX = cf.TX, NT = cf.NT;
-        const dim3 block(TX * bp.Pmax);
+        const dim3 block(bp.threads);
         const size_t lds = bp.lds;
 #define CASE_YZB(MM, TT, NN)                                                                                  \
     if (M == MM && TX == TT && NT == NN) {                                                                    \
@@ -419,6 +507,41 @@ static fdtd_status batch_autotune_impl(fdtd_plan_s* p, int reps, double* best_ms
         }
         p->cfg[axis] = best;
         if (best_ms) best_ms[axis] = tbest / reps;
+    }
+    // Joint choice: the configurations tuned above with separate launches, or
+    // one launch per sub-step (x lines fused) with both y and z in the y or in
+    // the z configuration; timed over sub-step pairs launched on the stream.
+    if (st == FDTD_OK) {
+        const KCfg tuned[3] = {p->cfg[0], p->cfg[1], p->cfg[2]};
+        std::vector<std::array<KCfg, 3>> cand = {{tuned[0], tuned[1], tuned[2]}};
+        for (int src = 1; src <= 2; ++src) {
+            if (src == 2 && same_kcfg(tuned[1], tuned[2])) break;
+            const KCfg c0{8, 0, 0, 0, tuned[0].remap}, cy = tuned[src];
+            if (!batch_cfg_valid(p, 0, c0) || !batch_cfg_valid(p, 1, cy) || !batch_cfg_valid(p, 2, cy)) continue;
+            p->cfg[0] = c0;
+            p->cfg[1] = p->cfg[2] = cy;
+            if (fused_ok(p)) cand.push_back({c0, cy, cy});
+        }
+        int ibest = 0;
+        float tbest = 1e30f;
+        for (size_t i = 0; i < cand.size() && cand.size() > 1 && st == FDTD_OK; ++i) {
+            for (int a = 0; a < 3; ++a) p->cfg[a] = cand[i][a];
+            batch_clear(b);
+            float ms = 0.0f;
+            for (int r = 0; r <= reps && st == FDTD_OK; ++r) {   // r = 0: build the tables, warm up
+                if (r == 1 && hipEventRecord(e0, p->stream) != hipSuccess) st = FDTD_EDEVICE;
+                if (st == FDTD_OK) st = batch_substep<T, S>(p, 0, 0.5, p->stream);
+                if (st == FDTD_OK) st = batch_substep<T, S>(p, 1, 0.5, p->stream);
+            }
+            if (st != FDTD_OK) break;
+            if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = FDTD_EDEVICE;
+                break;
+            }
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < tbest) { tbest = ms; ibest = (int)i; }
+        }
+        for (int a = 0; a < 3; ++a) p->cfg[a] = cand[ibest][a];
     }
     batch_clear(b);
     (void)hipEventDestroy(e0);

@@ -50,9 +50,12 @@ struct Timing {
 // the grids' pass arguments and a work list of (grid, block) items.
 struct BatchPass {
     int op = 0;
-    int mask = 0;             // pairs k of operator op in this launch (bit k); all on one axis
-                              // family with one kernel configuration (x, or y and z)
-    int w = 0;                // line axis of the first pair (selects the configuration)
+    int mask = 0;             // pairs k of operator op in this launch (bit k): the x pair, y/z
+                              // pairs of one kernel configuration, or all three (fused)
+    int w = 0;                // line axis of the first pair (selects the configuration); a fused
+                              // launch has its y/z pairs first
+    int ex0 = -1;             // fused launch: first x-line entry of tab; -1 otherwise
+    int threads = 0;          // threads per block
     double frac = 0.0;        // theta = frac * dt of each grid
     void* tab = nullptr;      // device PassArgs<T, S>[ngrids x pairs in mask], pair-major
     void* items = nullptr;    // device int2[nitems]

@@ -123,7 +123,14 @@ def test_batch_invalid():
     assert L.fdtd_run(plan._h, pe, pe, 1, None, None, 1) == -1
     with pytest.raises(FdtdError, match="EINVAL"):
         plan.set_kernel_config(1, chunk=16, tile_x=24, block_threads=512)
+    # x lines fused into the y/z launch: the batch default; single grids have no such launch
+    assert plan.kernel_config(0)["block_threads"] == 0
     plan.close()
+    from paper_2011_14043_amd import Plan
+    sp = Plan(16, 16, 16, dt, h, h, h, eps_r=torch.ones(16, 16, 16))
+    with pytest.raises(FdtdError, match="EINVAL"):
+        sp.set_kernel_config(0, chunk=8, block_threads=0)
+    sp.close()
 
 
 # ---------------------------------------------------------------------------
@@ -227,24 +234,25 @@ def test_graph_replays_match_eager_single_grids(small_refs, scheme):
         p.close()
 
 
-@pytest.mark.parametrize("split", [False, True], ids=["yz-one-launch", "yz-separate"])
+@pytest.mark.parametrize("launch", ["fused", "yz-one-launch", "yz-separate"])
 @pytest.mark.parametrize("refine", [False, True], ids=["f32", "f32r"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1"])
-def test_batch_bitwise_equals_single_grids(scheme, refine, split):
+def test_batch_bitwise_equals_single_grids(scheme, refine, launch):
     """Grids whose chunk counts are the same powers of two in both paths run
-    the same arithmetic: the batch (graph replays, one launch per sub-step for
-    the y and z passes when they share a configuration, else one each) equals
-    the single-grid plans (eager) bit for bit, over 17 steps (two replays of
-    the eight-step graph)."""
+    the same arithmetic: the batch (graph replays; a sub-step as one launch
+    with the x lines fused, or the x pass alone and the y and z passes in one
+    launch, or one launch each) equals the single-grid plans (eager) bit for
+    bit, over 17 steps (two replays of the eight-step graph)."""
     from paper_2011_14043_amd import BatchPlan, Plan
+    split = launch == "yz-separate"
     if split and refine:
         pytest.skip("refined batched passes use 8-slot chunks only")
     h = 1e-3
     dt = W.yee_dt(h, h, h, 5.0)
     grids = _grids([(32, 64, 32), (64, 32, 64)], seed=300)
 
-    def configure(p):
-        p.set_kernel_config(0, chunk=8, block_threads=256, remap=1)
+    def configure(p, batch=False):
+        p.set_kernel_config(0, chunk=8, block_threads=0 if (batch and launch == "fused") else 256, remap=1)
         p.set_kernel_config(1, chunk=8, tile_x=16, block_threads=1024, remap=1)
         if split:
             p.set_kernel_config(2, chunk=16, tile_x=16, block_threads=512, remap=1)
@@ -253,7 +261,8 @@ def test_batch_bitwise_equals_single_grids(scheme, refine, split):
 
     bp = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in grids], dt, h, h, h,
                    scheme=scheme, dtype=torch.float32, refine=refine)
-    configure(bp)
+    configure(bp, batch=True)
+    assert bp.kernel_config(0)["block_threads"] == (0 if launch == "fused" else 256)
     fb = [_fields(u0, torch.float32) for (*_, u0) in grids]
     bp.run(fb, 17)
     torch.cuda.synchronize()
