@@ -276,3 +276,34 @@ def test_batch_bitwise_equals_single_grids(scheme, refine, launch):
         p.close()
         for a, b in zip(E + H, Eb + Hb):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec,yz", [("f32", (8, 16, 1024)), ("f32", (8, 32, 512)), ("f32", (16, 32, 1024)),
+                                     ("f32", (16, 16, 512)), ("f32r", (8, 16, 1024)), ("f64", (8, 8, 512)),
+                                     ("f64", (8, 16, 1024)), ("f64", (16, 16, 512))])
+def test_batch_fused_bitwise_equals_separate(prec, yz):
+    """One launch per sub-step (x-line blocks inside the y/z launch, in blocks
+    of its size) against the x pass as a launch of its own: the same line
+    solves in other blocks, so bit-for-bit equal, over 12 uneven cavities and
+    17 steps, for every y/z configuration the fused launch is built for."""
+    from paper_2011_14043_amd import BatchPlan
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    grids = _grids(W.cavity_batch(12, seed=7), seed=500)
+    print(f"[case] fused vs separate {prec} yz={yz}", flush=True)
+    out = []
+    for fused in (False, True):
+        bp = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in grids], dt, h, h, h,
+                       dtype=dtype, refine=prec == "f32r")
+        bp.set_kernel_config(0, chunk=8, block_threads=0 if fused else 256, remap=1)
+        for ax in (1, 2):
+            bp.set_kernel_config(ax, chunk=yz[0], tile_x=yz[1], block_threads=yz[2], remap=1)
+        f = [_fields(u0, dtype) for (*_, u0) in grids]
+        bp.run(f, 17)
+        torch.cuda.synchronize()
+        bp.close()
+        out.append(f)
+    for (Ea, Ha), (Eb, Hb) in zip(*out):
+        for a, b in zip(Ea + Ha, Eb + Hb):
+            assert torch.equal(a, b)
