@@ -229,9 +229,10 @@ class Plan:
 
 
 class BatchPlan(Plan):
-    """Independent grids stepped together, one launch per line pass over all
-    grids and one captured HIP graph per time step (fdtd_plan_batch;
-    fundamental forms).  grids: list of (nx, ny, nz, eps_r or None)."""
+    """Independent grids stepped together: by default one launch per sub-step
+    (its three line passes) over all grids of a group, eight time steps per
+    captured HIP graph (fdtd_plan_batch; fundamental forms).  grids: list of
+    (nx, ny, nz, eps_r or None)."""
 
     def __init__(self, grids, dt, dx, dy, dz, scheme="adi", dtype=None, stream=None, device=None,
                  solve_dtype=None, refine=False):

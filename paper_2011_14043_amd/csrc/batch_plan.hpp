@@ -283,7 +283,7 @@ static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t
     return batch_launch_mode<T, S, FUND>(p, bp, st);
 }
 
-// One sub-step (operator op, theta = frac * dt) of every grid: two or three launches.
+// One sub-step (operator op, theta = frac * dt) of every grid: one, two or three launches.
 template <typename T, typename S>
 static fdtd_status batch_substep(fdtd_plan_s* p, int op, double frac, hipStream_t st) {
     int masks[3];
@@ -341,8 +341,9 @@ static fdtd_status batch_graph(fdtd_plan_s* p) {
     Batch* b = p->batch;
     if (b->exec) return FDTD_OK;
     const SchemeDef& sd = kSchemes[p->d.scheme];
-    // The launches of a sub-step update disjoint arrays: capture them as
-    // parallel branches (fork on events, join before the next sub-step).
+    // A sub-step of several launches (no fused launch): they update disjoint
+    // arrays, so they are captured as parallel branches (fork on events, join
+    // before the next sub-step).  A fused sub-step is one node of a chain.
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     fdtd_status st = FDTD_OK;
     hipStream_t br[3] = {b->cap, b->fork[0], b->fork[1]};
