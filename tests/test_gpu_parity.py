@@ -14,6 +14,7 @@ import workloads as W
 from oracle.source import Source as OSource
 
 from . import _analytic as an
+from ._sampled import lod1_zline
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -275,6 +276,51 @@ def test_cavity_mode_at_full_size(n, prec, steps):
     err = math.sqrt(num / den)
     print(f"[case] cavity mode {n}^3 {prec}: rel-L2 {err:.3e}")
     assert err < {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6, "f32r": 1e-5}[prec]
+
+
+@pytest.fixture(scope="module")
+def full_size_case():
+    """512^3, the benchmark's medium (32 random eps_r boxes, seed 2), CFL 5,
+    N(0,1) fields (seed 3)."""
+    n, h = 512, 1e-3
+    return n, h, W.yee_dt(h, h, h, 5.0), W.random_box_eps(n, n, n, seed=2, nboxes=32), W.random_fields(n, n, n, seed=3)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lod1_sampled_lines_full_size(full_size_case, prec):
+    """One fundamental LOD1 step at 512^3 (FP32 in the benchmark's kernel
+    configuration, and FP64): Ex and Hy on sampled z lines, next to the walls
+    and inside, element by element against the oracle's sub-steps on the thin
+    slabs those lines depend on (``_sampled.lod1_zline``, pinned against
+    whole-grid oracle steps).  Bars as for a few steps: 2e-5 (FP32), 1e-11
+    (FP64), energy-weighted relative L2 over the sampled lines."""
+    Plan, _ = _lib()
+    n, h, dt, eps, u0 = full_size_case
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    print(f"[case] LOD1 sampled lines 512^3 {prec}", flush=True)
+    E = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[3:]]
+    plan = Plan(n, n, n, dt, h, h, h, scheme="lod1", form="fundamental", dtype=dtype, eps_r=torch.from_numpy(eps))
+    if prec == "f32":
+        plan.set_kernel_config(0, chunk=8, block_threads=128, remap=0)
+        for ax in (1, 2):
+            plan.set_kernel_config(ax, chunk=16, tile_x=32, block_threads=1024, remap=1)
+    plan.run(E, H, 1)
+    torch.cuda.synchronize()
+    plan.close()
+    eps64 = eps.astype(np.float64)
+    num = den = 0.0
+    for i0, j0 in [(0, 1), (257, 300), (n - 1, n - 1), (100, 2)]:
+        ref_ex, ref_hy = lod1_zline(eps64, u0[0][:, :, i0], u0[5][:, :, i0], u0[2][:, j0, :], u0[4][:, j0, :],
+                                    i0, j0, h, dt)
+        got_ex = E[0][:, j0, i0].double().cpu().numpy()
+        got_hy = H[1][:, j0, i0].double().cpu().numpy()
+        num += 8.8541878128e-12 * np.sum((got_ex - ref_ex) ** 2) + 1.25663706212e-6 * np.sum((got_hy - ref_hy) ** 2)
+        den += 8.8541878128e-12 * np.sum(ref_ex ** 2) + 1.25663706212e-6 * np.sum(ref_hy ** 2)
+    del E, H
+    err = math.sqrt(num / den)
+    print(f"[case] LOD1 sampled lines 512^3 {prec}: rel-L2 {err:.3e}", flush=True)
+    assert err < {"f32": 2e-5, "f64": 1e-11}[prec]
 
 
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
