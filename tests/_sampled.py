@@ -1,8 +1,10 @@
-"""Sampled outputs of one fundamental LOD1 (SS1) step at any grid size, for
-parity at sizes the oracle's whole-grid steps do not reach.
+"""Sampled outputs of one LOD1 (SS1) step, fundamental or conventional form,
+at any grid size, for parity at sizes the oracle's whole-grid steps do not
+reach.
 
 One LOD1 step applies the A sub-step, then the B sub-step, both with
-theta = dt/2 (Sec. III, the LOD family).  Every pair pass couples samples
+theta = dt/2 (Sec. III for the fundamental form, eq. (orgLOD) for the
+conventional one, whose right side applies the same operator).  Every pair pass couples samples
 along its own line only, so Ex and Hy on one z line (i0, j0) after the step
 depend on:
 * Ex after A on that line: the A pass of the pair (Ex, Hz) along y, whose
@@ -10,7 +12,8 @@ depend on:
 * Hy after A on that line: the A pass of the pair (Ez, Hy) along x, whose
   lines at y index j0 use Ez, Hy and the cells of the plane y = j0;
 and then on the B pass of the pair (Ex, Hy) along z on that line.
-The oracle's own sub-step (``oracle.fundamental.lod_substep``) runs each of
+The oracle's own sub-step (``oracle.fundamental.lod_substep``, or
+``oracle.conventional.substep`` with X = Y) runs each of
 these on a thin grid that holds exactly those lines: one cell wide in x
 (x = i0) or two cells wide in y (cells j0 - 1 and j0, so that y index j0 is
 interior), with the same cells, hence the same per-node eps_r (the node
@@ -23,15 +26,23 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+from oracle import conventional
 from oracle.fundamental import LOD_MAIN, lod_substep
 from oracle.yee import CIDX
+
+
+def _substep(form):
+    if form == "fundamental":
+        return lod_substep
+    assert form == "conventional"
+    return lambda u, op, theta, g: conventional.substep(u, op, op, theta, g)
 
 
 def _zeros(nx, ny, nz):
     return [np.zeros((nz + 1, ny + 1, nx + 1)) for _ in range(6)]
 
 
-def lod1_zline(eps_r, ex_x, hz_x, ez_y, hy_y, i0, j0, h, dt):
+def lod1_zline(eps_r, ex_x, hz_x, ez_y, hy_y, i0, j0, h, dt, form="fundamental"):
     """Ex and Hy on the z line (x index i0, y index j0) after one LOD1 step.
 
     eps_r: cells (nz, ny, nx); ex_x, hz_x: Ex and Hz at x index i0, arrays
@@ -42,22 +53,24 @@ def lod1_zline(eps_r, ex_x, hz_x, ez_y, hy_y, i0, j0, h, dt):
     assert 0 <= i0 < nx and 1 <= j0 <= ny - 1
     (op_a, fa, _), (op_b, fb, _) = LOD_MAIN["lod1"]
     assert (op_a, op_b) == ("A", "B")
+    assert [m[:3] for m in conventional.MAIN["lod1"]] == [("A", "A", fa), ("B", "B", fb)]
+    sub = _substep(form)
     # A: pair (Ex, Hz) along y on the plane x = i0
     g1 = oracle.Grid(1, ny, nz, h, h, h, dt, eps_r[:, :, i0:i0 + 1])
     u = _zeros(1, ny, nz)
     u[CIDX["Ex"]][:, :, 0] = ex_x
     u[CIDX["Hz"]][:, :, 0] = hz_x
-    ex_a = lod_substep(u, "A", fa * dt, g1)[CIDX["Ex"]][:, j0, 0]
+    ex_a = sub(u, "A", fa * dt, g1)[CIDX["Ex"]][:, j0, 0]
     # A: pair (Ez, Hy) along x on the plane y = j0
     g2 = oracle.Grid(nx, 2, nz, h, h, h, dt, eps_r[:, j0 - 1:j0 + 1, :])
     u = _zeros(nx, 2, nz)
     u[CIDX["Ez"]][:, 1, :] = ez_y
     u[CIDX["Hy"]][:, 1, :] = hy_y
-    hy_a = lod_substep(u, "A", fa * dt, g2)[CIDX["Hy"]][:, 1, i0]
+    hy_a = sub(u, "A", fa * dt, g2)[CIDX["Hy"]][:, 1, i0]
     # B: pair (Ex, Hy) along z on the line (i0, j0)
     g3 = oracle.Grid(1, 2, nz, h, h, h, dt, eps_r[:, j0 - 1:j0 + 1, i0:i0 + 1])
     u = _zeros(1, 2, nz)
     u[CIDX["Ex"]][:, 1, 0] = ex_a
     u[CIDX["Hy"]][:, 1, 0] = hy_a
-    out = lod_substep(u, "B", fb * dt, g3)
+    out = sub(u, "B", fb * dt, g3)
     return out[CIDX["Ex"]][:, 1, 0], out[CIDX["Hy"]][:, 1, 0]

@@ -286,10 +286,11 @@ def full_size_case():
     return n, h, W.yee_dt(h, h, h, 5.0), W.random_box_eps(n, n, n, seed=2, nboxes=32), W.random_fields(n, n, n, seed=3)
 
 
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_lod1_sampled_lines_full_size(full_size_case, prec):
-    """One fundamental LOD1 step at 512^3 (FP32 in the benchmark's kernel
-    configuration, and FP64): Ex and Hy on sampled z lines, next to the walls
+def test_lod1_sampled_lines_full_size(full_size_case, prec, form):
+    """One LOD1 step, fundamental and conventional form, at 512^3 (FP32 in the
+    benchmark's kernel configuration, and FP64): Ex and Hy on sampled z lines, next to the walls
     and inside, element by element against the oracle's sub-steps on the thin
     slabs those lines depend on (``_sampled.lod1_zline``, pinned against
     whole-grid oracle steps).  Bars as for a few steps: 2e-5 (FP32), 1e-11
@@ -297,10 +298,10 @@ def test_lod1_sampled_lines_full_size(full_size_case, prec):
     Plan, _ = _lib()
     n, h, dt, eps, u0 = full_size_case
     dtype = torch.float32 if prec == "f32" else torch.float64
-    print(f"[case] LOD1 sampled lines 512^3 {prec}", flush=True)
+    print(f"[case] LOD1 {form} sampled lines 512^3 {prec}", flush=True)
     E = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[:3]]
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[3:]]
-    plan = Plan(n, n, n, dt, h, h, h, scheme="lod1", form="fundamental", dtype=dtype, eps_r=torch.from_numpy(eps))
+    plan = Plan(n, n, n, dt, h, h, h, scheme="lod1", form=form, dtype=dtype, eps_r=torch.from_numpy(eps))
     if prec == "f32":
         plan.set_kernel_config(0, chunk=8, block_threads=128, remap=0)
         for ax in (1, 2):
@@ -312,14 +313,14 @@ def test_lod1_sampled_lines_full_size(full_size_case, prec):
     num = den = 0.0
     for i0, j0 in [(0, 1), (257, 300), (n - 1, n - 1), (100, 2)]:
         ref_ex, ref_hy = lod1_zline(eps64, u0[0][:, :, i0], u0[5][:, :, i0], u0[2][:, j0, :], u0[4][:, j0, :],
-                                    i0, j0, h, dt)
+                                    i0, j0, h, dt, form)
         got_ex = E[0][:, j0, i0].double().cpu().numpy()
         got_hy = H[1][:, j0, i0].double().cpu().numpy()
         num += 8.8541878128e-12 * np.sum((got_ex - ref_ex) ** 2) + 1.25663706212e-6 * np.sum((got_hy - ref_hy) ** 2)
         den += 8.8541878128e-12 * np.sum(ref_ex ** 2) + 1.25663706212e-6 * np.sum(ref_hy ** 2)
     del E, H
     err = math.sqrt(num / den)
-    print(f"[case] LOD1 sampled lines 512^3 {prec}: rel-L2 {err:.3e}", flush=True)
+    print(f"[case] LOD1 {form} sampled lines 512^3 {prec}: rel-L2 {err:.3e}", flush=True)
     assert err < {"f32": 2e-5, "f64": 1e-11}[prec]
 
 

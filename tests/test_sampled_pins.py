@@ -6,22 +6,24 @@ import pytest
 
 import oracle
 import workloads as W
+from oracle import conventional
 from oracle.fundamental import lod_step
 from oracle.yee import CIDX
 from ._sampled import lod1_zline
 
 
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
 @pytest.mark.parametrize("nx,ny,nz,seed", [(9, 11, 13, 1), (16, 7, 10, 2)])
-def test_sampled_lod1_equals_whole_grid(nx, ny, nz, seed):
+def test_sampled_lod1_equals_whole_grid(nx, ny, nz, seed, form):
     h = 1e-3
     dt = W.yee_dt(h, h, h, 5.0)
     eps = W.random_box_eps(nx, ny, nz, seed=seed, nboxes=6).astype(np.float64)
     u0 = W.random_fields(nx, ny, nz, seed=seed + 10)
     g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
-    ref = lod_step("lod1", u0, g, 0)
+    ref = lod_step("lod1", u0, g, 0) if form == "fundamental" else conventional.step("lod1", u0, g, 0)
     for i0, j0 in [(0, 1), (nx // 2, ny // 2), (nx - 1, ny - 1), (1, ny - 2)]:
         ex, hy = lod1_zline(eps, u0[CIDX["Ex"]][:, :, i0], u0[CIDX["Hz"]][:, :, i0],
-                            u0[CIDX["Ez"]][:, j0, :], u0[CIDX["Hy"]][:, j0, :], i0, j0, h, dt)
+                            u0[CIDX["Ez"]][:, j0, :], u0[CIDX["Hy"]][:, j0, :], i0, j0, h, dt, form)
         want_ex = ref[CIDX["Ex"]][:, j0, i0]
         want_hy = ref[CIDX["Hy"]][:, j0, i0]
         assert np.max(np.abs(want_ex)) > 0.1 and np.max(np.abs(want_hy)) > 1e-4
