@@ -74,3 +74,38 @@ def lod1_zline(eps_r, ex_x, hz_x, ez_y, hy_y, i0, j0, h, dt, form="fundamental")
     u[CIDX["Hy"]][:, 1, 0] = hy_a
     out = sub(u, "B", fb * dt, g3)
     return out[CIDX["Ex"]][:, 1, 0], out[CIDX["Hy"]][:, 1, 0]
+
+
+def lod1_xline(eps_r, ey_y, hx_y, ex_z, hz_z, j0, k0, h, dt, form="fundamental"):
+    """Ey and Hz on the x line (y index j0, z index k0) after one LOD1 step.
+
+    Ey after A on that line comes from the pair (Ey, Hx) along z on the
+    plane y = j0 (a grid one cell wide in y), Hz after A from the pair
+    (Ex, Hz) along y on the plane z = k0 (cells k0 - 1 and k0, so that z
+    index k0 is interior); then the B pass of the pair (Ey, Hz) along x.
+    ey_y, hx_y: Ey and Hx at y index j0, arrays (nz+1, nx+1); ex_z, hz_z:
+    Ex and Hz at z index k0, arrays (ny+1, nx+1).  Needs 0 <= j0 < ny and
+    1 <= k0 <= nz - 1.  Returns (Ey, Hz), each of length nx + 1 (FP64)."""
+    nz, ny, nx = eps_r.shape
+    assert 0 <= j0 < ny and 1 <= k0 <= nz - 1
+    (_, fa, _), (_, fb, _) = LOD_MAIN["lod1"]
+    sub = _substep(form)
+    # A: pair (Ey, Hx) along z on the plane y = j0
+    g1 = oracle.Grid(nx, 1, nz, h, h, h, dt, eps_r[:, j0:j0 + 1, :])
+    u = _zeros(nx, 1, nz)
+    u[CIDX["Ey"]][:, 0, :] = ey_y
+    u[CIDX["Hx"]][:, 0, :] = hx_y
+    ey_a = sub(u, "A", fa * dt, g1)[CIDX["Ey"]][k0, 0, :]
+    # A: pair (Ex, Hz) along y on the plane z = k0
+    g2 = oracle.Grid(nx, ny, 2, h, h, h, dt, eps_r[k0 - 1:k0 + 1, :, :])
+    u = _zeros(nx, ny, 2)
+    u[CIDX["Ex"]][1, :, :] = ex_z
+    u[CIDX["Hz"]][1, :, :] = hz_z
+    hz_a = sub(u, "A", fa * dt, g2)[CIDX["Hz"]][1, j0, :]
+    # B: pair (Ey, Hz) along x on the line (j0, k0)
+    g3 = oracle.Grid(nx, 1, 2, h, h, h, dt, eps_r[k0 - 1:k0 + 1, j0:j0 + 1, :])
+    u = _zeros(nx, 1, 2)
+    u[CIDX["Ey"]][1, 0, :] = ey_a
+    u[CIDX["Hz"]][1, 0, :] = hz_a
+    out = sub(u, "B", fb * dt, g3)
+    return out[CIDX["Ey"]][1, 0, :], out[CIDX["Hz"]][1, 0, :]

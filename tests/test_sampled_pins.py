@@ -9,7 +9,7 @@ import workloads as W
 from oracle import conventional
 from oracle.fundamental import lod_step
 from oracle.yee import CIDX
-from ._sampled import lod1_zline
+from ._sampled import lod1_xline, lod1_zline
 
 
 @pytest.mark.parametrize("form", ["fundamental", "conventional"])
@@ -29,6 +29,25 @@ def test_sampled_lod1_equals_whole_grid(nx, ny, nz, seed, form):
         assert np.max(np.abs(want_ex)) > 0.1 and np.max(np.abs(want_hy)) > 1e-4
         assert np.max(np.abs(ex - want_ex)) <= 1e-13 * np.max(np.abs(want_ex))
         assert np.max(np.abs(hy - want_hy)) <= 1e-13 * np.max(np.abs(want_hy))
+
+
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+@pytest.mark.parametrize("nx,ny,nz,seed", [(9, 11, 13, 1), (16, 7, 10, 2)])
+def test_sampled_lod1_xline_equals_whole_grid(nx, ny, nz, seed, form):
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=seed, nboxes=6).astype(np.float64)
+    u0 = W.random_fields(nx, ny, nz, seed=seed + 10)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    ref = lod_step("lod1", u0, g, 0) if form == "fundamental" else conventional.step("lod1", u0, g, 0)
+    for j0, k0 in [(0, 1), (ny // 2, nz // 2), (ny - 1, nz - 1), (1, nz - 2)]:
+        ey, hz = lod1_xline(eps, u0[CIDX["Ey"]][:, j0, :], u0[CIDX["Hx"]][:, j0, :],
+                            u0[CIDX["Ex"]][k0, :, :], u0[CIDX["Hz"]][k0, :, :], j0, k0, h, dt, form)
+        want_ey = ref[CIDX["Ey"]][k0, j0, :]
+        want_hz = ref[CIDX["Hz"]][k0, j0, :]
+        assert np.max(np.abs(want_ey)) > 0.1 and np.max(np.abs(want_hz)) > 1e-4
+        assert np.max(np.abs(ey - want_ey)) <= 1e-13 * np.max(np.abs(want_ey))
+        assert np.max(np.abs(hz - want_hz)) <= 1e-13 * np.max(np.abs(want_hz))
 
 
 def test_sampled_lod1_sees_a_planted_error():
