@@ -109,3 +109,38 @@ def lod1_xline(eps_r, ey_y, hx_y, ex_z, hz_z, j0, k0, h, dt, form="fundamental")
     u[CIDX["Hz"]][1, 0, :] = hz_a
     out = sub(u, "B", fb * dt, g3)
     return out[CIDX["Ey"]][1, 0, :], out[CIDX["Hz"]][1, 0, :]
+
+
+def lod1_yline(eps_r, ez_z, hy_z, ey_x, hx_x, k0, i0, h, dt, form="fundamental"):
+    """Ez and Hx on the y line (z index k0, x index i0) after one LOD1 step.
+
+    Ez after A on that line comes from the pair (Ez, Hy) along x on the
+    plane z = k0 (a grid one cell wide in z), Hx after A from the pair
+    (Ey, Hx) along z on the plane x = i0 (cells i0 - 1 and i0, so that x
+    index i0 is interior); then the B pass of the pair (Ez, Hx) along y.
+    ez_z, hy_z: Ez and Hy at z index k0, arrays (ny+1, nx+1); ey_x, hx_x:
+    Ey and Hx at x index i0, arrays (nz+1, ny+1).  Needs 0 <= k0 < nz and
+    1 <= i0 <= nx - 1.  Returns (Ez, Hx), each of length ny + 1 (FP64)."""
+    nz, ny, nx = eps_r.shape
+    assert 0 <= k0 < nz and 1 <= i0 <= nx - 1
+    (_, fa, _), (_, fb, _) = LOD_MAIN["lod1"]
+    sub = _substep(form)
+    # A: pair (Ez, Hy) along x on the plane z = k0
+    g1 = oracle.Grid(nx, ny, 1, h, h, h, dt, eps_r[k0:k0 + 1, :, :])
+    u = _zeros(nx, ny, 1)
+    u[CIDX["Ez"]][0, :, :] = ez_z
+    u[CIDX["Hy"]][0, :, :] = hy_z
+    ez_a = sub(u, "A", fa * dt, g1)[CIDX["Ez"]][0, :, i0]
+    # A: pair (Ey, Hx) along z on the plane x = i0
+    g2 = oracle.Grid(2, ny, nz, h, h, h, dt, eps_r[:, :, i0 - 1:i0 + 1])
+    u = _zeros(2, ny, nz)
+    u[CIDX["Ey"]][:, :, 1] = ey_x
+    u[CIDX["Hx"]][:, :, 1] = hx_x
+    hx_a = sub(u, "A", fa * dt, g2)[CIDX["Hx"]][k0, :, 1]
+    # B: pair (Ez, Hx) along y on the line (k0, i0)
+    g3 = oracle.Grid(2, ny, 1, h, h, h, dt, eps_r[k0:k0 + 1, :, i0 - 1:i0 + 1])
+    u = _zeros(2, ny, 1)
+    u[CIDX["Ez"]][0, :, 1] = ez_a
+    u[CIDX["Hx"]][0, :, 1] = hx_a
+    out = sub(u, "B", fb * dt, g3)
+    return out[CIDX["Ez"]][0, :, 1], out[CIDX["Hx"]][0, :, 1]

@@ -14,7 +14,7 @@ import workloads as W
 from oracle.source import Source as OSource
 
 from . import _analytic as an
-from ._sampled import lod1_xline, lod1_zline
+from ._sampled import lod1_xline, lod1_yline, lod1_zline
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -290,10 +290,10 @@ def full_size_case():
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_lod1_sampled_lines_full_size(full_size_case, prec, form):
     """One LOD1 step, fundamental and conventional form, at 512^3 (FP32 in the
-    benchmark's kernel configuration, and FP64): Ex and Hy on sampled z lines
-    and Ey and Hz on sampled x lines, next to the walls and inside, element
-    by element against the oracle's sub-steps on the thin slabs those lines
-    depend on (``_sampled.lod1_zline`` and ``lod1_xline``, pinned against
+    benchmark's kernel configuration, and FP64): Ex and Hy on sampled z lines,
+    Ey and Hz on x lines, Ez and Hx on y lines, next to the walls and inside,
+    element by element against the oracle's sub-steps on the thin slabs those
+    lines depend on (``_sampled.lod1_zline``, ``_xline``, ``_yline``, pinned against
     whole-grid oracle steps).  Bars as for a few steps: 2e-5 (FP32), 1e-11
     (FP64), energy-weighted relative L2 over the sampled lines."""
     Plan, _ = _lib()
@@ -326,6 +326,13 @@ def test_lod1_sampled_lines_full_size(full_size_case, prec, form):
         got_hz = H[2][k0, j0, :].double().cpu().numpy()
         num += 8.8541878128e-12 * np.sum((got_ey - ref_ey) ** 2) + 1.25663706212e-6 * np.sum((got_hz - ref_hz) ** 2)
         den += 8.8541878128e-12 * np.sum(ref_ey ** 2) + 1.25663706212e-6 * np.sum(ref_hz ** 2)
+    for k0, i0 in [(0, 1), (257, 300), (n - 1, n - 1), (100, 2)]:
+        ref_ez, ref_hx = lod1_yline(eps64, u0[2][k0, :, :], u0[4][k0, :, :], u0[1][:, :, i0], u0[3][:, :, i0],
+                                    k0, i0, h, dt, form)
+        got_ez = E[2][k0, :, i0].double().cpu().numpy()
+        got_hx = H[0][k0, :, i0].double().cpu().numpy()
+        num += 8.8541878128e-12 * np.sum((got_ez - ref_ez) ** 2) + 1.25663706212e-6 * np.sum((got_hx - ref_hx) ** 2)
+        den += 8.8541878128e-12 * np.sum(ref_ez ** 2) + 1.25663706212e-6 * np.sum(ref_hx ** 2)
     del E, H
     err = math.sqrt(num / den)
     print(f"[case] LOD1 {form} sampled lines 512^3 {prec}: rel-L2 {err:.3e}", flush=True)

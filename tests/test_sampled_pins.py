@@ -9,7 +9,7 @@ import workloads as W
 from oracle import conventional
 from oracle.fundamental import lod_step
 from oracle.yee import CIDX
-from ._sampled import lod1_xline, lod1_zline
+from ._sampled import lod1_xline, lod1_yline, lod1_zline
 
 
 @pytest.mark.parametrize("form", ["fundamental", "conventional"])
@@ -48,6 +48,25 @@ def test_sampled_lod1_xline_equals_whole_grid(nx, ny, nz, seed, form):
         assert np.max(np.abs(want_ey)) > 0.1 and np.max(np.abs(want_hz)) > 1e-4
         assert np.max(np.abs(ey - want_ey)) <= 1e-13 * np.max(np.abs(want_ey))
         assert np.max(np.abs(hz - want_hz)) <= 1e-13 * np.max(np.abs(want_hz))
+
+
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+@pytest.mark.parametrize("nx,ny,nz,seed", [(9, 11, 13, 1), (16, 7, 10, 2)])
+def test_sampled_lod1_yline_equals_whole_grid(nx, ny, nz, seed, form):
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=seed, nboxes=6).astype(np.float64)
+    u0 = W.random_fields(nx, ny, nz, seed=seed + 10)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps)
+    ref = lod_step("lod1", u0, g, 0) if form == "fundamental" else conventional.step("lod1", u0, g, 0)
+    for k0, i0 in [(0, 1), (nz // 2, nx // 2), (nz - 1, nx - 1), (1, nx - 2)]:
+        ez, hx = lod1_yline(eps, u0[CIDX["Ez"]][k0, :, :], u0[CIDX["Hy"]][k0, :, :],
+                            u0[CIDX["Ey"]][:, :, i0], u0[CIDX["Hx"]][:, :, i0], k0, i0, h, dt, form)
+        want_ez = ref[CIDX["Ez"]][k0, :, i0]
+        want_hx = ref[CIDX["Hx"]][k0, :, i0]
+        assert np.max(np.abs(want_ez)) > 0.1 and np.max(np.abs(want_hx)) > 1e-4
+        assert np.max(np.abs(ez - want_ez)) <= 1e-13 * np.max(np.abs(want_ez))
+        assert np.max(np.abs(hx - want_hx)) <= 1e-13 * np.max(np.abs(want_hx))
 
 
 def test_sampled_lod1_sees_a_planted_error():
