@@ -99,6 +99,12 @@ def pass_nodes(n):
 TIMING_EVERY = 8
 
 
+# precision keys: f32 = FP32 fields and solves as the library chooses (refined
+# below sigma = 2, i.e. at CFL 5 and 10), f32r = refined, f32p = plain FP32
+# solves, f32s64 = FP32 fields with FP64 solves, f64
+REFINE = {"f32r": True, "f32p": False}
+
+
 def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5):
     import torch
     from paper_2011_14043_amd import Plan, Source
@@ -111,7 +117,8 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     H = [torch.zeros(shape, dtype=dtype, device=dev) for _ in range(3)]
     src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
-                eps_r=torch.from_numpy(eps), refine=prec == "f32r")
+                eps_r=torch.from_numpy(eps), refine=REFINE.get(prec))
+    refined = plan.refined
     if tune:
         plan.autotune(tune_reps)
     cfg = [plan.kernel_config(ax) for ax in range(3)]
@@ -139,7 +146,7 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     if scheme == "adi" and form == "conventional":           # + the two cross-coupled arrays
         alg_bytes_step = npass * pass_nodes(n) * (bpn + 2 * (8 if prec == "f64" else 4))
     hbm_frac = alg_bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-    out = dict(scheme=scheme, form=form, prec=prec, ms_per_step=ms, mcells_per_s=mcells,
+    out = dict(scheme=scheme, form=form, prec=prec, refined=refined, ms_per_step=ms, mcells_per_s=mcells,
                alg_bytes_per_step=alg_bytes_step, hbm_frac_alg=hbm_frac, main_ms=tm["main_ms"],
                yz_ms_avg=tm["yz_ms_avg"], x_ms_avg=tm["x_ms_avg"], yz_launches=tm["yz_launches"],
                x_launches=tm["x_launches"], finite=finite, kernel_config=cfg)
@@ -416,7 +423,7 @@ def main():
         # the smaller size of the same workload (256^3), plain and refined FP32
         in256 = make_inputs(256)
         extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256)
-                                             for prec in ("f32", "f32r")]
+                                             for prec in ("f32", "f32p")]
         # the other CFL numbers of the 512^3 workload: the passes have no
         # data-dependent control flow, so the step time should not move
         import workloads as W
@@ -429,7 +436,7 @@ def main():
             cfl_rows.append(r)
         extras["adi_fundamental_512cube_cfl_1_and_10"] = cfl_rows
     if args.variants != "none":
-        todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32r"), ("adi", "fundamental", "f32s64"),
+        todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32p"), ("adi", "fundamental", "f32s64"),
                 ("adi", "conventional", "f32s64"),
                 ("adi", "fundamental", "f64"), ("adi", "conventional", "f64"),
                 ("lod1", "fundamental", "f32"), ("ss2", "fundamental", "f32"), ("lod2", "fundamental", "f32"),

@@ -88,16 +88,28 @@ typedef enum {
     FDTD_DYAKONOV = 4, FDTD_DOUGLAS_GUNN = 5, FDTD_CRANK_NICOLSON = 6
 } fdtd_scheme;
 typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
-/* Precision: FDTD_F32 keeps fields in FP32 and solves in FP32; FDTD_F64 uses
- * FP64 for both; FDTD_F32_F64SOLVE keeps fields in FP32 (FP32 HBM traffic)
- * but forms every right-hand side, tridiagonal solve and update in FP64
- * registers, rounding once per stored value.  FDTD_F32_REFINE is FDTD_F32
- * with one step of iterative refinement of every tridiagonal solve (the
- * residual r - T V formed with the unrounded sigma, and a second solve with
- * the same factors, all in FP32), which removes the fixed rounding bias of
- * the FP32 factors and of 2 + sigma; fundamental forms only (else
- * FDTD_EUNSUPPORTED), nx, ny, nz <= 512. */
-typedef enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_F32_F64SOLVE = 2, FDTD_F32_REFINE = 3 } fdtd_dtype;
+/* Precision.  FDTD_F64 uses FP64 for fields and solves.  FDTD_F32_F64SOLVE
+ * keeps fields in FP32 (FP32 HBM traffic) but forms every right-hand side,
+ * tridiagonal solve and update in FP64 registers, rounding once per stored
+ * value.  FDTD_F32_PLAIN keeps fields in FP32 and solves in FP32.
+ * FDTD_F32_REFINE is FDTD_F32_PLAIN with one step of iterative refinement of
+ * every tridiagonal solve (the residual r - T V formed with the unrounded
+ * sigma, and a second solve with the same factors, all in FP32), which
+ * removes the fixed rounding bias of the FP32 factors and of 2 + sigma;
+ * fundamental forms only (else FDTD_EUNSUPPORTED), nx, ny, nz <= 512.
+ * FDTD_F32 (FP32 fields and arithmetic) chooses between the two: the line
+ * systems are -V[j-1] + (2 + sigma) V[j] - V[j+1] = r with
+ * sigma = eps mu dw^2 / theta^2 (Sec. III-A multiplied by 2 sigma), and FP32
+ * spaces numbers near 2 by 2.4e-7, so a sigma well below 1 (large time
+ * steps) is perturbed by the same relative amount at every step and the
+ * phase error grows linearly with the step count (3e-4 after 1000 steps at
+ * sigma = 0.12).  FDTD_F32 therefore refines when the plan's smallest sigma
+ * (smallest eps_r and cell size, theta = dt/2) is below 2 -- a CFL number
+ * above about 2.4 in vacuum on cubic cells -- wherever refinement is built
+ * (fundamental forms, nx, ny, nz <= 512); else it runs as FDTD_F32_PLAIN.
+ * fdtd_get_refined tells which. */
+typedef enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_F32_F64SOLVE = 2, FDTD_F32_REFINE = 3,
+               FDTD_F32_PLAIN = 4 } fdtd_dtype;
 
 typedef struct {
     int nx, ny, nz;            /* cells per axis, each >= 2                               */
@@ -106,7 +118,8 @@ typedef struct {
     double dx, dy, dz;         /* cell sizes [m], > 0                                     */
     int scheme;                /* fdtd_scheme                                             */
     int form;                  /* fdtd_form                                               */
-    int dtype;                 /* fdtd_dtype; nx, ny, nz <= 1024 (FDTD_F32), <= 512 else  */
+    int dtype;                 /* fdtd_dtype; nx, ny, nz <= 1024 (FDTD_F32,               */
+                               /* FDTD_F32_PLAIN), <= 512 else                            */
     const float* eps_r;        /* relative permittivity per cell, (nz, ny, nx) row-major, */
                                /* x fastest, > 0; host or device pointer, copied by       */
                                /* fdtd_plan (may be freed afterwards).  NULL means 1.     */
@@ -133,6 +146,10 @@ typedef struct { int i, j, k; double f0, tau, t0, amp; } fdtd_source;
  * `hip_stream` (hipStream_t or NULL for the default stream) is used by every
  * later call.  The step counter starts at 0. */
 fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out);
+
+/* *refined (host) = 1 if the plan's FP32 line solves are refined
+ * (FDTD_F32_REFINE, or FDTD_F32 below the sigma threshold above), else 0. */
+fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined);
 
 /* Advance the caller's fields by `nsteps` >= 0 full time steps:
  *   input processing (ADI: u^0 -> (1/2 I + dt/4 B) u^0, the link of

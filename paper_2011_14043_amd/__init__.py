@@ -42,6 +42,27 @@ class Source:
         return _lib.FdtdSource(self.i, self.j, self.k, self.f0, self.tau, self.t0, self.amp)
 
 
+def _dtype_code(dtype, solve, refine):
+    """fdtd_dtype of (field type, solve type, refine): for float32 fields and
+    solves, refine None lets the library choose (FDTD_F32), True forces
+    refined solves (FDTD_F32_REFINE), False plain ones (FDTD_F32_PLAIN); other
+    precisions take refine None or False."""
+    import torch
+    if dtype not in (torch.float32, torch.float64):
+        raise ValueError("dtype must be float32 or float64")
+    if dtype == torch.float64 and solve != torch.float64:
+        raise ValueError("float64 fields need float64 solves")
+    if refine and (dtype != torch.float32 or solve != torch.float32):
+        raise ValueError("refine applies to float32 fields with float32 solves")
+    if dtype == torch.float64:
+        return _lib.DTYPES["f64"]
+    if solve == torch.float64:
+        return _lib.DTYPES["f32_f64solve"]
+    if refine is None:
+        return _lib.DTYPES["f32"]
+    return _lib.DTYPES["f32_refine"] if refine else _lib.DTYPES["f32_plain"]
+
+
 def _ptrs(ts, dtype, shape, device):
     import torch
     if len(ts) != 3:
@@ -59,23 +80,18 @@ class Plan:
     """One simulation plan (fdtd_plan).  Not thread-safe."""
 
     def __init__(self, nx, ny, nz, dt, dx, dy, dz, scheme="adi", form="fundamental",
-                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None, refine=False):
+                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None, refine=None):
         """dtype: field storage (float32/float64); solve_dtype: arithmetic of the
         line solves (defaults to dtype; float64 with float32 fields selects
-        FDTD_F32_F64SOLVE); refine: FP32 solves refined once (FDTD_F32_REFINE,
-        float32 fields and solves, fundamental forms)."""
+        FDTD_F32_F64SOLVE); refine (float32 fields and solves): None lets the
+        library refine the FP32 solves where the time step needs it (FDTD_F32),
+        True always refines them once (FDTD_F32_REFINE, fundamental forms),
+        False never (FDTD_F32_PLAIN).  `refined` tells what the plan does."""
         import torch
         L = _lib.lib()
         self.dtype = dtype if dtype is not None else torch.float32
-        if self.dtype not in (torch.float32, torch.float64):
-            raise ValueError("dtype must be float32 or float64")
         solve = solve_dtype if solve_dtype is not None else self.dtype
-        if self.dtype == torch.float64 and solve != torch.float64:
-            raise ValueError("float64 fields need float64 solves")
-        if refine and (self.dtype != torch.float32 or solve != torch.float32):
-            raise ValueError("refine applies to float32 fields with float32 solves")
-        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else (3 if refine else 0))
-        self.refine = bool(refine)
+        code = _dtype_code(self.dtype, solve, refine)
         self.shape = (nz + 1, ny + 1, nx + 1)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         eps_ptr = None
@@ -100,6 +116,12 @@ class Plan:
         self._h = h
         self._eps_keep = None
         self.scheme, self.form = scheme, form
+        self.refined = self._refined()
+
+    def _refined(self) -> bool:
+        r = ctypes.c_int()
+        _lib.check(_lib.lib().fdtd_get_refined(self._h, ctypes.byref(r)), "fdtd_get_refined")
+        return bool(r.value)
 
     def run(self, E, H, nsteps, source: Source | None = None, energy_every: int = 0):
         """Advance E, H in place by nsteps; returns the energy trace (list) if
@@ -235,18 +257,12 @@ class BatchPlan(Plan):
     (nx, ny, nz, eps_r or None)."""
 
     def __init__(self, grids, dt, dx, dy, dz, scheme="adi", dtype=None, stream=None, device=None,
-                 solve_dtype=None, refine=False):
+                 solve_dtype=None, refine=None):
         import torch
         L = _lib.lib()
         self.dtype = dtype if dtype is not None else torch.float32
-        if self.dtype not in (torch.float32, torch.float64):
-            raise ValueError("dtype must be float32 or float64")
         solve = solve_dtype if solve_dtype is not None else self.dtype
-        if self.dtype == torch.float64 and solve != torch.float64:
-            raise ValueError("float64 fields need float64 solves")
-        if refine and (self.dtype != torch.float32 or solve != torch.float32):
-            raise ValueError("refine applies to float32 fields with float32 solves")
-        code = 1 if self.dtype == torch.float64 else (2 if solve == torch.float64 else (3 if refine else 0))
+        code = _dtype_code(self.dtype, solve, refine)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.shapes = []
         keep = []
@@ -271,6 +287,7 @@ class BatchPlan(Plan):
                        "fdtd_plan_batch")
         self._h = h
         self.scheme, self.form = scheme, "fundamental"
+        self.refined = self._refined()
 
     def run(self, fields, nsteps):
         """fields: list of (E, H) per grid, updated in place (asynchronous)."""

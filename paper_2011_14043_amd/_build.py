@@ -1,15 +1,23 @@
-"""Build step: compile the HIP sources of the library for gfx950 (hipcc)."""
+"""Build step: compile the HIP sources of the library for gfx950 (hipcc).
+
+csrc/fdtd.hip (the C ABI, host code and the small kernels) and the parts of
+csrc/kern_inst.hip (the line-pass kernel instantiations, -DFDTD_PART=n) are
+compiled to objects in parallel and linked into libfdtd.so."""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "fdtd.hip")
+KERN_SRC = os.path.join(HERE, "csrc", "kern_inst.hip")
+KERN_PARTS = 14   # kern_inst.hip: FDTD_PART = 0 .. 13
 LIB = os.path.join(HERE, "libfdtd.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # no packed FP32 arithmetic: some of its forms have given silently wrong results on gfx950
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -30,15 +38,42 @@ def c_check_cmd(out: str) -> list[str]:
             "-Wl,-rpath,$ORIGIN/../../paper_2011_14043_amd", "-Wl,-rpath," + os.path.join(rocm, "lib")]
 
 
-def build(verbose: bool = False) -> str:
+def _jobs() -> int:
+    try:
+        n = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(16, n if n > 0 else (os.cpu_count() or 4)))
+
+
+def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     """Compile libfdtd.so in-tree, then the plain-C check program that links
     it; returns the library's path.  Raises on failure."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    flags = HIPCC_FLAGS + list(extra_flags or [])
+    jobs = [(SRC, os.path.join(OBJ_DIR, "fdtd.o"), [])]
+    for part in range(KERN_PARTS):
+        jobs.append((KERN_SRC, os.path.join(OBJ_DIR, f"kern_{part}.o"), [f"-DFDTD_PART={part}"]))
+
+    def compile_one(job):
+        src, obj, defs = job
+        cmd = [hipcc, *flags, *defs, "-c", "-o", obj, src]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return cmd, res
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        results = list(ex.map(compile_one, jobs))
+    for cmd, res in results:
+        if res.returncode != 0:
+            raise RuntimeError("hipcc failed: " + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+        if verbose:
+            print(" ".join(cmd))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc, *flags, "-shared", "-o", tmp, *[j[1] for j in jobs]]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc link failed:\n" + res.stdout + res.stderr)
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, LIB)

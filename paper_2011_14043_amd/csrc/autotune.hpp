@@ -124,10 +124,11 @@ static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
 }
 
 // Text cache of tuned configurations: one line per key
-//   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>", "cfg": [[M,TX,NT,wpb,remap],[...],[...]]}
+//   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>,<refine>", "cfg": [[M,TX,NT,wpb,remap],[...],[...]]}
 static std::string tune_key(const fdtd_plan_s* p) {
     char b[160];
-    std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme, p->d.form);
+    std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d,%d", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme, p->d.form,
+                  p->refine);
     return b;
 }
 

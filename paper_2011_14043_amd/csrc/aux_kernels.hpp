@@ -5,6 +5,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "line_solver.hpp"   // recip
+#include "xcd.hpp"
+
 namespace fdtd {
 
 struct Dims {
@@ -61,6 +64,8 @@ struct AuxCoef {
     double eps0, mu0;
     double rmu0, rdx, rdy, rdz;   // 1/mu0, 1/dx, 1/dy, 1/dz (formed on the host)
     double link;                  // ADI: dt/4 (state = 1/2 u + dt/4 B u); 0 for a plain copy
+    int fin_form;                 // energy of a fundamental ADI state in output form (static H
+                                  // still hold 1/2 u, i.e. their link value)
 };
 
 // (B u)_c at a node, operator B of eq. (AMat) with Yee central differences.
@@ -77,35 +82,115 @@ __device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, dou
     }
 }
 
+// Row kernels: block b covers the node row r = (j, k) = (r mod (ny+1), r div
+// (ny+1)) and its threads loop over i, so j and k, the row offsets and the
+// (j, k) parts of the extent and dynamic tests are uniform per block.  Rows
+// are handed out XCD-aware (r = xcd_remap(b)): neighbouring rows, which share
+// the input kernel's stencil rows and the caller layout's unaligned 128-byte
+// lines, run in one L2.
+constexpr int kRowThreads = 128;
+inline dim3 row_grid(const Dims& d) { return dim3((unsigned)((d.ny + 1) * (d.nz + 1))); }
+
 // Input processing: caller fields -> state.  link != 0: the ADI/LOD1 link
 // U = (1/2 I + dt/4 B) u (Sec. II-E); else U = u.  Non-dynamic E -> 0.
-template <typename T>
-__global__ void load_state_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps, Dims d, AuxCoef k_) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
-    if (idx >= nn) return;
-    const Node nd = node_of(unsigned(idx), d);
-    const int i = nd.i, j = nd.j, k = nd.k;
-    const long long so = (long long)k * d.plane + (long long)j * d.px + i;
-    auto get = [&](int c, int ii, int jj, int kk) { return phys<T>(f, c, ii, jj, kk, d); };
-    const double inv_eps = 1.0 / (k_.eps0 * double(eps[so]));
+// Row kernel (row_grid, kRowThreads threads), arithmetic in A (the solve
+// precision: FP32 plans form the link in FP32, one more rounding than the
+// stored value already has).  Each dynamic E takes the difference of its
+// partner H across its own position, each dynamic H that of its partner E
+// (B of eq. (AMat)); E off its dynamic set is 0, also where it enters a
+// difference.
+template <typename T, typename A = double>
+__global__ void __launch_bounds__(kRowThreads) load_state_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps,
+                                                                 Dims d, AuxCoef k_) {
+    const int r = xcd_remap(int(blockIdx.x), int(gridDim.x));
+    const int j = r % (d.ny + 1), k = r / (d.ny + 1);
+    const long long nx1 = d.nx + 1;
+    const long long srow = (long long)k * d.plane + (long long)j * d.px;
+    const long long crow = (long long)k * d.cplane + (long long)j * nx1;
+    const A L = A(k_.link), half = A(0.5);
+    const A rdx = A(k_.rdx), rdy = A(k_.rdy), rdz = A(k_.rdz), cmu = L * A(k_.rmu0);
+    // (j, k) parts of the dynamic sets (uniform per block)
+    const bool jin = j >= 1 && j < d.ny, kin = k >= 1 && k < d.nz, jlo = j < d.ny, klo = k < d.nz;
+    const bool jin1 = j + 1 < d.ny, kin1 = k + 1 < d.nz;   // E at j+1 (Ez) / k+1 (Ex) dynamic
+    const T* Ex = f.c[0] + crow; const T* Ey = f.c[1] + crow; const T* Ez = f.c[2] + crow;
+    const T* Hx = f.c[3] + crow; const T* Hy = f.c[4] + crow; const T* Hz = f.c[5] + crow;
+    for (int i = int(threadIdx.x); i <= d.nx; i += kRowThreads) {
+        const long long so = srow + i;
+        const bool ilo = i < d.nx, iin = i >= 1 && i < d.nx, iin1 = i + 1 < d.nx;
+        A u[6];
+        u[0] = (ilo && jin && kin) ? A(Ex[i]) : A(0);
+        u[1] = (iin && jlo && kin) ? A(Ey[i]) : A(0);
+        u[2] = (iin && jin && klo) ? A(Ez[i]) : A(0);
+        u[3] = (jlo && klo) ? A(Hx[i]) : A(0);
+        u[4] = (ilo && klo) ? A(Hy[i]) : A(0);
+        u[5] = (ilo && jlo) ? A(Hz[i]) : A(0);
+        if (k_.link == 0.0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const double u = double(get(c, i, j, k));
-        double v = u;
-        if (k_.link != 0.0) {
-            const bool dyn = is_dynamic(c, i, j, k, d);
-            const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, k_) : 0.0;
-            v = 0.5 * u + k_.link * bu;
+            for (int c = 0; c < 6; ++c) s.c[c][so] = T(u[c]);
+            continue;
         }
-        s.c[c][so] = T(v);
+        const A ce = L * recip(A(k_.eps0) * A(eps[so]));   // dt/4 / eps
+        A v[6];
+        // E: U = 1/2 E - (dt/4)/eps d_w H   (dynamic samples; else 0)
+        v[0] = u[0];
+        if (ilo && jin && kin) v[0] = fused(-ce, (A(Hy[i]) - A(Hy[i - d.cplane])) * rdz, half * u[0]);
+        v[1] = u[1];
+        if (iin && jlo && kin) v[1] = fused(-ce, (A(Hz[i]) - A(Hz[i - 1])) * rdx, half * u[1]);
+        v[2] = u[2];
+        if (iin && jin && klo) v[2] = fused(-ce, (A(Hx[i]) - A(Hx[i - nx1])) * rdy, half * u[2]);
+        // H: U = 1/2 H - (dt/4)/mu d_w E   (dynamic samples; static normal H: 1/2 H)
+        v[3] = half * u[3];
+        if (iin && jlo && klo) {
+            const A ez1 = (iin && jin1) ? A(Ez[i + nx1]) : A(0);
+            v[3] = fused(-cmu, (ez1 - u[2]) * rdy, v[3]);
+        }
+        v[4] = half * u[4];
+        if (ilo && jin && klo) {
+            const A ex1 = (ilo && jin && kin1) ? A(Ex[i + d.cplane]) : A(0);
+            v[4] = fused(-cmu, (ex1 - u[0]) * rdz, v[4]);
+        }
+        v[5] = half * u[5];
+        if (ilo && jlo && kin) {
+            const A ey1 = (iin1 && jlo && kin) ? A(Ey[i + 1]) : A(0);
+            v[5] = fused(-cmu, (ey1 - u[1]) * rdx, v[5]);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s.c[c][so] = T(v[c]);
     }
 }
 
-// Output processing: state (and, for ADI, the state before the last B
-// sub-step) -> caller fields.  ADI: u = U_old + U_new (+ src_add at the Ez
-// sample of the source, where the sub-step subtracted g/2), the v of the last
-// B sub-step; else u = U.  Entries outside the box are not written.
+// Output processing: state -> caller fields, one thread per node of a row
+// (grid as load_state_kernel).  E off its dynamic set is 0; H normal to a wall
+// (static) is doubled when static_twice (a fundamental ADI state keeps it as
+// 1/2 u, the link value); entries outside the box are not written.  The state
+// of a fundamental ADI run is in output form here (u = U_old + U_new, stored
+// by the passes of the last B sub-step); the other schemes' state is u.
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) store_out_kernel(FieldPtrs<T> s, FieldPtrsW<T> f, Dims d,
+                                                                int static_twice) {
+    const int r = xcd_remap(int(blockIdx.x), int(gridDim.x));
+    const int j = r % (d.ny + 1), k = r / (d.ny + 1);
+    const long long srow = (long long)k * d.plane + (long long)j * d.px;
+    const long long crow = (long long)k * d.cplane + (long long)j * (d.nx + 1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const T* src = s.c[c] + srow;
+        T* dst = f.c[c] + crow;
+        for (int i = int(threadIdx.x); i <= d.nx; i += kRowThreads) {
+            if (!in_extent(c, i, j, k, d)) continue;
+            const bool dyn = is_dynamic(c, i, j, k, d);
+            T v = src[i];
+            if (c < 3) v = dyn ? v : T(0);
+            else if (static_twice && !dyn) v = v + v;
+            dst[i] = v;
+        }
+    }
+}
+
+// Output processing of the batched ADI: state (and the state before the last
+// B sub-step) -> caller fields: u = U_old + U_new, the v of the last B
+// sub-step (Sec. II-E link); else u = U.  Entries outside the box are not
+// written.
 template <typename T>
 __global__ void store_state_kernel(FieldPtrs<T> s, FieldPtrs<T> s_old, FieldPtrsW<T> f, Dims d, int add_old,
                                    long long src_off, double src_add) {
@@ -154,13 +239,13 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
                 if (ii < 0 || jj < 0 || kk < 0 || ii > d.nx || jj > d.ny || kk > d.nz) return T(0);
                 return s.c[c][(long long)kk * d.plane + (long long)jj * d.px + ii];
             };
-            const double inv_eps = 1.0 / ew;
+            const double inv_eps = recip(ew);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const double u = double(get(c, i, j, k));
                 const bool dyn = is_dynamic(c, i, j, k, d);
                 const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, k_) : 0.0;
-                const double v = 0.5 * u + k_.link * bu;
+                const double v = (k_.fin_form && c >= 3 && !dyn) ? u : 0.5 * u + k_.link * bu;
                 acc += (c < 3 ? ew : k_.mu0) * v * v;
             }
         }

@@ -204,83 +204,19 @@ static fdtd_status batch_pass(fdtd_plan_s* p, int op, int mask, double frac, con
     return FDTD_OK;
 }
 
-template <typename T, typename S, int MODE>
-static fdtd_status batch_launch_mode(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
-    const int w = bp.w;
-    const KCfg& cf = p->cfg[w];
-    const bool mat = p->batch->mat;
-    const auto* tab = static_cast<const PassArgs<T, S>*>(bp.tab);
-    const auto* items = static_cast<const int2*>(bp.items);
-    const dim3 grid((unsigned)bp.nitems);
-    if (bp.ex0 >= 0) {
-        // fused sub-step: x lines with 8-slot chunks inside the y/z launch
-        const int M = cf.M, TX = cf.TX, NT = cf.NT, ex0 = bp.ex0;
-        const dim3 block(bp.threads);
-        const size_t lds = bp.lds;
-        if (p->cfg[0].M != 8) return FDTD_EINVAL;
-#define CASE_SUB(MM, TT, NN)                                                                                  \
-    if (M == MM && TX == TT && NN == NT) {                                                                    \
-        if constexpr (MODE != FUND_REF || MM == 8) {                                                          \
-            if (mat)                                                                                          \
-                hipLaunchKernelGGL((pass_sub_batch_kernel<T, S, 8, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, \
-                                   items, ex0);                                                               \
-            else                                                                                              \
-                hipLaunchKernelGGL((pass_sub_batch_kernel<T, S, 8, MM, MODE, TT, NN, false>), grid, block, lds, st, tab, \
-                                   items, ex0);                                                               \
-        } else {                                                                                              \
-            return FDTD_EUNSUPPORTED;                                                                         \
-        }                                                                                                     \
-    } else
-        if constexpr (sizeof(S) == 4) {
-            CASE_SUB(8, 16, 1024) CASE_SUB(8, 32, 512) CASE_SUB(16, 32, 1024) CASE_SUB(16, 16, 512)
-            return FDTD_EUNSUPPORTED;
-        } else {
-            CASE_SUB(8, 8, 512) CASE_SUB(8, 16, 1024) CASE_SUB(16, 16, 512) return FDTD_EUNSUPPORTED;
-        }
-#undef CASE_SUB
-    } else if (w == 0) {
-        const dim3 block(bp.threads);
-        if (cf.M == 8) {
-            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, true>), grid, block, 0, st, tab, items);
-            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 8, MODE, false>), grid, block, 0, st, tab, items);
-        } else if constexpr (MODE != FUND_REF) {
-            if (mat) hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, true>), grid, block, 0, st, tab, items);
-            else hipLaunchKernelGGL((pass_x_batch_kernel<T, S, 16, MODE, false>), grid, block, 0, st, tab, items);
-        } else {
-            return FDTD_EUNSUPPORTED;
-        }
-    } else {
-        const int M = cf.M, TX = cf.TX, NT = cf.NT;
-        const dim3 block(bp.threads);
-        const size_t lds = bp.lds;
-#define CASE_YZB(MM, TT, NN)                                                                                  \
-    if (M == MM && TX == TT && NT == NN) {                                                                    \
-        if constexpr (MODE != FUND_REF || MM == 8) {                                                          \
-            if (mat)                                                                                          \
-                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, items); \
-            else                                                                                              \
-                hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, false>), grid, block, lds, st, tab, items); \
-        } else {                                                                                              \
-            return FDTD_EUNSUPPORTED;                                                                         \
-        }                                                                                                     \
-    } else
-        if constexpr (sizeof(S) == 4) {
-            CASE_YZB(16, 32, 1024) CASE_YZB(16, 16, 512) CASE_YZB(8, 16, 1024) CASE_YZB(32, 16, 512) CASE_YZB(8, 32, 512)
-            return FDTD_EUNSUPPORTED;
-        } else {
-            CASE_YZB(16, 16, 512) CASE_YZB(8, 8, 512) CASE_YZB(8, 16, 1024) return FDTD_EUNSUPPORTED;
-        }
-#undef CASE_YZB
-    }
-    HIPCHK(hipGetLastError());
-    return FDTD_OK;
-}
 template <typename T, typename S>
 static fdtd_status batch_launch(fdtd_plan_s* p, const BatchPass& bp, hipStream_t st) {
-    if constexpr (sizeof(S) == 4) {
-        if (p->refine) return batch_launch_mode<T, S, FUND_REF>(p, bp, st);
-    }
-    return batch_launch_mode<T, S, FUND>(p, bp, st);
+    const KCfg& cf = p->cfg[bp.w];
+    const int kmode = (sizeof(S) == 4 && p->refine) ? FUND_REF : FUND;
+    const int kind = bp.ex0 >= 0 ? 2 : (bp.w == 0 ? 0 : 1);
+    if (kind == 2 && p->cfg[0].M != 8) return FDTD_EINVAL;
+    const int r = dispatch_batch<T, S>(kmode, kind, cf.M, cf.TX, cf.NT, p->batch->mat, dim3((unsigned)bp.nitems),
+                                       dim3(bp.threads), kind == 0 ? 0 : bp.lds, st,
+                                       static_cast<const PassArgs<T, S>*>(bp.tab), static_cast<const int2*>(bp.items),
+                                       bp.ex0);
+    if (r != DISPATCH_OK) return FDTD_EUNSUPPORTED;
+    HIPCHK(hipGetLastError());
+    return FDTD_OK;
 }
 
 // One sub-step (operator op, theta = frac * dt) of every grid: one, two or three launches.
@@ -393,12 +329,16 @@ static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H
     };
     fdtd_status st = batch_tables<T, S>(p);
     if (st != FDTD_OK) return st;
+    if (adi && nsteps > 0) {   // the state before the last B sub-step (output processing)
+        for (fdtd_plan_s* sub : b->subs)
+            if (!sub->snap) HIPCHK(hipMalloc(&sub->snap, sizeof(T) * sub->dims.comp * 6));
+    }
     for (int g = 0; g < n; ++g) {
         fdtd_plan_s* sub = b->subs[g];
         const Dims& dm = sub->dims;
         const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
         const AuxCoef kin = aux_coef(sub->d, adi ? 0.25 * sub->d.dt : 0.0);
-        hipLaunchKernelGGL((load_state_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream,
+        hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
                            caller(g), state_ptrs_w<T>(sub, 0), sub->eps, dm, kin);
         HIPCHK(hipGetLastError());
     }

@@ -1,6 +1,7 @@
-// fdtd.hip -- the C ABI of libfdtd.so.  One translation unit: the plan state,
-// pass launches, autotuner, run loop, adjoint gradient and batch plans live in
-// the headers included below, in that order.
+// fdtd.hip -- the C ABI of libfdtd.so.  The plan state, pass launches,
+// autotuner, run loop, adjoint gradient and batch plans live in the headers
+// included below, in that order; the line-pass kernels are instantiated in
+// kern_inst.hip (pass_dispatch.hpp).
 //
 // Schemes (Sec. II of the paper) as sequences of sub-steps; each sub-step
 // applies the Cayley factor of A or B with half-span theta through three
@@ -29,9 +30,8 @@
 #include "../../include/fdtd.h"
 #include "adjoint_kernels.hpp"
 #include "aux_kernels.hpp"
-#include "batch_kernels.hpp"
 #include "cn_kernels.hpp"
-#include "pass_kernels.hpp"
+#include "pass_dispatch.hpp"
 #include "plan_state.hpp"
 #include "pass_launch.hpp"
 #include "autotune.hpp"
@@ -66,7 +66,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     if (!(d->dt > 0) || !(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return FDTD_EINVAL;
     if (!std::isfinite(d->dt) || !std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz))
         return FDTD_EINVAL;
-    if (d->scheme < 0 || d->scheme > 6 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 3)
+    if (d->scheme < 0 || d->scheme > 6 || d->form < 0 || d->form > 1 || d->dtype < 0 || d->dtype > 4)
         return FDTD_EINVAL;
     const bool cn = d->scheme == FDTD_CRANK_NICOLSON;
     if (cn && d->dtype != FDTD_F64) return FDTD_EUNSUPPORTED;
@@ -80,27 +80,32 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     }
     if (d->boundary != 0) return FDTD_EUNSUPPORTED;
     if (d->mu_r != nullptr) return FDTD_EUNSUPPORTED;
-    const bool refine = d->dtype == FDTD_F32_REFINE;
-    if (refine && d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
+    if (d->dtype == FDTD_F32_REFINE && d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
     const int nmax = std::max(d->nx, std::max(d->ny, d->nz));
     // register budget (refined solves: 8-slot chunks on at most 64 lanes)
-    if (nmax > (d->dtype == FDTD_F32 ? 1024 : 512)) return FDTD_EUNSUPPORTED;
+    const bool f32_any = d->dtype == FDTD_F32 || d->dtype == FDTD_F32_PLAIN;
+    if (nmax > (f32_any ? 1024 : 512)) return FDTD_EUNSUPPORTED;
     const long long ncells = (long long)d->nx * d->ny * d->nz;
     std::vector<float> eps_host;
+    float eps_min = 1.0f;
     if (d->eps_r) {
         eps_host.resize(ncells);
         if (hipMemcpy(eps_host.data(), d->eps_r, sizeof(float) * ncells, hipMemcpyDefault) != hipSuccess)
             return FDTD_EINVAL;
         for (long long c = 0; c < ncells; ++c)
             if (!(eps_host[c] > 0.0f) || !std::isfinite(eps_host[c])) return FDTD_EINVAL;
+        eps_min = *std::min_element(eps_host.begin(), eps_host.end());
     }
     fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
     if (!p) return FDTD_ENOMEM;
     p->d = *d;
     p->d.eps_r = nullptr;
-    if (refine) {
+    p->req_dtype = d->dtype;
+    if (d->dtype == FDTD_F32_REFINE || (d->dtype == FDTD_F32 && !cn && f32_refine_wanted(*d, eps_min))) {
         p->refine = 1;
         p->d.dtype = FDTD_F32;   // FP32 storage and arithmetic; only the fundamental passes differ
+    } else if (d->dtype == FDTD_F32_PLAIN) {
+        p->d.dtype = FDTD_F32;
     }
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
@@ -131,9 +136,6 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     hipError_t e;
     if ((e = hipMalloc(&p->state, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
     if ((e = hipMemset(p->state, 0, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
-    if (d->scheme == FDTD_ADI && d->form == FDTD_FUNDAMENTAL) {
-        if ((e = hipMalloc(&p->snap, p->esz * dm.comp * 6)) != hipSuccess) return fail(from_hip(e));
-    }
     // eps_r at node indices (owned index, clamped to the last cell), padded rows
     std::vector<float> en((size_t)dm.comp, 1.0f);
     for (int k = 0; k <= d->nz; ++k)
@@ -214,6 +216,12 @@ fdtd_status fdtd_step(fdtd_plan_t p, void* const E[3], void* const H[3], const f
 fdtd_status fdtd_set_step(fdtd_plan_t p, long long n) {
     if (!plan_ok(p) || n < 0) return FDTD_EINVAL;
     p->step = n;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined) {
+    if (!plan_ok(p) || !refined) return FDTD_EINVAL;
+    *refined = p->refine;
     return FDTD_OK;
 }
 
@@ -379,7 +387,7 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
     *out = nullptr;
     for (int g = 0; g < n; ++g) {
         if (d[g].scheme != d[0].scheme || d[g].form != d[0].form || d[g].dtype != d[0].dtype) return FDTD_EINVAL;
-        if (d[g].scheme < 0 || d[g].scheme > 6 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 3)
+        if (d[g].scheme < 0 || d[g].scheme > 6 || d[g].form < 0 || d[g].form > 1 || d[g].dtype < 0 || d[g].dtype > 4)
             return FDTD_EINVAL;
     }
     if (d[0].form != FDTD_FUNDAMENTAL || d[0].scheme == FDTD_CRANK_NICOLSON) return FDTD_EUNSUPPORTED;
@@ -401,6 +409,11 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
         for (fdtd_plan_s* sub : subs) (void)fdtd_destroy(sub);
         return st;
     }
+    // one launch serves every grid: an FDTD_F32 batch refines all its grids'
+    // solves if any grid needs it (refinement never loses accuracy)
+    bool any_refine = false;
+    for (const fdtd_plan_s* sub : subs) any_refine = any_refine || sub->refine;
+    for (fdtd_plan_s* sub : subs) sub->refine = any_refine ? 1 : 0;
     // per-step working set of each grid: six field arrays and the medium
     std::vector<size_t> bytes(n);
     size_t total = 0;
@@ -419,12 +432,9 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
         return FDTD_ENOMEM;
     }
     p->batch = b;
-    p->d = d[0];
-    p->d.eps_r = nullptr;
-    if (d[0].dtype == FDTD_F32_REFINE) {
-        p->refine = 1;
-        p->d.dtype = FDTD_F32;
-    }
+    p->d = subs[0]->d;
+    p->req_dtype = d[0].dtype;
+    p->refine = any_refine ? 1 : 0;
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
     p->esz = d[0].dtype == FDTD_F64 ? 8 : 4;
@@ -595,12 +605,9 @@ static fdtd_status batch_from_subs(const fdtd_desc& d0, const std::vector<fdtd_p
         for (fdtd_plan_s* sub : subs) (void)fdtd_destroy(sub);
         return FDTD_ENOMEM;
     }
-    p->d = d0;
-    p->d.eps_r = nullptr;
-    if (d0.dtype == FDTD_F32_REFINE) {
-        p->refine = 1;
-        p->d.dtype = FDTD_F32;
-    }
+    p->d = subs[0]->d;   // storage/solve kind as normalized by fdtd_plan
+    p->req_dtype = d0.dtype;
+    p->refine = subs[0]->refine;   // equal for all grids (fdtd_plan_batch)
     p->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&p->device);
     p->esz = d0.dtype == FDTD_F64 ? 8 : 4;

@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "line_solver.hpp"
+#include "xcd.hpp"
 
 namespace fdtd {
 
@@ -73,17 +74,20 @@ struct PassArgs {
     int src_a, src_b, src_j;   // source sample in line coordinates (src_a < 0: none)
     S src_pre, src_post;
     const double* src_pre_dev; // if set, the value of src_pre is read from device memory
+    double fsrc;          // FIN passes: added to E at the source sample (the g/2 the pass subtracts)
 };
 
-// Blocks are dispatched round-robin over the 8 XCDs (block L -> XCD L % 8),
-// each with its own L2.  With remap, XCD c receives a contiguous range of
-// work items, so spatially adjacent tiles (which share 128-byte lines and
-// neighbour rows) run on the same XCD at about the same time.
-__device__ __forceinline__ int xcd_remap(int L, int G) {
-    const int c = L & 7, q = L >> 3;
-    const int per = G >> 3, rem = G & 7;
-    return c * per + (c < rem ? c : rem) + q;
+// Output form of one slot in a FIN pass (the last B sub-step of a fundamental
+// ADI run): the field v of that sub-step, u = U_old + U_new (Sec. II-E link),
+// with U_new rounded as the state would store it, U_old as loaded, summed in
+// FP64 and rounded once to the field type; at the source sample the g/2 the
+// pass subtracted is added back.
+template <typename T, typename S>
+__device__ __forceinline__ void fin_value(const PassArgs<T, S>& a, T& oe, T& oh, T ue_old, T uh_old, bool at_src) {
+    oe = T(double(oe) + double(ue_old) + (at_src ? a.fsrc : 0.0));
+    oh = T(double(oh) + double(uh_old));
 }
+
 
 template <int MODE> struct ModeCE { static constexpr int v = IsFund<MODE>::v ? -1 : 0; };
 template <int MODE> struct ModeCH { static constexpr int v = (MODE == CONV_LOD) ? 1 : 0; };
@@ -253,7 +257,7 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 // ---------------------------------------------------------------------------
 // Body of one block of x-line work: block `blk` of the pass described by `a`
 // (lines blk * waves * 64/P ...); ctab = the per-material coefficients in LDS (MAT).
-template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN = false>
 __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const CoefTab<S>* ctab) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
@@ -467,6 +471,18 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
 #pragma unroll
     for (int i = 0; i < M; ++i) { te[i] = T(eo[i]); th[i] = T(ho[i]); }
     if (!live) return;
+    if constexpr (FIN) {
+        // output form, in place: U_old of this thread's own slots is loaded
+        // again before they are overwritten
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (FULL || j0 + i < n) {
+                fin_value<T, S>(a, te[i], th[i], Buf<T>::ld(rE, vo, i * ES), Buf<T>::ld(rH, vo, i * ES),
+                                src_here && i == si);
+            }
+        }
+        if (first) te[0] = T(0);   // the wall
+    }
     const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
     if (FULL || j0 + M <= n) {
         st_chunk<T, M>(wE, vo, te);
@@ -482,11 +498,14 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     }
 }
 
-template <typename T, typename S, int M, int MODE, bool FULL, bool MAT>
+// FIN: the pass stores the output form u = U_old + U_new of its pair instead
+// of U_new (output processing of the last B sub-step of a fundamental ADI run;
+// a separate instantiation, so the other passes carry none of its registers).
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
-    pass_x_body<T, S, M, MODE, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), ctab);
+    pass_x_body<T, S, M, MODE, FULL, MAT, FIN>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), ctab);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,7 +521,7 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // 9 P (TX+1) elements (13 P (TX+1) for refined solves, whose second
 // separator exchange has areas of its own).  TX * P must be a multiple of 64
 // (whole waves).
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN = false>
 __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const CoefTab<S>* ctab,
                                              bool valid) {
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
@@ -742,12 +761,26 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
         for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
     }
     if (!live) return;
+    T ot[M], oh[M];   // the values stored
+#pragma unroll
+    for (int i = 0; i < M; ++i) { ot[i] = T(eo[i]); oh[i] = T(ho[i]); }
+    if constexpr (FIN) {
+        // output form, in place (see the x lines)
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (FULL || j0 + i < n) {
+                fin_value<T, S>(a, ot[i], oh[i], Buf<T>::ld(rE, vo, i * swb), Buf<T>::ld(rH, vo, i * swb),
+                                src_here && i == si);
+            }
+        }
+        if (first) ot[0] = T(0);   // the wall
+    }
     const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         if (FULL || j0 + i < n) {
-            Buf<T>::st(T(eo[i]), wE, vo, i * swb);
-            Buf<T>::st(T(ho[i]), wH, vo, i * swb);
+            Buf<T>::st(ot[i], wE, vo, i * swb);
+            Buf<T>::st(oh[i], wH, vo, i * swb);
         }
     }
 }
@@ -761,13 +794,13 @@ struct YzOcc {
     static constexpr int v = (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI && MODE != FUND_REF) ? 8 : 1;
 };
 
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT>
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN>
 __global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT>::v)) pass_yz_kernel(PassArgs<T, S> a) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     extern __shared__ unsigned char smem_raw[];
-    pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
-                                                   threadIdx.x, reinterpret_cast<S*>(smem_raw), ctab, true);
+    pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT, FIN>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
+                                                        threadIdx.x, reinterpret_cast<S*>(smem_raw), ctab, true);
 }
 
 }  // namespace fdtd

@@ -8,53 +8,6 @@
 namespace fdtd {
 
 // ---------------------------------------------------------------------------
-// kernel launch helpers (variants: full lines, material-index eps_r)
-// ---------------------------------------------------------------------------
-template <typename T, typename S, int M, int MODE>
-static void launch_x(bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
-    if (full) {
-        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, true, false>), g, b, 0, st, a);
-    } else {
-        if (mat) hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((pass_x_kernel<T, S, M, MODE, false, false>), g, b, 0, st, a);
-    }
-}
-// Refined solves are built for FP32: x lines with 8-slot chunks, y/z lines
-// with 8- or 16-slot chunks.
-template <typename S, int M> struct HasRefX { static constexpr bool v = sizeof(S) == 4 && M == 8; };
-template <typename S, int M> struct HasRefYZ { static constexpr bool v = sizeof(S) == 4 && (M == 8 || M == 16); };
-template <typename T, typename S, int M>
-static bool launch_x_mode(int mode, bool full, bool mat, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
-    if (mode == FUND) launch_x<T, S, M, FUND>(full, mat, g, b, st, a);
-    else if (mode == CONV_LOD) launch_x<T, S, M, CONV_LOD>(full, mat, g, b, st, a);
-    else if (mode == CONV_ADI) launch_x<T, S, M, CONV_ADI>(full, mat, g, b, st, a);
-    else if constexpr (HasRefX<S, M>::v) launch_x<T, S, M, FUND_REF>(full, mat, g, b, st, a);
-    else return false;
-    return true;
-}
-template <typename T, typename S, int M, int TX, int NT, int MODE>
-static void launch_yz(bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
-    if (full) {
-        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, true>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, false>), g, b, lds, st, a);
-    } else {
-        if (mat) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, true>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, false>), g, b, lds, st, a);
-    }
-}
-template <typename T, typename S, int M, int TX, int NT>
-static bool launch_yz_mode(int mode, bool full, bool mat, dim3 g, dim3 b, size_t lds, hipStream_t st,
-                           const PassArgs<T, S>& a) {
-    if (mode == FUND) launch_yz<T, S, M, TX, NT, FUND>(full, mat, g, b, lds, st, a);
-    else if (mode == CONV_LOD) launch_yz<T, S, M, TX, NT, CONV_LOD>(full, mat, g, b, lds, st, a);
-    else if (mode == CONV_ADI) launch_yz<T, S, M, TX, NT, CONV_ADI>(full, mat, g, b, lds, st, a);
-    else if constexpr (HasRefYZ<S, M>::v) launch_yz<T, S, M, TX, NT, FUND_REF>(full, mat, g, b, lds, st, a);
-    else return false;
-    return true;
-}
-
-// ---------------------------------------------------------------------------
 // one line pass
 // ---------------------------------------------------------------------------
 // Right-hand-side injection of one sub-step at the E samples stored at node
@@ -84,9 +37,15 @@ static Inject source_inject(const fdtd_plan_s* p, const fdtd_source* src, double
     return in;
 }
 
+// Output processing fused into the passes of the last B sub-step of a
+// fundamental ADI run: they store u = U_old + U_new instead of U_new.
+struct Fin {
+    double src;       // g/2 of this sub-step, added back at the source sample
+};
+
 // Coefficients of the input/output and energy kernels (reciprocals formed here).
 static AuxCoef aux_coef(const fdtd_desc& d, double link) {
-    return AuxCoef{kEps0, kMu0, 1.0 / kMu0, 1.0 / d.dx, 1.0 / d.dy, 1.0 / d.dz, link};
+    return AuxCoef{kEps0, kMu0, 1.0 / kMu0, 1.0 / d.dx, 1.0 / d.dy, 1.0 / d.dz, link, 0};
 }
 
 template <typename T>
@@ -108,7 +67,7 @@ struct PassShape {
 // kernel configuration for the line axis.
 template <typename T, typename S>
 static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
-                       const Inject* inj, PassArgs<T, S>& a, PassShape& sh) {
+                       const Inject* inj, PassArgs<T, S>& a, PassShape& sh, const Fin* fin = nullptr) {
     const PairDef& pd = kPairs[op][k];
     const Dims& d = p->dims;
     std::memset(&a, 0, sizeof(a));
@@ -198,14 +157,15 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
         sh.lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
     }
     sh.full = a.P * cf.M == a.n_w;
+    if (fin) a.fsrc = fin->src;
 }
 
 template <typename T, typename S>
 static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
-                               const Inject* inj, bool timed) {
+                               const Inject* inj, bool timed, const Fin* fin = nullptr) {
     PassArgs<T, S> a;
     PassShape sh;
-    build_pass<T, S>(p, op, k, theta, mode, set_in, set_out, inj, a, sh);
+    build_pass<T, S>(p, op, k, theta, mode, set_in, set_out, inj, a, sh, fin);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         Timing& tm = p->tm;
@@ -224,26 +184,15 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     }
     const KCfg& cf = p->cfg[sh.w];
     const int kmode = (mode == FUND && p->refine) ? FUND_REF : mode;
-    bool built = true;
+    const bool fused = fin != nullptr;
+    int r;
     if (sh.w == 0) {
-        if (cf.M == 8) built = launch_x_mode<T, S, 8>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
-        else built = launch_x_mode<T, S, 16>(kmode, sh.full, sh.mat, sh.grid, sh.block, p->stream, a);
+        r = dispatch_x<T, S>(kmode, cf.M, sh.full, sh.mat, fused, sh.grid, sh.block, p->stream, a);
     } else {
-        const int M = cf.M, TX = cf.TX, NT = cf.NT;
         const size_t lds = kmode == FUND_REF ? sh.lds / 9 * 13 : sh.lds;   // refined: second exchange areas
-#define CASE_YZ(MM, TT, NN)                                                                                    \
-    if (M == MM && TX == TT && NT == NN) {                                                                     \
-        built = launch_yz_mode<T, S, MM, TT, NN>(kmode, sh.full, sh.mat, sh.grid, sh.block, lds, p->stream, a); \
-    } else
-        if constexpr (sizeof(S) == 4) {
-            CASE_YZ(16, 32, 1024) CASE_YZ(16, 16, 512) CASE_YZ(8, 16, 1024) CASE_YZ(32, 16, 512) CASE_YZ(8, 32, 512)
-            return FDTD_EUNSUPPORTED;
-        } else {
-            CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) CASE_YZ(8, 16, 1024) return FDTD_EUNSUPPORTED;
-        }
-#undef CASE_YZ
+        r = dispatch_yz<T, S>(kmode, cf.M, cf.TX, cf.NT, sh.full, sh.mat, fused, sh.grid, sh.block, lds, p->stream, a);
     }
-    if (!built) return FDTD_EUNSUPPORTED;
+    if (r != DISPATCH_OK) return FDTD_EUNSUPPORTED;
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(e1, p->stream));
     return FDTD_OK;
@@ -251,10 +200,11 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
 
 template <typename T, typename S>
 static fdtd_status substep(fdtd_plan_s* p, int op, double theta, int mode, int& cur, const Inject* inj,
-                           bool timed) {
+                           bool timed, const Fin* fin = nullptr) {
     const int out = (mode == CONV_ADI) ? 1 - cur : cur;
     for (int k = 0; k < 3; ++k) {
-        fdtd_status st = launch_pass<T, S>(p, op, k, theta, mode, set_ptr<T>(p, cur), set_ptr<T>(p, out), inj, timed);
+        fdtd_status st =
+            launch_pass<T, S>(p, op, k, theta, mode, set_ptr<T>(p, cur), set_ptr<T>(p, out), inj, timed, fin);
         if (st != FDTD_OK) return st;
     }
     cur = out;

@@ -18,6 +18,25 @@ static const PairDef kPairs[2][3] = {
     {{0, 4, 2, 0, 1, -1}, {1, 5, 0, 1, 2, -1}, {2, 3, 1, 2, 0, -1}},   // B
 };
 
+// FDTD_F32 plans refine their line solves below this sigma.  The FP32
+// diagonal 2 + sigma is rounded to a spacing of 2.4e-7 near 2, a fixed
+// relative perturbation of up to 1.2e-7 / sigma of the medium at every step;
+// its phase error grows linearly with the step count (plain FP32, 1000 steps
+// of random-box media: 3e-4 at sigma >= 0.12, 4e-5 to 6e-5 at sigma >= 0.48).
+// Below sigma = 2 (relative perturbation 6e-8) refinement is switched on.
+static constexpr double kRefineSigma = 2.0;
+
+// Does an FDTD_F32 plan of `d` (scheme already mapped to a line-pass scheme)
+// with smallest relative permittivity eps_min refine its solves?  Only where
+// refined passes are built: fundamental forms, at most 512 cells per axis.
+static bool f32_refine_wanted(const fdtd_desc& d, float eps_min) {
+    if (d.form != FDTD_FUNDAMENTAL) return false;
+    if (std::max(d.nx, std::max(d.ny, d.nz)) > 512) return false;
+    const double h = std::min(d.dx, std::min(d.dy, d.dz));
+    const double theta = 0.5 * d.dt;   // the largest half-span of every scheme's sub-steps
+    return kEps0 * kMu0 * double(eps_min) * h * h / (theta * theta) < kRefineSigma;
+}
+
 struct SubStep { int op; double theta_frac; double t_frac; };
 struct SchemeDef { int nsub; SubStep sub[3]; };
 static const SchemeDef kSchemes[4] = {
@@ -88,7 +107,7 @@ struct fdtd_plan_s {
     fdtd::Dims dims;
     size_t esz;
     void* state = nullptr;    // 6 (or 12 for original ADI) arrays, padded layout
-    void* snap = nullptr;     // ADI: state before the last B sub-step
+    void* snap = nullptr;     // grid of an ADI batch: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
@@ -113,7 +132,9 @@ struct fdtd_plan_s {
     fdtd::Timing tm;
     fdtd::KCfg cfg[3];        // per line axis x, y, z
     int tuned = 0;
-    int refine = 0;           // FDTD_F32_REFINE: fundamental passes refine each solve once
+    int refine = 0;           // FP32 fundamental passes refine each solve once (FDTD_F32_REFINE, or
+                              // FDTD_F32 below kRefineSigma)
+    int req_dtype = 0;        // the dtype the caller asked for (d.dtype holds the storage/solve kind)
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
     int fam_n[2] = {0, 0};

@@ -26,10 +26,15 @@ static FieldPtrsW<T> state_ptrs_w(fdtd_plan_s* p, int set) {
     return f;
 }
 
+// Energy of the main-iteration state (ADI: of (1/2 I + dt/4 B) u, the
+// fundamental state itself, the conventional one through the link).
+// fin_form: a fundamental ADI state in output form (after the last B
+// sub-step of a run), whose energy is taken through the link as well.
 template <typename T>
-static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst) {
+static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst, bool fin_form = false) {
     AuxCoef k = aux_coef(p->d, 0.0);
-    if (p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL) k.link = 0.25 * p->d.dt;
+    if (p->d.scheme == FDTD_ADI && (p->d.form == FDTD_CONVENTIONAL || fin_form)) k.link = 0.25 * p->d.dt;
+    k.fin_form = fin_form ? 1 : 0;
     hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
                        state_ptrs<T>(p, set), p->eps, p->dims, k, p->partial);
     HIPCHK(hipGetLastError());
@@ -46,8 +51,6 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     const bool adi = d.scheme == FDTD_ADI;
     const bool conv = d.form == FDTD_CONVENTIONAL;
     const int mode = conv ? (adi ? CONV_ADI : CONV_LOD) : FUND;
-    const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
-    const unsigned gblocks = (unsigned)((nn + 255) / 256);
     FieldPtrs<T> caller;
     FieldPtrsW<T> caller_w;
     for (int c = 0; c < 3; ++c) {
@@ -65,7 +68,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     }
     // input processing
     const AuxCoef kin = aux_coef(d, (adi && !conv) ? 0.25 * d.dt : 0.0);
-    hipLaunchKernelGGL((load_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
+    hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(dm), dim3(kRowThreads), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
                        p->eps, dm, kin);
     HIPCHK(hipGetLastError());
     int cur = 0;
@@ -90,25 +93,28 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
         fdtd_status st = energy_into<T>(p, cur, p->energy_dev);
         if (st != FDTD_OK) return st;
     }
-    double last_b_g = 0.0;   // source term of the last B sub-step (ADI output correction)
+    // Output processing of the fundamental ADI rides on the passes of the
+    // run's last B sub-step: they store u = U_old + U_new (the v of that
+    // sub-step, with g/2 added back at the source) instead of U_new, so the
+    // state before it need not be kept; store_out_kernel copies the state to
+    // the caller.  The other schemes' state is u after their last sub-step.
+    const bool fin_adi = adi && !conv;
+    Fin fin{0.0};
     for (int n = 0; n < nsteps; ++n) {
         const long long nglob = p->step + n;
         for (int u = 0; u < sd.nsub; ++u) {
             const SubStep& ss = sd.sub[u];
             const double theta = ss.theta_frac * d.dt;
             const double g = source_value(src, theta, (double(nglob) + ss.t_frac) * d.dt);
-            if (adi && !conv && n == nsteps - 1 && ss.op == 1) {
-                HIPCHK(hipMemcpyAsync(p->snap, comp_ptr<T>(p, cur, 0), sizeof(T) * dm.comp * 6,
-                                      hipMemcpyDeviceToDevice, p->stream));
-            }
             const Inject inj = source_inject(p, src, g, mode);
             const bool timed = tm.per_launch > 0 && n % tm.per_launch == 0;
-            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, timed);
+            const bool last = fin_adi && n == nsteps - 1 && u == sd.nsub - 1;
+            if (last) fin.src = src ? 0.5 * g : 0.0;
+            fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, timed, last ? &fin : nullptr);
             if (st != FDTD_OK) return st;
-            if (ss.op == 1) last_b_g = g;
         }
         if (energy && (n + 1) % every == 0) {
-            fdtd_status st = energy_into<T>(p, cur, p->energy_dev + (n + 1) / every);
+            fdtd_status st = energy_into<T>(p, cur, p->energy_dev + (n + 1) / every, fin_adi && n == nsteps - 1);
             if (st != FDTD_OK) return st;
         }
     }
@@ -119,12 +125,8 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
             fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false);
             if (st != FDTD_OK) return st;
         }
-        const bool add_old = adi && !conv;
-        FieldPtrs<T> old;
-        for (int c = 0; c < 6; ++c) old.c[c] = reinterpret_cast<const T*>(p->snap ? p->snap : p->state) + (size_t)c * dm.comp;
-        const long long src_off = src ? (long long)src->k * dm.plane + (long long)src->j * dm.px + src->i : -1;
-        hipLaunchKernelGGL((store_state_kernel<T>), dim3(gblocks), dim3(256), 0, p->stream, state_ptrs<T>(p, cur),
-                           old, caller_w, dm, add_old ? 1 : 0, src_off, 0.5 * last_b_g);
+        hipLaunchKernelGGL((store_out_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream, state_ptrs<T>(p, cur),
+                           caller_w, dm, fin_adi ? 1 : 0);
         HIPCHK(hipGetLastError());
     }
     p->step += nsteps;

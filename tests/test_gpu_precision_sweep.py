@@ -1,18 +1,21 @@
 """Precision sweep: 128^3 cells, random-box eps_r (32 boxes), N(0,1) fields,
 CFL number 10, 1000 steps, every fundamental scheme, FP64 / FP32-storage with
-FP64 solves / pure FP32 / pure FP32 with refined solves on the GPU against the
-FP64 oracle (fixtures written by tests/golden/make_precision_sweep.py, which
-calls only the oracle).
+FP64 solves / FP32 (the library's choice) / FP32 with refined solves / plain
+FP32 solves on the GPU against the FP64 oracle (fixtures written by
+tests/golden/make_precision_sweep.py, which calls only the oracle).
 
-Reported at steps 100, 500, 1000: the energy-weighted relative L2 error over
-4096 seeded samples per component, and the relative error of the field's
-energy norm.  Bars: FP64 1e-10; FP32 storage with FP64 solves 1e-4 and pure
-FP32 with one refinement step per solve 1e-4 (the accuracy target for FP32
-fields after 1000 steps); plain FP32 arithmetic 1e-3, limited by the coherent
-rounding of the tridiagonal factors at sigma = eps mu dw^2 / theta^2 << 1,
-which is the same at every step.  Every scheme is also swept at CFL 5, the
-CFL number of the 512^3 workload (fixtures precision_sweep_<scheme>_cfl5.npz),
-where all three FP32-field modes meet 1e-4."""
+Reported and checked at steps 100, 500 and 1000: the energy-weighted relative
+L2 error over 4096 seeded samples per component, and the relative error of the
+field's energy norm.  Bars: FP64 1e-10; every FP32-field mode the library
+chooses by default (FP64 solves, FDTD_F32, refined FP32) 1e-4, the accuracy
+target for FP32 fields after 1000 steps.  FDTD_F32 refines its solves at these
+time steps (sigma = eps mu dw^2 / theta^2 < 2); plain FP32 solves
+(FDTD_F32_PLAIN) are swept too, as the comparison: their fixed rounding of the
+diagonal 2 + sigma (a relative perturbation up to 1.2e-7 / sigma of the medium,
+the same at every step) makes the phase error grow linearly with the step
+count, to 3e-4 at CFL 10 (bar 1e-3) and 4e-5 to 9e-5 at CFL 5 (bar 2e-4).
+Every scheme is also swept at CFL 5, the CFL number of the 512^3 workload
+(fixtures precision_sweep_<scheme>_cfl5.npz)."""
 import os
 
 import numpy as np
@@ -27,10 +30,12 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 DEV = "cuda:0"
-PREC = {"f64": (torch.float64, torch.float64), "f32s64": (torch.float32, torch.float64),
-        "f32": (torch.float32, torch.float32), "f32r": (torch.float32, torch.float32)}
-BAR = {"f64": 1e-10, "f32s64": 1e-4, "f32": 1e-3, "f32r": 1e-4}
-BAR_CFL5 = {"f32s64": 1e-4, "f32": 1e-4, "f32r": 1e-4}
+# precision key -> (field dtype, solve dtype, refine: None = the library's choice)
+PREC = {"f64": (torch.float64, torch.float64, None), "f32s64": (torch.float32, torch.float64, None),
+        "f32": (torch.float32, torch.float32, None), "f32r": (torch.float32, torch.float32, True),
+        "f32p": (torch.float32, torch.float32, False)}
+BAR = {"f64": 1e-10, "f32s64": 1e-4, "f32": 1e-4, "f32r": 1e-4, "f32p": 1e-3}
+BAR_CFL5 = {"f32s64": 1e-4, "f32": 1e-4, "f32r": 1e-4, "f32p": 2e-4}
 
 
 def _golden(scheme):
@@ -54,11 +59,13 @@ def _sweep(c, ref, scheme, prec):
     from paper_2011_14043_amd import Plan
     n = c["n"]
     assert int(ref["n"]) == n
-    dtype, solve = PREC[prec]
+    dtype, solve, refine = PREC[prec]
     E = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][:3]]
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][3:]]
     plan = Plan(n, n, n, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve,
-                eps_r=torch.tensor(c["eps"]), refine=prec == "f32r")
+                eps_r=torch.tensor(c["eps"]), refine=refine)
+    # FDTD_F32 refines at these time steps (smallest sigma 0.12 at CFL 10, 0.48 at CFL 5)
+    assert plan.refined == (prec in ("f32", "f32r"))
     done = 0
     errs, nerrs = [], []
     for m, step in enumerate(ref["steps"]):
@@ -83,14 +90,14 @@ def _sweep(c, ref, scheme, prec):
     return errs, nerrs
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r"])
+@pytest.mark.parametrize("prec", ["f64", "f32s64", "f32", "f32r", "f32p"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
 def test_precision_sweep(setup, scheme, prec):
     ref = _golden(scheme)
     print(f"[case] precision sweep 128^3 CFL10 {scheme}/{prec}", flush=True)
     errs, nerrs = _sweep(setup, ref, scheme, prec)
-    assert errs[-1] <= BAR[prec], errs
-    assert nerrs[-1] <= BAR[prec], nerrs
+    assert max(errs) <= BAR[prec], errs       # steps 100, 500 and 1000
+    assert max(nerrs) <= BAR[prec], nerrs
 
 
 @pytest.fixture(scope="module")
@@ -101,7 +108,7 @@ def setup_cfl5(setup):
     return c
 
 
-@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r"])
+@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r", "f32p"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
 def test_precision_cfl5(setup_cfl5, scheme, prec):
     """The same sweep at CFL 5, the CFL number of the 512^3 workload."""
@@ -109,6 +116,5 @@ def test_precision_cfl5(setup_cfl5, scheme, prec):
     assert float(ref["cfl"]) == 5.0
     print(f"[case] precision sweep 128^3 CFL5 {scheme}/{prec}", flush=True)
     errs, nerrs = _sweep(setup_cfl5, ref, scheme, prec)
-    assert errs[-1] <= BAR_CFL5[prec], errs
-    # the energy norm of plain FP32 SS2 ends at 9.3e-5: its bar is the field bar doubled
-    assert nerrs[-1] <= (2 if prec == "f32" else 1) * BAR_CFL5[prec], nerrs
+    assert max(errs) <= BAR_CFL5[prec], errs
+    assert max(nerrs) <= BAR_CFL5[prec], nerrs
