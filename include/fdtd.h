@@ -262,6 +262,19 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
 fdtd_status fdtd_diff_norm(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
                            void* const Hb[3], double* out);
 
+/* fdtd_diff_norm without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as fdtd_diff_norm
+ * (and bit for bit the same out[]); its work area -- at most 2 x 1024
+ * partial sums and the 2 results, 16,400 bytes -- is a static device array
+ * of the library, one per GPU, held until the process ends (no grid size
+ * needs more: the first reduction stage takes at most 1024 blocks).  Every
+ * call on a GPU shares that array, so calls that overlap on one GPU (other
+ * host threads, other streams) race; calls in sequence are independent
+ * (each writes every value it reads).  Calls no hipMalloc or hipFree. */
+fdtd_status fdtd_diff_norm_noalloc(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
+                                   void* const Hb[3], double* out);
+
 /* Conjugate-gradient controls of a Crank-Nicolson plan (else
  * FDTD_EUNSUPPORTED): stop when |r| <= tol |b| (0 < tol < 1, checked every
  * fourth iteration) or after maxit >= 1 iterations.  Defaults 1e-12, 500. */

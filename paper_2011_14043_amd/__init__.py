@@ -173,6 +173,18 @@ class Plan:
                    "fdtd_diff_norm")
         return out[0], out[1]
 
+    def diff_norm_noalloc(self, Ea, Ha, Eb, Hb):
+        """diff_norm through fdtd_diff_norm_noalloc: no device allocation (its
+        work area is the library's static per-GPU array; overlapping calls on
+        one GPU race)."""
+        out = (ctypes.c_double * 2)()
+        _lib.check(_lib.lib().fdtd_diff_norm_noalloc(self._h, _ptrs(Ea, self.dtype, self.shape, self.device),
+                                                     _ptrs(Ha, self.dtype, self.shape, self.device),
+                                                     _ptrs(Eb, self.dtype, self.shape, self.device),
+                                                     _ptrs(Hb, self.dtype, self.shape, self.device), out),
+                   "fdtd_diff_norm_noalloc")
+        return out[0], out[1]
+
     def set_cg(self, tol: float = 1e-12, maxit: int = 500):
         """Conjugate-gradient controls of a Crank-Nicolson plan."""
         _lib.check(_lib.lib().fdtd_set_cg(self._h, float(tol), int(maxit)), "fdtd_set_cg")

@@ -21,8 +21,8 @@ DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2, "f32_refine": 3, "f32_plain": 4
 
 EXPORTS = ("fdtd_plan", "fdtd_get_refined", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
            "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-           "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_set_cg",
-           "fdtd_last_cg", "fdtd_destroy", "fdtd_strerror")
+           "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_diff_norm_noalloc",
+           "fdtd_set_cg", "fdtd_last_cg", "fdtd_destroy", "fdtd_strerror")
 
 
 class FdtdDesc(ctypes.Structure):
@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
     L.fdtd_run_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int]
     L.fdtd_diff_norm.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                  ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double)]
+    L.fdtd_diff_norm_noalloc.argtypes = L.fdtd_diff_norm.argtypes
     L.fdtd_set_cg.argtypes = [vp, ctypes.c_double, ctypes.c_int]
     L.fdtd_last_cg.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.fdtd_destroy.argtypes = [vp]
@@ -89,8 +90,8 @@ def lib() -> ctypes.CDLL:
     L.fdtd_strerror.restype = ctypes.c_char_p
     for name in ("fdtd_plan", "fdtd_get_refined", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
                  "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
-                 "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_set_cg",
-                 "fdtd_last_cg", "fdtd_destroy"):
+                 "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_diff_norm_noalloc",
+                 "fdtd_set_cg", "fdtd_last_cg", "fdtd_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +44,73 @@
 using namespace fdtd;
 
 static bool plan_ok(fdtd_plan_t p) { return p != nullptr && p->magic == 0xFD7DFD7Du; }
+
+// ---------------------------------------------------------------------------
+// fdtd_diff_norm and its variant without allocation
+// ---------------------------------------------------------------------------
+// Device work area of fdtd_diff_norm_noalloc: the partial sums of the
+// two-stage reduction and its two results.  Each GPU the library runs on
+// holds one copy until the process ends; in host code its address is taken
+// per device with hipGetSymbolAddress (scratch_ptr), never from the name.
+constexpr int kScratchDoubles = 2 * 1024 + 2;   // 16,400 bytes
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch[kMaxDevices];   // per device, resolved on first use
+static std::mutex g_scratch_mu;
+
+// Address of `scratch` on device `dev` (which must be current).
+static fdtd_status scratch_ptr(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return FDTD_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FDTD_EDEVICE;
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return FDTD_OK;
+}
+
+// Blocks of the first reduction stage of fdtd_diff_norm: one per 256 nodes,
+// at most the plan's npartial (1024).
+static int diff_blocks(const fdtd_plan_s* p) {
+    const long long nn = (long long)(p->dims.nx + 1) * (p->dims.ny + 1) * (p->dims.nz + 1);
+    return (int)std::min<long long>(p->npartial, (nn + 255) / 256);
+}
+static int diff_work_doubles(const fdtd_plan_s* p) { return 2 * p->npartial + 2; }
+
+// The reduction of fdtd_diff_norm with device work area `work` (2 npartial + 2
+// doubles): per-block partials, then the two sums in fixed order.
+static fdtd_status diff_norm_impl(fdtd_plan_s* p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
+                                  void* const Hb[3], double* out, double* work) {
+    const int nb = diff_blocks(p);
+    const AuxCoef k = aux_coef(p->d, 0.0);
+    auto launch = [&](auto tag) -> fdtd_status {
+        using T = decltype(tag);
+        FieldPtrs<T> fa, fb;
+        for (int c = 0; c < 3; ++c) {
+            fa.c[c] = static_cast<const T*>(Ea[c]);
+            fa.c[3 + c] = static_cast<const T*>(Ha[c]);
+            fb.c[c] = static_cast<const T*>(Eb[c]);
+            fb.c[3 + c] = static_cast<const T*>(Hb[c]);
+        }
+        hipLaunchKernelGGL((diff_partial_kernel<T>), dim3(nb), dim3(256), 0, p->stream, fa, fb, p->eps, p->dims, k,
+                           work);
+        HIPCHK(hipGetLastError());
+        return FDTD_OK;
+    };
+    const fdtd_status st = p->d.dtype == FDTD_F64 ? launch(double()) : launch(float());
+    if (st != FDTD_OK) return st;
+    double* res = work + 2 * p->npartial;
+    for (int m = 0; m < 2; ++m) {
+        hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, work + m * nb, nb, res + m);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(out, res, sizeof(double) * 2, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return std::isfinite(out[0]) && std::isfinite(out[1]) ? FDTD_OK : FDTD_ENONFINITE;
+}
 
 extern "C" {
 
@@ -507,36 +575,26 @@ fdtd_status fdtd_diff_norm(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], 
     int dev_now = -1;
     (void)hipGetDevice(&dev_now);
     if (dev_now != p->device) (void)hipSetDevice(p->device);
-    auto body = [&]() -> fdtd_status {
-        const int nb = p->npartial;
-        if (!p->diff_dev) HIPCHK(hipMalloc(&p->diff_dev, sizeof(double) * (2 * nb + 2)));
-        const AuxCoef k = aux_coef(p->d, 0.0);
-        auto launch = [&](auto tag) -> fdtd_status {
-            using T = decltype(tag);
-            FieldPtrs<T> fa, fb;
-            for (int c = 0; c < 3; ++c) {
-                fa.c[c] = static_cast<const T*>(Ea[c]);
-                fa.c[3 + c] = static_cast<const T*>(Ha[c]);
-                fb.c[c] = static_cast<const T*>(Eb[c]);
-                fb.c[3 + c] = static_cast<const T*>(Hb[c]);
-            }
-            hipLaunchKernelGGL((diff_partial_kernel<T>), dim3(nb), dim3(256), 0, p->stream, fa, fb, p->eps, p->dims, k,
-                               p->diff_dev);
-            HIPCHK(hipGetLastError());
-            return FDTD_OK;
-        };
-        const fdtd_status st = p->d.dtype == FDTD_F64 ? launch(double()) : launch(float());
-        if (st != FDTD_OK) return st;
-        for (int m = 0; m < 2; ++m) {
-            hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, p->diff_dev + m * nb, nb,
-                               p->diff_dev + 2 * nb + m);
-            HIPCHK(hipGetLastError());
-        }
-        HIPCHK(hipMemcpyAsync(out, p->diff_dev + 2 * nb, sizeof(double) * 2, hipMemcpyDeviceToHost, p->stream));
-        HIPCHK(hipStreamSynchronize(p->stream));
-        return std::isfinite(out[0]) && std::isfinite(out[1]) ? FDTD_OK : FDTD_ENONFINITE;
-    };
-    const fdtd_status st = body();
+    fdtd_status st = FDTD_OK;
+    if (!p->diff_dev && hipMalloc(&p->diff_dev, sizeof(double) * diff_work_doubles(p)) != hipSuccess)
+        st = FDTD_ENOMEM;
+    if (st == FDTD_OK) st = diff_norm_impl(p, Ea, Ha, Eb, Hb, out, p->diff_dev);
+    if (dev_now != p->device) (void)hipSetDevice(dev_now);
+    return st;
+}
+
+fdtd_status fdtd_diff_norm_noalloc(fdtd_plan_t p, void* const Ea[3], void* const Ha[3], void* const Eb[3],
+                                   void* const Hb[3], double* out) {
+    if (!plan_ok(p) || p->batch || !Ea || !Ha || !Eb || !Hb || !out) return FDTD_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!Ea[c] || !Ha[c] || !Eb[c] || !Hb[c]) return FDTD_EINVAL;
+    if (diff_work_doubles(p) > kScratchDoubles) return FDTD_EINVAL;   // never: at most 2 * 1024 + 2
+    int dev_now = -1;
+    (void)hipGetDevice(&dev_now);
+    if (dev_now != p->device) (void)hipSetDevice(p->device);
+    double* work = nullptr;
+    fdtd_status st = scratch_ptr(p->device, &work);
+    if (st == FDTD_OK) st = diff_norm_impl(p, Ea, Ha, Eb, Hb, out, work);
     if (dev_now != p->device) (void)hipSetDevice(dev_now);
     return st;
 }
