@@ -205,6 +205,32 @@ def test_design_gradient_vs_central_fd(design, design_fd, prec, tol):
     assert worst <= 10 * tol, (worst, adj, fd)
 
 
+@pytest.mark.parametrize("seed,box", [(0, (0, 5, 0, 4, 0, 6)), (1, (1, 4, 0, 3, 2, 6))],
+                         ids=["whole-grid", "sub-box"])
+def test_autograd_function_vs_oracle_tiny(seed, box):
+    """The torch.autograd front end (ProbeEnergy / probe_energy): J and
+    x.grad = dJ/d eps_r over a design box of the 5 x 4 x 6 grid, with random
+    initial fields and a source, against the FP64 oracle's reverse-mode
+    gradient, element by element (FP64, <= 1e-9 of the largest entry)."""
+    from paper_2011_14043_amd.autograd import ProbeProblem, probe_energy
+    c = _tiny(seed)
+    steps = 10
+    print(f"[case] autograd vs oracle tiny 5x4x6 seed={seed} box={box}", flush=True)
+    J_ref, g_ref = adjoint.gradient(c["g"], c["u0"], steps, c["src"], c["probe"])
+    i0, i1, j0, j1, k0, k1 = box
+    E0, H0 = _fields(c["u0"], "f64")
+    pb = ProbeProblem(c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["h"], c["h"], torch.tensor(c["eps"]), box,
+                      steps, c["probe"], _gsrc(c["src"]), E0=E0, H0=H0, dtype=torch.float64, ckpt_every=3)
+    x = torch.tensor(c["eps"][k0:k1, j0:j1, i0:i1], dtype=torch.float64, device=DEV, requires_grad=True)
+    J = probe_energy(x, pb)
+    J.backward()
+    assert abs(float(J) - J_ref) <= 1e-9 * abs(J_ref), (float(J), J_ref)
+    want = g_ref[k0:k1, j0:j1, i0:i1]
+    err = float(np.abs(x.grad.cpu().numpy() - want).max()) / float(np.abs(g_ref).max())
+    print(f"  J rel {abs(float(J) - J_ref) / J_ref:.2e}  x.grad rel(max) {err:.2e}", flush=True)
+    assert err <= 1e-9, err
+
+
 def test_autograd_function_matches_directional_fd():
     """ProbeEnergy.backward returns dJ/d eps_design: its inner product with a
     random direction matches the central difference of J along it (FP64)."""

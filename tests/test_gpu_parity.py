@@ -241,15 +241,21 @@ def _mode_on_gpu(nx, ny, nz, h, mnp, amps, dtype):
     return out
 
 
-@pytest.mark.parametrize("n,prec,steps", [(128, "f64", 20), (512, "f32", 10), (512, "f32s64", 10),
-                                          (512, "f32r", 10)],
-                         ids=["128-f64", "512-f32", "512-f32s64", "512-f32r"])
-def test_cavity_mode_at_full_size(n, prec, steps):
+@pytest.mark.parametrize("n,prec,steps,form", [(128, "f64", 20, "fundamental"), (512, "f32", 10, "fundamental"),
+                                               (512, "f32s64", 10, "fundamental"), (512, "f32r", 10, "fundamental"),
+                                               (512, "f32", 10, "conventional"), (512, "f64", 10, "conventional"),
+                                               (512, "f32s64", 10, "conventional")],
+                         ids=["128-f64", "512-f32", "512-f32s64", "512-f32r", "512-f32-conv", "512-f64-conv",
+                              "512-f32s64-conv"])
+def test_cavity_mode_at_full_size(n, prec, steps, form):
     """A PEC cavity mode evolves by the exact 6x6 ADI amplification matrix at
-    any grid size (property pin at the benchmark size, 512^3, in the kernel
-    configuration the autotuner picks for the benchmark: x lines 8-slot chunks
-    in 128-thread blocks, y/z lines 16-slot chunks, 32-wide tiles, 1024-thread
-    variant, XCD-aware order)."""
+    any grid size (eq. (clsADI); the fundamental form equals it): property pin
+    at the benchmark size, 512^3.  Fundamental FP32 in the kernel
+    configuration of the benchmark's FP32 plans (x lines 8-slot chunks in
+    128-thread blocks, y/z lines 16-slot chunks, 32-wide tiles, 1024-thread
+    variant, XCD-aware order); conventional ADI (the baseline of the
+    fundamental-versus-conventional comparison, its cross-term passes) in
+    whatever configuration the autotuner picks, as in the benchmark."""
     Plan, _ = _lib()
     h = 1e-3
     dt = W.yee_dt(h, h, h, 5.0)
@@ -260,9 +266,12 @@ def test_cavity_mode_at_full_size(n, prec, steps):
     amp = np.linalg.matrix_power(M, steps) @ a
     dtype, solve = PREC[prec]
     fields = _mode_on_gpu(n, n, n, h, mnp, a, dtype)
-    plan = Plan(n, n, n, dt, h, h, h, scheme="adi", form="fundamental", dtype=dtype, solve_dtype=solve,
-                refine=prec in REFINED)
-    if n == 512 and prec in ("f32", "f32r"):
+    plan = Plan(n, n, n, dt, h, h, h, scheme="adi", form=form, dtype=dtype, solve_dtype=solve,
+                refine=True if prec in REFINED else (False if prec == "f32" else None))
+    if form == "conventional":
+        plan.autotune(3)
+        print(f"  autotuned: {[plan.kernel_config(ax) for ax in range(3)]}", flush=True)
+    elif n == 512 and prec in ("f32", "f32r"):
         plan.set_kernel_config(0, chunk=8, block_threads=128, remap=0)
         for ax in (1, 2):
             plan.set_kernel_config(ax, chunk=16, tile_x=32, block_threads=1024, remap=1)
@@ -274,7 +283,7 @@ def test_cavity_mode_at_full_size(n, prec, steps):
     num = sum(wi * float(torch.sum((f.double() - r) ** 2)) for wi, f, r in zip(w, fields, ref))
     den = sum(wi * float(torch.sum(r ** 2)) for wi, r in zip(w, ref))
     err = math.sqrt(num / den)
-    print(f"[case] cavity mode {n}^3 {prec}: rel-L2 {err:.3e}")
+    print(f"[case] cavity mode {n}^3 {prec} {form}: rel-L2 {err:.3e}")
     assert err < {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6, "f32r": 1e-5}[prec]
 
 

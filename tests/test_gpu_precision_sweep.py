@@ -14,8 +14,9 @@ time steps (sigma = eps mu dw^2 / theta^2 < 2); plain FP32 solves
 diagonal 2 + sigma (a relative perturbation up to 1.2e-7 / sigma of the medium,
 the same at every step) makes the phase error grow linearly with the step
 count, to 3e-4 at CFL 10 (bar 1e-3) and 4e-5 to 9e-5 at CFL 5 (bar 2e-4).
-Every scheme is also swept at CFL 5, the CFL number of the 512^3 workload
-(fixtures precision_sweep_<scheme>_cfl5.npz)."""
+Every scheme is also swept at CFL 5, the CFL number of the 512^3 workload,
+and at CFL 1, the other end of its CFL range, where sigma >= 12 and FDTD_F32
+solves plainly (fixtures precision_sweep_<scheme>_cfl5.npz, _cfl1.npz)."""
 import os
 
 import numpy as np
@@ -55,7 +56,7 @@ def setup():
     return dict(n=n, h=h, dt=dt, eps=eps, u0=u0, g=g)
 
 
-def _sweep(c, ref, scheme, prec):
+def _sweep(c, ref, scheme, prec, expect_refined=None):
     from paper_2011_14043_amd import Plan
     n = c["n"]
     assert int(ref["n"]) == n
@@ -64,8 +65,10 @@ def _sweep(c, ref, scheme, prec):
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][3:]]
     plan = Plan(n, n, n, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.tensor(c["eps"]), refine=refine)
-    # FDTD_F32 refines at these time steps (smallest sigma 0.12 at CFL 10, 0.48 at CFL 5)
-    assert plan.refined == (prec in ("f32", "f32r"))
+    # FDTD_F32 refines at CFL 10 and 5 (smallest sigma 0.12 and 0.48), not at CFL 1 (12)
+    if expect_refined is None:
+        expect_refined = prec in ("f32", "f32r")
+    assert plan.refined == expect_refined
     done = 0
     errs, nerrs = [], []
     for m, step in enumerate(ref["steps"]):
@@ -118,3 +121,23 @@ def test_precision_cfl5(setup_cfl5, scheme, prec):
     errs, nerrs = _sweep(setup_cfl5, ref, scheme, prec)
     assert max(errs) <= BAR_CFL5[prec], errs
     assert max(nerrs) <= BAR_CFL5[prec], nerrs
+
+
+@pytest.fixture(scope="module")
+def setup_cfl1(setup):
+    c = dict(setup)
+    c["dt"] = W.yee_dt(c["h"], c["h"], c["h"], 1.0)
+    c["g"] = oracle.Grid(c["n"], c["n"], c["n"], c["h"], c["h"], c["h"], c["dt"], c["eps"])
+    return c
+
+
+@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r"])
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_precision_cfl1(setup_cfl1, scheme, prec):
+    """The same sweep at CFL 1 (smallest sigma 12: FDTD_F32 does not refine)."""
+    ref = _golden(f"{scheme}_cfl1")
+    assert float(ref["cfl"]) == 1.0
+    print(f"[case] precision sweep 128^3 CFL1 {scheme}/{prec}", flush=True)
+    errs, nerrs = _sweep(setup_cfl1, ref, scheme, prec, expect_refined=prec == "f32r")
+    assert max(errs) <= 1e-4, errs
+    assert max(nerrs) <= 1e-4, nerrs
