@@ -53,9 +53,9 @@ def kernel_hash():
     return hsh.hexdigest()[:16]
 
 
-def profiled_traffic(cfg_y, cfg_z):
+def profiled_traffic(cfg_y, cfg_z, refined):
     pr = PROFILED
-    if not pr or pr["kernel_hash"] != kernel_hash():
+    if not pr or pr["kernel_hash"] != kernel_hash() or pr.get("refined") != refined:
         return None
     want = pr["config"]
     for c in (cfg_y, cfg_z):
@@ -80,12 +80,16 @@ def make_inputs(n, seed_eps=2, seed_src=2):
     return h, dt, eps, ci
 
 
-def bytes_per_node(dtype_code, material_index=True):
-    # read E, H and the medium; write E, H.  The medium is a one-byte material
-    # index when the plan has <= 256 distinct eps_r values (this workload has
-    # 33), else an FP32 eps_r.
-    w = 8 if dtype_code == "f64" else 4
-    return 4 * w + (1 if material_index else 4)
+def bytes_per_slot(prec, conv_adi=False, material_index=False):
+    """Bytes one line pass moves per (E, H) slot: read E and H (and, for
+    conventional ADI, the two cross-coupled arrays), read the medium, write E
+    and H.  Algorithmic (the default): the medium is the FP32 eps_r, the
+    per-unit figure the roofline is priced on (20 B FP32, 36 B FP64, 28 / 52 B
+    conventional ADI).  material_index: the plan's actual medium read, a
+    one-byte material index (this workload has 33 materials)."""
+    w = 8 if prec == "f64" else 4
+    words = 6 if conv_adi else 4
+    return words * w + (1 if material_index else 4)
 
 
 def pass_nodes(n):
@@ -105,7 +109,69 @@ TIMING_EVERY = 8
 REFINE = {"f32r": True, "f32p": False}
 
 
-def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5):
+class Fp64Refs:
+    """FP64 GPU runs of the same workload (fundamental form of each scheme;
+    the FP64 path matches the FP64 oracle to 1e-11), the reference of the
+    relative L2 error reported for every result.  Kept per (n, scheme, dt,
+    warmup, steps); cleared when the grid size changes."""
+
+    def __init__(self):
+        self.cache = {}
+        self.n = None
+        self.diff_plan = None
+
+    def _clear(self):
+        if self.diff_plan is not None:
+            self.diff_plan.close()
+        self.cache, self.diff_plan = {}, None
+
+    def get(self, n, scheme, steps, warmup, inputs):
+        import torch
+        from paper_2011_14043_amd import Plan, Source
+        if n != self.n:
+            self._clear()
+            self.n = n
+        h, dt, eps, ci = inputs
+        base = {"dyakonov": "adi", "douglas_gunn": "adi"}.get(scheme, scheme)
+        key = (base, dt, warmup, steps)
+        if key not in self.cache:
+            dev = torch.device("cuda", 0)
+            shape = (n + 1, n + 1, n + 1)
+            E = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(3)]
+            H = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(3)]
+            src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
+            plan = Plan(n, n, n, dt, h, h, h, scheme=base, form="fundamental", dtype=torch.float64,
+                        eps_r=torch.from_numpy(eps))
+            if warmup:
+                plan.run(E, H, warmup, source=src)
+            plan.set_step(0)
+            plan.run(E, H, steps, source=src)
+            torch.cuda.synchronize()
+            if self.diff_plan is None:
+                self.diff_plan = plan
+            else:
+                plan.close()
+            self.cache[key] = (E, H)
+        return self.cache[key]
+
+    def rel_l2(self, n, scheme, steps, warmup, inputs, E, H):
+        """Energy-weighted relative L2 distance (fdtd_diff_norm, FP64 on the
+        device) of E, H from the FP64 reference run."""
+        import math
+        import torch
+        Er, Hr = self.get(n, scheme, steps, warmup, inputs)
+        Ed = [t.to(torch.float64) for t in E]
+        Hd = [t.to(torch.float64) for t in H]
+        num, den = self.diff_plan.diff_norm(Ed, Hd, Er, Hr)
+        del Ed, Hd
+        return math.sqrt(num / den) if den > 0 else None
+
+    def close(self):
+        self._clear()
+
+
+def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5,
+                refs=None):
     import torch
     from paper_2011_14043_amd import Plan, Source
     h, dt, eps, ci = inputs
@@ -135,21 +201,23 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     tm = plan.last_timing()
     finite = all(bool(torch.isfinite(t).all()) for t in E + H)
     plan.close()
-    del E, H
-    torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     cells = n ** 3
     mcells = cells / (ms * 1e-3) / 1e6
-    bpn = bytes_per_node(prec)
     npass = 9 if scheme == "ss2" else 6
-    alg_bytes_step = npass * pass_nodes(n) * bpn          # line passes only
-    if scheme == "adi" and form == "conventional":           # + the two cross-coupled arrays
-        alg_bytes_step = npass * pass_nodes(n) * (bpn + 2 * (8 if prec == "f64" else 4))
-    hbm_frac = alg_bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    conv_adi = scheme == "adi" and form == "conventional"
+    alg_bytes_step = npass * pass_nodes(n) * bytes_per_slot(prec, conv_adi)          # line passes only
+    act_bytes_step = npass * pass_nodes(n) * bytes_per_slot(prec, conv_adi, material_index=True)
     out = dict(scheme=scheme, form=form, prec=prec, refined=refined, ms_per_step=ms, mcells_per_s=mcells,
-               alg_bytes_per_step=alg_bytes_step, hbm_frac_alg=hbm_frac, main_ms=tm["main_ms"],
+               alg_bytes_per_step=alg_bytes_step,
+               hbm_frac_alg=alg_bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               hbm_frac_actual_bytes=act_bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, main_ms=tm["main_ms"],
                yz_ms_avg=tm["yz_ms_avg"], x_ms_avg=tm["x_ms_avg"], yz_launches=tm["yz_launches"],
                x_launches=tm["x_launches"], finite=finite, kernel_config=cfg)
+    if refs is not None:
+        out["rel_l2_vs_gpu_fp64"] = refs.rel_l2(n, scheme, steps, warmup, inputs, E, H)
+    del E, H
+    torch.cuda.empty_cache()
     log(json.dumps(out))
     return out
 
@@ -213,7 +281,7 @@ def run_batch(steps, warmup, prec="f32"):
     out = dict(workload="64 cavities U[16,96]^3, fundamental ADI, CFL 5", prec=prec, cells=cells, steps=steps,
                ms_per_step=ms, mcells_per_s=cells / (ms * 1e-3) / 1e6, main_ms_per_step=main_ms,
                sequential_single_ms_per_step=seq_ms, sequential_single_mcells_per_s=cells / (seq_ms * 1e-3) / 1e6,
-               hbm_frac_alg=6 * cells * bytes_per_node(prec) / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               hbm_frac_alg=6 * cells * bytes_per_slot(prec) / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                kernel_config=cfg, finite=finite)
     log(json.dumps(out))
     return out
@@ -304,27 +372,71 @@ def run_cn(n=256, steps=10, tol=1e-12):
     return out
 
 
+def _pinned_one_core():
+    """Context: run on one core of the allowed set (sched_setaffinity), one BLAS thread."""
+    import contextlib
+    from threadpoolctl import threadpool_limits
+
+    @contextlib.contextmanager
+    def ctx():
+        old = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+        core = min(old) if old else None
+        try:
+            if core is not None:
+                os.sched_setaffinity(0, {core})
+            with threadpool_limits(limits=1):
+                yield core
+        finally:
+            if old is not None:
+                os.sched_setaffinity(0, old)
+    return ctx()
+
+
 def cpu_baseline(n=256, steps=3):
-    """The FP64 oracle (fundamental ADI) on the host, single thread, on a
-    bounded sample of the same workload (n^3 cells, `steps` steps)."""
+    """The FP64 oracle on the host, one thread pinned to one core, on bounded
+    samples of the workloads: the headline sample (fundamental ADI on n^3
+    cells of the 512^3 workload's medium and source, `steps` steps) and, as
+    detail, both forms of ADI on the 24^3 cavity (200 steps, full), the 128^3
+    precision-sweep grid (2 steps, with the time 1000 steps would take) and
+    the conventional form of the headline sample."""
     import numpy as np
     import oracle
     import workloads as W
     from oracle.source import Source as OSource
-    from threadpoolctl import threadpool_limits
     h, dt, eps, ci = make_inputs(n)
     g = oracle.Grid(n, n, n, h, h, h, dt, eps)
-    u0 = W.zero_fields(n, n, n)
-    src = OSource(*ci)
-    with threadpool_limits(limits=1):
+    detail = []
+
+    def timed(label, scheme, form, grid, u0, nsteps, src, cells, full_steps=None):
         t0 = time.perf_counter()
-        oracle.run("adi", "fundamental", g, u0, steps, src)
+        oracle.run(scheme, form, grid, u0, nsteps, src)
         t1 = time.perf_counter()
-    rate = n ** 3 * steps / (t1 - t0) / 1e6
-    return {"value": rate, "unit": "Mcell/s", "cores": 1, "kind": "oracle",
+        row = {"sample": label, "scheme": scheme, "form": form, "cells": cells, "steps": nsteps,
+               "seconds": t1 - t0, "mcells_per_s": cells * nsteps / (t1 - t0) / 1e6}
+        if full_steps:
+            row["seconds_for_%d_steps" % full_steps] = (t1 - t0) / nsteps * full_steps
+        detail.append(row)
+        return row
+
+    with _pinned_one_core() as core:
+        head = timed(f"{n}^3 random boxes + source", "adi", "fundamental", g, W.zero_fields(n, n, n), steps,
+                     OSource(*ci), n ** 3)
+        timed(f"{n}^3 random boxes + source", "adi", "conventional", g, W.zero_fields(n, n, n), 2, OSource(*ci),
+              n ** 3)
+        h1 = 1e-3
+        g1 = oracle.Grid(24, 24, 24, h1, h1, h1, W.yee_dt(h1, h1, h1, 4.0))
+        u1 = W.random_fields(24, 24, 24, seed=1)
+        for form in ("fundamental", "conventional"):
+            timed("24^3 vacuum cavity, CFL 4 (full)", "adi", form, g1, u1, 200, None, 24 ** 3)
+        g3 = oracle.Grid(128, 128, 128, h1, h1, h1, W.yee_dt(h1, h1, h1, 10.0),
+                         W.random_box_eps(128, 128, 128, seed=2, nboxes=32))
+        u3 = W.random_fields(128, 128, 128, seed=3)
+        for form in ("fundamental", "conventional"):
+            timed("128^3 precision sweep, CFL 10", "adi", form, g3, u3, 2, None, 128 ** 3, full_steps=1000)
+    return {"value": head["mcells_per_s"], "unit": "Mcell/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 NumPy oracle, fundamental ADI, {n}^3 cells of the same random-box/source "
-                      f"workload, {steps} step(s), single thread ({t1 - t0:.1f} s)",
-            "host": host_info()}
+                      f"workload, {steps} step(s), one thread pinned to core {core} ({head['seconds']:.1f} s)",
+            "host": host_info(), "detail": detail}
 
 
 def host_info():
@@ -413,34 +525,17 @@ def main():
     n = args.n
     inputs = make_inputs(n)
     log(f"[bench] {n}^3, {args.steps} steps, warmup {args.warmup}")
-    head = run_variant(n, "adi", "fundamental", "f32", args.steps, args.warmup, inputs, tune_reps=10)
+    refs = Fp64Refs()
+    head = run_variant(n, "adi", "fundamental", "f32", args.steps, args.warmup, inputs, tune_reps=10, refs=refs)
     variants = []
     extras = {}
-    if not args.no_extras:
-        extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
-        extras["adjoint_gradient"] = run_adjoint()
-        extras["crank_nicolson_256cube"] = run_cn()
-        # the smaller size of the same workload (256^3), plain and refined FP32
-        in256 = make_inputs(256)
-        extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256)
-                                             for prec in ("f32", "f32p")]
-        # the other CFL numbers of the 512^3 workload: the passes have no
-        # data-dependent control flow, so the step time should not move
-        import workloads as W
-        h0, _, eps0, ci0 = inputs
-        cfl_rows = []
-        for cfl in (1.0, 10.0):
-            r = run_variant(n, "adi", "fundamental", "f32", max(10, args.steps // 4), 2,
-                            (h0, W.yee_dt(h0, h0, h0, cfl), eps0, ci0))
-            r["cfl"] = cfl
-            cfl_rows.append(r)
-        extras["adi_fundamental_512cube_cfl_1_and_10"] = cfl_rows
     if args.variants != "none":
         todo = [("adi", "conventional", "f32"), ("adi", "fundamental", "f32p"), ("adi", "fundamental", "f32s64"),
                 ("adi", "conventional", "f32s64"),
                 ("adi", "fundamental", "f64"), ("adi", "conventional", "f64"),
                 ("lod1", "fundamental", "f32"), ("ss2", "fundamental", "f32"), ("lod2", "fundamental", "f32"),
                 ("lod1", "conventional", "f32"), ("ss2", "conventional", "f32"), ("lod2", "conventional", "f32"),
+                ("lod1", "fundamental", "f32p"), ("ss2", "fundamental", "f32p"), ("lod2", "fundamental", "f32p"),
                 ("dyakonov", "fundamental", "f32"), ("douglas_gunn", "fundamental", "f32"),
                 ("lod1", "fundamental", "f64"), ("ss2", "fundamental", "f64"), ("lod2", "fundamental", "f64"),
                 ("lod1", "conventional", "f64"), ("ss2", "conventional", "f64"), ("lod2", "conventional", "f64")]
@@ -448,17 +543,46 @@ def main():
             todo = [tuple(v.split("/")) for v in args.variants.split(",")]
         vsteps = max(10, args.steps // 4)
         for sch, form, prec in todo:
-            variants.append(run_variant(n, sch, form, prec, vsteps, 2, inputs))
-    # roofline of the dominant kernel: the y/z-line pass (4 of the 6 passes per step)
-    bpn = bytes_per_node("f32")
-    yz_bytes = pass_nodes(n) * bpn
+            variants.append(run_variant(n, sch, form, prec, vsteps, 2, inputs, refs=refs))
+    if not args.no_extras:
+        # the other CFL numbers of the 512^3 workload: the passes have no
+        # data-dependent control flow, so the step time moves only where
+        # FDTD_F32 refines (CFL 5 and 10) or not (CFL 1)
+        import workloads as W
+        h0, _, eps0, ci0 = inputs
+        cfl_rows = []
+        for cfl in (1.0, 10.0):
+            for prec in ("f32", "f32p"):
+                r = run_variant(n, "adi", "fundamental", prec, max(10, args.steps // 4), 2,
+                                (h0, W.yee_dt(h0, h0, h0, cfl), eps0, ci0), refs=refs)
+                r["cfl"] = cfl
+                cfl_rows.append(r)
+        extras["adi_fundamental_512cube_cfl_1_and_10"] = cfl_rows
+        refs.close()
+        extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
+        extras["adjoint_gradient"] = run_adjoint()
+        extras["crank_nicolson_256cube"] = run_cn()
+        # the smaller size of the same workload (256^3), FP32 as the library runs it and plain
+        in256 = make_inputs(256)
+        extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256, refs=refs)
+                                             for prec in ("f32", "f32p")]
+    refs.close()
+    # roofline of the dominant kernel: the y/z-line pass (4 of the 6 passes
+    # per step), priced on the algorithmic bytes per slot (read E, H, FP32
+    # eps_r; write E, H: 20 B); the plan actually reads a one-byte material
+    # index instead of eps_r (17 B), reported beside it
+    yz_bytes = pass_nodes(n) * bytes_per_slot("f32")
+    yz_bytes_act = pass_nodes(n) * bytes_per_slot("f32", material_index=True)
     yz_ms = head["yz_ms_avg"]
     achieved = yz_bytes / (yz_ms * 1e-3) / 1e9 if yz_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic(head["kernel_config"][1], head["kernel_config"][2]),
-            "kernel": "pass_yz_kernel (fundamental, FP32)", "bytes_per_launch": yz_bytes,
-            "avg_launch_ms": yz_ms, "launches": head["yz_launches"]}
+            "traffic": profiled_traffic(head["kernel_config"][1], head["kernel_config"][2], head["refined"]),
+            "kernel": "pass_yz_kernel (fundamental, FP32%s)" % (", refined solves" if head["refined"] else ""),
+            "bytes_per_slot": bytes_per_slot("f32"), "slots_per_launch": pass_nodes(n),
+            "bytes_per_launch": yz_bytes, "avg_launch_ms": yz_ms, "launches": head["yz_launches"],
+            "bytes_per_slot_actual": bytes_per_slot("f32", material_index=True),
+            "frac_actual_bytes": yz_bytes_act / (yz_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if yz_ms > 0 else 0.0}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -469,8 +593,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fundamental ADI, {n}^3 cells, random-box eps_r (32 boxes, U[1,12]), "
                                f"Ez Gaussian-pulse source, CFL 5, PEC",
-                   "cells": n ** 3, "scheme": "adi", "form": "fundamental", "fields": "f32", "solve": "f32"},
+                   "cells": n ** 3, "scheme": "adi", "form": "fundamental", "fields": "f32",
+                   "solve": "f32, refined once" if head["refined"] else "f32"},
         "hbm_frac_alg": head["hbm_frac_alg"],
+        "hbm_frac_actual_bytes": head["hbm_frac_actual_bytes"],
+        "rel_l2_vs_gpu_fp64": head.get("rel_l2_vs_gpu_fp64"),
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,

@@ -220,14 +220,28 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     // a one-byte material index per node (the passes then read 17 instead of
     // 20 bytes per FP32 slot); the table of values lives in LDS.
     if (!std::getenv("FDTD_NO_MATERIAL_INDEX")) {
-        std::vector<float> uniq(eps_host.begin(), eps_host.end());
-        uniq.push_back(1.0f);
-        std::sort(uniq.begin(), uniq.end());
-        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        // distinct values, sorted; the scan stops at the 257th
+        std::vector<float> uniq{1.0f};
+        float last = 1.0f;
+        for (float v : eps_host) {
+            if (v == last) continue;   // runs of one value (boxes) cost one comparison
+            last = v;
+            auto it = std::lower_bound(uniq.begin(), uniq.end(), v);
+            if (it != uniq.end() && *it == v) continue;
+            uniq.insert(it, v);
+            if (uniq.size() > 256) break;
+        }
         if (uniq.size() <= 256) {
             std::vector<unsigned char> idx((size_t)dm.comp);
-            for (size_t m = 0; m < idx.size(); ++m)
-                idx[m] = (unsigned char)(std::lower_bound(uniq.begin(), uniq.end(), en[m]) - uniq.begin());
+            float lv = uniq[0];
+            unsigned char li = 0;
+            for (size_t m = 0; m < idx.size(); ++m) {
+                if (en[m] != lv) {
+                    lv = en[m];
+                    li = (unsigned char)(std::lower_bound(uniq.begin(), uniq.end(), lv) - uniq.begin());
+                }
+                idx[m] = li;
+            }
             p->nmat = (int)uniq.size();
             if ((e = hipMalloc(&p->mat, (size_t)dm.comp)) != hipSuccess) return fail(from_hip(e));
             if ((e = hipMemcpy(p->mat, idx.data(), (size_t)dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
