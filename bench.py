@@ -29,16 +29,17 @@ HBM_PEAK_GBS = 8000.0
 
 
 # HBM traffic of the dominant kernel from rocprofv3 counters (FETCH_SIZE and
-# WRITE_SIZE in KiB per dispatch, averaged over the y and z passes of the
-# timed steps; calibration factors from a 1 GiB device copy).  Valid only for
-# the kernel sources whose hash is recorded and the profiled y/z
-# configuration; otherwise the bench reports traffic = null.
+# WRITE_SIZE in KiB per dispatch, median over its y and z dispatches;
+# calibration factors from a 1 GiB device copy).  Valid only for the kernel
+# sources whose hash is recorded, the profiled y/z configuration and the same
+# refinement; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "d82b047710e89874",
-    "config": [16, 32, 1024, 1],                             # chunk, tile_x, block_threads, remap (y and z)
-    "fetch_kib": {"y": 596611.0, "z": 596813.5},
-    "write_kib": {"y": 1047552.0, "z": 1047552.0},
-    "fetch_factor": 1048576.0 / 524299.5,                   # 1 GiB copy: FETCH_SIZE 524299.5 KiB
+    "kernel_hash": "624c7e03d2e97f4b",
+    "config": [16, 16, 512, 1],                              # chunk, tile_x, block_threads, remap (y and z)
+    "refined": True,
+    "fetch_kib": 595466.0,                                   # median over the y and z dispatches
+    "write_kib": 1067615.0,
+    "fetch_factor": 1048576.0 / 524299.5,                    # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
     "profile": "profiles/pass_kernels_adi_fundamental_f32_512cube.md",
 }
@@ -61,9 +62,7 @@ def profiled_traffic(cfg_y, cfg_z, refined):
     for c in (cfg_y, cfg_z):
         if [c["chunk"], c["tile_x"], c["block_threads"], c["remap"]] != want:
             return None
-    fetch = sum(pr["fetch_kib"].values()) / len(pr["fetch_kib"]) * 1024 * pr["fetch_factor"]
-    write = sum(pr["write_kib"].values()) / len(pr["write_kib"]) * 1024 * pr["write_factor"]
-    return fetch + write
+    return pr["fetch_kib"] * 1024 * pr["fetch_factor"] + pr["write_kib"] * 1024 * pr["write_factor"]
 
 
 def log(*a):
