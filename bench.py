@@ -323,6 +323,41 @@ def run_adjoint(prec="f32", steps=500, ckpt=50):
     return out
 
 
+def run_graphs(steps=500, warmup=20):
+    """Forward runs of the 128 x 128 x 64 design workload's grid and source
+    (FP32, CFL 5) with the main steps replayed from captured graphs of 8
+    steps (the default) and with every pass launched directly."""
+    import torch
+    import workloads as W
+    from paper_2011_14043_amd import Plan, Source
+    p = W.design_problem(seed=5)
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 5.0)
+    shape = (p["nz"] + 1, p["ny"] + 1, p["nx"] + 1)
+    out = {"workload": "128x128x64, design-box eps_r, Ez source, CFL 5, fundamental ADI, FP32", "steps": steps}
+    for graph in (8, 0):
+        E = [torch.zeros(shape, dtype=torch.float32, device="cuda") for _ in range(3)]
+        H = [torch.zeros(shape, dtype=torch.float32, device="cuda") for _ in range(3)]
+        plan = Plan(p["nx"], p["ny"], p["nz"], dt, h, h, h, dtype=torch.float32, eps_r=torch.from_numpy(p["eps"]))
+        plan.autotune(3)
+        plan.set_graph(graph)
+        src = Source(*p["src"])
+        plan.run(E, H, warmup, source=src)
+        torch.cuda.synchronize()
+        plan.set_step(0)
+        t0 = time.perf_counter()
+        plan.run(E, H, steps, source=src)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        key = "graphs" if graph else "direct"
+        out[f"{key}_ms_per_step"] = ms
+        out[f"{key}_mcells_per_s"] = p["nx"] * p["ny"] * p["nz"] / (ms * 1e-3) / 1e6
+        plan.close()
+    out["direct_over_graphs"] = out["direct_ms_per_step"] / out["graphs_ms_per_step"]
+    log(json.dumps(out))
+    return out
+
+
 def run_cn(n=256, steps=10, tol=1e-12):
     """Crank-Nicolson without factorization (FP64, one CG solve per step), in
     fundamental and classical form, against fundamental ADI (FP64) on the same
@@ -487,7 +522,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-cavity and adjoint lines")
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--only", choices=["batch", "adjoint", "cn"], default=None,
+    ap.add_argument("--only", choices=["batch", "adjoint", "cn", "graphs"], default=None,
                     help="run only the batched-cavity or the adjoint measurement and print its JSON")
     ap.add_argument("--cpu-schemes", action="store_true",
                     help="only time the FP64 oracle per scheme and form on the host (no GPU) and print its JSON")
@@ -520,6 +555,9 @@ def main():
         return
     if args.only == "cn":
         print(json.dumps(run_cn()), flush=True)
+        return
+    if args.only == "graphs":
+        print(json.dumps(run_graphs()), flush=True)
         return
     n = args.n
     inputs = make_inputs(n)
@@ -560,6 +598,7 @@ def main():
         refs.close()
         extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
         extras["adjoint_gradient"] = run_adjoint()
+        extras["graphs_128x128x64"] = run_graphs()
         extras["crank_nicolson_256cube"] = run_cn()
         # the smaller size of the same workload (256^3), FP32 as the library runs it and plain
         in256 = make_inputs(256)

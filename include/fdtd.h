@@ -172,6 +172,18 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
 /* fdtd_run with nsteps = 1 and no energy. */
 fdtd_status fdtd_step(fdtd_plan_t p, void* const E[3], void* const H[3], const fdtd_source* src);
 
+/* Captured graphs of a single-grid plan (else FDTD_EINVAL): fdtd_run replays
+ * a HIP graph of `steps` main-iteration steps (1 <= steps <= 64; default 8)
+ * for the steps before its last one, and launches the rest directly; 0
+ * launches every step directly.  Runs with an energy trace or per-launch
+ * timing never use graphs.  The graph is captured on the first run that
+ * uses it and again when the source cell or a kernel configuration changes;
+ * the source terms of a run are computed on the host (as for direct
+ * launches), copied to the device once per run, and each replay reads its
+ * window of them, so replays and direct launches give the same fields bit for
+ * bit.  Crank-Nicolson plans: FDTD_EUNSUPPORTED. */
+fdtd_status fdtd_set_graph(fdtd_plan_t p, int steps);
+
 /* Set the plan's step counter (the source time origin). */
 fdtd_status fdtd_set_step(fdtd_plan_t p, long long n);
 

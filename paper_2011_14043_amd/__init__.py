@@ -144,6 +144,10 @@ class Plan:
         _lib.check(L.fdtd_step(self._h, _ptrs(E, self.dtype, self.shape, self.device),
                                _ptrs(H, self.dtype, self.shape, self.device), src), "fdtd_step")
 
+    def set_graph(self, steps: int):
+        """Steps per captured HIP graph of fdtd_run (0: launch every step directly)."""
+        _lib.check(_lib.lib().fdtd_set_graph(self._h, int(steps)), "fdtd_set_graph")
+
     def set_step(self, n: int):
         _lib.check(_lib.lib().fdtd_set_step(self._h, int(n)), "fdtd_set_step")
 

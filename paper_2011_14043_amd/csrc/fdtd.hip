@@ -301,6 +301,17 @@ fdtd_status fdtd_set_step(fdtd_plan_t p, long long n) {
     return FDTD_OK;
 }
 
+fdtd_status fdtd_set_graph(fdtd_plan_t p, int steps) {
+    if (!plan_ok(p) || p->batch || steps < 0 || steps > 64) return FDTD_EINVAL;
+    if (p->cg) return FDTD_EUNSUPPORTED;   // Crank-Nicolson: no line passes
+    if (steps != p->graph_steps) {
+        (void)hipStreamSynchronize(p->stream);
+        graph_clear(p);
+        p->graph_steps = steps;
+    }
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined) {
     if (!plan_ok(p) || !refined) return FDTD_EINVAL;
     *refined = p->refine;
@@ -644,6 +655,12 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
         delete p->batch;
         p->batch = nullptr;
     }
+    graph_clear(p);
+    if (p->gstream) (void)hipStreamDestroy(p->gstream);
+    if (p->src_copied) (void)hipEventDestroy(p->src_copied);
+    if (p->src_dev) (void)hipFree(p->src_dev);
+    if (p->src_win) (void)hipFree(p->src_win);
+    if (p->src_host) (void)hipHostFree(p->src_host);
     if (p->state) (void)hipFree(p->state);
     if (p->snap) (void)hipFree(p->snap);
     if (p->eps) (void)hipFree(p->eps);

@@ -73,7 +73,8 @@ struct PassArgs {
     S cH2, hE3;           // CONV_ADI cross-term coefficients
     int src_a, src_b, src_j;   // source sample in line coordinates (src_a < 0: none)
     S src_pre, src_post;
-    const double* src_pre_dev; // if set, the value of src_pre is read from device memory
+    const double* src_pre_dev;  // if set, the value of src_pre is read from device memory
+    const double* src_post_dev; // if set, the value of src_post is read from device memory
     double fsrc;          // FIN passes: added to E at the source sample (the g/2 the pass subtracts)
 };
 
@@ -464,8 +465,9 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     }
     eo[0] = first ? S(0) : eo[0];
     if (IsFund<MODE>::v && __builtin_expect(src_wave, 0)) {
+        const S post = a.src_post_dev ? S(*a.src_post_dev) : a.src_post;
 #pragma unroll
-        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
+        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? post : S(0);
     }
     T te[M], th[M];
 #pragma unroll
@@ -757,8 +759,9 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     }
     eo[0] = first ? S(0) : eo[0];
     if (IsFund<MODE>::v && __builtin_expect(src_wave, 0)) {
+        const S post = a.src_post_dev ? S(*a.src_post_dev) : a.src_post;
 #pragma unroll
-        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? a.src_post : S(0);
+        for (int i = 0; i < M; ++i) eo[i] -= (src_here && i == si) ? post : S(0);
     }
     if (!live) return;
     T ot[M], oh[M];   // the values stored

@@ -13,13 +13,15 @@ namespace fdtd {
 // Right-hand-side injection of one sub-step at the E samples stored at node
 // (i, j, k): component c (bit c of mask) gets `pre` added to its state before
 // the solve (FUND; the conventional forms add it to the right-hand side) and
-// `post` subtracted from the FUND output.  pre_dev (device, 3 doubles),
-// if set, supplies the pre values instead.
+// `post` subtracted from the FUND output.  pre_dev / post_dev (device, 3
+// doubles each), if set, supply the pre / post values instead (captured
+// graphs, adjoint seeds).
 struct Inject {
     int i = 0, j = 0, k = 0;
     unsigned mask = 0;
     double pre[3] = {0, 0, 0}, post[3] = {0, 0, 0};
     const double* pre_dev = nullptr;
+    const double* post_dev = nullptr;
 };
 
 // The physical source of a sub-step with source term g (fdtd_source).
@@ -119,6 +121,7 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
         a.src_pre = S(inj->pre[pd.ce]);
         a.src_post = S(inj->post[pd.ce]);
         a.src_pre_dev = inj->pre_dev ? inj->pre_dev + pd.ce : nullptr;
+        a.src_post_dev = inj->post_dev ? inj->post_dev + pd.ce : nullptr;
     }
     const int ne = axis_cells(d, pd.e), nt = axis_cells(d, pd.t);
     const KCfg& cf = p->cfg[pd.w];

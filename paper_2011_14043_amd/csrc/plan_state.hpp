@@ -139,6 +139,22 @@ struct fdtd_plan_s {
     double fam_ms[2] = {0, 0};
     int fam_n[2] = {0, 0};
     fdtd::Batch* batch = nullptr;   // batch plan: the grids and their tables
+    // Single-grid runs: main-iteration steps captured as a HIP graph of
+    // graph_steps steps (0: no graphs), replayed on the plan's stream.  The
+    // source values of every sub-step of a run are computed on the host into
+    // the pinned table src_host, copied once to src_dev, and each replay
+    // first copies its window of src_dev into src_win, which the captured
+    // passes read.
+    int graph_steps = 8;
+    hipStream_t gstream = nullptr;        // private capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    long long gkey[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // what the captured graph depends on
+    double* src_dev = nullptr;            // [steps][sub-steps][pre xyz, post xyz]
+    double* src_win = nullptr;            // one graph's window of src_dev
+    double* src_host = nullptr;           // pinned staging of src_dev
+    size_t src_cap = 0;                   // doubles in src_dev and src_host
+    hipEvent_t src_copied = nullptr;      // the last staging copy has been read
     unsigned magic = 0xFD7DFD7Du;
 };
 

@@ -43,6 +43,131 @@ static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst, bool fin_fo
     return FDTD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// captured step graphs (single-grid runs)
+// ---------------------------------------------------------------------------
+static void graph_clear(fdtd_plan_s* p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+}
+
+// What a captured graph depends on: steps per graph, the source cell, the
+// kernel configuration of the three line axes.
+static void graph_key(const fdtd_plan_s* p, const fdtd_source* src, long long (&k)[8]) {
+    k[0] = p->graph_steps;
+    k[1] = src ? 1 : 0;
+    k[2] = src ? src->i : -1;
+    k[3] = src ? src->j : -1;
+    k[4] = src ? src->k : -1;
+    for (int a = 0; a < 3; ++a) {
+        const KCfg& c = p->cfg[a];
+        k[5 + a] = (long long)c.M | ((long long)c.TX << 8) | ((long long)c.NT << 16) | ((long long)c.wpb << 32) |
+                   ((long long)c.remap << 40);
+    }
+}
+
+// Source terms of sub-step u of main step n of a run (host, as the eager
+// loop computes them): pre and post of the Ez sample.
+static void source_terms(fdtd_plan_s* p, const fdtd_source* src, int mode, long long nglob, int u, double* pre,
+                         double* post) {
+    const SubStep& ss = kSchemes[p->d.scheme].sub[u];
+    const double theta = ss.theta_frac * p->d.dt;
+    const Inject inj = source_inject(p, src, source_value(src, theta, (double(nglob) + ss.t_frac) * p->d.dt), mode);
+    *pre = inj.pre[2];
+    *post = inj.post[2];
+}
+
+// Capture graph_steps main-iteration steps (all sub-steps, state set 0 in,
+// set 0 out) on the plan's private stream; with a source, the passes read
+// their pre/post values from src_win.
+template <typename T, typename S>
+static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mode) {
+    graph_clear(p);
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    const int K = p->graph_steps;
+    if (!p->gstream) HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    if (src && !p->src_win) HIPCHK(hipMalloc(&p->src_win, sizeof(double) * 6 * 3 * 64));
+    if ((size_t)K * sd.nsub * 6 > 6 * 3 * 64) return FDTD_EINVAL;
+    hipStream_t user = p->stream;
+    p->stream = p->gstream;
+    fdtd_status st = FDTD_OK;
+    if (hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) st = FDTD_EDEVICE;
+    int cur = 0;
+    for (int q = 0; q < K && st == FDTD_OK; ++q) {
+        for (int u = 0; u < sd.nsub && st == FDTD_OK; ++u) {
+            const SubStep& ss = sd.sub[u];
+            Inject inj;
+            if (src) {
+                inj.i = src->i; inj.j = src->j; inj.k = src->k;
+                inj.mask = 4u;   // Ez
+                inj.pre_dev = p->src_win + (size_t)(q * sd.nsub + u) * 6;
+                inj.post_dev = inj.pre_dev + 3;
+            }
+            st = substep<T, S>(p, ss.op, ss.theta_frac * p->d.dt, mode, cur, src ? &inj : nullptr, false);
+        }
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    p->stream = user;
+    if (st != FDTD_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != FDTD_OK ? st : from_hip(e);
+    }
+    p->graph = g;
+    HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    graph_key(p, src, p->gkey);
+    return FDTD_OK;
+}
+
+// Main steps [0, ngraph * graph_steps) of a run as graph replays.
+template <typename T, typename S>
+static fdtd_status run_graphs(fdtd_plan_s* p, const fdtd_source* src, int mode, int ngraph) {
+    const SchemeDef& sd = kSchemes[p->d.scheme];
+    const int K = p->graph_steps;
+    const size_t per_graph = (size_t)K * sd.nsub * 6;
+    if (src) {
+        // the source terms of the covered steps, once per run
+        const size_t need = (size_t)ngraph * per_graph;
+        if (need > p->src_cap) {
+            if (p->src_copied) HIPCHK(hipEventSynchronize(p->src_copied));
+            if (p->src_dev) HIPCHK(hipFree(p->src_dev));
+            if (p->src_host) HIPCHK(hipHostFree(p->src_host));
+            p->src_dev = nullptr;
+            p->src_host = nullptr;
+            p->src_cap = 0;
+            HIPCHK(hipMalloc(&p->src_dev, sizeof(double) * need));
+            HIPCHK(hipHostMalloc(&p->src_host, sizeof(double) * need, hipHostMallocDefault));
+            p->src_cap = need;
+        }
+        if (!p->src_copied) HIPCHK(hipEventCreateWithFlags(&p->src_copied, hipEventDisableTiming));
+        HIPCHK(hipEventSynchronize(p->src_copied));   // the previous run's copy has read the staging
+        double* h = p->src_host;
+        for (int n = 0; n < ngraph * K; ++n)
+            for (int u = 0; u < sd.nsub; ++u) {
+                double* r = h + ((size_t)n * sd.nsub + u) * 6;
+                r[0] = r[1] = r[3] = r[4] = 0.0;
+                source_terms(p, src, mode, p->step + n, u, &r[2], &r[5]);
+            }
+        HIPCHK(hipMemcpyAsync(p->src_dev, h, sizeof(double) * need, hipMemcpyHostToDevice, p->stream));
+        HIPCHK(hipEventRecord(p->src_copied, p->stream));
+    }
+    long long key[8];
+    graph_key(p, src, key);
+    if (!p->gexec || std::memcmp(key, p->gkey, sizeof(key)) != 0) {
+        fdtd_status st = graph_capture<T, S>(p, src, mode);
+        if (st != FDTD_OK) return st;
+    }
+    for (int m = 0; m < ngraph; ++m) {
+        if (src)
+            HIPCHK(hipMemcpyAsync(p->src_win, p->src_dev + (size_t)m * per_graph, sizeof(double) * per_graph,
+                                  hipMemcpyDeviceToDevice, p->stream));
+        HIPCHK(hipGraphLaunch(p->gexec, p->stream));
+    }
+    return FDTD_OK;
+}
+
 template <typename T, typename S>
 static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], int nsteps, const fdtd_source* src,
                             double* energy, int every) {
@@ -100,7 +225,15 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // the caller.  The other schemes' state is u after their last sub-step.
     const bool fin_adi = adi && !conv;
     Fin fin{0.0};
-    for (int n = 0; n < nsteps; ++n) {
+    // Steps before the last one run as replays of a captured graph of
+    // graph_steps steps (no energy trace or per-launch timing), the rest
+    // directly.
+    const int ngraph = (p->graph_steps > 0 && !energy && tm.per_launch == 0) ? (nsteps - 1) / p->graph_steps : 0;
+    if (ngraph > 0) {
+        fdtd_status st = run_graphs<T, S>(p, src, mode, ngraph);
+        if (st != FDTD_OK) return st;
+    }
+    for (int n = ngraph * p->graph_steps; n < nsteps; ++n) {
         const long long nglob = p->step + n;
         for (int u = 0; u < sd.nsub; ++u) {
             const SubStep& ss = sd.sub[u];
