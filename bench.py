@@ -103,7 +103,7 @@ TIMING_EVERY = 8
 
 
 # precision keys: f32 = FP32 fields and solves as the library chooses (refined
-# below sigma = 2, i.e. at CFL 5 and 10), f32r = refined, f32p = plain FP32
+# wherever refined passes are built), f32r = refined, f32p = plain FP32
 # solves, f32s64 = FP32 fields with FP64 solves, f64
 REFINE = {"f32r": True, "f32p": False}
 
@@ -221,7 +221,7 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     return out
 
 
-def run_batch(steps, warmup, prec="f32"):
+def run_batch(steps, warmup, prec="f32", singles=True):
     """64 independent PEC cavities, sizes U[16, 96] per axis (seed 4), random-box
     eps_r and N(0,1) fields per cavity, fundamental ADI, CFL 5: one launch per
     line pass over the cavities of a group (groups that fit the MALL), captured
@@ -244,7 +244,8 @@ def run_batch(steps, warmup, prec="f32"):
         grids.append((nx, ny, nz, torch.from_numpy(eps)))
         fields.append(([torch.tensor(a, dtype=dtype, device=dev) for a in u0[:3]],
                        [torch.tensor(a, dtype=dtype, device=dev) for a in u0[3:]]))
-    plan = BatchPlan(grids, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve)
+    plan = BatchPlan(grids, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve, refine=REFINE.get(prec))
+    refined = plan.refined
     plan.autotune(3)
     cfg = [plan.kernel_config(ax) for ax in range(3)]
     plan.run(fields, warmup)
@@ -259,29 +260,32 @@ def run_batch(steps, warmup, prec="f32"):
     cells = int(sum(np.prod(sz) for sz in sizes))
     ms = (t1 - t0) * 1e3 / steps
     main_ms = tm["main_ms"] / steps
-    # the same cavities one after the other, each its own (autotuned) single-grid plan
-    from paper_2011_14043_amd import Plan
-    singles = []
-    for (nx, ny, nz, eps) in grids:
-        sp = Plan(nx, ny, nz, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve, eps_r=eps)
-        sp.autotune(1)
-        singles.append(sp)
-    for sp, (E, H) in zip(singles, fields):
-        sp.run(E, H, warmup)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for sp, (E, H) in zip(singles, fields):
-        sp.run(E, H, steps)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for sp in singles:
-        sp.close()
-    seq_ms = (t3 - t2) * 1e3 / steps
-    out = dict(workload="64 cavities U[16,96]^3, fundamental ADI, CFL 5", prec=prec, cells=cells, steps=steps,
-               ms_per_step=ms, mcells_per_s=cells / (ms * 1e-3) / 1e6, main_ms_per_step=main_ms,
-               sequential_single_ms_per_step=seq_ms, sequential_single_mcells_per_s=cells / (seq_ms * 1e-3) / 1e6,
+    out = dict(workload="64 cavities U[16,96]^3, fundamental ADI, CFL 5", prec=prec, refined=refined, cells=cells,
+               steps=steps, ms_per_step=ms, mcells_per_s=cells / (ms * 1e-3) / 1e6, main_ms_per_step=main_ms,
                hbm_frac_alg=6 * cells * bytes_per_slot(prec) / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                kernel_config=cfg, finite=finite)
+    if singles:
+        # the same cavities one after the other, each its own (autotuned) single-grid plan
+        from paper_2011_14043_amd import Plan
+        plans = []
+        for (nx, ny, nz, eps) in grids:
+            sp = Plan(nx, ny, nz, dt, h, h, h, scheme="adi", dtype=dtype, solve_dtype=solve, eps_r=eps,
+                      refine=REFINE.get(prec))
+            sp.autotune(1)
+            plans.append(sp)
+        for sp, (E, H) in zip(plans, fields):
+            sp.run(E, H, warmup)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for sp, (E, H) in zip(plans, fields):
+            sp.run(E, H, steps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for sp in plans:
+            sp.close()
+        seq_ms = (t3 - t2) * 1e3 / steps
+        out["sequential_single_ms_per_step"] = seq_ms
+        out["sequential_single_mcells_per_s"] = cells / (seq_ms * 1e-3) / 1e6
     log(json.dumps(out))
     return out
 
@@ -548,7 +552,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": nel * 4, "copies": 5}), flush=True)
         return
     if args.only == "batch":
-        print(json.dumps(run_batch(args.batch_steps, 5)), flush=True)
+        print(json.dumps([run_batch(args.batch_steps, 5),
+                          run_batch(args.batch_steps, 5, prec="f32p", singles=False)]), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(run_adjoint()), flush=True)
@@ -584,7 +589,7 @@ def main():
     if not args.no_extras:
         # the other CFL numbers of the 512^3 workload: the passes have no
         # data-dependent control flow, so the step time moves only where
-        # FDTD_F32 refines (CFL 5 and 10) or not (CFL 1)
+        # FDTD_F32 (refined) and plain FP32 solves at both ends of the CFL range
         import workloads as W
         h0, _, eps0, ci0 = inputs
         cfl_rows = []
@@ -597,6 +602,7 @@ def main():
         extras["adi_fundamental_512cube_cfl_1_and_10"] = cfl_rows
         refs.close()
         extras["batch_64_cavities"] = run_batch(args.batch_steps, 5)
+        extras["batch_64_cavities_plain_f32"] = run_batch(args.batch_steps, 5, prec="f32p", singles=False)
         extras["adjoint_gradient"] = run_adjoint()
         extras["graphs_128x128x64"] = run_graphs()
         extras["crank_nicolson_256cube"] = run_cn()

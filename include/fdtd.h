@@ -97,17 +97,17 @@ typedef enum { FDTD_FUNDAMENTAL = 0, FDTD_CONVENTIONAL = 1 } fdtd_form;
  * sigma, and a second solve with the same factors, all in FP32), which
  * removes the fixed rounding bias of the FP32 factors and of 2 + sigma;
  * fundamental forms only (else FDTD_EUNSUPPORTED), nx, ny, nz <= 512.
- * FDTD_F32 (FP32 fields and arithmetic) chooses between the two: the line
- * systems are -V[j-1] + (2 + sigma) V[j] - V[j+1] = r with
- * sigma = eps mu dw^2 / theta^2 (Sec. III-A multiplied by 2 sigma), and FP32
- * spaces numbers near 2 by 2.4e-7, so a sigma well below 1 (large time
- * steps) is perturbed by the same relative amount at every step and the
- * phase error grows linearly with the step count (3e-4 after 1000 steps at
- * sigma = 0.12).  FDTD_F32 therefore refines when the plan's smallest sigma
- * (smallest eps_r and cell size, theta = dt/2) is below 2 -- a CFL number
- * above about 2.4 in vacuum on cubic cells -- wherever refinement is built
- * (fundamental forms, nx, ny, nz <= 512); else it runs as FDTD_F32_PLAIN.
- * fdtd_get_refined tells which. */
+ * FDTD_F32 (FP32 fields and arithmetic) refines wherever refined passes are
+ * built (fundamental forms, nx, ny, nz <= 512, no permeability map) and runs
+ * as FDTD_F32_PLAIN elsewhere: the line systems are
+ * -V[j-1] + (2 + sigma) V[j] - V[j+1] = r with sigma = eps mu dw^2 / theta^2
+ * (Sec. III-A multiplied by 2 sigma), and plain FP32 solves round both 2 +
+ * sigma (FP32 spaces numbers near 2 by 2.4e-7: a relative perturbation of
+ * the medium of up to 1.2e-7 / sigma) and the medium-only factors the same
+ * way at every step, so their error grows linearly with the step count
+ * (after 1000 steps: 3e-4 at sigma = 0.12, 4e-5 to 6e-5 at sigma >= 0.48 and
+ * at sigma = 12); refined solves stay near 1e-5, for 1 % to 3 % of the step
+ * time.  fdtd_get_refined tells which. */
 typedef enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_F32_F64SOLVE = 2, FDTD_F32_REFINE = 3,
                FDTD_F32_PLAIN = 4 } fdtd_dtype;
 
@@ -124,8 +124,13 @@ typedef struct {
                                /* x fastest, > 0; host or device pointer, copied by       */
                                /* fdtd_plan (may be freed afterwards).  NULL means 1.     */
                                /* The E sample stored at [k][j][i] uses cell [k][j][i].   */
-    const float* mu_r;         /* relative permeability per cell; only NULL (== 1) is     */
-                               /* implemented (else FDTD_EUNSUPPORTED)                    */
+    const float* mu_r;         /* relative permeability per cell (eq. (bd): d = dt/(2 mu)),*/
+                               /* layout, ownership and checks as eps_r; NULL means 1.    */
+                               /* The H sample stored at [k][j][i] uses cell [k][j][i].   */
+                               /* A map that is not all ones: line passes with per-row    */
+                               /* off-diagonals (each axis <= 512, no FDTD_F32_REFINE,    */
+                               /* not for FDTD_CRANK_NICOLSON or fdtd_plan_batch:         */
+                               /* FDTD_EUNSUPPORTED); FDTD_F32 then solves plainly.       */
     int boundary;              /* 0 = PEC on all faces (the only value)                   */
 } fdtd_desc;
 
@@ -264,7 +269,7 @@ fdtd_status fdtd_grad_eps(fdtd_plan_t p, void* const E[3], void* const H[3], int
  * FDTD_EINVAL for a batch plan):
  *   out[0] = sum eps |Ea - Eb|^2 + mu |Ha - Hb|^2,  out[1] = sum eps |Eb|^2 + mu |Hb|^2
  * over the samples inside each component's extent, eps = eps0 eps_r of the
- * sample's owning cell (as in the energy trace), mu = mu0; so
+ * sample's owning cell (as in the energy trace), mu = mu0 mu_r likewise; so
  * sqrt(out[0] / out[1]) is the energy-weighted relative L2 distance of Ea, Ha
  * from Eb, Hb.  Ea, Ha, Eb, Hb: device arrays in the caller's field layout and
  * the plan's element type (read only); out: host array of 2.  Two-stage

@@ -80,13 +80,15 @@ class Plan:
     """One simulation plan (fdtd_plan).  Not thread-safe."""
 
     def __init__(self, nx, ny, nz, dt, dx, dy, dz, scheme="adi", form="fundamental",
-                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None, refine=None):
+                 dtype=None, eps_r=None, stream=None, device=None, solve_dtype=None, refine=None, mu_r=None):
         """dtype: field storage (float32/float64); solve_dtype: arithmetic of the
         line solves (defaults to dtype; float64 with float32 fields selects
         FDTD_F32_F64SOLVE); refine (float32 fields and solves): None lets the
-        library refine the FP32 solves where the time step needs it (FDTD_F32),
+        library choose (FDTD_F32: refined wherever refined passes are built),
         True always refines them once (FDTD_F32_REFINE, fundamental forms),
-        False never (FDTD_F32_PLAIN).  `refined` tells what the plan does."""
+        False never (FDTD_F32_PLAIN).  `refined` tells what the plan does.
+        eps_r, mu_r: relative permittivity and permeability per cell,
+        (nz, ny, nx); None means 1."""
         import torch
         L = _lib.lib()
         self.dtype = dtype if dtype is not None else torch.float32
@@ -94,19 +96,20 @@ class Plan:
         code = _dtype_code(self.dtype, solve, refine)
         self.shape = (nz + 1, ny + 1, nx + 1)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        eps_ptr = None
-        self._eps_keep = None
-        if eps_r is not None:
-            e = eps_r
-            if not isinstance(e, torch.Tensor):
-                e = torch.as_tensor(e)
-            e = e.to(dtype=torch.float32).contiguous()
-            if tuple(e.shape) != (nz, ny, nx):
-                raise ValueError("eps_r must have shape (nz, ny, nx)")
-            self._eps_keep = e
-            eps_ptr = e.data_ptr()
+        keep = []
+
+        def cell_map(m, name):
+            if m is None:
+                return None
+            t = m if isinstance(m, torch.Tensor) else torch.as_tensor(m)
+            t = t.to(dtype=torch.float32).contiguous()
+            if tuple(t.shape) != (nz, ny, nx):
+                raise ValueError(f"{name} must have shape (nz, ny, nx)")
+            keep.append(t)
+            return t.data_ptr()
+
         desc = _lib.FdtdDesc(nx, ny, nz, dt, dx, dy, dz, _lib.SCHEMES[scheme], _lib.FORMS[form],
-                             code, eps_ptr, None, 0)
+                             code, cell_map(eps_r, "eps_r"), cell_map(mu_r, "mu_r"), 0)
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.stream = s
@@ -114,7 +117,7 @@ class Plan:
             _lib.check(L.fdtd_plan(ctypes.byref(desc), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)),
                        "fdtd_plan")
         self._h = h
-        self._eps_keep = None
+        del keep
         self.scheme, self.form = scheme, form
         self.refined = self._refined()
 

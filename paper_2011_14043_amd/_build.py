@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "fdtd.hip")
 KERN_SRC = os.path.join(HERE, "csrc", "kern_inst.hip")
-KERN_PARTS = 14   # kern_inst.hip: FDTD_PART = 0 .. 13
+KERN_PARTS = 17   # kern_inst.hip: FDTD_PART = 0 .. 16
 LIB = os.path.join(HERE, "libfdtd.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 

@@ -16,6 +16,7 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     if (p->refine && (axis == 0 ? c.M != 8 : c.M > 16)) return false;   // refined solves built
     if (axis == 0) {
         if (c.M != 8 && c.M != 16) return false;
+        if (p->mu && c.M != 8) return false;
         if (c.wpb < 1 || c.wpb > 4) return false;
         return next_pow2((n + c.M - 1) / c.M) <= 64;
     }
@@ -24,7 +25,13 @@ static bool cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c) {
     if (p->d.dtype == FDTD_F64 && p->d.scheme == FDTD_ADI && p->d.form == FDTD_CONVENTIONAL && c.NT == 1024)
         return false;
     bool inst = false;
-    if (p->d.dtype == FDTD_F32) {
+    if (p->mu) {
+        if (p->d.dtype == FDTD_F32) {
+            for (const auto& v : kYzMuF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
+        } else {
+            for (const auto& v : kYzMuF64) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
+        }
+    } else if (p->d.dtype == FDTD_F32) {
         for (const auto& v : kYzF32) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
     } else {
         for (const auto& v : kYzF64) inst = inst || (v[0] == c.M && v[1] == c.TX && v[2] == c.NT);
@@ -46,6 +53,16 @@ static std::vector<KCfg> cfg_candidates(const fdtd_plan_s* p, int axis) {
                     KCfg c{M, 0, 0, wpb, remap};
                     if (cfg_valid(p, axis, c)) out.push_back(c);
                 }
+        } else if (p->mu && p->d.dtype == FDTD_F32) {
+            for (const auto& v : kYzMuF32) {
+                KCfg c{v[0], v[1], v[2], 0, remap};
+                if (cfg_valid(p, axis, c)) out.push_back(c);
+            }
+        } else if (p->mu) {
+            for (const auto& v : kYzMuF64) {
+                KCfg c{v[0], v[1], v[2], 0, remap};
+                if (cfg_valid(p, axis, c)) out.push_back(c);
+            }
         } else if (p->d.dtype == FDTD_F32) {
             for (const auto& v : kYzF32) {
                 KCfg c{v[0], v[1], v[2], 0, remap};
@@ -67,6 +84,8 @@ static void default_cfg(fdtd_plan_s* p) {
         std::vector<KCfg> pref;
         if (axis == 0) {
             pref = {{8, 0, 0, 4, 1}, {16, 0, 0, 4, 1}};
+        } else if (p->mu) {
+            pref = {{16, 16, 512, 0, 1}, {8, 16, 512, 0, 1}, {8, 8, 512, 0, 1}};
         } else if (p->d.dtype == FDTD_F32) {
             pref = {{16, 16, 512, 0, 1}, {16, 32, 1024, 0, 1}, {32, 16, 512, 0, 1}, {8, 16, 1024, 0, 1},
                     {8, 32, 512, 0, 1}};
@@ -127,8 +146,8 @@ static fdtd_status autotune_impl(fdtd_plan_s* p, int reps, double* best_ms) {
 //   {"key": "<nx>,<ny>,<nz>,<dtype>,<scheme>,<form>,<refine>", "cfg": [[M,TX,NT,wpb,remap],[...],[...]]}
 static std::string tune_key(const fdtd_plan_s* p) {
     char b[160];
-    std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d,%d", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme, p->d.form,
-                  p->refine);
+    std::snprintf(b, sizeof(b), "%d,%d,%d,%d,%d,%d,%d%s", p->d.nx, p->d.ny, p->d.nz, p->d.dtype, p->d.scheme,
+                  p->d.form, p->refine, p->mu ? ",mu" : "");
     return b;
 }
 

@@ -69,16 +69,17 @@ struct AuxCoef {
 };
 
 // (B u)_c at a node, operator B of eq. (AMat) with Yee central differences.
-// inv_eps = 1/(eps0 eps_r) at the node.
+// inv_eps = 1/(eps0 eps_r), inv_mu = 1/(mu0 mu_r) at the node.
 template <typename T, typename F>
-__device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, double inv_eps, const AuxCoef& q) {
+__device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, double inv_eps, double inv_mu,
+                                          const AuxCoef& q) {
     switch (c) {
         case 0: return -inv_eps * (double(get(4, i, j, k)) - double(get(4, i, j, k - 1))) * q.rdz;   // -dHy/dz
         case 1: return -inv_eps * (double(get(5, i, j, k)) - double(get(5, i - 1, j, k))) * q.rdx;   // -dHz/dx
         case 2: return -inv_eps * (double(get(3, i, j, k)) - double(get(3, i, j - 1, k))) * q.rdy;   // -dHx/dy
-        case 3: return -q.rmu0 * (double(get(2, i, j + 1, k)) - double(get(2, i, j, k))) * q.rdy;    // -dEz/dy
-        case 4: return -q.rmu0 * (double(get(0, i, j, k + 1)) - double(get(0, i, j, k))) * q.rdz;    // -dEx/dz
-        default: return -q.rmu0 * (double(get(1, i + 1, j, k)) - double(get(1, i, j, k))) * q.rdx;   // -dEy/dx
+        case 3: return -inv_mu * (double(get(2, i, j + 1, k)) - double(get(2, i, j, k))) * q.rdy;    // -dEz/dy
+        case 4: return -inv_mu * (double(get(0, i, j, k + 1)) - double(get(0, i, j, k))) * q.rdz;    // -dEx/dz
+        default: return -inv_mu * (double(get(1, i + 1, j, k)) - double(get(1, i, j, k))) * q.rdx;   // -dEy/dx
     }
 }
 
@@ -98,10 +99,10 @@ inline dim3 row_grid(const Dims& d) { return dim3((unsigned)((d.ny + 1) * (d.nz 
 // stored value already has).  Each dynamic E takes the difference of its
 // partner H across its own position, each dynamic H that of its partner E
 // (B of eq. (AMat)); E off its dynamic set is 0, also where it enters a
-// difference.
+// difference.  mu: mu_r in the state layout, or NULL (mu = mu0).
 template <typename T, typename A = double>
 __global__ void __launch_bounds__(kRowThreads) load_state_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps,
-                                                                 Dims d, AuxCoef k_) {
+                                                                 const float* mu, Dims d, AuxCoef k_) {
     const int r = xcd_remap(int(blockIdx.x), int(gridDim.x));
     const int j = r % (d.ny + 1), k = r / (d.ny + 1);
     const long long nx1 = d.nx + 1;
@@ -139,20 +140,21 @@ __global__ void __launch_bounds__(kRowThreads) load_state_kernel(FieldPtrs<T> f,
         v[2] = u[2];
         if (iin && jin && klo) v[2] = fused(-ce, (A(Hx[i]) - A(Hx[i - nx1])) * rdy, half * u[2]);
         // H: U = 1/2 H - (dt/4)/mu d_w E   (dynamic samples; static normal H: 1/2 H)
+        const A cm = mu ? cmu * recip(A(mu[so])) : cmu;
         v[3] = half * u[3];
         if (iin && jlo && klo) {
             const A ez1 = (iin && jin1) ? A(Ez[i + nx1]) : A(0);
-            v[3] = fused(-cmu, (ez1 - u[2]) * rdy, v[3]);
+            v[3] = fused(-cm, (ez1 - u[2]) * rdy, v[3]);
         }
         v[4] = half * u[4];
         if (ilo && jin && klo) {
             const A ex1 = (ilo && jin && kin1) ? A(Ex[i + d.cplane]) : A(0);
-            v[4] = fused(-cmu, (ex1 - u[0]) * rdz, v[4]);
+            v[4] = fused(-cm, (ex1 - u[0]) * rdz, v[4]);
         }
         v[5] = half * u[5];
         if (ilo && jlo && kin) {
             const A ey1 = (iin1 && jlo && kin) ? A(Ey[i + 1]) : A(0);
-            v[5] = fused(-cmu, (ey1 - u[1]) * rdx, v[5]);
+            v[5] = fused(-cm, (ey1 - u[1]) * rdx, v[5]);
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) s.c[c][so] = T(v[c]);
@@ -215,10 +217,11 @@ __global__ void store_state_kernel(FieldPtrs<T> s, FieldPtrs<T> s_old, FieldPtrs
 
 // Energy sum eps |E|^2 + mu |H|^2 over all samples of a state, FP64, first
 // stage: one partial per block (fixed order => deterministic).
-// link != 0 (original ADI): evaluated on (1/2 I + dt/4 B) u.
+// link != 0 (original ADI): evaluated on (1/2 I + dt/4 B) u.  mu: mu_r in
+// the state layout, or NULL.
 template <typename T>
-__global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, const float* eps, Dims d, AuxCoef k_,
-                                                             double* partial) {
+__global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, const float* eps, const float* mu, Dims d,
+                                                             AuxCoef k_, double* partial) {
     __shared__ double red[256];
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     double acc = 0.0;
@@ -228,25 +231,26 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
         const int i = nd.i, j = nd.j, k = nd.k;
         const long long so = (long long)k * d.plane + (long long)j * d.px + i;
         const double ew = k_.eps0 * double(eps[so]);
+        const double mw = mu ? k_.mu0 * double(mu[so]) : k_.mu0;
         if (k_.link == 0.0) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const double u = double(s.c[c][so]);
-                acc += (c < 3 ? ew : k_.mu0) * u * u;
+                acc += (c < 3 ? ew : mw) * u * u;
             }
         } else {
             auto get = [&](int c, int ii, int jj, int kk) -> T {
                 if (ii < 0 || jj < 0 || kk < 0 || ii > d.nx || jj > d.ny || kk > d.nz) return T(0);
                 return s.c[c][(long long)kk * d.plane + (long long)jj * d.px + ii];
             };
-            const double inv_eps = recip(ew);
+            const double inv_eps = recip(ew), inv_mu = recip(mw);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const double u = double(get(c, i, j, k));
                 const bool dyn = is_dynamic(c, i, j, k, d);
-                const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, k_) : 0.0;
+                const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, inv_mu, k_) : 0.0;
                 const double v = (k_.fin_form && c >= 3 && !dyn) ? u : 0.5 * u + k_.link * bu;
-                acc += (c < 3 ? ew : k_.mu0) * v * v;
+                acc += (c < 3 ? ew : mw) * v * v;
             }
         }
     }
@@ -262,11 +266,11 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
 // Weighted squared distance of two field sets in the caller's layout, FP64,
 // first stage: per block, sum eps |E_a - E_b|^2 + mu |H_a - H_b|^2 and
 // sum eps |E_b|^2 + mu |H_b|^2 over the samples inside each component's
-// extent (eps of the sample's owning node), into partial[b] and
-// partial[gridDim.x + b] (fixed order => deterministic).
+// extent (eps and mu of the sample's owning node; mu NULL: mu0), into
+// partial[b] and partial[gridDim.x + b] (fixed order => deterministic).
 template <typename T>
-__global__ void __launch_bounds__(256) diff_partial_kernel(FieldPtrs<T> fa, FieldPtrs<T> fb, const float* eps, Dims d,
-                                                           AuxCoef k_, double* partial) {
+__global__ void __launch_bounds__(256) diff_partial_kernel(FieldPtrs<T> fa, FieldPtrs<T> fb, const float* eps,
+                                                           const float* mu, Dims d, AuxCoef k_, double* partial) {
     __shared__ double red[2][256];
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     double num = 0.0, den = 0.0;
@@ -275,10 +279,11 @@ __global__ void __launch_bounds__(256) diff_partial_kernel(FieldPtrs<T> fa, Fiel
         const Node nd = node_of(unsigned(idx), d);
         const long long so = (long long)nd.k * d.plane + (long long)nd.j * d.px + nd.i;
         const double ew = k_.eps0 * double(eps[so]);
+        const double mw = mu ? k_.mu0 * double(mu[so]) : k_.mu0;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             if (!in_extent(c, nd.i, nd.j, nd.k, d)) continue;
-            const double w = c < 3 ? ew : k_.mu0;
+            const double w = c < 3 ? ew : mw;
             const double vb = double(fb.c[c][idx]);
             const double dv = double(fa.c[c][idx]) - vb;
             num += w * dv * dv;

@@ -339,7 +339,7 @@ static fdtd_status run_batch_impl(fdtd_plan_s* p, void* const* E, void* const* H
         const long long nn = (long long)(dm.nx + 1) * (dm.ny + 1) * (dm.nz + 1);
         const AuxCoef kin = aux_coef(sub->d, adi ? 0.25 * sub->d.dt : 0.0);
         hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
-                           caller(g), state_ptrs_w<T>(sub, 0), sub->eps, dm, kin);
+                           caller(g), state_ptrs_w<T>(sub, 0), sub->eps, sub->mu, dm, kin);
         HIPCHK(hipGetLastError());
     }
     if (d.scheme == FDTD_LOD2) {

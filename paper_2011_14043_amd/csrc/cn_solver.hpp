@@ -112,7 +112,7 @@ static fdtd_status cn_run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3
         p->energy_cap = nrec;
     }
     hipLaunchKernelGGL((load_state_kernel<double>), row_grid(p->dims), dim3(kRowThreads), 0, p->stream, caller,
-                       state_ptrs_w<double>(p, 0), p->eps, dm, aux_coef(p->d, 0.0));
+                       state_ptrs_w<double>(p, 0), p->eps, p->mu, dm, aux_coef(p->d, 0.0));
     HIPCHK(hipGetLastError());
     Timing& tm = p->tm;
     tm.used = 0;

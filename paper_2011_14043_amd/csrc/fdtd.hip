@@ -95,7 +95,7 @@ static fdtd_status diff_norm_impl(fdtd_plan_s* p, void* const Ea[3], void* const
             fb.c[c] = static_cast<const T*>(Eb[c]);
             fb.c[3 + c] = static_cast<const T*>(Hb[c]);
         }
-        hipLaunchKernelGGL((diff_partial_kernel<T>), dim3(nb), dim3(256), 0, p->stream, fa, fb, p->eps, p->dims, k,
+        hipLaunchKernelGGL((diff_partial_kernel<T>), dim3(nb), dim3(256), 0, p->stream, fa, fb, p->eps, p->mu, p->dims, k,
                            work);
         HIPCHK(hipGetLastError());
         return FDTD_OK;
@@ -147,29 +147,39 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
         d = &as_adi;
     }
     if (d->boundary != 0) return FDTD_EUNSUPPORTED;
-    if (d->mu_r != nullptr) return FDTD_EUNSUPPORTED;
     if (d->dtype == FDTD_F32_REFINE && d->form != FDTD_FUNDAMENTAL) return FDTD_EUNSUPPORTED;
     const int nmax = std::max(d->nx, std::max(d->ny, d->nz));
     // register budget (refined solves: 8-slot chunks on at most 64 lanes)
     const bool f32_any = d->dtype == FDTD_F32 || d->dtype == FDTD_F32_PLAIN;
     if (nmax > (f32_any ? 1024 : 512)) return FDTD_EUNSUPPORTED;
     const long long ncells = (long long)d->nx * d->ny * d->nz;
-    std::vector<float> eps_host;
-    float eps_min = 1.0f;
-    if (d->eps_r) {
-        eps_host.resize(ncells);
-        if (hipMemcpy(eps_host.data(), d->eps_r, sizeof(float) * ncells, hipMemcpyDefault) != hipSuccess)
-            return FDTD_EINVAL;
+    // eps_r, mu_r per cell (host or device pointers), each > 0 and finite
+    auto read_map = [&](const float* src, std::vector<float>& dst) -> bool {
+        dst.resize(ncells);
+        if (hipMemcpy(dst.data(), src, sizeof(float) * ncells, hipMemcpyDefault) != hipSuccess) return false;
         for (long long c = 0; c < ncells; ++c)
-            if (!(eps_host[c] > 0.0f) || !std::isfinite(eps_host[c])) return FDTD_EINVAL;
-        eps_min = *std::min_element(eps_host.begin(), eps_host.end());
+            if (!(dst[c] > 0.0f) || !std::isfinite(dst[c])) return false;
+        return true;
+    };
+    std::vector<float> eps_host, mu_host;
+    if (d->eps_r && !read_map(d->eps_r, eps_host)) return FDTD_EINVAL;
+    if (d->mu_r) {
+        if (!read_map(d->mu_r, mu_host)) return FDTD_EINVAL;
+        // a map of ones is unit permeability: the plan runs the mu = mu0 passes
+        if (std::all_of(mu_host.begin(), mu_host.end(), [](float v) { return v == 1.0f; })) mu_host.clear();
     }
+    const bool has_mu = !mu_host.empty();
+    // Variable permeability: line passes with per-row off-diagonals (8-slot
+    // chunks, at most 512 cells per axis, no refinement); Crank-Nicolson plans
+    // take unit permeability.
+    if (has_mu && (cn || d->dtype == FDTD_F32_REFINE || nmax > 512)) return FDTD_EUNSUPPORTED;
     fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
     if (!p) return FDTD_ENOMEM;
     p->d = *d;
     p->d.eps_r = nullptr;
+    p->d.mu_r = nullptr;
     p->req_dtype = d->dtype;
-    if (d->dtype == FDTD_F32_REFINE || (d->dtype == FDTD_F32 && !cn && f32_refine_wanted(*d, eps_min))) {
+    if (d->dtype == FDTD_F32_REFINE || (d->dtype == FDTD_F32 && !cn && f32_refine_wanted(*d, has_mu))) {
         p->refine = 1;
         p->d.dtype = FDTD_F32;   // FP32 storage and arithmetic; only the fundamental passes differ
     } else if (d->dtype == FDTD_F32_PLAIN) {
@@ -191,6 +201,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
         if (p->state) (void)hipFree(p->state);
         if (p->snap) (void)hipFree(p->snap);
         if (p->eps) (void)hipFree(p->eps);
+        if (p->mu) (void)hipFree(p->mu);
         if (p->partial) (void)hipFree(p->partial);
         if (p->mat) (void)hipFree(p->mat);
         if (p->mat_eps) (void)hipFree(p->mat_eps);
@@ -204,22 +215,34 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     hipError_t e;
     if ((e = hipMalloc(&p->state, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
     if ((e = hipMemset(p->state, 0, p->esz * dm.comp * 6 * sets)) != hipSuccess) return fail(from_hip(e));
-    // eps_r at node indices (owned index, clamped to the last cell), padded rows
-    std::vector<float> en((size_t)dm.comp, 1.0f);
-    for (int k = 0; k <= d->nz; ++k)
-        for (int j = 0; j <= d->ny; ++j)
-            for (int i = 0; i <= d->nx; ++i) {
-                const int kk = std::min(k, d->nz - 1), jj = std::min(j, d->ny - 1), ii = std::min(i, d->nx - 1);
-                en[(size_t)k * dm.plane + (size_t)j * dm.px + i] =
-                    eps_host.empty() ? 1.0f : eps_host[((size_t)kk * d->ny + jj) * d->nx + ii];
-            }
+    // eps_r (and mu_r) at node indices (owned index, clamped to the last
+    // cell), padded rows
+    auto node_map = [&](const std::vector<float>& cells) {
+        std::vector<float> nm((size_t)dm.comp, 1.0f);
+        for (int k = 0; k <= d->nz; ++k)
+            for (int j = 0; j <= d->ny; ++j)
+                for (int i = 0; i <= d->nx; ++i) {
+                    const int kk = std::min(k, d->nz - 1), jj = std::min(j, d->ny - 1), ii = std::min(i, d->nx - 1);
+                    nm[(size_t)k * dm.plane + (size_t)j * dm.px + i] =
+                        cells.empty() ? 1.0f : cells[((size_t)kk * d->ny + jj) * d->nx + ii];
+                }
+        return nm;
+    };
+    const std::vector<float> en = node_map(eps_host);
     if ((e = hipMalloc(&p->eps, sizeof(float) * dm.comp)) != hipSuccess) return fail(from_hip(e));
     if ((e = hipMemcpy(p->eps, en.data(), sizeof(float) * dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(from_hip(e));
+    if (has_mu) {
+        const std::vector<float> mn = node_map(mu_host);
+        if ((e = hipMalloc(&p->mu, sizeof(float) * dm.comp)) != hipSuccess) return fail(from_hip(e));
+        if ((e = hipMemcpy(p->mu, mn.data(), sizeof(float) * dm.comp, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(from_hip(e));
+    }
     // Piecewise-constant media: at most 256 distinct eps_r values are stored as
     // a one-byte material index per node (the passes then read 17 instead of
-    // 20 bytes per FP32 slot); the table of values lives in LDS.
-    if (!std::getenv("FDTD_NO_MATERIAL_INDEX")) {
+    // 20 bytes per FP32 slot); the table of values lives in LDS.  Plans with a
+    // permeability map read both maps instead.
+    if (!has_mu && !std::getenv("FDTD_NO_MATERIAL_INDEX")) {
         // distinct values, sorted; the scan stops at the 257th
         std::vector<float> uniq{1.0f};
         float last = 1.0f;
@@ -498,6 +521,9 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
         st = fdtd_plan(&d[g], hip_stream, &sub);
         if (st == FDTD_OK) subs.push_back(sub);
     }
+    // batched passes take unit permeability
+    for (const fdtd_plan_s* sub : subs)
+        if (sub->mu) st = FDTD_EUNSUPPORTED;
     if (st != FDTD_OK) {
         for (fdtd_plan_s* sub : subs) (void)fdtd_destroy(sub);
         return st;
@@ -657,6 +683,10 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     }
     graph_clear(p);
     if (p->gstream) (void)hipStreamDestroy(p->gstream);
+    for (hipStream_t f : p->gfork)
+        if (f) (void)hipStreamDestroy(f);
+    for (hipEvent_t e : p->gev)
+        if (e) (void)hipEventDestroy(e);
     if (p->src_copied) (void)hipEventDestroy(p->src_copied);
     if (p->src_dev) (void)hipFree(p->src_dev);
     if (p->src_win) (void)hipFree(p->src_win);
@@ -664,6 +694,7 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->state) (void)hipFree(p->state);
     if (p->snap) (void)hipFree(p->snap);
     if (p->eps) (void)hipFree(p->eps);
+    if (p->mu) (void)hipFree(p->mu);
     if (p->partial) (void)hipFree(p->partial);
     if (p->energy_dev) (void)hipFree(p->energy_dev);
     if (p->mat) (void)hipFree(p->mat);

@@ -15,6 +15,10 @@ namespace fdtd {
     template int dispatch_x_m<T, S, MODE>(int, bool, bool, bool, dim3, dim3, hipStream_t, const PassArgs<T, S>&); \
     template int dispatch_yz_m<T, S, MODE>(int, int, int, bool, bool, bool, dim3, dim3, size_t, hipStream_t,    \
                                            const PassArgs<T, S>&);
+#define FDTD_MU(T, S, MODE)                                                                                   \
+    template int dispatch_x_mu_m<T, S, MODE>(int, bool, bool, dim3, dim3, hipStream_t, const PassArgs<T, S>&); \
+    template int dispatch_yz_mu_m<T, S, MODE>(int, int, int, bool, bool, dim3, dim3, size_t, hipStream_t,      \
+                                              const PassArgs<T, S>&);
 #define FDTD_BATCH(T, S, MODE)                                                                                 \
     template int dispatch_batch_m<T, S, MODE>(int, int, int, int, bool, dim3, dim3, size_t, hipStream_t,     \
                                               const PassArgs<T, S>*, const int2*, int);
@@ -47,6 +51,18 @@ FDTD_BATCH(float, float, FUND_REF)
 FDTD_BATCH(double, double, FUND)
 #elif FDTD_PART == 13
 FDTD_BATCH(float, double, FUND)
+#elif FDTD_PART == 14
+FDTD_MU(float, float, FUND)
+FDTD_MU(float, float, CONV_LOD)
+FDTD_MU(float, float, CONV_ADI)
+#elif FDTD_PART == 15
+FDTD_MU(double, double, FUND)
+FDTD_MU(double, double, CONV_LOD)
+FDTD_MU(double, double, CONV_ADI)
+#elif FDTD_PART == 16
+FDTD_MU(float, double, FUND)
+FDTD_MU(float, double, CONV_LOD)
+FDTD_MU(float, double, CONV_ADI)
 #else
 #error "FDTD_PART out of range"
 #endif

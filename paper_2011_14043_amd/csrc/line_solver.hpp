@@ -167,6 +167,97 @@ __device__ __forceinline__ void chunk_finish(const Chunk<T, M>& c, T Sp, T S, T 
 }
 
 // ---------------------------------------------------------------------------
+// Variable permeability.  With mu varying along the line the scaled system is
+//     -m[j-1] V[j-1] + (sigma[j] + m[j-1] + m[j]) V[j] - m[j] V[j+1] = r[j],
+// m[j] = mu0 / mu at the H sample j + 1/2 (stored at slot j): symmetric,
+// strictly diagonally dominant, off-diagonals that differ from row to row.
+// A chunk's interior system T (rows 0..M-2) has lower off-diagonals
+// m[i-1] (m[-1] = mp, the H sample before the chunk) and upper ones m[i]:
+//     x_i = y_i + ah_i (mp S_{l-1}) + gh_i (m[M-2] S_l),
+// y = T^-1 r, ah = T^-1 e_0, gh = T^-1 e_{M-2} (Thomas' sweeps with the
+// off-diagonals).  The separator row of chunk l,
+//     -m[M-2] x_{M-2} + dg S_l - m[M-1] x'_0 = r,
+// takes the same form as with unit off-diagonals once chunk l stores
+// m[M-2] times its last interior values and chunk l+1 stores mp' = m[M-1]
+// times its first ones (ChunkMu below): separator_row and the PCR are shared.
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+struct ChunkMu : Chunk<T, M> {
+    T qv[M];        // H update coefficient per slot (q0 m[i])
+    T q0;
+    T mp, mL;       // m[-1], m[M-2]
+};
+
+// Local elimination of one chunk with off-diagonals m (see above); q0 is the
+// H update coefficient for mu = mu0.  Stores a0, g0, y0 (first interior slot)
+// times mp and aL, gL, yL (last interior slot) times m[M-2].
+template <typename T, int M, int CE, int CH>
+__device__ __forceinline__ void chunk_eliminate_mu(const T (&dg)[M], const T (&r)[M], const T (&ue)[M],
+                                                   const T (&uh)[M], const T (&m)[M], T mp, T q0,
+                                                   ChunkMu<T, M>& c) {
+    static_assert(M >= 2, "chunk needs an interior slot and a separator");
+    T g[M - 1], d[M - 1], p[M - 1];
+    g[0] = recip(dg[0]);
+    d[0] = r[0] * g[0];
+    p[0] = g[0];
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+        const T l = m[i - 1];
+        g[i] = recip(dg[i] - l * l * g[i - 1]);
+        d[i] = fused(l, d[i - 1], r[i]) * g[i];
+        p[i] = l * p[i - 1] * g[i];
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) c.qv[i] = q0 * m[i];
+    c.q0 = q0;
+    c.mp = mp;
+    c.mL = m[M - 2];
+    T y = d[M - 2], a = p[M - 2], gm = g[M - 2];
+    c.yL = c.mL * y; c.aL = c.mL * mp * a; c.gL = c.mL * c.mL * gm;
+    c.W[M - 2] = y + T(CE) * ue[M - 2];
+    c.Z[M - 2] = uh[M - 2] + c.qv[M - 2] * ((T(0) - y) + T(CH) * (ue[M - 1] - ue[M - 2]));
+    c.al[M - 2] = a;
+    c.ga[M - 2] = gm;
+#pragma unroll
+    for (int i = M - 3; i >= 0; --i) {
+        const T e = m[i] * g[i];
+        const T yi = fused(e, y, d[i]);
+        const T ai = fused(e, a, p[i]);
+        const T gi = e * gm;
+        c.W[i] = yi + T(CE) * ue[i];
+        c.Z[i] = uh[i] + c.qv[i] * ((y - yi) + T(CH) * (ue[i + 1] - ue[i]));
+        c.al[i] = ai;
+        c.ga[i] = gi;
+        y = yi; a = ai; gm = gi;
+    }
+    c.y0 = mp * y; c.a0 = mp * mp * a; c.g0 = mp * c.mL * gm;
+    c.W[M - 1] = ue[M - 1];
+    c.Z[M - 1] = uh[M - 1];
+    c.al[M - 1] = T(0);
+    c.ga[M - 1] = T(0);
+    c.dgS = dg[M - 1];
+    c.rS = r[M - 1];
+}
+
+// Final values of a ChunkMu given S_{l-1} (Sp), S_l (S) and xs = m[M-1] times
+// the first value of chunk l+1 (what the separator exchange yields from the
+// scaled first-slot values), with that slot's U_e value uen for CH = 1.
+template <typename T, int M, int CE, int CH>
+__device__ __forceinline__ void chunk_finish_mu(const ChunkMu<T, M>& c, T Sp, T S, T xs, T uen, T (&eo)[M],
+                                                T (&ho)[M]) {
+    const T sp = c.mp * Sp, sl = c.mL * S;
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) eo[i] = c.W[i] + c.al[i] * sp + c.ga[i] * sl;
+#pragma unroll
+    for (int i = 0; i < M - 2; ++i)
+        ho[i] = c.Z[i] + c.qv[i] * ((c.al[i + 1] - c.al[i]) * sp + (c.ga[i + 1] - c.ga[i]) * sl);
+    ho[M - 2] = c.Z[M - 2] + c.qv[M - 2] * ((S - c.al[M - 2] * sp) - c.ga[M - 2] * sl);
+    eo[M - 1] = S + T(CE) * c.W[M - 1];
+    // q[M-1] (x'_0 - S) = q0 xs - q[M-1] S
+    ho[M - 1] = c.Z[M - 1] + ((c.q0 * xs - c.qv[M - 1] * S) + c.qv[M - 1] * (T(CH) * (uen - c.W[M - 1])));
+}
+
+// ---------------------------------------------------------------------------
 // Refined solves.  The coefficients of the elimination (pivots, influence
 // vectors, the separator system) depend only on the medium, so in FP32 their
 // rounding is the same at every time step: a fixed perturbation of the

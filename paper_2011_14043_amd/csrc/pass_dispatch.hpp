@@ -26,6 +26,15 @@ template <typename T, typename S, int MODE>
 int dispatch_yz_m(int M, int TX, int NT, bool full, bool mat, bool fin, dim3 g, dim3 b, size_t lds, hipStream_t st,
                   const PassArgs<T, S>& a);
 
+// Plans with a permeability map (MU variants, modes FUND, CONV_LOD,
+// CONV_ADI): x lines with 8-slot chunks, y/z lines of the variants
+// kYzMuF32 / kYzMuF64; no material index.
+template <typename T, typename S, int MODE>
+int dispatch_x_mu_m(int M, bool full, bool fin, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a);
+template <typename T, typename S, int MODE>
+int dispatch_yz_mu_m(int M, int TX, int NT, bool full, bool fin, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                     const PassArgs<T, S>& a);
+
 // One batched launch of mode MODE (FUND, FUND_REF).  kind 0: x lines alone
 // (chunk M); 1: y/z lines of variant {M, TX, NT}; 2: a whole sub-step, y/z
 // lines of that variant with the x lines (8-slot chunks) from table entry ex0
@@ -61,6 +70,28 @@ inline int dispatch_yz(int kmode, int M, int TX, int NT, bool full, bool mat, bo
         case FUND_REF:
             if constexpr (HasRef<S>::v) return dispatch_yz_m<T, S, FUND_REF>(M, TX, NT, full, mat, fin, g, b, lds, st, a);
             break;
+    }
+    return DISPATCH_NOT_BUILT;
+}
+
+template <typename T, typename S>
+inline int dispatch_x_mu(int kmode, int M, bool full, bool fin, dim3 g, dim3 b, hipStream_t st,
+                         const PassArgs<T, S>& a) {
+    switch (kmode) {
+        case FUND: return dispatch_x_mu_m<T, S, FUND>(M, full, fin, g, b, st, a);
+        case CONV_LOD: return dispatch_x_mu_m<T, S, CONV_LOD>(M, full, fin, g, b, st, a);
+        case CONV_ADI: return dispatch_x_mu_m<T, S, CONV_ADI>(M, full, fin, g, b, st, a);
+    }
+    return DISPATCH_NOT_BUILT;
+}
+
+template <typename T, typename S>
+inline int dispatch_yz_mu(int kmode, int M, int TX, int NT, bool full, bool fin, dim3 g, dim3 b, size_t lds,
+                          hipStream_t st, const PassArgs<T, S>& a) {
+    switch (kmode) {
+        case FUND: return dispatch_yz_mu_m<T, S, FUND>(M, TX, NT, full, fin, g, b, lds, st, a);
+        case CONV_LOD: return dispatch_yz_mu_m<T, S, CONV_LOD>(M, TX, NT, full, fin, g, b, lds, st, a);
+        case CONV_ADI: return dispatch_yz_mu_m<T, S, CONV_ADI>(M, TX, NT, full, fin, g, b, lds, st, a);
     }
     return DISPATCH_NOT_BUILT;
 }
@@ -145,6 +176,54 @@ int dispatch_yz_m(int M, int TX, int NT, bool full, bool mat, bool fin, dim3 g, 
         CASE_YZ(16, 16, 512) CASE_YZ(8, 8, 512) CASE_YZ(8, 16, 1024)
     }
 #undef CASE_YZ
+    return DISPATCH_NOT_BUILT;
+}
+
+// Permeability-map variants (the fused output form only for the
+// fundamental forms).
+template <typename T, typename S, int MODE>
+int dispatch_x_mu_m(int M, bool full, bool fin, dim3 g, dim3 b, hipStream_t st, const PassArgs<T, S>& a) {
+    if (M != 8 || (fin && MODE != FUND)) return DISPATCH_NOT_BUILT;
+    if constexpr (MODE == FUND) {
+        if (fin) {
+            if (full) hipLaunchKernelGGL((pass_x_kernel<T, S, 8, MODE, true, false, true, true>), g, b, 0, st, a);
+            else hipLaunchKernelGGL((pass_x_kernel<T, S, 8, MODE, false, false, true, true>), g, b, 0, st, a);
+            return DISPATCH_OK;
+        }
+    }
+    if (full) hipLaunchKernelGGL((pass_x_kernel<T, S, 8, MODE, true, false, false, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((pass_x_kernel<T, S, 8, MODE, false, false, false, true>), g, b, 0, st, a);
+    return DISPATCH_OK;
+}
+
+template <typename T, typename S, int M, int TX, int NT, int MODE>
+int launch_yz_mu(bool full, bool fin, dim3 g, dim3 b, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
+    if (fin && MODE != FUND) return DISPATCH_NOT_BUILT;
+    if constexpr (MODE == FUND) {
+        if (fin) {
+            if (full)
+                hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, false, true, true>), g, b, lds, st, a);
+            else
+                hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, false, true, true>), g, b, lds, st, a);
+            return DISPATCH_OK;
+        }
+    }
+    if (full) hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, true, false, false, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((pass_yz_kernel<T, S, M, MODE, TX, NT, false, false, false, true>), g, b, lds, st, a);
+    return DISPATCH_OK;
+}
+
+template <typename T, typename S, int MODE>
+int dispatch_yz_mu_m(int M, int TX, int NT, bool full, bool fin, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                     const PassArgs<T, S>& a) {
+#define CASE_YZ_MU(MM, TT, NN) \
+    if (M == MM && TX == TT && NT == NN) return launch_yz_mu<T, S, MM, TT, NN, MODE>(full, fin, g, b, lds, st, a);
+    if constexpr (sizeof(S) == 4) {
+        CASE_YZ_MU(16, 16, 512) CASE_YZ_MU(8, 16, 512) CASE_YZ_MU(8, 8, 512)
+    } else {
+        CASE_YZ_MU(8, 16, 512) CASE_YZ_MU(8, 8, 512)
+    }
+#undef CASE_YZ_MU
     return DISPATCH_NOT_BUILT;
 }
 

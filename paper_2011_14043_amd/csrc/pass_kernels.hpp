@@ -54,6 +54,7 @@ struct PassArgs {
     const T* H2;          // CONV_ADI: H component of Y's E row (shifted along t)
     const T* E3;          // CONV_ADI: E component of Y's H row (shifted along e)
     const float* eps;     // relative permittivity at node index (node layout)
+    const float* mu;      // MU variants: relative permeability at node index (node layout)
     const unsigned char* mat;   // MAT variants: material index at node index (node layout)
     const float* mat_eps;       // MAT variants: eps_r of each material (<= 256 entries)
     int nmat;
@@ -237,6 +238,37 @@ __device__ __forceinline__ void slot_rhs(const PassArgs<T, S>& a, SlotCoef<S> sc
     }
 }
 
+// MU variants (variable permeability): rhs, diagonal and right-side
+// coefficient c of one slot with m = mu0/mu at the H samples below (mlo) and
+// above (mhi) it; eps_r from the FP32 map.  In FP32 sigma is taken as
+// fl(m_lo + m_hi + sigma) - (m_lo + m_hi), so that the diagonal and the right
+// side use one value (as make_sigma does for unit off-diagonals).
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ void slot_rhs_mu(const PassArgs<T, S>& a, float eps, S mlo, S mhi, S ue, S uh, S uh_m,
+                                            S ue_m, S ue_p, S x2, S& dg, S& r, S& c) {
+    const S dsum = mlo + mhi;
+    S sig;
+    if constexpr (sizeof(S) == 4) {
+        sig = S(a.Ks) * eps;
+        dg = dsum + sig;
+        sig = dg - dsum;
+    } else {
+        sig = a.Ks * double(eps);
+        dg = dsum + sig;
+    }
+    c = IsFund<MODE>::v ? sig + sig : sig;
+    const S dh = uh - uh_m;
+    S hterm = dh * a.kap_hi;
+    if constexpr (sizeof(S) == 4) hterm = __builtin_fmaf(dh, a.kap_lo, hterm);
+    if constexpr (IsFund<MODE>::v) {
+        r = c * ue + hterm;
+    } else if constexpr (MODE == CONV_LOD) {
+        r = c * ue + hterm + (mhi * (ue_p - ue) - mlo * (ue - ue_m));
+    } else {
+        r = c * ue + hterm + x2;
+    }
+}
+
 // Source term at slot si of this chunk (rhs: 2 sigma pre or sigma pre).
 // sigma is recovered from the diagonal: dg - 2 is exact.
 template <typename T, typename S, int MODE, int M>
@@ -250,6 +282,14 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
     }
 }
 
+// The same with the right-side coefficients c of the slots given (MU variants).
+template <typename T, typename S, int M>
+__device__ __forceinline__ void add_source_c(const PassArgs<T, S>& a, int si, const S (&c)[M], S (&r)[M]) {
+    const S pre = a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre;
+#pragma unroll
+    for (int i = 0; i < M; ++i) r[i] += (i == si) ? c[i] * pre : S(0);
+}
+
 // ---------------------------------------------------------------------------
 // x lines: contiguous axis.  One line per segment of P lanes of a wave; lane
 // `ls` owns slots [ls*M, ls*M+M), loaded with 16-byte buffer loads (rows are
@@ -258,8 +298,9 @@ __device__ __forceinline__ void add_source(const PassArgs<T, S>& a, int si, cons
 // ---------------------------------------------------------------------------
 // Body of one block of x-line work: block `blk` of the pass described by `a`
 // (lines blk * waves * 64/P ...); ctab = the per-material coefficients in LDS (MAT).
-template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN = false>
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN = false, bool MU = false>
 __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const CoefTab<S>* ctab) {
+    static_assert(!(MU && (MAT || MODE == FUND_REF)), "MU variants read eps_r maps and solve without refinement");
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
     const int P = a.P;
@@ -281,16 +322,21 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const int vo = lel * ES, vo_e = lel * 4;
     const Rsrc rE = make_rsrc(a.Ein, wbase, a.comp, ES), rH = make_rsrc(a.Hin, wbase, a.comp, ES);
     const Rsrc rP = make_rsrc(a.eps, wbase, a.comp, 4);
+    const Rsrc rMu = make_rsrc(a.mu, wbase, a.comp, 4);
 
     S ue[M], uh[M];
     SlotCoef<S> sc[M];
     unsigned idp[(M + 3) / 4] = {};   // refined solves: material indices, 4 per word
+    float eps_s[M], mur_s[M];         // MU: eps_r and mu_r per slot
     {
         T te[M], th[M];
         if (!FULL && j0 >= n) {
             // chunk past the end of its line (power-of-two padding): no loads
 #pragma unroll
-            for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); sc[i] = SlotCoef<S>{S(0), S(2)}; }
+            for (int i = 0; i < M; ++i) {
+                te[i] = T(0); th[i] = T(0); sc[i] = SlotCoef<S>{S(0), S(2)};
+                eps_s[i] = 1.0f; mur_s[i] = 1.0f;
+            }
         } else {
             ld_chunk<T, M>(rE, vo, te);
             ld_chunk<T, M>(rH, vo, th);
@@ -301,6 +347,9 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
                 for (int i = 0; i < M; ++i) sc[i] = coef_from_tab<T, S, MODE>(a, ctab, id[i]);
 #pragma unroll
                 for (int i = 0; i < M; ++i) idp[i >> 2] |= id[i] << (8 * (i & 3));
+            } else if constexpr (MU) {
+                ld_chunk<float, M>(rP, vo_e, eps_s);
+                ld_chunk<float, M>(rMu, vo_e, mur_s);
             } else {
                 float ep[M];
                 ld_chunk<float, M>(rP, vo_e, ep);
@@ -319,6 +368,14 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const bool beyond = j0 > n;
     const int vo_prev = (first || beyond) ? vo : vo - ES;
     const S uh_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rH, vo_prev, 0));
+    // MU: m = mu0/mu at the H samples of the chunk's slots (0 past the line)
+    // and at the one before it
+    S mm[M], m_prev = S(0);
+    if constexpr (MU) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) mm[i] = (FULL || j0 + i < n) ? recip(S(mur_s[i])) : S(0);
+        m_prev = (first || beyond) ? S(0) : recip(S(Buf<float>::ld(rMu, vo_e - 4, 0)));
+    }
     S ue_prev = S(0), ue_next = S(0);
     if constexpr (MODE == CONV_LOD) {
         ue_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rE, vo_prev, 0));
@@ -343,18 +400,22 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
             const bool in = FULL || j0 + i < n;
             D[i + 1] = in ? S(e3b[i]) - S(e3a[i]) : S(0);
             x2[i] = in ? a.cH2 * (S(h2a[i]) - S(h2b[i])) : S(0);
-            uh[i] += a.hE3 * D[i + 1];
+            uh[i] += (MU ? a.hE3 * mm[i] : a.hE3) * D[i + 1];
         }
-        uh_m_eff += a.hE3 * D[0];
+        uh_m_eff += (MU ? a.hE3 * m_prev : a.hE3) * D[0];
     }
 
-    S dg[M], r[M];
+    S dg[M], r[M], cc[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        slot_rhs<T, S, MODE>(a, sc[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        if constexpr (MU)
+            slot_rhs_mu<T, S, MODE>(a, eps_s[i], (i == 0) ? m_prev : mm[i - 1], mm[i], ue[i], uh[i], um, em, epv,
+                                    (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i], cc[i]);
+        else
+            slot_rhs<T, S, MODE>(a, sc[i], ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
         if (!FULL) {
             const bool out = j0 + i >= n;
             dg[i] = out ? Big<S>::v : dg[i];
@@ -367,7 +428,10 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) {
+        if constexpr (MU) add_source_c<T, S, M>(a, src_here ? si : -1, cc, r);
+        else add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    }
     // separator system across the P lanes of the line (all lanes shuffle):
     // own last interior slot (aL, gL, yL), separator row (dgS, rS), and the
     // next chunk's first slot (a0n, g0n, y0; zero past the line).  Returns
@@ -454,6 +518,14 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
             eo[i] += rho[i];
             ho[i] = fused(a.q, dn - rho[i], ho[i]);
         }
+    } else if constexpr (MU) {
+        ChunkMu<S, M> c;
+        chunk_eliminate_mu<S, M, CE, CH>(dg, r, ue, uh, mm, m_prev, a.q, c);
+        const S a0n_r = __shfl_down(c.a0, 1, P), g0n_r = __shfl_down(c.g0, 1, P);
+        const S a0n = has_next ? a0n_r : S(0), g0n = has_next ? g0n_r : S(0);
+        S Sl, Sp, xs;
+        separators(c.aL, c.gL, c.yL, c.dgS, c.rS, a0n, g0n, c.y0, Sl, Sp, xs);
+        chunk_finish_mu<S, M, CE, CH>(c, Sp, Sl, xs, ue_next, eo, ho);
     } else {
         Chunk<S, M> c;
         chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
@@ -503,11 +575,13 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
 // FIN: the pass stores the output form u = U_old + U_new of its pair instead
 // of U_new (output processing of the last B sub-step of a fundamental ADI run;
 // a separate instantiation, so the other passes carry none of its registers).
-template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN>
+// MU: variable permeability (eps_r and mu_r maps, no material index).
+template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN, bool MU = false>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
-    pass_x_body<T, S, M, MODE, FULL, MAT, FIN>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), ctab);
+    pass_x_body<T, S, M, MODE, FULL, MAT, FIN, MU>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
+                                                   ctab);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,9 +597,11 @@ __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
 // 9 P (TX+1) elements (13 P (TX+1) for refined solves, whose second
 // separator exchange has areas of its own).  TX * P must be a multiple of 64
 // (whole waves).
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN = false>
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN = false,
+          bool MU = false>
 __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, int t, S* sm, const CoefTab<S>* ctab,
                                              bool valid) {
+    static_assert(!(MU && (MAT || MODE == FUND_REF)), "MU variants read eps_r maps and solve without refinement");
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
     constexpr int CPW = 64 / TX;                  // chunks per wave
@@ -565,12 +641,16 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     S ue[M], uh[M], x2[M];
     unsigned id[M];      // MAT: material index per slot
     float epf[M];        // else: eps_r per slot
+    float mur_s[M];      // MU: mu_r per slot
     const Rsrc rM = make_rsrc(a.mat, wbase, a.comp, 1);
+    const Rsrc rMu = make_rsrc(a.mu, wbase, a.comp, 4);
     T te[M], th[M];
     if (!FULL && j0 >= n) {
         // chunk past the end of its line (power-of-two padding): no loads
 #pragma unroll
-        for (int i = 0; i < M; ++i) { te[i] = T(0); th[i] = T(0); id[i] = 0u; epf[i] = 1.0f; }
+        for (int i = 0; i < M; ++i) {
+            te[i] = T(0); th[i] = T(0); id[i] = 0u; epf[i] = 1.0f; mur_s[i] = 1.0f;
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -578,6 +658,7 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
             th[i] = Buf<T>::ld(rH, vo, i * swb);
             if constexpr (MAT) id[i] = __builtin_amdgcn_raw_buffer_load_b8(rM, lel, i * (int)sw, 0);
             else epf[i] = Buf<float>::ld(rP, vo_e, i * swf);
+            if constexpr (MU) mur_s[i] = Buf<float>::ld(rMu, vo_e, i * swf);
         }
     }
 #pragma unroll
@@ -591,6 +672,15 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     // slot j0-1 through resources based one slot earlier (offsets stay >= 0)
     const Rsrc rHm = make_rsrc(a.Hin, wbase - sw, a.comp, ES);
     const S uh_prev = (first || beyond) ? S(0) : S(Buf<T>::ld(rHm, vo, 0));
+    // MU: m = mu0/mu at the H samples of the chunk's slots (0 past the line)
+    // and at the one before it
+    S mm[M], m_prev = S(0);
+    if constexpr (MU) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) mm[i] = (FULL || j0 + i < n) ? recip(S(mur_s[i])) : S(0);
+        const Rsrc rMum = make_rsrc(a.mu, wbase - sw, a.comp, 4);
+        m_prev = (first || beyond) ? S(0) : recip(S(Buf<float>::ld(rMum, vo_e, 0)));
+    }
     S ue_prev = S(0), ue_next = S(0);
     if constexpr (MODE == CONV_LOD) {
         const Rsrc rEm = make_rsrc(a.Ein, wbase - sw, a.comp, ES);
@@ -611,19 +701,24 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
             const S h2 = S(Buf<T>::ld(r2, vo, i * swb)) - S(Buf<T>::ld(r2t, vo, i * swb));
             D[i + 1] = in ? d : S(0);
             x2[i] = in ? a.cH2 * h2 : S(0);
-            uh[i] += a.hE3 * D[i + 1];
+            uh[i] += (MU ? a.hE3 * mm[i] : a.hE3) * D[i + 1];
         }
-        uh_m_eff += a.hE3 * D[0];
+        uh_m_eff += (MU ? a.hE3 * m_prev : a.hE3) * D[0];
     }
 
-    S dg[M], r[M];
+    S dg[M], r[M], cc[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const S um = (i == 0) ? uh_m_eff : uh[i - 1];
         const S em = (i == 0) ? ue_prev : ue[i - 1];
         const S epv = (i == M - 1) ? ue_next : ue[i + 1];
-        const SlotCoef<S> sci = MAT ? coef_from_tab<T, S, MODE>(a, ctab, id[i]) : coef_of<S, MODE>(a.Ks, epf[i]);
-        slot_rhs<T, S, MODE>(a, sci, ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        if constexpr (MU) {
+            slot_rhs_mu<T, S, MODE>(a, epf[i], (i == 0) ? m_prev : mm[i - 1], mm[i], ue[i], uh[i], um, em, epv,
+                                    (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i], cc[i]);
+        } else {
+            const SlotCoef<S> sci = MAT ? coef_from_tab<T, S, MODE>(a, ctab, id[i]) : coef_of<S, MODE>(a.Ks, epf[i]);
+            slot_rhs<T, S, MODE>(a, sci, ue[i], uh[i], um, em, epv, (MODE == CONV_ADI) ? x2[i] : S(0), dg[i], r[i]);
+        }
         if (!FULL) {
             const bool out = j0 + i >= n;
             dg[i] = out ? Big<S>::v : dg[i];
@@ -635,7 +730,10 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     const int si = (ia == a.src_a && ib == a.src_b && live) ? a.src_j - j0 : -1;
     const bool src_here = si >= 0 && si < M;
     const bool src_wave = __ballot(src_here) != 0;
-    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    if (MODE != FUND_REF && __builtin_expect(src_wave, 0)) {
+        if constexpr (MU) add_source_c<T, S, M>(a, src_here ? si : -1, cc, r);
+        else add_source<T, S, MODE, M>(a, src_here ? si : -1, dg, r);
+    }
     // Separator system: every chunk's end values go through LDS (slots
     // 0-2: first interior slot alpha, gamma, y; 3-5: last interior slot;
     // 6, 7: separator diagonal and right side), the P chunks of a line are
@@ -746,6 +844,19 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
             eo[i] += rho[i];
             ho[i] = fused(a.q, dn - rho[i], ho[i]);
         }
+    } else if constexpr (MU) {
+        // first and last interior values scaled by their off-diagonals (see
+        // ChunkMu): the exchange and xn (= m[M-1] times the next chunk's
+        // first value) as for unit off-diagonals
+        ChunkMu<S, M> c;
+        chunk_eliminate_mu<S, M, CE, CH>(dg, r, ue, uh, mm, m_prev, a.q, c);
+        EP(0, p, tx) = c.a0; EP(1, p, tx) = c.g0; EP(2, p, tx) = c.y0;
+        EP(3, p, tx) = c.aL; EP(4, p, tx) = c.gL; EP(5, p, tx) = c.yL;
+        EP(6, p, tx) = c.dgS; EP(7, p, tx) = c.rS;
+        separators(0);
+        S Sl, Sp, xs;
+        read_separators(0, Sl, Sp, xs);
+        chunk_finish_mu<S, M, CE, CH>(c, Sp, Sl, xs, ue_next, eo, ho);
     } else {
         Chunk<S, M> c;
         chunk_eliminate<S, M, CE, CH>(dg, r, ue, uh, a.q, c);
@@ -792,18 +903,21 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
 // chunks (modes without the cross-term arrays) fit in 64 VGPRs, so two
 // 1024-thread blocks share a CU and one block's loads overlap the other's LDS
 // phase.
-template <typename S, int M, int MODE, int NT>
+template <typename S, int M, int MODE, int NT, bool MU>
 struct YzOcc {
-    static constexpr int v = (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI && MODE != FUND_REF) ? 8 : 1;
+    static constexpr int v =
+        (sizeof(S) == 4 && M <= 8 && NT == 1024 && MODE != CONV_ADI && MODE != FUND_REF && !MU) ? 8 : 1;
 };
 
-template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN>
-__global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT>::v)) pass_yz_kernel(PassArgs<T, S> a) {
+// MU: variable permeability (eps_r and mu_r maps, no material index).
+template <typename T, typename S, int M, int MODE, int TX, int NT, bool FULL, bool MAT, bool FIN, bool MU = false>
+__global__ void __launch_bounds__(NT, (YzOcc<S, M, MODE, NT, MU>::v)) pass_yz_kernel(PassArgs<T, S> a) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     extern __shared__ unsigned char smem_raw[];
-    pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT, FIN>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
-                                                        threadIdx.x, reinterpret_cast<S*>(smem_raw), ctab, true);
+    pass_yz_body<T, S, M, MODE, TX, NT, FULL, MAT, FIN, MU>(
+        a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x), threadIdx.x, reinterpret_cast<S*>(smem_raw),
+        ctab, true);
 }
 
 }  // namespace fdtd

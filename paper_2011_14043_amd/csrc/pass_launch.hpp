@@ -62,6 +62,7 @@ struct PassShape {
     size_t lds = 0;
     bool full = false;    // every line fills its P*M slots exactly
     bool mat = false;     // material-index variant
+    bool mu = false;      // permeability-map variant
 };
 
 // Arguments and launch shape of the pass of pair k of operator op (half-span
@@ -79,6 +80,8 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
     a.Eout = set_out + pd.ce * cs;
     a.Hout = set_out + pd.ch * cs;
     a.eps = p->eps;
+    a.mu = p->mu;
+    sh.mu = p->mu != nullptr;
     a.mat = p->mat;
     a.mat_eps = p->mat_eps;
     a.nmat = p->nmat;
@@ -189,7 +192,11 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     const int kmode = (mode == FUND && p->refine) ? FUND_REF : mode;
     const bool fused = fin != nullptr;
     int r;
-    if (sh.w == 0) {
+    if (sh.mu) {
+        r = sh.w == 0 ? dispatch_x_mu<T, S>(kmode, cf.M, sh.full, fused, sh.grid, sh.block, p->stream, a)
+                      : dispatch_yz_mu<T, S>(kmode, cf.M, cf.TX, cf.NT, sh.full, fused, sh.grid, sh.block, sh.lds,
+                                             p->stream, a);
+    } else if (sh.w == 0) {
         r = dispatch_x<T, S>(kmode, cf.M, sh.full, sh.mat, fused, sh.grid, sh.block, p->stream, a);
     } else {
         const size_t lds = kmode == FUND_REF ? sh.lds / 9 * 13 : sh.lds;   // refined: second exchange areas

@@ -18,23 +18,18 @@ static const PairDef kPairs[2][3] = {
     {{0, 4, 2, 0, 1, -1}, {1, 5, 0, 1, 2, -1}, {2, 3, 1, 2, 0, -1}},   // B
 };
 
-// FDTD_F32 plans refine their line solves below this sigma.  The FP32
-// diagonal 2 + sigma is rounded to a spacing of 2.4e-7 near 2, a fixed
-// relative perturbation of up to 1.2e-7 / sigma of the medium at every step;
-// its phase error grows linearly with the step count (plain FP32, 1000 steps
-// of random-box media: 3e-4 at sigma >= 0.12, 4e-5 to 6e-5 at sigma >= 0.48).
-// Below sigma = 2 (relative perturbation 6e-8) refinement is switched on.
-static constexpr double kRefineSigma = 2.0;
-
 // Does an FDTD_F32 plan of `d` (scheme already mapped to a line-pass scheme)
-// with smallest relative permittivity eps_min refine its solves?  Only where
-// refined passes are built: fundamental forms, at most 512 cells per axis.
-static bool f32_refine_wanted(const fdtd_desc& d, float eps_min) {
-    if (d.form != FDTD_FUNDAMENTAL) return false;
-    if (std::max(d.nx, std::max(d.ny, d.nz)) > 512) return false;
-    const double h = std::min(d.dx, std::min(d.dy, d.dz));
-    const double theta = 0.5 * d.dt;   // the largest half-span of every scheme's sub-steps
-    return kEps0 * kMu0 * double(eps_min) * h * h / (theta * theta) < kRefineSigma;
+// refine its solves?  Wherever refined passes are built: fundamental forms, at
+// most 512 cells per axis, unit permeability.  Plain FP32 solves carry two
+// fixed roundings at every step: of the diagonal 2 + sigma (a relative
+// perturbation of up to 1.2e-7 / sigma of the medium, whose phase error grows
+// linearly with the step count: 3e-4 after 1000 steps at sigma = 0.12) and of
+// the medium-only factors (an amplification slightly off unit modulus,
+// whatever sigma: 4e-5 to 6e-5 after 1000 steps at sigma = 12 as at 0.48).
+// One refinement step removes both for 1 % to 3 % of the step time.
+static bool f32_refine_wanted(const fdtd_desc& d, bool has_mu) {
+    if (d.form != FDTD_FUNDAMENTAL || has_mu) return false;
+    return std::max(d.nx, std::max(d.ny, d.nz)) <= 512;
 }
 
 struct SubStep { int op; double theta_frac; double t_frac; };
@@ -55,6 +50,11 @@ struct KCfg { int M, TX, NT, wpb, remap; };
 // Instantiated y/z-line variants {M, TX, NT} by solve precision.
 static const int kYzF32[][3] = {{16, 32, 1024}, {16, 16, 512}, {8, 16, 1024}, {32, 16, 512}, {8, 32, 512}};
 static const int kYzF64[][3] = {{16, 16, 512}, {8, 8, 512}, {8, 16, 1024}};
+// Plans with a permeability map (per-row off-diagonals, more registers per
+// slot): x lines with 8-slot chunks; these y/z variants (16-slot chunks for
+// FP32 solves only).
+static const int kYzMuF32[][3] = {{16, 16, 512}, {8, 16, 512}, {8, 8, 512}};
+static const int kYzMuF64[][3] = {{8, 16, 512}, {8, 8, 512}};
 
 struct Timing {
     int per_launch = 0;           // 0: off; k >= 1: every launch of every k-th main-loop step
@@ -109,6 +109,7 @@ struct fdtd_plan_s {
     void* state = nullptr;    // 6 (or 12 for original ADI) arrays, padded layout
     void* snap = nullptr;     // grid of an ADI batch: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
+    float* mu = nullptr;      // mu_r in node layout (plans with a permeability map; else NULL)
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
     // 3 x 1024 partial sums, scalars; CG controls and the last run's statistics
@@ -133,7 +134,7 @@ struct fdtd_plan_s {
     fdtd::KCfg cfg[3];        // per line axis x, y, z
     int tuned = 0;
     int refine = 0;           // FP32 fundamental passes refine each solve once (FDTD_F32_REFINE, or
-                              // FDTD_F32 below kRefineSigma)
+                              // FDTD_F32 where refined passes are built)
     int req_dtype = 0;        // the dtype the caller asked for (d.dtype holds the storage/solve kind)
     double last_main_ms = 0.0;
     double fam_ms[2] = {0, 0};
@@ -147,6 +148,8 @@ struct fdtd_plan_s {
     // passes read.
     int graph_steps = 8;
     hipStream_t gstream = nullptr;        // private capture stream
+    hipStream_t gfork[2] = {nullptr, nullptr};        // capture branches: the three pair passes
+    hipEvent_t gev[3] = {nullptr, nullptr, nullptr};  // of a sub-step are independent
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     long long gkey[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // what the captured graph depends on

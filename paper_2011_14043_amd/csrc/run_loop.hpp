@@ -36,7 +36,7 @@ static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst, bool fin_fo
     if (p->d.scheme == FDTD_ADI && (p->d.form == FDTD_CONVENTIONAL || fin_form)) k.link = 0.25 * p->d.dt;
     k.fin_form = fin_form ? 1 : 0;
     hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
-                       state_ptrs<T>(p, set), p->eps, p->dims, k, p->partial);
+                       state_ptrs<T>(p, set), p->eps, p->mu, p->dims, k, p->partial);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, p->partial, p->npartial, dst);
     HIPCHK(hipGetLastError());
@@ -88,6 +88,10 @@ static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mod
     const SchemeDef& sd = kSchemes[p->d.scheme];
     const int K = p->graph_steps;
     if (!p->gstream) HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    for (hipStream_t& f : p->gfork)
+        if (!f) HIPCHK(hipStreamCreateWithFlags(&f, hipStreamNonBlocking));
+    for (hipEvent_t& e : p->gev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (src && !p->src_win) HIPCHK(hipMalloc(&p->src_win, sizeof(double) * 6 * 3 * 64));
     if ((size_t)K * sd.nsub * 6 > 6 * 3 * 64) return FDTD_EINVAL;
     hipStream_t user = p->stream;
@@ -105,7 +109,26 @@ static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mod
                 inj.pre_dev = p->src_win + (size_t)(q * sd.nsub + u) * 6;
                 inj.post_dev = inj.pre_dev + 3;
             }
-            st = substep<T, S>(p, ss.op, ss.theta_frac * p->d.dt, mode, cur, src ? &inj : nullptr, false);
+            // The three pair passes of a sub-step write disjoint arrays and read
+            // nothing another of them writes (conventional ADI reads its cross
+            // terms from the other buffer set), so they are captured as
+            // parallel branches: fork on an event, join before the next sub-step.
+            const int out = (mode == CONV_ADI) ? 1 - cur : cur;
+            hipStream_t br[3] = {p->gstream, p->gfork[0], p->gfork[1]};
+            if (hipEventRecord(p->gev[0], p->gstream) != hipSuccess) st = FDTD_EDEVICE;
+            for (int l = 1; l < 3 && st == FDTD_OK; ++l)
+                if (hipStreamWaitEvent(br[l], p->gev[0], 0) != hipSuccess) st = FDTD_EDEVICE;
+            for (int k = 0; k < 3 && st == FDTD_OK; ++k) {
+                p->stream = br[k];
+                st = launch_pass<T, S>(p, ss.op, k, ss.theta_frac * p->d.dt, mode, set_ptr<T>(p, cur),
+                                       set_ptr<T>(p, out), src ? &inj : nullptr, false);
+            }
+            p->stream = p->gstream;
+            for (int l = 1; l < 3 && st == FDTD_OK; ++l)
+                if (hipEventRecord(p->gev[l], br[l]) != hipSuccess ||
+                    hipStreamWaitEvent(p->gstream, p->gev[l], 0) != hipSuccess)
+                    st = FDTD_EDEVICE;
+            cur = out;
         }
     }
     hipGraph_t g = nullptr;
@@ -194,7 +217,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // input processing
     const AuxCoef kin = aux_coef(d, (adi && !conv) ? 0.25 * d.dt : 0.0);
     hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(dm), dim3(kRowThreads), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
-                       p->eps, dm, kin);
+                       p->eps, p->mu, dm, kin);
     HIPCHK(hipGetLastError());
     int cur = 0;
     if (adi && conv) {

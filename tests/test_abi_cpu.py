@@ -54,7 +54,7 @@ def _desc(**kw):
     (dict(scheme=8), -1), (dict(scheme=-1), -1), (dict(form=2), -1), (dict(dtype=7), -1),
     (dict(scheme=4, form=1), -4), (dict(scheme=5, form=1), -4), (dict(scheme=7), -1),
     (dict(scheme=6), -4), (dict(scheme=6, dtype=0, form=1), -4), (dict(scheme=6, dtype=3), -4),
-    (dict(boundary=1), -4), (dict(mu_r=12345), -4), (dict(nx=2000), -4), (dict(nz=600, dtype=1), -4),
+    (dict(boundary=1), -4), (dict(mu_r=12345), -1), (dict(nx=2000), -4), (dict(nz=600, dtype=1), -4),
     (dict(dtype=5), -1), (dict(dtype=3, form=1), -4), (dict(dtype=3, ny=600), -4),
     (dict(scheme=6, dtype=4), -4), (dict(dtype=4, nx=1100), -4),
 ])

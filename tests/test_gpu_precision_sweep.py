@@ -8,15 +8,16 @@ Reported and checked at steps 100, 500 and 1000: the energy-weighted relative
 L2 error over 4096 seeded samples per component, and the relative error of the
 field's energy norm.  Bars: FP64 1e-10; every FP32-field mode the library
 chooses by default (FP64 solves, FDTD_F32, refined FP32) 1e-4, the accuracy
-target for FP32 fields after 1000 steps.  FDTD_F32 refines its solves at these
-time steps (sigma = eps mu dw^2 / theta^2 < 2); plain FP32 solves
+target for FP32 fields after 1000 steps.  FDTD_F32 refines its solves (the
+fundamental forms refine wherever refined passes are built); plain FP32 solves
 (FDTD_F32_PLAIN) are swept too, as the comparison: their fixed rounding of the
 diagonal 2 + sigma (a relative perturbation up to 1.2e-7 / sigma of the medium,
-the same at every step) makes the phase error grow linearly with the step
-count, to 3e-4 at CFL 10 (bar 1e-3) and 4e-5 to 9e-5 at CFL 5 (bar 2e-4).
-Every scheme is also swept at CFL 5, the CFL number of the 512^3 workload,
-and at CFL 1, the other end of its CFL range, where sigma >= 12 and FDTD_F32
-solves plainly (fixtures precision_sweep_<scheme>_cfl5.npz, _cfl1.npz)."""
+sigma = eps mu dw^2 / theta^2) and of the medium-only factors, the same at
+every step, makes their error grow linearly with the step count, to 3e-4 at
+CFL 10 (bar 1e-3), 4e-5 to 9e-5 at CFL 5 (bar 2e-4) and 4e-5 to 6e-5 at
+CFL 1 (bar 1e-4).  Every scheme is also swept at CFL 5, the CFL number of
+the 512^3 workload, and at CFL 1, the other end of its CFL range (fixtures
+precision_sweep_<scheme>_cfl5.npz, _cfl1.npz)."""
 import os
 
 import numpy as np
@@ -65,7 +66,7 @@ def _sweep(c, ref, scheme, prec, expect_refined=None):
     H = [torch.tensor(a, dtype=dtype, device=DEV) for a in c["u0"][3:]]
     plan = Plan(n, n, n, c["dt"], c["h"], c["h"], c["h"], scheme=scheme, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.tensor(c["eps"]), refine=refine)
-    # FDTD_F32 refines at CFL 10 and 5 (smallest sigma 0.12 and 0.48), not at CFL 1 (12)
+    # FDTD_F32 refines the fundamental forms' solves (at every CFL number)
     if expect_refined is None:
         expect_refined = prec in ("f32", "f32r")
     assert plan.refined == expect_refined
@@ -131,13 +132,13 @@ def setup_cfl1(setup):
     return c
 
 
-@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r"])
+@pytest.mark.parametrize("prec", ["f32s64", "f32", "f32r", "f32p"])
 @pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
 def test_precision_cfl1(setup_cfl1, scheme, prec):
-    """The same sweep at CFL 1 (smallest sigma 12: FDTD_F32 does not refine)."""
+    """The same sweep at CFL 1 (smallest sigma 12)."""
     ref = _golden(f"{scheme}_cfl1")
     assert float(ref["cfl"]) == 1.0
     print(f"[case] precision sweep 128^3 CFL1 {scheme}/{prec}", flush=True)
-    errs, nerrs = _sweep(setup_cfl1, ref, scheme, prec, expect_refined=prec == "f32r")
+    errs, nerrs = _sweep(setup_cfl1, ref, scheme, prec)
     assert max(errs) <= 1e-4, errs
     assert max(nerrs) <= 1e-4, nerrs

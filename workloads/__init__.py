@@ -106,6 +106,14 @@ def random_box_eps(nx: int, ny: int, nz: int, seed: int, nboxes: int = 32,
     return eps
 
 
+def random_mu(nx: int, ny: int, nz: int, seed: int, vmin: float = 1.0, vmax: float = 3.0) -> np.ndarray:
+    """Relative permeability per cell, shape (nz, ny, nx), FP32: U[vmin, vmax]
+    independently in every cell (the most irregular medium: every H sample of
+    a line differs from its neighbours)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(vmin, vmax, (nz, ny, nx)).astype(np.float32)
+
+
 def design_region_eps(nx: int, ny: int, nz: int, box: tuple[int, int, int, int, int, int],
                       seed: int) -> np.ndarray:
     """eps_r = 1 outside the design box (x0, y0, z0, sx, sy, sz); per-voxel U[1,12]
