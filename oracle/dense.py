@@ -11,12 +11,16 @@ Schemes are then the plain matrix formulae of Sec. II:
   fundamental: (fasterADI)+(fastADIi)+(fasterADIo), (fastLOD), (fastSS2),
                (fastLOD2)+(fastLOD2i)+(fastLOD2o)
 Every solve is ``numpy.linalg.solve`` on the dense system.
+
+Grids of order 4 (the fourth-order staggered differences of ``yee``) are
+assembled the same way, row by row, each row taking the four partner samples
+along the pair's axis, folded onto their images across a PEC wall.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .yee import COMPONENTS, CIDX, EPS0, MU0, Grid, dynamic_mask
+from .yee import COMPONENTS, CIDX, EPS0, MU0, PAIRS, W4, Grid, dynamic_mask
 
 
 class DenseSystem:
@@ -35,7 +39,10 @@ class DenseSystem:
         else:
             self.A = np.zeros((self.n, self.n))
             self.B = np.zeros((self.n, self.n))
-        self._assemble()
+        if g.order == 4:
+            self._assemble4()
+        else:
+            self._assemble()
         if sparse:
             from scipy.sparse import csr_matrix
             self.A, self.B = ([csr_matrix((np.array([t[2] for t in M]), ([t[0] for t in M], [t[1] for t in M])),
@@ -98,6 +105,43 @@ class DenseSystem:
                 self._add(A, r, "Ex", k, j, i, -inv / dy)
                 self._add(B, r, "Ey", k, j, i + 1, -inv / dx)  # -dEy/dx
                 self._add(B, r, "Ey", k, j, i, inv / dx)
+
+    def _assemble4(self):
+        """A and B with the fourth-order differences: for the pair (E, H, w, s)
+        of an operator, an E row at integer position p along w takes the H
+        samples at p - 3/2 .. p + 3/2 (stored p-2 .. p+1) with weights W4 / h
+        times s/eps; an H row at p + 1/2 takes the E samples at p-1 .. p+2 times
+        s/mu.  Across a wall an H sample is its even image, an E sample its odd
+        image (a wall E itself is 0)."""
+        g = self.g
+        cells = {"x": g.nx, "y": g.ny, "z": g.nz}
+        for r, (c, k, j, i) in enumerate(self.nodes):
+            inv = 1.0 / self._material(c, k, j, i)
+            for name in ("A", "B"):
+                M = self.op(name)
+                for ce, ch, w, s in PAIRS[name]:
+                    if c not in (ce, ch):
+                        continue
+                    n, h = cells[w], g.spacing(w)
+                    pos = {"x": i, "y": j, "z": k}[w]
+
+                    def at(q):
+                        return (q, j, i) if w == "z" else ((k, q, i) if w == "y" else (k, j, q))
+                    for t in range(4):
+                        if c == ce:
+                            q = pos - 2 + t                       # H stored index
+                            if q < 0:
+                                q = -1 - q
+                            elif q > n - 1:
+                                q = 2 * n - 1 - q
+                            self._add(M, r, ch, *at(q), s * inv * W4[t] / h)
+                        else:
+                            q, sgn = pos - 1 + t, 1.0             # E position
+                            if q < 0:
+                                q, sgn = -q, -1.0
+                            elif q > n:
+                                q, sgn = 2 * n - q, -1.0
+                            self._add(M, r, ce, *at(q), sgn * s * inv * W4[t] / h)
 
     # -- conversions --------------------------------------------------------
     def to_vec(self, u) -> np.ndarray:

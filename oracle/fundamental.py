@@ -39,7 +39,7 @@ from __future__ import annotations
 import numpy as np
 
 from .implicit import line_operator_solve, solve_implicit
-from .yee import CIDX, PAIRS, Grid, apply_operator, diff_to_half, diff_to_integer, dynamic_mask, energy
+from .yee import CIDX, PAIRS, Grid, apply_operator, d_half, d_int, dynamic_mask, energy
 
 E_COMPS = ("Ex", "Ey", "Ez")
 H_COMPS = ("Hx", "Hy", "Hz")
@@ -51,7 +51,7 @@ def _implicit(op: str, e_rhs_src, h_src, theta: float, g: Grid):
     out = {}
     for ce, ch, w, s in PAIRS[op]:
         b = theta / g.eps
-        rhs = e_rhs_src[ce] + s * b * diff_to_integer(h_src[ch], w, g.spacing(w))
+        rhs = e_rhs_src[ce] + s * b * d_int(h_src[ch], w, g)
         out[ce] = line_operator_solve(rhs, ce, ch, w, 0.5 * theta * theta, 0.5, g)
     return out
 
@@ -60,7 +60,7 @@ def _h_update(op: str, h: dict, v: dict, theta: float, g: Grid, sign: float = 1.
     """H <- H + s d d_w V for the three pairs of `op` (dynamic H nodes only)."""
     for ce, ch, w, s in PAIRS[op]:
         d = theta / g.mu
-        h[ch] = h[ch] + sign * s * d * diff_to_half(v[ce], w, g.spacing(w)) * dynamic_mask(ch, g)
+        h[ch] = h[ch] + sign * s * d * d_half(v[ce], w, g) * dynamic_mask(ch, g)
 
 
 # ----------------------------------------------------------------------------

@@ -9,7 +9,11 @@ PEC cavity modes on the Yee grid.  For integer mode numbers (m, n, p) the fields
 (k_w = m_w pi / L_w), sampled at the Yee positions, satisfy the PEC walls, and
 the staggered central difference maps each profile to another one of the set:
   d_w sin(k_w w) = K_w cos(k_w w),  d_w cos(k_w w) = -K_w sin(k_w w),
-  K_w = (2/dw) sin(k_w dw / 2).
+  K_w = (2/dw) sin(k_w dw / 2)
+(order 2).  The fourth-order staggered difference (1, -27, 27, -1)/(24 dw) maps
+them the same way with K_w = (27 sin(k_w dw / 2) - sin(3 k_w dw / 2)) / (12 dw)
+(order 4), since the odd/even images across the PEC walls continue the sines
+and cosines.
 Hence the operators A and B of eq. (AMat) act on the six amplitudes as exact
 6x6 matrices (below), every scheme acts on them as a product of 6x6 Cayley
 factors, and the exact semi-discrete solution is expm(t (A + B)).
@@ -26,15 +30,19 @@ MU0 = 1.25663706212e-6
 C0 = 1.0 / math.sqrt(EPS0 * MU0)
 
 
-def wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p):
+def wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order=2):
     k = (m * math.pi / (nx * dx), n * math.pi / (ny * dy), p * math.pi / (nz * dz))
-    K = tuple(2.0 / h * math.sin(kw * h / 2.0) for kw, h in zip(k, (dx, dy, dz)))
+    if order == 4:
+        K = tuple((27.0 * math.sin(kw * h / 2.0) - math.sin(1.5 * kw * h)) / (12.0 * h)
+                  for kw, h in zip(k, (dx, dy, dz)))
+    else:
+        K = tuple(2.0 / h * math.sin(kw * h / 2.0) for kw, h in zip(k, (dx, dy, dz)))
     return k, K
 
 
-def mode_matrices(nx, ny, nz, dx, dy, dz, m, n, p, eps=EPS0, mu=MU0):
+def mode_matrices(nx, ny, nz, dx, dy, dz, m, n, p, eps=EPS0, mu=MU0, order=2):
     """6x6 matrices of A and B on the amplitudes (a1..a6) of the (m, n, p) mode."""
-    _, (Kx, Ky, Kz) = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p)
+    _, (Kx, Ky, Kz) = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order)
     A = np.zeros((6, 6))
     B = np.zeros((6, 6))
     # A: Ex<-(1/eps) dy Hz, Ey<-(1/eps) dz Hx, Ez<-(1/eps) dx Hy, Hx<-(1/mu) dz Ey, ...
@@ -134,11 +142,11 @@ def exact(A, B, t):
     return sl.expm(t * (A + B))
 
 
-def adi_dispersion_cos(nx, ny, nz, dx, dy, dz, m, n, p, dt, c=C0):
+def adi_dispersion_cos(nx, ny, nz, dx, dy, dz, m, n, p, dt, c=C0, order=2):
     """Closed form cos(w~ dt) of the ADI amplification on mode (m, n, p):
     (cx cy + cy cz + cz cx - 1)/2 with c_w = (1 - s_w^2)/(1 + s_w^2),
-    s_w = (c dt / dw) sin(k_w dw / 2)."""
-    _, K = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p)
+    s_w = (c dt / 2) K_w (order 2: (c dt / dw) sin(k_w dw / 2))."""
+    _, K = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order)
     s = [c * dt / 2 * Kw for Kw in K]
     cw = [(1 - x * x) / (1 + x * x) for x in s]
     return (cw[0] * cw[1] + cw[1] * cw[2] + cw[2] * cw[0] - 1) / 2
