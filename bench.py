@@ -91,6 +91,35 @@ def bytes_per_slot(prec, conv_adi=False, material_index=False):
     return words * w + (1 if material_index else 4)
 
 
+def order4_moved_bytes_per_slot(prec):
+    """Bytes a fourth-order line pass moves per slot: forward sweep reads E, H
+    and eps_r and writes four solve words (three multipliers and the
+    substituted right side), the backward sweep reads them back with E and H
+    and writes E and H: 6 field words + 4 + 8 solve words (60 B FP32, 116 B
+    FP64, 92 B FP32 fields with FP64 solves)."""
+    t = 8 if prec == "f64" else 4
+    sv = 8 if prec in ("f64", "f32s64") else 4
+    return 6 * t + 4 + 8 * sv
+
+
+def run_order4(n, precs, steps, warmup, inputs, refs):
+    """Fundamental ADI with the fourth-order differences on the n^3 workload:
+    per precision the run, the per-pass times and the fraction of 8 TB/s on
+    the scope's bytes (20 / 36 B per slot) and on the bytes the passes move."""
+    rows = []
+    for prec in precs:
+        r = run_variant(n, "adi", "fundamental", prec, steps, warmup, inputs, tune=False, refs=refs, order=4)
+        main = r["main_ms"] / steps
+        npass = 6
+        r["main_ms_per_step"] = main
+        r["moved_bytes_per_slot"] = order4_moved_bytes_per_slot(prec)
+        r["hbm_frac_moved_bytes_main"] = npass * pass_nodes(n) * r["moved_bytes_per_slot"] / (main * 1e-3) / 1e9 \
+            / HBM_PEAK_GBS
+        r["hbm_frac_alg_main"] = npass * pass_nodes(n) * bytes_per_slot(prec) / (main * 1e-3) / 1e9 / HBM_PEAK_GBS
+        rows.append(r)
+    return rows
+
+
 def pass_nodes(n):
     # every pass of a cubic n^3 grid covers n * (n-1) lines of n slots
     return n * (n - 1) * n
@@ -124,7 +153,7 @@ class Fp64Refs:
             self.diff_plan.close()
         self.cache, self.diff_plan = {}, None
 
-    def get(self, n, scheme, steps, warmup, inputs):
+    def get(self, n, scheme, steps, warmup, inputs, order=2):
         import torch
         from paper_2011_14043_amd import Plan, Source
         if n != self.n:
@@ -132,7 +161,7 @@ class Fp64Refs:
             self.n = n
         h, dt, eps, ci = inputs
         base = {"dyakonov": "adi", "douglas_gunn": "adi"}.get(scheme, scheme)
-        key = (base, dt, warmup, steps)
+        key = (base, dt, warmup, steps, order)
         if key not in self.cache:
             dev = torch.device("cuda", 0)
             shape = (n + 1, n + 1, n + 1)
@@ -141,6 +170,8 @@ class Fp64Refs:
             src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
             plan = Plan(n, n, n, dt, h, h, h, scheme=base, form="fundamental", dtype=torch.float64,
                         eps_r=torch.from_numpy(eps))
+            if order != 2:
+                plan.set_order(order)
             if warmup:
                 plan.run(E, H, warmup, source=src)
             plan.set_step(0)
@@ -153,12 +184,12 @@ class Fp64Refs:
             self.cache[key] = (E, H)
         return self.cache[key]
 
-    def rel_l2(self, n, scheme, steps, warmup, inputs, E, H):
+    def rel_l2(self, n, scheme, steps, warmup, inputs, E, H, order=2):
         """Energy-weighted relative L2 distance (fdtd_diff_norm, FP64 on the
         device) of E, H from the FP64 reference run."""
         import math
         import torch
-        Er, Hr = self.get(n, scheme, steps, warmup, inputs)
+        Er, Hr = self.get(n, scheme, steps, warmup, inputs, order)
         Ed = [t.to(torch.float64) for t in E]
         Hd = [t.to(torch.float64) for t in H]
         num, den = self.diff_plan.diff_norm(Ed, Hd, Er, Hr)
@@ -170,7 +201,7 @@ class Fp64Refs:
 
 
 def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_EVERY, tune=True, tune_reps=5,
-                refs=None):
+                refs=None, order=2):
     import torch
     from paper_2011_14043_amd import Plan, Source
     h, dt, eps, ci = inputs
@@ -183,6 +214,8 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
     src = Source(*ci, f0=10e9, tau=0.1e-9, t0=0.4e-9, amp=1.0e10)
     plan = Plan(n, n, n, dt, h, h, h, scheme=scheme, form=form, dtype=dtype, solve_dtype=solve,
                 eps_r=torch.from_numpy(eps), refine=REFINE.get(prec))
+    if order != 2:
+        plan.set_order(order)
     refined = plan.refined
     if tune:
         plan.autotune(tune_reps)
@@ -213,8 +246,10 @@ def run_variant(n, scheme, form, prec, steps, warmup, inputs, per_launch=TIMING_
                hbm_frac_actual_bytes=act_bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, main_ms=tm["main_ms"],
                yz_ms_avg=tm["yz_ms_avg"], x_ms_avg=tm["x_ms_avg"], yz_launches=tm["yz_launches"],
                x_launches=tm["x_launches"], finite=finite, kernel_config=cfg)
+    if order != 2:
+        out["order"] = order
     if refs is not None:
-        out["rel_l2_vs_gpu_fp64"] = refs.rel_l2(n, scheme, steps, warmup, inputs, E, H)
+        out["rel_l2_vs_gpu_fp64"] = refs.rel_l2(n, scheme, steps, warmup, inputs, E, H, order)
     del E, H
     torch.cuda.empty_cache()
     log(json.dumps(out))
@@ -526,7 +561,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-cavity and adjoint lines")
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--only", choices=["batch", "adjoint", "cn", "graphs"], default=None,
+    ap.add_argument("--only", choices=["batch", "adjoint", "cn", "graphs", "order4"], default=None,
                     help="run only the batched-cavity or the adjoint measurement and print its JSON")
     ap.add_argument("--cpu-schemes", action="store_true",
                     help="only time the FP64 oracle per scheme and form on the host (no GPU) and print its JSON")
@@ -563,6 +598,12 @@ def main():
         return
     if args.only == "graphs":
         print(json.dumps(run_graphs()), flush=True)
+        return
+    if args.only == "order4":
+        refs = Fp64Refs()
+        rows = run_order4(args.n, ("f32", "f64"), 10, 2, make_inputs(args.n), refs)
+        refs.close()
+        print(json.dumps(rows), flush=True)
         return
     n = args.n
     inputs = make_inputs(n)
@@ -606,6 +647,8 @@ def main():
         extras["adjoint_gradient"] = run_adjoint()
         extras["graphs_128x128x64"] = run_graphs()
         extras["crank_nicolson_256cube"] = run_cn()
+        # fourth-order differences (fdtd_set_order), fundamental ADI on the same 512^3 workload
+        extras["adi_fundamental_order4_512cube"] = run_order4(n, ("f32",), 10, 2, inputs, refs)
         # the smaller size of the same workload (256^3), FP32 as the library runs it and plain
         in256 = make_inputs(256)
         extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256, refs=refs)

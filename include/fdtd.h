@@ -153,8 +153,28 @@ typedef struct { int i, j, k; double f0, tau, t0, amp; } fdtd_source;
 fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out);
 
 /* *refined (host) = 1 if the plan's FP32 line solves are refined
- * (FDTD_F32_REFINE, or FDTD_F32 below the sigma threshold above), else 0. */
+ * (FDTD_F32_REFINE, or FDTD_F32 where refined passes are built), else 0. */
 fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined);
+
+/* Accuracy order of the staggered first differences d_w of the updating
+ * equations (Sec. III-A; its closing remark leaves the difference operators
+ * open: higher order, optimized, compact): 2 (the Yee differences, the
+ * default) or 4, the fourth-order staggered difference
+ *   d_w f = (f[-3/2] - 27 f[-1/2] + 27 f[+1/2] - f[+3/2]) / (24 dw),
+ * used in every implicit line equation, explicit H update and input/output
+ * operator.  Near a PEC wall the stencil reaches image samples across it
+ * (tangential E odd about the wall, tangential H even), which keeps A and B
+ * skew-adjoint in the energy norm, so the schemes remain unconditionally
+ * stable and energy-conserving; each line system then couples every E
+ * sample to three neighbours on either side (symmetric positive definite,
+ * solved by one thread per line).  Order 4: single-grid plans of the
+ * fundamental forms (ADI, LOD1, SS2, LOD2, D'Yakonov, Douglas-Gunn) with unit
+ * permeability and without FDTD_F32_REFINE (else FDTD_EUNSUPPORTED); FDTD_F32
+ * plans then solve plainly; the plan allocates a work area of 12 arrays of
+ * its state's size in the solve precision (FDTD_ENOMEM).  Batch plans:
+ * FDTD_EINVAL.  Synchronizes the plan's stream; takes effect at the next
+ * run. */
+fdtd_status fdtd_set_order(fdtd_plan_t p, int order);
 
 /* Advance the caller's fields by `nsteps` >= 0 full time steps:
  *   input processing (ADI: u^0 -> (1/2 I + dt/4 B) u^0, the link of

@@ -119,6 +119,7 @@ class Plan:
         self._h = h
         del keep
         self.scheme, self.form = scheme, form
+        self.order = 2
         self.refined = self._refined()
 
     def _refined(self) -> bool:
@@ -150,6 +151,14 @@ class Plan:
     def set_graph(self, steps: int):
         """Steps per captured HIP graph of fdtd_run (0: launch every step directly)."""
         _lib.check(_lib.lib().fdtd_set_graph(self._h, int(steps)), "fdtd_set_graph")
+
+    def set_order(self, order: int):
+        """Accuracy order of the staggered differences: 2 (Yee) or 4
+        (fdtd_set_order; fundamental forms, unit permeability).  Refreshes
+        `refined`."""
+        _lib.check(_lib.lib().fdtd_set_order(self._h, int(order)), "fdtd_set_order")
+        self.order = int(order)
+        self.refined = self._refined()
 
     def set_step(self, n: int):
         _lib.check(_lib.lib().fdtd_set_step(self._h, int(n)), "fdtd_set_step")

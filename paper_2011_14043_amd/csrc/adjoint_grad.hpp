@@ -86,10 +86,10 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
     } while (0)
 
     // forward sweep: J, checkpoints every K steps
-    const AuxCoef kin = aux_coef(d, 0.25 * d.dt);
-    hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(p->dims), dim3(kRowThreads), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
-                       p->eps, p->mu, dm, kin);
-    HIPCHK(hipGetLastError());
+    {
+        const fdtd_status st = load_state<T, S>(p, caller, 0.25 * d.dt);
+        if (st != FDTD_OK) return st;
+    }
     HIPCHK(hipMemsetAsync(Jd, 0, 256, p->stream));
     for (int n = 0; n < nsteps; ++n) {
         if (want && n % K == 0) HIPCHK(hipMemcpyAsync(ckpt(n / K), st0, ssz, hipMemcpyDeviceToDevice, p->stream));

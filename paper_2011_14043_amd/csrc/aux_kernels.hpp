@@ -66,6 +66,7 @@ struct AuxCoef {
     double link;                  // ADI: dt/4 (state = 1/2 u + dt/4 B u); 0 for a plain copy
     int fin_form;                 // energy of a fundamental ADI state in output form (static H
                                   // still hold 1/2 u, i.e. their link value)
+    int order;                    // 4: the fourth-order differences (apply_B4); else second order
 };
 
 // (B u)_c at a node, operator B of eq. (AMat) with Yee central differences.
@@ -80,6 +81,71 @@ __device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, dou
         case 3: return -inv_mu * (double(get(2, i, j + 1, k)) - double(get(2, i, j, k))) * q.rdy;    // -dEz/dy
         case 4: return -inv_mu * (double(get(0, i, j, k + 1)) - double(get(0, i, j, k))) * q.rdz;    // -dEx/dz
         default: return -inv_mu * (double(get(1, i + 1, j, k)) - double(get(1, i, j, k))) * q.rdx;   // -dEy/dx
+    }
+}
+
+// (B u)_c at a node with the fourth-order staggered differences, weights
+// (1, -27, 27, -1) / 24 over the four partner samples along the pair's axis
+// (B pairs: Ex-Hy along z, Ey-Hz along x, Ez-Hx along y), folded across a PEC
+// wall onto image samples: H even (stored index -1 -> 0, n -> n-1), E odd
+// (position -p -> -E_p, n + p -> -E_{n-p}; E on a wall is 0).  `get` returns
+// the physical sample (0 for E off its dynamic set).
+template <typename F>
+__device__ __forceinline__ double apply_B4(F get, int c, int i, int j, int k, double inv_eps, double inv_mu,
+                                           const AuxCoef& q, const Dims& d) {
+    constexpr double w[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
+    const int axis = (c == 1 || c == 5) ? 0 : ((c == 2 || c == 3) ? 1 : 2);
+    const int partner = c < 3 ? (c == 0 ? 4 : (c == 1 ? 5 : 3)) : (c == 3 ? 2 : (c == 4 ? 0 : 1));
+    const int n = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
+    const int pos = axis == 0 ? i : (axis == 1 ? j : k);
+    const double rh = axis == 0 ? q.rdx : (axis == 1 ? q.rdy : q.rdz);
+    auto at = [&](int p) -> double {
+        return double(axis == 0 ? get(partner, p, j, k) : (axis == 1 ? get(partner, i, p, k) : get(partner, i, j, p)));
+    };
+    double s = 0.0;
+    if (c < 3) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int qh = pos - 2 + t;
+            qh = qh < 0 ? -1 - qh : (qh > n - 1 ? 2 * n - 1 - qh : qh);
+            s += w[t] * at(qh);
+        }
+        return -inv_eps * s * rh;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int pe = pos - 1 + t;
+        double sg = 1.0;
+        if (pe < 0) { pe = -pe; sg = -1.0; }
+        else if (pe > n) { pe = 2 * n - pe; sg = -1.0; }
+        s += sg * w[t] * at(pe);
+    }
+    return -inv_mu * s * rh;
+}
+
+// Input processing with the fourth-order differences: U = 1/2 u + link (B u)
+// (the ADI link of Sec. II-E) in FP64, one thread per node (once per run).
+// Non-dynamic E -> 0, static normal H -> 1/2 u.
+template <typename T>
+__global__ void load_state4_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps, const float* mu, Dims d,
+                                   AuxCoef k_) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
+    if (idx >= nn) return;
+    const Node nd = node_of(unsigned(idx), d);
+    const int i = nd.i, j = nd.j, k = nd.k;
+    const long long so = (long long)k * d.plane + (long long)j * d.px + i;
+    auto get = [&](int c, int ii, int jj, int kk) -> T { return phys(f, c, ii, jj, kk, d); };
+    const double inv_eps = 1.0 / (k_.eps0 * double(eps[so]));
+    const double inv_mu = 1.0 / (k_.mu0 * (mu ? double(mu[so]) : 1.0));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double u = double(get(c, i, j, k));
+        const bool dyn = is_dynamic(c, i, j, k, d);
+        double v;
+        if (c < 3) v = dyn ? 0.5 * u + k_.link * apply_B4(get, c, i, j, k, inv_eps, inv_mu, k_, d) : 0.0;
+        else v = dyn ? 0.5 * u + k_.link * apply_B4(get, c, i, j, k, inv_eps, inv_mu, k_, d) : 0.5 * u;
+        s.c[c][so] = T(v);
     }
 }
 
@@ -248,7 +314,9 @@ __global__ void __launch_bounds__(256) energy_partial_kernel(FieldPtrs<T> s, con
             for (int c = 0; c < 6; ++c) {
                 const double u = double(get(c, i, j, k));
                 const bool dyn = is_dynamic(c, i, j, k, d);
-                const double bu = dyn ? apply_B<T>(get, c, i, j, k, inv_eps, inv_mu, k_) : 0.0;
+                const double bu = !dyn ? 0.0
+                                  : (k_.order == 4 ? apply_B4(get, c, i, j, k, inv_eps, inv_mu, k_, d)
+                                                   : apply_B<T>(get, c, i, j, k, inv_eps, inv_mu, k_));
                 const double v = (k_.fin_form && c >= 3 && !dyn) ? u : 0.5 * u + k_.link * bu;
                 acc += (c < 3 ? ew : mw) * v * v;
             }

@@ -32,6 +32,7 @@
 #include "adjoint_kernels.hpp"
 #include "aux_kernels.hpp"
 #include "cn_kernels.hpp"
+#include "order4_kernels.hpp"
 #include "pass_dispatch.hpp"
 #include "plan_state.hpp"
 #include "pass_launch.hpp"
@@ -335,6 +336,33 @@ fdtd_status fdtd_set_graph(fdtd_plan_t p, int steps) {
     return FDTD_OK;
 }
 
+fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
+    if (!plan_ok(p) || p->batch || (order != 2 && order != 4)) return FDTD_EINVAL;
+    if (order == p->order) return FDTD_OK;
+    if (order == 4) {
+        // fundamental forms of the line-pass schemes, unit permeability, no
+        // refined solves
+        if (p->cg || p->d.form != FDTD_FUNDAMENTAL || p->mu || p->req_dtype == FDTD_F32_REFINE)
+            return FDTD_EUNSUPPORTED;
+        if (!p->scr4) {
+            const size_t ssz = (p->d.dtype == FDTD_F32) ? sizeof(float) : sizeof(double);
+            if (hipMalloc(&p->scr4, ssz * 12 * (size_t)p->dims.comp) != hipSuccess) {
+                p->scr4 = nullptr;
+                return FDTD_ENOMEM;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(p->stream);
+    graph_clear(p);
+    p->order = order;
+    // refined solves exist for the second-order passes only
+    p->refine = (order == 2 && (p->req_dtype == FDTD_F32_REFINE ||
+                                (p->req_dtype == FDTD_F32 && f32_refine_wanted(p->d, p->mu != nullptr))))
+                    ? 1
+                    : 0;
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined) {
     if (!plan_ok(p) || !refined) return FDTD_EINVAL;
     *refined = p->refine;
@@ -388,6 +416,12 @@ fdtd_status fdtd_last_timing(fdtd_plan_t p, double* main_ms, double* fam_ms_avg,
 fdtd_status fdtd_autotune(fdtd_plan_t p, int reps, double* best_ms) {
     if (!plan_ok(p) || reps < 1) return FDTD_EINVAL;
     if (p->cg) return FDTD_EUNSUPPORTED;   // Crank-Nicolson: no line passes
+    if (p->order == 4) {
+        // one launch shape (a thread per line): nothing to tune
+        p->tuned = 1;
+        if (best_ms) best_ms[0] = best_ms[1] = best_ms[2] = 0.0;
+        return FDTD_OK;
+    }
     if (p->batch && !p->batch->groups.empty()) {
         // each group tunes for its own grids; best_ms: one pass over all groups
         double tot[3] = {0, 0, 0};
@@ -695,6 +729,7 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->snap) (void)hipFree(p->snap);
     if (p->eps) (void)hipFree(p->eps);
     if (p->mu) (void)hipFree(p->mu);
+    if (p->scr4) (void)hipFree(p->scr4);
     if (p->partial) (void)hipFree(p->partial);
     if (p->energy_dev) (void)hipFree(p->energy_dev);
     if (p->mat) (void)hipFree(p->mat);

@@ -166,6 +166,59 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
     if (fin) a.fsrc = fin->src;
 }
 
+// Band of D^T D (the fourth-order difference D, folded onto the wall images)
+// for a line of n cells: rows 1..3 (lo) and n-3..n-1 (hi), entries
+// {A_jj, A_j,j-1, A_j,j-2, A_j,j-3}, 0 where a column is not an unknown.
+static void band4_rows(int n, double lo[3][4], double hi[3][4]) {
+    static const double w[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
+    auto coef = [n](int h, int p) {   // D[h][p]: H sample h, E unknown p
+        double c = 0.0;
+        for (int t = 0; t < 4; ++t) {
+            int q = h - 1 + t;
+            double sg = 1.0;
+            if (q < 0) { q = -q; sg = -1.0; }
+            else if (q > n) { q = 2 * n - q; sg = -1.0; }
+            if (q == p && q >= 1 && q <= n - 1) c += sg * w[t];
+        }
+        return c;
+    };
+    auto A = [&](int j, int k) {
+        double s = 0.0;
+        for (int h = std::max(0, std::max(j, k) - 2); h <= std::min(n - 1, std::min(j, k) + 1); ++h)
+            s += coef(h, j) * coef(h, k);
+        return s;
+    };
+    for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 4; ++t) {
+            const int jl = r + 1, jh = n - 3 + r;
+            lo[r][t] = (jl <= n - 1 && jl - t >= 1) ? A(jl, jl - t) : 0.0;
+            hi[r][t] = (jh >= 1 && jh - t >= 1) ? A(jh, jh - t) : 0.0;
+        }
+}
+
+// A fourth-order pass (pair k of operator op, fundamental form, in place).
+template <typename T, typename S>
+static fdtd_status launch_pass4(fdtd_plan_s* p, int op, int k, double theta, T* set, const Inject* inj,
+                                const Fin* fin) {
+    Pass4Args<T, S> a4;
+    PassShape sh;
+    build_pass<T, S>(p, op, k, theta, FUND, set, set, inj, a4.p, sh, fin);
+    a4.nlines = (long long)a4.p.na * a4.p.nb;
+    a4.scr = reinterpret_cast<S*>(p->scr4) + (size_t)k * 4 * p->dims.comp;
+    band4_rows(a4.p.n_w, a4.blo, a4.bhi);
+    if (sh.w == 0) {
+        // x lines: 64 lines per one-wave block, rows staged through LDS (sw = 1)
+        const dim3 grid((unsigned)((a4.nlines + 63) / 64)), block(64);
+        if (fin) hipLaunchKernelGGL((pass4_x_kernel<T, S, true>), grid, block, 0, p->stream, a4);
+        else hipLaunchKernelGGL((pass4_x_kernel<T, S, false>), grid, block, 0, p->stream, a4);
+    } else {
+        const dim3 grid((unsigned)((a4.nlines + 127) / 128)), block(128);
+        if (fin) hipLaunchKernelGGL((pass4_kernel<T, S, true>), grid, block, 0, p->stream, a4);
+        else hipLaunchKernelGGL((pass4_kernel<T, S, false>), grid, block, 0, p->stream, a4);
+    }
+    return FDTD_OK;
+}
+
 template <typename T, typename S>
 static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T* set_in, T* set_out,
                                const Inject* inj, bool timed, const Fin* fin = nullptr) {
@@ -192,7 +245,13 @@ static fdtd_status launch_pass(fdtd_plan_s* p, int op, int k, double theta, int 
     const int kmode = (mode == FUND && p->refine) ? FUND_REF : mode;
     const bool fused = fin != nullptr;
     int r;
-    if (sh.mu) {
+    if (p->order == 4) {
+        // fourth-order differences: fundamental forms, in place (set_in == set_out)
+        if (mode != FUND || set_in != set_out) return FDTD_EUNSUPPORTED;
+        fdtd_status st = launch_pass4<T, S>(p, op, k, theta, set_out, inj, fin);
+        if (st != FDTD_OK) return st;
+        r = DISPATCH_OK;
+    } else if (sh.mu) {
         r = sh.w == 0 ? dispatch_x_mu<T, S>(kmode, cf.M, sh.full, fused, sh.grid, sh.block, p->stream, a)
                       : dispatch_yz_mu<T, S>(kmode, cf.M, cf.TX, cf.NT, sh.full, fused, sh.grid, sh.block, sh.lds,
                                              p->stream, a);

@@ -110,6 +110,8 @@ struct fdtd_plan_s {
     void* snap = nullptr;     // grid of an ADI batch: state before the last B sub-step
     float* eps = nullptr;     // node layout, padded
     float* mu = nullptr;      // mu_r in node layout (plans with a permeability map; else NULL)
+    int order = 2;            // accuracy order of the staggered differences (fdtd_set_order: 2 or 4)
+    void* scr4 = nullptr;     // order 4: line-solve work area, 3 pairs x 4 arrays x comp (solve type)
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
     // 3 x 1024 partial sums, scalars; CG controls and the last run's statistics

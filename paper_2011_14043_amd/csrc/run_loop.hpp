@@ -35,10 +35,29 @@ static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst, bool fin_fo
     AuxCoef k = aux_coef(p->d, 0.0);
     if (p->d.scheme == FDTD_ADI && (p->d.form == FDTD_CONVENTIONAL || fin_form)) k.link = 0.25 * p->d.dt;
     k.fin_form = fin_form ? 1 : 0;
+    k.order = p->order;
     hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
                        state_ptrs<T>(p, set), p->eps, p->mu, p->dims, k, p->partial);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, p->stream, p->partial, p->npartial, dst);
+    HIPCHK(hipGetLastError());
+    return FDTD_OK;
+}
+
+// Input processing into state set 0: U = 1/2 u + link B u (link = dt/4 for
+// the ADI link of Sec. II-E), else U = u; with the plan's difference order.
+template <typename T, typename S>
+static fdtd_status load_state(fdtd_plan_s* p, const FieldPtrs<T>& caller, double link) {
+    AuxCoef kin = aux_coef(p->d, link);
+    kin.order = p->order;
+    if (p->order == 4 && link != 0.0) {
+        const long long nn = (long long)(p->dims.nx + 1) * (p->dims.ny + 1) * (p->dims.nz + 1);
+        hipLaunchKernelGGL((load_state4_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream, caller,
+                           state_ptrs_w<T>(p, 0), p->eps, p->mu, p->dims, kin);
+    } else {
+        hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(p->dims), dim3(kRowThreads), 0, p->stream, caller,
+                           state_ptrs_w<T>(p, 0), p->eps, p->mu, p->dims, kin);
+    }
     HIPCHK(hipGetLastError());
     return FDTD_OK;
 }
@@ -215,10 +234,10 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
         p->energy_cap = nrec;
     }
     // input processing
-    const AuxCoef kin = aux_coef(d, (adi && !conv) ? 0.25 * d.dt : 0.0);
-    hipLaunchKernelGGL((load_state_kernel<T, S>), row_grid(dm), dim3(kRowThreads), 0, p->stream, caller, state_ptrs_w<T>(p, 0),
-                       p->eps, p->mu, dm, kin);
-    HIPCHK(hipGetLastError());
+    {
+        const fdtd_status st = load_state<T, S>(p, caller, (adi && !conv) ? 0.25 * d.dt : 0.0);
+        if (st != FDTD_OK) return st;
+    }
     int cur = 0;
     if (adi && conv) {
         HIPCHK(hipMemcpyAsync(comp_ptr<T>(p, 1, 0), comp_ptr<T>(p, 0, 0), sizeof(T) * dm.comp * 6,

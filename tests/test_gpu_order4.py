@@ -1,0 +1,233 @@
+"""Fourth-order staggered differences on the GPU (fdtd_set_order(plan, 4))
+against the FP64 oracle with grid order 4, whose operators and schemes are
+pinned on the CPU (tests/test_oracle_order4.py).
+
+Checked: every fundamental scheme at every precision on a ragged grid with
+random eps_r boxes, a point source and CFL 10 (fields and energy trace); long
+x lines; a cavity mode at 64^3 against the exact 6x6 evolution with
+K4 = (27 sin(k h/2) - sin(3 k h/2)) / (12 h); exact energy conservation at
+CFL 20; captured graphs against direct launches; the adjoint gradient against
+the oracle's reverse mode; switching back to second order; the argument
+checks.  Bars as for the second-order passes: FP64 1e-11, FP32 fields with
+FP64 solves 2e-6, FP32 2e-5 over tens of steps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import adjoint
+from oracle.source import Source as OSource
+
+from . import _analytic as an
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
+        "f32s64": (torch.float32, torch.float64)}
+TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
+STEPS, EVERY = 8, 2
+
+
+def _fields(u0, dtype):
+    return ([torch.tensor(a, dtype=dtype, device=DEV) for a in u0[:3]],
+            [torch.tensor(a, dtype=dtype, device=DEV) for a in u0[3:]])
+
+
+def _plan(c, scheme, prec, order=4, **kw):
+    from paper_2011_14043_amd import Plan
+    dtype, solve = PREC[prec]
+    p = Plan(c["nx"], c["ny"], c["nz"], c["dt"], c["hx"], c["hy"], c["hz"], scheme=scheme, dtype=dtype,
+             solve_dtype=solve, eps_r=None if c.get("eps") is None else torch.tensor(c["eps"]), **kw)
+    p.set_order(order)
+    return p
+
+
+def _gsrc(s):
+    from paper_2011_14043_amd import Source
+    return None if s is None else Source(s.i, s.j, s.k, f0=s.f0, tau=s.tau, t0=s.t0, amp=s.amp)
+
+
+@pytest.fixture(scope="module")
+def case():
+    nx, ny, nz = 23, 19, 27
+    hx, hy, hz = 1e-3, 1.2e-3, 0.9e-3
+    dt = W.yee_dt(hx, hy, hz, 10.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=61, nboxes=8)
+    u0 = W.random_fields(nx, ny, nz, seed=62)
+    ci = W.interior_cell(nx, ny, nz, seed=63, margin=4)
+    src = OSource(*ci, amp=1e12, t0=3 * dt, tau=3 * dt, f0=1 / (12 * dt))
+    g = oracle.Grid(nx, ny, nz, hx, hy, hz, dt, eps, order=4)
+    refs = {s: oracle.run(s, "fundamental", g, u0, STEPS, src, EVERY) for s in oracle.SCHEMES + oracle.SPLITTINGS}
+    return dict(nx=nx, ny=ny, nz=nz, hx=hx, hy=hy, hz=hz, dt=dt, eps=eps, u0=u0, src=src, g=g, refs=refs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32s64"])
+@pytest.mark.parametrize("scheme,key", [("adi", "adi"), ("lod1", "lod1"), ("ss2", "ss2"), ("lod2", "lod2"),
+                                        ("dyakonov", "dy"), ("douglas_gunn", "dg")])
+def test_order4_parity(case, scheme, key, prec):
+    c = case
+    print(f"[case] order 4 23x19x27 {scheme}/{prec}", flush=True)
+    p = _plan(c, scheme, prec)
+    assert not p.refined
+    E, H = _fields(c["u0"], PREC[prec][0])
+    tr = p.run(E, H, STEPS, source=_gsrc(c["src"]), energy_every=EVERY)
+    torch.cuda.synchronize()
+    p.close()
+    got = [t.double().cpu().numpy() for t in E + H]
+    ref, tr_ref = c["refs"][key]
+    err = oracle.yee.weighted_rel_l2(got, ref, c["g"])
+    terr = float(np.max(np.abs(np.array(tr) - np.array(tr_ref)) / np.abs(np.array(tr_ref))))
+    print(f"  rel-L2 {err:.3e}  energy {terr:.3e}", flush=True)
+    assert err < TOL[prec], err
+    assert terr < 10 * TOL[prec], terr
+    for n, comp in enumerate(W.COMPONENTS):
+        out = ~W.extent_mask(comp, c["nx"], c["ny"], c["nz"])
+        assert np.array_equal(got[n][out], c["u0"][n][out].astype(got[n].dtype))
+        if comp[0] == "E":
+            wall = W.wall_tangential_mask(comp, c["nx"], c["ny"], c["nz"]) & \
+                W.extent_mask(comp, c["nx"], c["ny"], c["nz"])
+            assert np.all(got[n][wall] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_order4_long_lines(prec):
+    """300-cell x lines (strided lanes) and 2-cell z lines, anisotropic cells."""
+    nx, ny, nz = 300, 5, 2
+    hx, hy, hz = 0.5e-3, 1e-3, 0.8e-3
+    dt = W.yee_dt(hx, hy, hz, 6.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=71, nboxes=6)
+    u0 = W.random_fields(nx, ny, nz, seed=72)
+    g = oracle.Grid(nx, ny, nz, hx, hy, hz, dt, eps, order=4)
+    ref, _ = oracle.run("adi", "fundamental", g, u0, 5)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=hx, hy=hy, hz=hz, dt=dt, eps=eps)
+    print(f"[case] order 4 long lines 300x5x2 {prec}", flush=True)
+    p = _plan(c, "adi", prec)
+    E, H = _fields(u0, PREC[prec][0])
+    p.run(E, H, 5)
+    torch.cuda.synchronize()
+    p.close()
+    err = oracle.yee.weighted_rel_l2([t.double().cpu().numpy() for t in E + H], ref, g)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32s64"])
+def test_order4_cavity_mode_64cube(prec):
+    """A (2, 1, 3) mode of a 64^3 vacuum box after 30 ADI steps at CFL 6,
+    against the closed-form 6x6 evolution with the fourth-order K4."""
+    n, h = 64, 1e-3
+    dt = W.yee_dt(h, h, h, 6.0)
+    mnp = (2, 1, 3)
+    a = np.random.default_rng(8).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(n, n, n, h, h, h, *mnp, order=4)
+    N = 30
+    ref = an.mode_fields(n, n, n, h, h, h, *mnp, np.linalg.matrix_power(an.scheme_matrix("adi", A6, B6, dt), N) @ a)
+    u0 = an.mode_fields(n, n, n, h, h, h, *mnp, a)
+    c = dict(nx=n, ny=n, nz=n, hx=h, hy=h, hz=h, dt=dt, eps=None)
+    print(f"[case] order 4 cavity mode 64^3 {prec}", flush=True)
+    p = _plan(c, "adi", prec)
+    E, H = _fields(u0, PREC[prec][0])
+    p.run(E, H, N)
+    torch.cuda.synchronize()
+    p.close()
+    g = oracle.Grid(n, n, n, h, h, h, dt)
+    err = oracle.yee.weighted_rel_l2([t.double().cpu().numpy() for t in E + H], ref, g)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("scheme", ["adi", "lod1", "ss2", "lod2"])
+def test_order4_energy_conserved(scheme):
+    """Exact energy conservation of the fourth-order Cayley sub-steps at CFL 20
+    (FP64, random media, 60 steps)."""
+    nx, ny, nz, h = 20, 17, 15, 1e-3
+    dt = W.yee_dt(h, h, h, 20.0)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=h, hy=h, hz=h, dt=dt, eps=W.random_box_eps(nx, ny, nz, seed=81, nboxes=6))
+    p = _plan(c, scheme, "f64")
+    E, H = _fields(W.random_fields(nx, ny, nz, seed=82), torch.float64)
+    tr = np.array(p.run(E, H, 60, energy_every=10))
+    p.close()
+    drift = float(np.abs(tr - tr[0]).max() / tr[0])
+    print(f"[case] order 4 energy {scheme}: drift {drift:.3e}", flush=True)
+    assert drift < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_order4_graphs_equal_direct(case, prec):
+    c = case
+    print(f"[case] order 4 graphs {prec}", flush=True)
+    pg = _plan(c, "adi", prec)
+    pe = _plan(c, "adi", prec)
+    pg.set_graph(4)
+    pe.set_graph(0)
+    fg, fe = _fields(c["u0"], PREC[prec][0]), _fields(c["u0"], PREC[prec][0])
+    for n in (13, 5, 9):
+        pg.run(*fg, n, source=_gsrc(c["src"]))
+        pe.run(*fe, n, source=_gsrc(c["src"]))
+        torch.cuda.synchronize()
+        for a, b in zip(fg[0] + fg[1], fe[0] + fe[1]):
+            assert torch.equal(a, b)
+    pg.close()
+    pe.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_order4_adjoint_gradient(prec):
+    nx, ny, nz, h = 5, 4, 6, 1e-3
+    dt = W.yee_dt(h, h, h, 3.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=91, nboxes=3)
+    u0 = W.random_fields(nx, ny, nz, seed=92)
+    src = OSource(2, 2, 2, amp=1e11, t0=3 * dt, tau=2 * dt, f0=1 / (10 * dt))
+    probe = (3, 2, 3)
+    steps = 10
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps, order=4)
+    J_ref, grad_ref = adjoint.gradient(g, u0, steps, src, probe)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=h, hy=h, hz=h, dt=dt, eps=eps)
+    p = _plan(c, "adi", prec)
+    E, H = _fields(u0, PREC[prec][0])
+    J, grad = p.grad_eps(E, H, steps, probe, _gsrc(src), (0, nx, 0, ny, 0, nz), 4)
+    p.close()
+    grad = grad.cpu().numpy()
+    gerr = np.max(np.abs(grad - grad_ref)) / np.max(np.abs(grad_ref))
+    jerr = abs(J - J_ref) / abs(J_ref)
+    print(f"[case] order 4 adjoint {prec}: J {jerr:.3e}  grad {gerr:.3e}", flush=True)
+    tol = 1e-9 if prec == "f64" else 2e-4
+    assert jerr < tol and gerr < tol
+
+
+def test_order4_back_to_second_order(case):
+    """set_order(4) then set_order(2) runs exactly the plan that never changed
+    (FP32: refined again)."""
+    c = case
+    p2 = _plan(c, "adi", "f32", order=2)
+    p42 = _plan(c, "adi", "f32")
+    assert not p42.refined
+    p42.set_order(2)
+    assert p42.refined == p2.refined
+    a, b = _fields(c["u0"], torch.float32), _fields(c["u0"], torch.float32)
+    p2.run(*a, 6, source=_gsrc(c["src"]))
+    p42.run(*b, 6, source=_gsrc(c["src"]))
+    torch.cuda.synchronize()
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert torch.equal(x, y)
+    p2.close()
+    p42.close()
+
+
+def test_order4_arguments(case):
+    from paper_2011_14043_amd import FdtdError, Plan
+    c = case
+    args = (c["nx"], c["ny"], c["nz"], c["dt"], c["hx"], c["hy"], c["hz"])
+    p = Plan(*args)
+    for bad in (0, 3, 6, -4):
+        with pytest.raises(FdtdError, match="EINVAL"):
+            p.set_order(bad)
+    p.close()
+    for kw in (dict(form="conventional"), dict(refine=True), dict(mu_r=torch.full((c["nz"], c["ny"], c["nx"]), 2.0)),
+               dict(scheme="crank_nicolson", dtype=torch.float64)):
+        q = Plan(*args, **kw)
+        with pytest.raises(FdtdError, match="EUNSUPPORTED"):
+            q.set_order(4)
+        q.close()
