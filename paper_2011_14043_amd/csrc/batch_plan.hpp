@@ -40,12 +40,17 @@ static KCfg x_alone_cfg(const fdtd_plan_s* p) {
     return c;
 }
 
+static bool refined_batch_cfg(int axis, const KCfg& c) {
+    return c.M == 8 || (axis != 0 && c.M == 16 && c.NT == 512);
+}
+
 static bool batch_cfg_valid(const fdtd_plan_s* p, int axis, const KCfg& c0) {
     KCfg c = c0;
     if (axis == 0 && c.wpb == 0) c.wpb = 4;
-    // refined batched passes: 8-slot chunks (the 16-slot y/z variant does not fit
-    // its registers with the batch addressing)
-    if (p->refine && c.M != 8) return false;
+    // refined batched passes: 8-slot chunks, or 16-slot y/z chunks in blocks of
+    // at most 512 threads (136 VGPRs with the batch addressing; a 1024-thread
+    // bound would cap them at 128)
+    if (p->refine && !refined_batch_cfg(axis, c)) return false;
     int Pmax = 1;
     for (const fdtd_plan_s* g : p->batch->subs) {
         if (!cfg_valid(g, axis, c)) return false;
@@ -84,7 +89,7 @@ static bool same_kcfg(const KCfg& a, const KCfg& b) {
 static bool fused_ok(const fdtd_plan_s* p) {
     if (p->cfg[0].wpb != 0 || p->cfg[0].M != 8 || !yz_same_cfg(p)) return false;
     const KCfg& c = p->cfg[1];
-    if (p->refine && c.M != 8) return false;
+    if (p->refine && !refined_batch_cfg(1, c)) return false;
     if (p->d.dtype == FDTD_F32) {
         for (const auto& v : kSubF32)
             if (v[0] == c.M && v[1] == c.TX && v[2] == c.NT) return true;

@@ -234,7 +234,7 @@ int dispatch_batch_m(int kind, int M, int TX, int NT, bool mat, dim3 grid, dim3 
         // fused sub-step: x lines with 8-slot chunks inside the y/z launch
 #define CASE_SUB(MM, TT, NN)                                                                                         \
     if (M == MM && TX == TT && NN == NT) {                                                                           \
-        if constexpr (MODE != FUND_REF || MM == 8) {                                                                 \
+        if constexpr (MODE != FUND_REF || MM == 8 || (MM == 16 && NN == 512)) {                                                                 \
             if (mat)                                                                                                 \
                 hipLaunchKernelGGL((pass_sub_batch_kernel<T, S, 8, MM, MODE, TT, NN, true>), grid, block, lds, st,  \
                                    tab, items, ex0);                                                                 \
@@ -270,7 +270,7 @@ int dispatch_batch_m(int kind, int M, int TX, int NT, bool mat, dim3 grid, dim3 
     }
 #define CASE_YZB(MM, TT, NN)                                                                                      \
     if (M == MM && TX == TT && NT == NN) {                                                                        \
-        if constexpr (MODE != FUND_REF || MM == 8) {                                                              \
+        if constexpr (MODE != FUND_REF || MM == 8 || (MM == 16 && NN == 512)) {                                                              \
             if (mat)                                                                                              \
                 hipLaunchKernelGGL((pass_yz_batch_kernel<T, S, MM, MODE, TT, NN, true>), grid, block, lds, st, tab, \
                                    items);                                                                        \

@@ -68,6 +68,30 @@ def test_batch_vs_oracle_small(small_refs, scheme, prec):
         assert err <= TOL[prec], (g, err)
 
 
+@pytest.mark.parametrize("launch", ["fused", "yz-one-launch"])
+@pytest.mark.parametrize("scheme", ["adi", "ss2"])
+def test_batch_refined_16slot_vs_oracle(small_refs, scheme, launch):
+    """Refined batched passes with 16-slot y/z chunks (512-thread blocks),
+    the x lines fused into the same launch or a launch of their own."""
+    from paper_2011_14043_amd import BatchPlan
+    c = small_refs
+    print(f"[case] batch 5 grids refined 16-slot {scheme} {launch}", flush=True)
+    plan = BatchPlan([(nx, ny, nz, torch.tensor(eps)) for (nx, ny, nz, eps, _) in c["grids"]], c["dt"], c["h"],
+                     c["h"], c["h"], scheme=scheme, dtype=torch.float32, refine=True)
+    plan.set_kernel_config(0, chunk=8, block_threads=0 if launch == "fused" else 256, remap=1)
+    for ax in (1, 2):
+        plan.set_kernel_config(ax, chunk=16, tile_x=16, block_threads=512, remap=1)
+    fields = [_fields(u0, torch.float32) for (*_, u0) in c["grids"]]
+    plan.run(fields, 10)
+    torch.cuda.synchronize()
+    plan.close()
+    for g, ((nx, ny, nz, eps, _), (E, H)) in enumerate(zip(c["grids"], fields)):
+        got = [t.double().cpu().numpy() for t in E + H]
+        gr = oracle.Grid(nx, ny, nz, c["h"], c["h"], c["h"], c["dt"], eps)
+        err = oracle.yee.weighted_rel_l2(got, c["refs"][scheme][g], gr)
+        assert err <= TOL["f32r"], (g, err)
+
+
 def test_batch_split_runs_and_configs_agree(small_refs):
     """12 steps in one call == 7 + 5 steps (input/output processing between
     calls is exact for ADI); every kernel configuration gives the same
@@ -305,8 +329,6 @@ def test_batch_bitwise_equals_single_grids(scheme, refine, launch):
     bit, over 17 steps (two replays of the eight-step graph)."""
     from paper_2011_14043_amd import BatchPlan, Plan
     split = launch == "yz-separate"
-    if split and refine:
-        pytest.skip("refined batched passes use 8-slot chunks only")
     h = 1e-3
     dt = W.yee_dt(h, h, h, 5.0)
     grids = _grids([(32, 64, 32), (64, 32, 64)], seed=300)
