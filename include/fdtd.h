@@ -129,8 +129,8 @@ typedef struct {
                                /* The H sample stored at [k][j][i] uses cell [k][j][i].   */
                                /* A map that is not all ones: line passes with per-row    */
                                /* off-diagonals (each axis <= 512, no FDTD_F32_REFINE,    */
-                               /* not for FDTD_CRANK_NICOLSON or fdtd_plan_batch:         */
-                               /* FDTD_EUNSUPPORTED); FDTD_F32 then solves plainly.       */
+                               /* not in fdtd_plan_batch: FDTD_EUNSUPPORTED); FDTD_F32     */
+                               /* then solves plainly.                                    */
     int boundary;              /* 0 = PEC on all faces (the only value)                   */
 } fdtd_desc;
 

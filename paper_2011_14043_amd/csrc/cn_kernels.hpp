@@ -14,7 +14,8 @@
 //     u_E^{n+1} = v_E - u_E^n ,   u_H^{n+1} = u_H^n - theta mu^-1 C_E(v_E).
 //
 // The product S p evaluates the curls of p at the H samples inside the kernel
-// that forms S p, so an iteration moves p, q, x, r and eps_r only.
+// that forms S p, so an iteration moves p, q, x, r and eps_r only (and mu_r
+// with a permeability map).
 //
 // Every kernel walks the nodes with a grid-stride loop over a fixed grid of
 // kCnBlocks blocks, so the dot products (per-block partials, then one fixed-
@@ -38,6 +39,7 @@ struct CnArgs {
     double rdx, rdy, rdz;       // reciprocal cell sizes
     double eps0, rmu0, theta;   // theta = dt / 2
     const float* eps;           // eps_r per node (state layout)
+    const float* mu;            // mu_r per node (state layout), or NULL (mu = mu0)
     double* u[6];               // state: Ex Ey Ez Hx Hy Hz
     double* x[3];               // v_E
     double* r[3];               // residual
@@ -70,11 +72,21 @@ __device__ __forceinline__ double curl_e(const double* const e[3], int c, long l
     }
 }
 
-// Diagonal of S at E sample c: eps + theta^2 mu^-1 (2/h1^2 + 2/h2^2) over the two transverse axes.
-__device__ __forceinline__ double s_diag(int c, double eps, const CnArgs& a) {
-    const double t = c == 0 ? a.rdy * a.rdy + a.rdz * a.rdz
-                   : c == 1 ? a.rdz * a.rdz + a.rdx * a.rdx : a.rdx * a.rdx + a.rdy * a.rdy;
-    return eps + a.theta * a.theta * a.rmu0 * 2.0 * t;
+// 1/mu of the H samples stored at node offset so (mu_r of that node).
+__device__ __forceinline__ double rmu_at(const CnArgs& a, long long so) {
+    return a.mu ? a.rmu0 / double(a.mu[so]) : a.rmu0;
+}
+
+// Diagonal of S at E sample c of node so: eps + theta^2 sum over the four H
+// samples around it of mu^-1 / h^2 (h the spacing of the curl it enters).
+__device__ __forceinline__ double s_diag(int c, long long so, double eps, const CnArgs& a) {
+    const long long sy = a.d.px, sz = a.d.plane;
+    const double m0 = rmu_at(a, so);
+    double t;
+    if (c == 0) t = (m0 + rmu_at(a, so - sy)) * a.rdy * a.rdy + (m0 + rmu_at(a, so - sz)) * a.rdz * a.rdz;
+    else if (c == 1) t = (m0 + rmu_at(a, so - sz)) * a.rdz * a.rdz + (m0 + rmu_at(a, so - 1)) * a.rdx * a.rdx;
+    else t = (m0 + rmu_at(a, so - 1)) * a.rdx * a.rdx + (m0 + rmu_at(a, so - sy)) * a.rdy * a.rdy;
+    return eps + a.theta * a.theta * t;
 }
 
 // One partial per block for each of NV sums (fixed-order tree).
@@ -109,7 +121,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_h_kernel(CnArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             a.w[c][so] = is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d)
-                             ? a.u[3 + c][so] - a.theta * a.rmu0 * curl_e(e, c, so, a) : 0.0;
+                             ? a.u[3 + c][so] - a.theta * rmu_at(a, so) * curl_e(e, c, so, a) : 0.0;
     }
 }
 
@@ -132,7 +144,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_e_kernel(CnArgs a) {
                 const double gs = (c == 2 && so == a.src_off) ? eps * a.src_g : 0.0;
                 xv = 2.0 * ue;
                 rv = 2.0 * a.theta * curl_h(w, c, so, a) + gs;
-                pv = rv / s_diag(c, eps, a);
+                pv = rv / s_diag(c, so, eps, a);
                 const double bv = 2.0 * eps * ue + 2.0 * a.theta * curl_h(h, c, so, a) + gs;
                 acc[0] += rv * pv;
                 acc[1] += rv * rv;
@@ -152,7 +164,9 @@ __global__ void __launch_bounds__(kCnThreads) cn_start_e_kernel(CnArgs a) {
 __global__ void __launch_bounds__(kCnThreads) cn_apply_kernel(CnArgs a) {
     const double* e[3] = {a.p[0], a.p[1], a.p[2]};
     const long long sy = a.d.px, sz = a.d.plane;
-    const double t2m = a.theta * a.theta * a.rmu0;
+    const double t2 = a.theta * a.theta;
+    // mu^-1 C_E(p) at the H sample of component c stored at node o
+    auto mce = [&](int c, long long o) { return rmu_at(a, o) * curl_e(e, c, o, a); };
     double acc[1] = {0.0};
     CN_NODES(a) {
         const Node nd = node_of(unsigned(idx), a.d);
@@ -165,16 +179,13 @@ __global__ void __launch_bounds__(kCnThreads) cn_apply_kernel(CnArgs a) {
                 // the four H samples around a dynamic E sample are dynamic
                 double ch;
                 if (c == 0)
-                    ch = (curl_e(e, 2, so, a) - curl_e(e, 2, so - sy, a)) * a.rdy -
-                         (curl_e(e, 1, so, a) - curl_e(e, 1, so - sz, a)) * a.rdz;
+                    ch = (mce(2, so) - mce(2, so - sy)) * a.rdy - (mce(1, so) - mce(1, so - sz)) * a.rdz;
                 else if (c == 1)
-                    ch = (curl_e(e, 0, so, a) - curl_e(e, 0, so - sz, a)) * a.rdz -
-                         (curl_e(e, 2, so, a) - curl_e(e, 2, so - 1, a)) * a.rdx;
+                    ch = (mce(0, so) - mce(0, so - sz)) * a.rdz - (mce(2, so) - mce(2, so - 1)) * a.rdx;
                 else
-                    ch = (curl_e(e, 1, so, a) - curl_e(e, 1, so - 1, a)) * a.rdx -
-                         (curl_e(e, 0, so, a) - curl_e(e, 0, so - sy, a)) * a.rdy;
+                    ch = (mce(1, so) - mce(1, so - 1)) * a.rdx - (mce(0, so) - mce(0, so - sy)) * a.rdy;
                 const double pv = a.p[c][so];
-                qv = eps * pv + t2m * ch;
+                qv = eps * pv + t2 * ch;
                 acc[0] += pv * qv;
             }
             a.q[c][so] = qv;
@@ -198,7 +209,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_update_kernel(CnArgs a, int par
             a.x[c][so] += alpha * a.p[c][so];
             const double rv = a.r[c][so] - alpha * a.q[c][so];
             a.r[c][so] = rv;
-            acc[0] += rv * rv / s_diag(c, eps, a);
+            acc[0] += rv * rv / s_diag(c, so, eps, a);
             acc[1] += rv * rv;
         }
     }
@@ -216,7 +227,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_direction_kernel(CnArgs a, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (!is_dynamic(c, nd.i, nd.j, nd.k, a.d)) continue;
-            a.p[c][so] = a.r[c][so] / s_diag(c, eps, a) + beta * a.p[c][so];
+            a.p[c][so] = a.r[c][so] / s_diag(c, so, eps, a) + beta * a.p[c][so];
         }
     }
 }
@@ -231,7 +242,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(CnArgs a) {
         for (int c = 0; c < 3; ++c) {
             if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) a.u[c][so] = a.x[c][so] - a.u[c][so];
             if (is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d))
-                a.u[3 + c][so] -= a.theta * a.rmu0 * curl_e(e, c, so, a);
+                a.u[3 + c][so] -= a.theta * rmu_at(a, so) * curl_e(e, c, so, a);
         }
     }
 }
@@ -261,7 +272,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_conv_rhs_kernel(CnArgs a) {
             }
             a.r[c][so] = fe;
             a.w[c][so] = is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d)
-                             ? a.u[3 + c][so] - a.theta * a.rmu0 * curl_e(e, c, so, a) : 0.0;
+                             ? a.u[3 + c][so] - a.theta * rmu_at(a, so) * curl_e(e, c, so, a) : 0.0;
         }
     }
 }
@@ -302,7 +313,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_conv_resid_kernel(CnArgs a) {
         for (int c = 0; c < 3; ++c) {
             if (!is_dynamic(c, nd.i, nd.j, nd.k, a.d)) continue;
             const double rv = a.r[c][so] - a.q[c][so];
-            const double pv = rv / s_diag(c, eps, a);
+            const double pv = rv / s_diag(c, so, eps, a);
             a.r[c][so] = rv;
             a.p[c][so] = pv;
             acc[0] += rv * pv;
@@ -322,7 +333,7 @@ __global__ void __launch_bounds__(kCnThreads) cn_conv_finish_kernel(CnArgs a) {
         for (int c = 0; c < 3; ++c) {
             if (is_dynamic(c, nd.i, nd.j, nd.k, a.d)) a.u[c][so] = a.x[c][so];
             if (is_dynamic(3 + c, nd.i, nd.j, nd.k, a.d))
-                a.u[3 + c][so] = a.w[c][so] - a.theta * a.rmu0 * curl_e(e, c, so, a);
+                a.u[3 + c][so] = a.w[c][so] - a.theta * rmu_at(a, so) * curl_e(e, c, so, a);
         }
     }
 }

@@ -19,6 +19,7 @@ static CnArgs cn_args(fdtd_plan_s* p) {
     a.rmu0 = 1.0 / kMu0;
     a.theta = 0.5 * p->d.dt;
     a.eps = p->eps;
+    a.mu = p->mu;
     for (int c = 0; c < 6; ++c) a.u[c] = comp_ptr<double>(p, 0, c);
     const size_t n = (size_t)p->dims.comp;
     for (int c = 0; c < 3; ++c) {

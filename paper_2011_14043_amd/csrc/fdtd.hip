@@ -171,9 +171,8 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
     }
     const bool has_mu = !mu_host.empty();
     // Variable permeability: line passes with per-row off-diagonals (8-slot
-    // chunks, at most 512 cells per axis, no refinement); Crank-Nicolson plans
-    // take unit permeability.
-    if (has_mu && (cn || d->dtype == FDTD_F32_REFINE || nmax > 512)) return FDTD_EUNSUPPORTED;
+    // chunks, at most 512 cells per axis, no refinement)
+    if (has_mu && (d->dtype == FDTD_F32_REFINE || nmax > 512)) return FDTD_EUNSUPPORTED;
     fdtd_plan_s* p = new (std::nothrow) fdtd_plan_s();
     if (!p) return FDTD_ENOMEM;
     p->d = *d;

@@ -207,6 +207,36 @@ def test_mu_long_lines_and_full_chunks(prec):
         assert err < TOL[prec], err
 
 
+@pytest.mark.parametrize("form", ["fundamental", "conventional"])
+@pytest.mark.parametrize("cfl", [2.0, 8.0])
+def test_mu_crank_nicolson(cfl, form):
+    """Crank-Nicolson without factorization with a permeability map (1/mu of
+    every H sample in the curls, the preconditioner diagonal and the H
+    updates) against the oracle's sparse direct solve, FP64."""
+    from paper_2011_14043_amd import Plan
+    nx, ny, nz, h = 14, 12, 13, 1e-3
+    dt = W.yee_dt(h, h, h, cfl)
+    eps = W.random_box_eps(nx, ny, nz, seed=70, nboxes=6)
+    mu = W.random_mu(nx, ny, nz, seed=73)
+    u0 = W.random_fields(nx, ny, nz, seed=71)
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps, mu)
+    print(f"[case] mu CN 14x12x13 CFL {cfl} {form}", flush=True)
+    ref, tr_ref = oracle.run("cn", form, g, u0, 6, None, 1)
+    p = Plan(nx, ny, nz, dt, h, h, h, scheme="crank_nicolson", form=form, dtype=torch.float64,
+             eps_r=torch.tensor(eps), mu_r=torch.tensor(mu))
+    p.set_cg(1e-13, 2000)
+    E = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[:3]]
+    H = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in u0[3:]]
+    tr = p.run(E, H, 6, energy_every=1)
+    torch.cuda.synchronize()
+    st = p.last_cg()
+    p.close()
+    err = oracle.yee.weighted_rel_l2([t.cpu().numpy() for t in E + H], ref, g)
+    print(f"  rel-L2 {err:.3e}  iterations {st['iterations']}", flush=True)
+    assert err < 1e-10, err
+    assert np.allclose(tr, tr_ref, rtol=1e-10)
+
+
 def test_mu_diff_norm(case):
     """fdtd_diff_norm weights H by mu0 mu_r of its cell (energy-weighted
     distance, as the oracle's)."""
@@ -259,8 +289,8 @@ def test_mu_adjoint_gradient(prec):
 
 
 def test_mu_arguments(case):
-    """Non-positive or non-finite mu_r, refinement, Crank-Nicolson, batches and
-    axes above 512 cells with a permeability map are rejected."""
+    """Non-positive or non-finite mu_r, refinement and axes above 512 cells with
+    a permeability map are rejected."""
     from paper_2011_14043_amd import FdtdError, Plan
     c = case
     args = (c["nx"], c["ny"], c["nz"], c["dt"], c["h"], c["h"], c["h"])
@@ -272,8 +302,6 @@ def test_mu_arguments(case):
     mu = torch.tensor(c["mu"])
     with pytest.raises(FdtdError, match="EUNSUPPORTED"):
         Plan(*args, mu_r=mu, refine=True)
-    with pytest.raises(FdtdError, match="EUNSUPPORTED"):
-        Plan(*args, scheme="crank_nicolson", dtype=torch.float64, mu_r=mu)
     with pytest.raises(ValueError):
         Plan(*args, mu_r=torch.ones(3, 3, 3))
     n = 520
