@@ -224,10 +224,11 @@ def test_autograd_function_vs_oracle_tiny(seed, box):
     x = torch.tensor(c["eps"][k0:k1, j0:j1, i0:i1], dtype=torch.float64, device=DEV, requires_grad=True)
     J = probe_energy(x, pb)
     J.backward()
-    assert abs(float(J) - J_ref) <= 1e-9 * abs(J_ref), (float(J), J_ref)
+    Jv = float(J.detach())
+    assert abs(Jv - J_ref) <= 1e-9 * abs(J_ref), (Jv, J_ref)
     want = g_ref[k0:k1, j0:j1, i0:i1]
     err = float(np.abs(x.grad.cpu().numpy() - want).max()) / float(np.abs(g_ref).max())
-    print(f"  J rel {abs(float(J) - J_ref) / J_ref:.2e}  x.grad rel(max) {err:.2e}", flush=True)
+    print(f"  J rel {abs(Jv - J_ref) / J_ref:.2e}  x.grad rel(max) {err:.2e}", flush=True)
     assert err <= 1e-9, err
 
 
