@@ -103,6 +103,9 @@ static void source_terms(fdtd_plan_s* p, const fdtd_source* src, int mode, long 
 // their pre/post values from src_win.
 template <typename T, typename S>
 static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mode) {
+    // replays of the old graph may still be queued: let them finish before its
+    // executable (kernel arguments included) is released
+    if (p->gexec) HIPCHK(hipStreamSynchronize(p->stream));
     graph_clear(p);
     const SchemeDef& sd = kSchemes[p->d.scheme];
     const int K = p->graph_steps;
