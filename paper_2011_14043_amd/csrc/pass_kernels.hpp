@@ -77,6 +77,13 @@ struct PassArgs {
     const double* src_pre_dev;  // if set, the value of src_pre is read from device memory
     const double* src_post_dev; // if set, the value of src_post is read from device memory
     double fsrc;          // FIN passes: added to E at the source sample (the g/2 the pass subtracts)
+    // FIN passes (the last pass of a run over its pair) store the run's output:
+    // with fin_add, u = U_old + U_new (fundamental ADI), else U_new; to Eout,
+    // Hout with pitches of their own (the caller's arrays, or the state's):
+    // along the transverse axes a, b and along the line, and the elements per
+    // component.
+    int fin_add;
+    long long sa_o, sb_o, sw_o, comp_o;
 };
 
 // Output form of one slot in a FIN pass (the last B sub-step of a fundamental
@@ -546,16 +553,32 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     for (int i = 0; i < M; ++i) { te[i] = T(eo[i]); th[i] = T(ho[i]); }
     if (!live) return;
     if constexpr (FIN) {
-        // output form, in place: U_old of this thread's own slots is loaded
-        // again before they are overwritten
+        // the run's output: U_old of this thread's own slots is loaded again
+        // (the output may overwrite them)
+        if (a.fin_add) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            if (FULL || j0 + i < n) {
-                fin_value<T, S>(a, te[i], th[i], Buf<T>::ld(rE, vo, i * ES), Buf<T>::ld(rH, vo, i * ES),
-                                src_here && i == si);
+            for (int i = 0; i < M; ++i) {
+                if (FULL || j0 + i < n) {
+                    fin_value<T, S>(a, te[i], th[i], Buf<T>::ld(rE, vo, i * ES), Buf<T>::ld(rH, vo, i * ES),
+                                    src_here && i == si);
+                }
             }
         }
         if (first) te[0] = T(0);   // the wall
+        // output pitches (rows of the caller's arrays need not be 16-byte
+        // aligned: element stores)
+        const long long wbo = (long long)(a.a_lo + int(line0 % a.na)) * a.sa_o +
+                              (long long)(a.b_lo + int(line0 / a.na)) * a.sb_o;
+        const int voo = (int((long long)ia * a.sa_o + (long long)ib * a.sb_o - wbo) + j0) * ES;
+        const Rsrc oE = make_rsrc(a.Eout, wbo, a.comp_o, ES), oH = make_rsrc(a.Hout, wbo, a.comp_o, ES);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (FULL || j0 + i < n) {
+                Buf<T>::st(te[i], oE, voo, i * ES);
+                Buf<T>::st(th[i], oH, voo, i * ES);
+            }
+        }
+        return;
     }
     const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
     if (FULL || j0 + M <= n) {
@@ -572,9 +595,10 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     }
 }
 
-// FIN: the pass stores the output form u = U_old + U_new of its pair instead
-// of U_new (output processing of the last B sub-step of a fundamental ADI run;
-// a separate instantiation, so the other passes carry none of its registers).
+// FIN: the last pass of a run over its pair stores the run's output, with the
+// output pitches: u = U_old + U_new with fin_add (output processing of the
+// last B sub-step of a fundamental ADI run), else U_new (a separate
+// instantiation, so the other passes carry none of its registers).
 // MU: variable permeability (eps_r and mu_r maps, no material index).
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN, bool MU = false>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
@@ -878,23 +902,31 @@ __device__ __forceinline__ void pass_yz_body(const PassArgs<T, S>& a, int blk, i
     T ot[M], oh[M];   // the values stored
 #pragma unroll
     for (int i = 0; i < M; ++i) { ot[i] = T(eo[i]); oh[i] = T(ho[i]); }
+    long long wb = wbase, ncomp = a.comp;
+    int vs = vo, sws = swb;
     if constexpr (FIN) {
-        // output form, in place (see the x lines)
+        // the run's output (see the x lines)
+        if (a.fin_add) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            if (FULL || j0 + i < n) {
-                fin_value<T, S>(a, ot[i], oh[i], Buf<T>::ld(rE, vo, i * swb), Buf<T>::ld(rH, vo, i * swb),
-                                src_here && i == si);
+            for (int i = 0; i < M; ++i) {
+                if (FULL || j0 + i < n) {
+                    fin_value<T, S>(a, ot[i], oh[i], Buf<T>::ld(rE, vo, i * swb), Buf<T>::ld(rH, vo, i * swb),
+                                    src_here && i == si);
+                }
             }
         }
         if (first) ot[0] = T(0);   // the wall
+        wb = (long long)tile0 * a.sa_o + (long long)ib * a.sb_o + (long long)pw0 * M * a.sw_o;
+        vs = (tx + (p - pw0) * M * (int)a.sw_o) * ES;
+        sws = (int)(a.sw_o * ES);
+        ncomp = a.comp_o;
     }
-    const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
+    const Rsrc wE = make_rsrc(a.Eout, wb, ncomp, ES), wH = make_rsrc(a.Hout, wb, ncomp, ES);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         if (FULL || j0 + i < n) {
-            Buf<T>::st(ot[i], wE, vo, i * swb);
-            Buf<T>::st(oh[i], wH, vo, i * swb);
+            Buf<T>::st(ot[i], wE, vs, i * sws);
+            Buf<T>::st(oh[i], wH, vs, i * sws);
         }
     }
 }

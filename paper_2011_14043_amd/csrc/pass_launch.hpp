@@ -39,10 +39,15 @@ static Inject source_inject(const fdtd_plan_s* p, const fdtd_source* src, double
     return in;
 }
 
-// Output processing fused into the passes of the last B sub-step of a
-// fundamental ADI run: they store u = U_old + U_new instead of U_new.
+// The last passes of a run store its output.  Fundamental ADI (add): u =
+// U_old + U_new, the output processing fused into the passes of the last B
+// sub-step; other schemes: U_new.  With E and H set, straight into the
+// caller's arrays (their own pitches), else in place in the state.
 struct Fin {
-    double src;       // g/2 of this sub-step, added back at the source sample
+    double src = 0.0;             // g/2 of this sub-step, added back at the source sample (add)
+    bool add = true;
+    void* const* E = nullptr;     // caller's E, H (or NULL: the state)
+    void* const* H = nullptr;
 };
 
 // Coefficients of the input/output and energy kernels (reciprocals formed here).
@@ -163,7 +168,31 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
         sh.lds = (size_t)9 * a.P * (TX + 1) * sizeof(S);
     }
     sh.full = a.P * cf.M == a.n_w;
-    if (fin) a.fsrc = fin->src;
+    a.sa_o = a.sa;
+    a.sb_o = a.sb;
+    a.sw_o = a.sw;
+    a.comp_o = a.comp;
+    if (fin) {
+        a.fsrc = fin->add ? fin->src : 0.0;
+        a.fin_add = fin->add ? 1 : 0;
+        if (fin->E) {
+            // the caller's arrays: x fastest, rows of nx+1, planes of cplane
+            auto cstride = [&](int ax) -> long long {
+                return ax == 0 ? 1 : (ax == 1 ? (long long)(d.nx + 1) : d.cplane);
+            };
+            a.Eout = static_cast<T*>(fin->E[pd.ce]);
+            a.Hout = static_cast<T*>(fin->H[pd.ch - 3]);
+            a.sw_o = cstride(pd.w);
+            if (pd.w == 0) {
+                a.sa_o = cstride(1);
+                a.sb_o = cstride(2);
+            } else {
+                a.sa_o = 1;
+                a.sb_o = cstride((pd.e == 0) ? pd.t : pd.e);
+            }
+            a.comp_o = d.ccomp;
+        }
+    }
 }
 
 // Band of D^T D (the fourth-order difference D, folded onto the wall images)

@@ -266,10 +266,22 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // Output processing of the fundamental ADI rides on the passes of the
     // run's last B sub-step: they store u = U_old + U_new (the v of that
     // sub-step, with g/2 added back at the source) instead of U_new, so the
-    // state before it need not be kept; store_out_kernel copies the state to
-    // the caller.  The other schemes' state is u after their last sub-step.
+    // state before it need not be kept.  The other schemes' output is U_new of
+    // their last sub-step (LOD2: of the output processing sub-step).  Unless
+    // an energy trace reads the final state (or the passes are the in-place
+    // fourth-order ones, or conventional with a permeability map), the last
+    // passes store the output straight into the caller's arrays and
+    // store_faces_kernel writes the wall samples no pass writes; else the
+    // state takes it and store_out_kernel copies it.
     const bool fin_adi = adi && !conv;
-    Fin fin{0.0};
+    const bool lod2 = d.scheme == FDTD_LOD2;
+    const bool direct = !energy && p->order == 2 && !(p->mu && conv);
+    Fin fin;
+    fin.add = fin_adi;
+    if (direct) {
+        fin.E = E;
+        fin.H = H;
+    }
     // Steps before the last one run as replays of a captured graph of
     // graph_steps steps (no energy trace or per-launch timing), the rest
     // directly.
@@ -286,8 +298,8 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
             const double g = source_value(src, theta, (double(nglob) + ss.t_frac) * d.dt);
             const Inject inj = source_inject(p, src, g, mode);
             const bool timed = tm.per_launch > 0 && n % tm.per_launch == 0;
-            const bool last = fin_adi && n == nsteps - 1 && u == sd.nsub - 1;
-            if (last) fin.src = src ? 0.5 * g : 0.0;
+            const bool last = (fin_adi || (direct && !lod2)) && n == nsteps - 1 && u == sd.nsub - 1;
+            if (last) fin.src = (fin_adi && src) ? 0.5 * g : 0.0;
             fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, timed, last ? &fin : nullptr);
             if (st != FDTD_OK) return st;
         }
@@ -299,12 +311,16 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     HIPCHK(hipEventRecord(tm.main1, p->stream));
     // output processing
     if (nsteps > 0) {
-        if (d.scheme == FDTD_LOD2) {
-            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false);
+        if (lod2) {
+            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false, direct ? &fin : nullptr);
             if (st != FDTD_OK) return st;
         }
-        hipLaunchKernelGGL((store_out_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream, state_ptrs<T>(p, cur),
-                           caller_w, dm, fin_adi ? 1 : 0);
+        if (direct)
+            hipLaunchKernelGGL((store_faces_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
+                               state_ptrs<T>(p, cur), caller_w, dm, fin_adi ? 1 : 0);
+        else
+            hipLaunchKernelGGL((store_out_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
+                               state_ptrs<T>(p, cur), caller_w, dm, fin_adi ? 1 : 0);
         HIPCHK(hipGetLastError());
     }
     p->step += nsteps;
