@@ -258,35 +258,44 @@ __global__ void __launch_bounds__(kRowThreads) store_out_kernel(FieldPtrs<T> s, 
 // The samples of a run's output that no line pass writes, when the last
 // passes of the run store straight into the caller's fields: E off its dynamic
 // set (0) and static H (the state's value, doubled when static_twice), all on
-// the walls.  Grid as load_state_kernel; a row off the y and z walls touches
-// only its two x-wall samples.
+// the walls.  Blocks [0, nface): one row on a y or z wall each (all i);
+// the rest: one thread per row off those walls, for its two x-wall samples.
 template <typename T>
 __global__ void __launch_bounds__(kRowThreads) store_faces_kernel(FieldPtrs<T> s, FieldPtrsW<T> f, Dims d,
-                                                                  int static_twice) {
-    const int r = xcd_remap(int(blockIdx.x), int(gridDim.x));
-    const int j = r % (d.ny + 1), k = r / (d.ny + 1);
-    const bool face_row = j == 0 || j == d.ny || k == 0 || k == d.nz;
-    if (!face_row && int(threadIdx.x) > 1) return;
-    const long long srow = (long long)k * d.plane + (long long)j * d.px;
-    const long long crow = (long long)k * d.cplane + (long long)j * (d.nx + 1);
+                                                                  int static_twice, int nface) {
+    auto put = [&](int c, int i, int j, int k) {
+        if (!in_extent(c, i, j, k, d) || is_dynamic(c, i, j, k, d)) return;
+        T* dst = f.c[c] + (long long)k * d.cplane + (long long)j * (d.nx + 1) + i;
+        if (c < 3) {
+            *dst = T(0);
+        } else {
+            const T v = s.c[c][(long long)k * d.plane + (long long)j * d.px + i];
+            *dst = static_twice ? T(v + v) : v;
+        }
+    };
+    if (int(blockIdx.x) < nface) {
+        int fb = int(blockIdx.x), j, k;
+        if (fb < 2 * (d.nz + 1)) {
+            j = (fb & 1) ? d.ny : 0;
+            k = fb >> 1;
+        } else {
+            fb -= 2 * (d.nz + 1);
+            k = (fb & 1) ? d.nz : 0;
+            j = 1 + (fb >> 1);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            for (int i = int(threadIdx.x); i <= d.nx; i += kRowThreads) put(c, i, j, k);
+        return;
+    }
+    const long long r = (long long)(int(blockIdx.x) - nface) * kRowThreads + threadIdx.x;
+    if (r >= (long long)(d.ny + 1) * (d.nz + 1)) return;
+    const int j = int(r % (d.ny + 1)), k = int(r / (d.ny + 1));
+    if (j == 0 || j == d.ny || k == 0 || k == d.nz) return;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const T* src = s.c[c] + srow;
-        T* dst = f.c[c] + crow;
-        auto put = [&](int i) {
-            if (!in_extent(c, i, j, k, d) || is_dynamic(c, i, j, k, d)) return;
-            if (c < 3) {
-                dst[i] = T(0);
-            } else {
-                const T v = src[i];
-                dst[i] = static_twice ? T(v + v) : v;
-            }
-        };
-        if (face_row) {
-            for (int i = int(threadIdx.x); i <= d.nx; i += kRowThreads) put(i);
-        } else {
-            put(threadIdx.x == 0 ? 0 : d.nx);
-        }
+        put(c, 0, j, k);
+        put(c, d.nx, j, k);
     }
 }
 

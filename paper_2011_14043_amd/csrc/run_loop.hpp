@@ -315,10 +315,13 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
             fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false, direct ? &fin : nullptr);
             if (st != FDTD_OK) return st;
         }
-        if (direct)
-            hipLaunchKernelGGL((store_faces_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
-                               state_ptrs<T>(p, cur), caller_w, dm, fin_adi ? 1 : 0);
-        else
+        if (direct) {
+            const int nface = 2 * (dm.nz + 1) + 2 * (dm.ny - 1);
+            const long long rows = (long long)(dm.ny + 1) * (dm.nz + 1);
+            const unsigned nblk = (unsigned)(nface + (rows + kRowThreads - 1) / kRowThreads);
+            hipLaunchKernelGGL((store_faces_kernel<T>), dim3(nblk), dim3(kRowThreads), 0, p->stream,
+                               state_ptrs<T>(p, cur), caller_w, dm, fin_adi ? 1 : 0, nface);
+        } else
             hipLaunchKernelGGL((store_out_kernel<T>), row_grid(dm), dim3(kRowThreads), 0, p->stream,
                                state_ptrs<T>(p, cur), caller_w, dm, fin_adi ? 1 : 0);
         HIPCHK(hipGetLastError());
