@@ -180,7 +180,9 @@ fdtd_status fdtd_set_order(fdtd_plan_t p, int order);
  *   input processing (ADI: u^0 -> (1/2 I + dt/4 B) u^0, the link of
  *   Sec. II-E; LOD2: (fastLOD2i)/(orgLOD2i)), nsteps main iterations, output
  *   processing (ADI: the field v of the last B sub-step; LOD2:
- *   (fastLOD2o)/(orgLOD2o)).
+ *   (fastLOD2o)/(orgLOD2o)).  Without an energy trace, the line passes of the
+ *   last sub-step (LOD2: of the output processing) store the output straight
+ *   into E, H, and a small kernel writes the wall samples no pass writes.
  * E[3] = {Ex, Ey, Ez}, H[3] = {Hx, Hy, Hz}: device pointers, read on entry and
  * overwritten on return (the same arrays may be reused by the next call).
  * `src` may be NULL.  If `energy` is non-NULL (host array of
@@ -214,7 +216,8 @@ fdtd_status fdtd_set_step(fdtd_plan_t p, long long n);
 
 /* Timing of the most recent fdtd_run (synchronizes the plan's stream).
  * main_ms: milliseconds between HIP events recorded on the plan's stream
- * around the main iterations (input/output processing excluded).
+ * around the main iterations (input processing and the LOD2 output sub-step
+ * excluded; the last main-iteration passes store the output).
  * fdtd_set_timing(p, k), k >= 1, before the run: HIP events bracket every
  * line pass of every k-th main-iteration step (steps 0, k, 2k, ...; k = 1:
  * every step) on the plan's stream, and pass_ms_avg[f] / pass_launches[f]
