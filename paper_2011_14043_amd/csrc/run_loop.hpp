@@ -275,6 +275,11 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // state takes it and store_out_kernel copies it.
     const bool fin_adi = adi && !conv;
     const bool lod2 = d.scheme == FDTD_LOD2;
+    // The last passes of a run are FIN instantiations wherever those are built
+    // (second-order passes except conventional ones with a permeability map;
+    // fourth-order ones for ADI only), whether the output goes to the caller
+    // or to the state, so both destinations get the same arithmetic.
+    const bool fin_last = fin_adi || (p->order == 2 && !(p->mu && conv));
     const bool direct = !energy && p->order == 2 && !(p->mu && conv);
     Fin fin;
     fin.add = fin_adi;
@@ -298,7 +303,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
             const double g = source_value(src, theta, (double(nglob) + ss.t_frac) * d.dt);
             const Inject inj = source_inject(p, src, g, mode);
             const bool timed = tm.per_launch > 0 && n % tm.per_launch == 0;
-            const bool last = (fin_adi || (direct && !lod2)) && n == nsteps - 1 && u == sd.nsub - 1;
+            const bool last = fin_last && !lod2 && n == nsteps - 1 && u == sd.nsub - 1;
             if (last) fin.src = (fin_adi && src) ? 0.5 * g : 0.0;
             fdtd_status st = substep<T, S>(p, ss.op, theta, mode, cur, &inj, timed, last ? &fin : nullptr);
             if (st != FDTD_OK) return st;
@@ -312,7 +317,7 @@ static fdtd_status run_impl(fdtd_plan_s* p, void* const E[3], void* const H[3], 
     // output processing
     if (nsteps > 0) {
         if (lod2) {
-            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false, direct ? &fin : nullptr);
+            fdtd_status st = substep<T, S>(p, 1, -0.25 * d.dt, mode, cur, nullptr, false, fin_last ? &fin : nullptr);
             if (st != FDTD_OK) return st;
         }
         if (direct) {
