@@ -66,9 +66,12 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
         for (int c = 0; c < 6; ++c) f.c[c] = base + (size_t)c * dm.comp;
         return f;
     };
-    auto record = [&](T* dst, double* pdst) -> fdtd_status {
+    // records of state set 0; with J, the probe energy of the B sub-step whose
+    // A-side record is pold
+    auto record = [&](T* dst, double* pdst, const double* pold = nullptr, double h = 0.0,
+                      double* J = nullptr) -> fdtd_status {
         hipLaunchKernelGGL((record_kernel<T>), dim3(dst ? rblocks : 1), dim3(256), 0, p->stream, fptrs(st0), dm, b,
-                           dst, probe_off, pdst);
+                           dst, probe_off, pdst, pold, h, d.dt, J);
         HIPCHK(hipGetLastError());
         return FDTD_OK;
     };
@@ -98,19 +101,21 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
         GCHK(fwd_sub(0, glob, 0.25, &gA));
         GCHK(record(nullptr, prb));
         GCHK(fwd_sub(1, glob, 0.75, &gB));
-        GCHK(record(nullptr, prb + 3));
-        hipLaunchKernelGGL(probe_kernel, dim3(1), dim3(64), 0, p->stream, prb, prb + 3,
-                           src_at_probe ? 0.5 * gB : 0.0, p->eps, probe_off, kEps0, d.dt, Jd, nullptr);
-        HIPCHK(hipGetLastError());
+        GCHK(record(nullptr, prb + 3, prb, src_at_probe ? 0.5 * gB : 0.0, Jd));   // J += dt |V|^2
     }
     if (want) {
         HIPCHK(hipMemsetAsync(adj, 0, ssz, p->stream));
         HIPCHK(hipMemsetAsync(grad_out, 0, sizeof(double) * nb, p->stream));
         const FieldPtrs<T> lam = fptrs(adj);
         const double scale = -0.5 * kEps0;
-        auto acc = [&](int m, double g) -> fdtd_status {
-            hipLaunchKernelGGL((grad_acc_kernel<T>), dim3(rblocks), dim3(256), 0, p->stream, lam, dm, b, recp(m),
-                               recp(m + 1), src_idx, 0.5 * g, scale, grad_out);
+        // the gradient terms m1, m2 (< 0: none) of the current adjoint state, with
+        // their sub-steps' source terms g1, g2; with mseed >= 0 also the seed of
+        // B sub-step mseed (records mseed and mseed + 1, source term gseed)
+        auto acc = [&](int m1, double g1, int m2, double g2, int mseed = -1, double gseed = 0.0) -> fdtd_status {
+            hipLaunchKernelGGL((grad_acc_kernel<T>), dim3(rblocks), dim3(256), 0, p->stream, lam, dm, b, rec, m1,
+                               0.5 * g1, m2, 0.5 * g2, src_idx, scale, grad_out, mseed >= 0 ? seed : nullptr,
+                               prb + 3 * std::max(mseed, 0), prb + 3 * (std::max(mseed, 0) + 1),
+                               src_at_probe ? 0.5 * gseed : 0.0, p->eps, probe_off, kEps0, d.dt);
             HIPCHK(hipGetLastError());
             return FDTD_OK;
         };
@@ -135,20 +140,19 @@ static fdtd_status grad_impl(fdtd_plan_s* p, void* const E[3], void* const H[3],
                 GCHK(fwd_sub(1, glob, 0.75, &gs[2 * q + 1]));
                 GCHK(record(recp(2 * q + 2), prb + 3 * (2 * q + 2)));
             }
-            // reverse sub-steps
+            // reverse sub-steps: before the B sub-step of step q, the terms of the
+            // state between steps q + 1 and q (the A term of step q + 1, the B
+            // term of step q) and the seed of step q; between its sub-steps the
+            // B and A terms; after step 0 of the segment its A term
             for (int q = L - 1; q >= 0; --q) {
                 const int mB = 2 * q + 1, mA = 2 * q;
                 const double gB = gs[mB], gA = gs[mA];
-                hipLaunchKernelGGL(probe_kernel, dim3(1), dim3(64), 0, p->stream, prb + 3 * mB, prb + 3 * (mB + 1),
-                                   src_at_probe ? 0.5 * gB : 0.0, p->eps, probe_off, kEps0, d.dt, nullptr, seed);
-                HIPCHK(hipGetLastError());
-                GCHK(acc(mB, gB));
+                GCHK(acc(q < L - 1 ? mA + 2 : -1, q < L - 1 ? gs[mA + 2] : 0.0, mB, gB, mB, gB));
                 GCHK(adj_sub(1, &seed_inj));
-                GCHK(acc(mB, gB));
-                GCHK(acc(mA, gA));
+                GCHK(acc(mB, gB, mA, gA));
                 GCHK(adj_sub(0, nullptr));
-                GCHK(acc(mA, gA));
             }
+            if (L > 0) GCHK(acc(0, gs[0], -1, 0.0));
         }
         if (nsteps > 0) {
             hipLaunchKernelGGL((grad_link_kernel<T>), dim3(rblocks), dim3(256), 0, p->stream, lam, caller, dm, b,

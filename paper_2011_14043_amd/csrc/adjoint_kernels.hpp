@@ -37,13 +37,25 @@ __device__ __forceinline__ long long box_node(const Box& b, const Dims& d, long 
 }
 
 // Record the E samples of the design cells of state s into rec ([3][nb], may
-// be NULL) and the three E samples of the probe node into prb (FP64).
+// be NULL) and the three E samples of the probe node into prb (FP64).  With J
+// (a B sub-step of the forward sweep): J += dt |V|^2 for the probe field
+// V = prb + prb_old (+ h_ez on Ez where the source sits on the probe node).
 template <typename T>
-__global__ void record_kernel(FieldPtrs<T> s, Dims d, Box b, T* rec, long long probe_off, double* prb) {
+__global__ void record_kernel(FieldPtrs<T> s, Dims d, Box b, T* rec, long long probe_off, double* prb,
+                              const double* prb_old, double h_ez, double dt, double* J) {
     const long long nb = (long long)b.bi * b.bj * b.bk;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx == 0 && prb) {
-        for (int c = 0; c < 3; ++c) prb[c] = double(s.c[c][probe_off]);
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double v = double(s.c[c][probe_off]);
+            prb[c] = v;
+            if (J) {
+                const double w = v + prb_old[c] + (c == 2 ? h_ez : 0.0);
+                acc += w * w;
+            }
+        }
+        if (J) *J += dt * acc;
     }
     if (!rec || idx >= nb) return;
     const long long so = box_node(b, d, idx);
@@ -51,39 +63,47 @@ __global__ void record_kernel(FieldPtrs<T> s, Dims d, Box b, T* rec, long long p
     for (int c = 0; c < 3; ++c) rec[c * nb + idx] = s.c[c][so];
 }
 
-// Probe field of a B sub-step, V = U_old + U_new (+ h_ez on Ez where the
-// source sits on the probe node): J += dt |V|^2; seed_c = 2 dt V_c / eps_abs.
-// One thread; either output may be NULL.
-__global__ void probe_kernel(const double* prb_old, const double* prb_new, double h_ez, const float* eps,
-                             long long probe_off, double eps0, double dt, double* J, double* seed) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double e = eps0 * double(eps[probe_off]);
-    double acc = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double v = prb_new[c] + prb_old[c] + (c == 2 ? h_ez : 0.0);
-        acc += v * v;
-        if (seed) seed[c] = 2.0 * dt * v / e;
-    }
-    if (J) *J += dt * acc;
-}
-
-// grad[idx] += scale * sum_c lam_c (rec_new - rec_old - h)_c, FP64.
-// h = h_ez on the Ez sample of box cell src_idx (-1: none).
+// Gradient terms of one adjoint state lam, in FP64:
+//     grad[idx] += scale sum_c lam_c (rec[m+1] - rec[m] - h)_c
+// for m = m1, then m = m2 (either < 0: none), rec[m] = the record [3][nb] of
+// sub-step state m, h = h1 (h2) on the Ez sample of box cell src_idx (-1:
+// none).  With seed (one thread): the adjoint seed of a B sub-step,
+// seed_c = 2 dt V_c / eps_abs, V = prb_new + prb_old (+ h_seed on Ez).
 template <typename T>
-__global__ void grad_acc_kernel(FieldPtrs<T> lam, Dims d, Box b, const T* rec_old, const T* rec_new,
-                                long long src_idx, double h_ez, double scale, double* grad) {
+__global__ void grad_acc_kernel(FieldPtrs<T> lam, Dims d, Box b, const T* rec, int m1, double h1, int m2,
+                                double h2, long long src_idx, double scale, double* grad, double* seed,
+                                const double* prb_old, const double* prb_new, double h_seed, const float* eps,
+                                long long probe_off, double eps0, double dt) {
     const long long nb = (long long)b.bi * b.bj * b.bk;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (seed && idx == 0) {
+        const double e = eps0 * double(eps[probe_off]);
+        for (int c = 0; c < 3; ++c) {
+            const double v = prb_new[c] + prb_old[c] + (c == 2 ? h_seed : 0.0);
+            seed[c] = 2.0 * dt * v / e;
+        }
+    }
     if (idx >= nb) return;
     const long long so = box_node(b, d, idx);
-    double acc = 0.0;
+    double l[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double dv = double(rec_new[c * nb + idx]) - double(rec_old[c * nb + idx]) -
-                          ((c == 2 && idx == src_idx) ? h_ez : 0.0);
-        acc += double(lam.c[c][so]) * dv;
+    for (int c = 0; c < 3; ++c) l[c] = double(lam.c[c][so]);
+    double g = grad[idx];
+    for (int t = 0; t < 2; ++t) {
+        const int m = t == 0 ? m1 : m2;
+        if (m < 0) continue;
+        const double h = t == 0 ? h1 : h2;
+        const T* r = rec + (size_t)m * 3 * nb;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double dv = double(r[(3 + c) * nb + idx]) - double(r[c * nb + idx]) -
+                              ((c == 2 && idx == src_idx) ? h : 0.0);
+            acc += l[c] * dv;
+        }
+        g += scale * acc;
     }
-    grad[idx] += scale * acc;
+    grad[idx] = g;
 }
 
 // Input-processing term: grad[idx] += scale * sum_c lam_c (U0 - u0/2)_c with
