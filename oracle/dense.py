@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .yee import COMPONENTS, CIDX, EPS0, MU0, PAIRS, W4, Grid, dynamic_mask
+from .yee import COMPONENTS, CIDX, EPS0, MU0, PAIRS, Grid, dynamic_mask
 
 
 class DenseSystem:
@@ -109,11 +109,12 @@ class DenseSystem:
     def _assemble4(self):
         """A and B with the fourth-order differences: for the pair (E, H, w, s)
         of an operator, an E row at integer position p along w takes the H
-        samples at p - 3/2 .. p + 3/2 (stored p-2 .. p+1) with weights W4 / h
+        samples at p - 3/2 .. p + 3/2 (stored p-2 .. p+1) with the grid's 4-point weights / h
         times s/eps; an H row at p + 1/2 takes the E samples at p-1 .. p+2 times
         s/mu.  Across a wall an H sample is its even image, an E sample its odd
         image (a wall E itself is 0)."""
         g = self.g
+        W = g.w4
         cells = {"x": g.nx, "y": g.ny, "z": g.nz}
         for r, (c, k, j, i) in enumerate(self.nodes):
             inv = 1.0 / self._material(c, k, j, i)
@@ -134,14 +135,14 @@ class DenseSystem:
                                 q = -1 - q
                             elif q > n - 1:
                                 q = 2 * n - 1 - q
-                            self._add(M, r, ch, *at(q), s * inv * W4[t] / h)
+                            self._add(M, r, ch, *at(q), s * inv * W[t] / h)
                         else:
                             q, sgn = pos - 1 + t, 1.0             # E position
                             if q < 0:
                                 q, sgn = -q, -1.0
                             elif q > n:
                                 q, sgn = 2 * n - q, -1.0
-                            self._add(M, r, ce, *at(q), sgn * s * inv * W4[t] / h)
+                            self._add(M, r, ce, *at(q), sgn * s * inv * W[t] / h)
 
     # -- conversions --------------------------------------------------------
     def to_vec(self, u) -> np.ndarray:

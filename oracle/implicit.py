@@ -38,7 +38,7 @@ from .tridiag import thomas
 from .yee import AXIS, CIDX, W4, Grid, d_half, d_int, dynamic_mask
 
 
-def diff4_matrices(n: int, h: float):
+def diff4_matrices(n: int, h: float, wts: np.ndarray = W4):
     """Matrices of the fourth-order differences on one line of n cells:
     Dh (n x (n-1)) maps the E unknowns j = 1..n-1 to the H samples j+1/2
     (j = 0..n-1); Di ((n-1) x n) maps the H samples to the E unknowns.  Images:
@@ -52,7 +52,7 @@ def diff4_matrices(n: int, h: float):
             elif p > n:
                 p, sgn = 2 * n - p, -1.0
             if 1 <= p <= n - 1:
-                Dh[hh, p - 1] += sgn * W4[t] / h
+                Dh[hh, p - 1] += sgn * wts[t] / h
     Di = np.zeros((n - 1, n))
     for j in range(1, n):
         for t in range(4):                  # H stored j - 2 + t
@@ -61,7 +61,7 @@ def diff4_matrices(n: int, h: float):
                 q = -1 - q
             elif q > n - 1:
                 q = 2 * n - 1 - q
-            Di[j - 1, q] += W4[t] / h
+            Di[j - 1, q] += wts[t] / h
     return Dh, Di
 
 
@@ -82,7 +82,7 @@ def line_operator_solve(rhs_e: np.ndarray, ce: str, ch: str, w: str, coef: float
         return np.zeros_like(rhs_e)
     if g.order == 4:
         # alpha V - coef (1/eps) Di (1/mu) Dh V, one dense system per line
-        Dh, Di = diff4_matrices(n, h)
+        Dh, Di = diff4_matrices(n, h, g.w4)
         e_j = eps[..., 1:n]
         mu_h = mu[..., 0:n]
         K = np.einsum("jh,...h,hk->...jk", Di, 1.0 / mu_h, Dh)

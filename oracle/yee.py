@@ -64,6 +64,7 @@ class Grid:
     eps_r: np.ndarray | None = None  # (nz, ny, nx) relative permittivity per cell
     mu_r: np.ndarray | None = None   # (nz, ny, nx) relative permeability per cell
     order: int = 2                   # accuracy order of the staggered first differences (2 or 4)
+    outer: float = -1.0 / 24.0       # order 4: outer weight b of the 4-point difference (stencil4)
     _cache: dict = field(default_factory=dict, repr=False)
 
     def __post_init__(self):
@@ -105,6 +106,11 @@ class Grid:
 
     def material(self, comp: str) -> np.ndarray:
         return self.eps if comp[0] == "E" else self.mu
+
+    @property
+    def w4(self) -> np.ndarray:
+        """Weights of the 4-point staggered difference (order 4)."""
+        return stencil4(self.outer)
 
 
 def dynamic_mask(comp: str, g: Grid) -> np.ndarray:
@@ -184,7 +190,43 @@ def diff_to_half(f: np.ndarray, w: str, h: float) -> np.ndarray:
 W4 = np.array([1.0, -27.0, 27.0, -1.0]) / 24.0
 
 
-def diff4_to_half(f: np.ndarray, w: str, h: float) -> np.ndarray:
+# The same remark names parameter-optimized operators.  Reading: the 4-point
+# staggered difference with a free outer weight b,
+#     d_w f = [(1 - 3b)(f[+1/2] - f[-1/2]) + b (f[+3/2] - f[-3/2])] / h,
+# exact on quadratics for every b (consistency fixes the inner weight), fourth
+# order only at b = -1/24 (W4), with the same image folding at the walls (so
+# d_int = -d_half^T still holds) and the modified wavenumber
+#     K(k) h = 2 (1 - 3b) sin(k h / 2) + 2 b sin(3 k h / 2).
+def stencil4(outer: float) -> np.ndarray:
+    """Weights of the samples at -3/2, -1/2, +1/2, +3/2 for outer weight b."""
+    inner = 1.0 - 3.0 * outer
+    return np.array([-outer, -inner, inner, outer])
+
+
+def modified_wavenumber4(outer: float, theta):
+    """K(k) h of the 4-point difference at theta = k h."""
+    return 2.0 * (1.0 - 3.0 * outer) * np.sin(theta / 2.0) + 2.0 * outer * np.sin(1.5 * theta)
+
+
+def optimized_outer(theta_max: float) -> float:
+    """Reading of the parameter-optimized operator: the outer weight b that
+    minimizes the squared error of the modified wavenumber, integral over
+    theta in [0, theta_max] of (K(k) h - theta)^2, a least-squares problem in
+    b: K h - theta = e0 + b g with e0 = 2 sin(theta/2) - theta and
+    g = 2 sin(3 theta/2) - 6 sin(theta/2), so b = -<e0, g> / <g, g>."""
+    from scipy.integrate import quad
+
+    def e0(t):
+        return 2.0 * np.sin(t / 2.0) - t
+
+    def g(t):
+        return 2.0 * np.sin(1.5 * t) - 6.0 * np.sin(t / 2.0)
+    num = quad(lambda t: e0(t) * g(t), 0.0, theta_max, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+    den = quad(lambda t: g(t) * g(t), 0.0, theta_max, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+    return -num / den
+
+
+def diff4_to_half(f: np.ndarray, w: str, h: float, wts: np.ndarray = W4) -> np.ndarray:
     """Fourth-order difference of the E samples (integer positions 0..n along
     w, tangential to the walls at 0 and n) at the half-integer positions
     j+1/2 (stored at j, j = 0..n-1), with odd images across the walls.  The
@@ -198,12 +240,12 @@ def diff4_to_half(f: np.ndarray, w: str, h: float) -> np.ndarray:
     ext[..., n + 2] = -a[..., n - 1]
     out = np.zeros_like(a)
     for j in range(n):                           # E at j-1, j, j+1, j+2 -> ext index +1
-        out[..., j] = (W4[0] * ext[..., j] + W4[1] * ext[..., j + 1] + W4[2] * ext[..., j + 2]
-                       + W4[3] * ext[..., j + 3]) / h
+        out[..., j] = (wts[0] * ext[..., j] + wts[1] * ext[..., j + 1] + wts[2] * ext[..., j + 2]
+                       + wts[3] * ext[..., j + 3]) / h
     return np.moveaxis(out, -1, ax)
 
 
-def diff4_to_integer(f: np.ndarray, w: str, h: float) -> np.ndarray:
+def diff4_to_integer(f: np.ndarray, w: str, h: float, wts: np.ndarray = W4) -> np.ndarray:
     """Fourth-order difference of the H samples (positions j+1/2 stored at j,
     j = 0..n-1) at the integer positions j = 1..n-1, with even images across
     the walls.  Entries 0 and n (walls) are 0."""
@@ -216,19 +258,19 @@ def diff4_to_integer(f: np.ndarray, w: str, h: float) -> np.ndarray:
     ext[..., n + 1] = a[..., n - 1]
     out = np.zeros_like(a)
     for j in range(1, n):                        # H stored j-2, j-1, j, j+1 -> ext index +1
-        out[..., j] = (W4[0] * ext[..., j - 1] + W4[1] * ext[..., j] + W4[2] * ext[..., j + 1]
-                       + W4[3] * ext[..., j + 2]) / h
+        out[..., j] = (wts[0] * ext[..., j - 1] + wts[1] * ext[..., j] + wts[2] * ext[..., j + 1]
+                       + wts[3] * ext[..., j + 2]) / h
     return np.moveaxis(out, -1, ax)
 
 
 def d_int(f: np.ndarray, w: str, g: Grid) -> np.ndarray:
     """The grid's first difference of H samples along w at the E positions."""
-    return diff4_to_integer(f, w, g.spacing(w)) if g.order == 4 else diff_to_integer(f, w, g.spacing(w))
+    return diff4_to_integer(f, w, g.spacing(w), g.w4) if g.order == 4 else diff_to_integer(f, w, g.spacing(w))
 
 
 def d_half(f: np.ndarray, w: str, g: Grid) -> np.ndarray:
     """The grid's first difference of E samples along w at the H positions."""
-    return diff4_to_half(f, w, g.spacing(w)) if g.order == 4 else diff_to_half(f, w, g.spacing(w))
+    return diff4_to_half(f, w, g.spacing(w), g.w4) if g.order == 4 else diff_to_half(f, w, g.spacing(w))
 
 
 def apply_operator(op: str, u, g: Grid):

@@ -30,9 +30,15 @@ MU0 = 1.25663706212e-6
 C0 = 1.0 / math.sqrt(EPS0 * MU0)
 
 
-def wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order=2):
+def wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order=2, outer=None):
+    """outer: order 4 with the outer weight b of the 4-point difference
+    [(1 - 3b)(f[+1/2] - f[-1/2]) + b (f[+3/2] - f[-3/2])] / dw, which maps the
+    profiles with K_w = (2/dw) ((1 - 3b) sin(k_w dw/2) + b sin(3 k_w dw/2))."""
     k = (m * math.pi / (nx * dx), n * math.pi / (ny * dy), p * math.pi / (nz * dz))
-    if order == 4:
+    if order == 4 and outer is not None:
+        K = tuple(2.0 / h * ((1.0 - 3.0 * outer) * math.sin(kw * h / 2.0) + outer * math.sin(1.5 * kw * h))
+                  for kw, h in zip(k, (dx, dy, dz)))
+    elif order == 4:
         K = tuple((27.0 * math.sin(kw * h / 2.0) - math.sin(1.5 * kw * h)) / (12.0 * h)
                   for kw, h in zip(k, (dx, dy, dz)))
     else:
@@ -40,9 +46,9 @@ def wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order=2):
     return k, K
 
 
-def mode_matrices(nx, ny, nz, dx, dy, dz, m, n, p, eps=EPS0, mu=MU0, order=2):
+def mode_matrices(nx, ny, nz, dx, dy, dz, m, n, p, eps=EPS0, mu=MU0, order=2, outer=None):
     """6x6 matrices of A and B on the amplitudes (a1..a6) of the (m, n, p) mode."""
-    _, (Kx, Ky, Kz) = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order)
+    _, (Kx, Ky, Kz) = wavenumbers(nx, ny, nz, dx, dy, dz, m, n, p, order, outer)
     A = np.zeros((6, 6))
     B = np.zeros((6, 6))
     # A: Ex<-(1/eps) dy Hz, Ey<-(1/eps) dz Hx, Ez<-(1/eps) dx Hy, Hx<-(1/mu) dz Ey, ...
