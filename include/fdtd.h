@@ -176,6 +176,27 @@ fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined);
  * run. */
 fdtd_status fdtd_set_order(fdtd_plan_t p, int order);
 
+/* Parameter-optimized operators (the closing remark of Sec. III-A names them
+ * without giving one).  The order-4 plans' difference is the 4-point
+ * staggered difference with outer weight b = `outer`:
+ *   d_w f = [(1 - 3b)(f[+1/2] - f[-1/2]) + b (f[+3/2] - f[-3/2])] / dw,
+ * exact on quadratics for every b, fourth order at b = -1/24 (the default);
+ * the wall images and the line solve are those of fdtd_set_order, so the
+ * schemes stay unconditionally stable and energy-conserving for every b.  A
+ * cavity mode of wavenumber k sees K(k) dw = 2 (1 - 3b) sin(k dw/2) +
+ * 2 b sin(3 k dw/2).  Order-4 plans only (else FDTD_EUNSUPPORTED);
+ * |outer| <= 0.25 (else FDTD_EINVAL).  Synchronizes the plan's stream; takes
+ * effect at the next run. */
+fdtd_status fdtd_set_stencil(fdtd_plan_t p, double outer);
+
+/* The outer weight b that minimizes the squared error of the modified
+ * wavenumber over a band: the integral over theta = k dw in [0, theta_max] of
+ * (K(k) dw - theta)^2, least squares in b (host computation, 64 x 8-point
+ * Gauss-Legendre quadrature).  0 < theta_max <= pi (theta_max = pi/2: four
+ * samples per wavelength), else FDTD_EINVAL; `outer`: host double.  A narrow
+ * band gives the fourth-order -1/24. */
+fdtd_status fdtd_stencil_optimized(double theta_max, double* outer);
+
 /* Advance the caller's fields by `nsteps` >= 0 full time steps:
  *   input processing (ADI: u^0 -> (1/2 I + dt/4 B) u^0, the link of
  *   Sec. II-E; LOD2: (fastLOD2i)/(orgLOD2i)), nsteps main iterations, output

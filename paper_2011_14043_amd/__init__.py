@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 from . import _lib
 
-__all__ = ["Plan", "BatchPlan", "Source", "FdtdError", "load_library", "ProbeEnergy", "probe_energy"]
+__all__ = ["Plan", "BatchPlan", "Source", "FdtdError", "load_library", "ProbeEnergy", "probe_energy", "optimized_stencil"]
 
 FdtdError = _lib.FdtdError
 
@@ -159,6 +159,11 @@ class Plan:
         _lib.check(_lib.lib().fdtd_set_order(self._h, int(order)), "fdtd_set_order")
         self.order = int(order)
         self.refined = self._refined()
+
+    def set_stencil(self, outer: float):
+        """Outer weight b of the order-4 plan's 4-point difference
+        (fdtd_set_stencil; -1/24: fourth order)."""
+        _lib.check(_lib.lib().fdtd_set_stencil(self._h, float(outer)), "fdtd_set_stencil")
 
     def set_step(self, n: int):
         _lib.check(_lib.lib().fdtd_set_step(self._h, int(n)), "fdtd_set_step")
@@ -336,6 +341,15 @@ class BatchPlan(Plan):
 
     def grad_eps(self, *a, **k):
         raise TypeError("the adjoint gradient is defined for single-grid plans")
+
+
+def optimized_stencil(theta_max: float) -> float:
+    """Outer weight of the 4-point difference that minimizes the squared
+    modified-wavenumber error over k dw in [0, theta_max]
+    (fdtd_stencil_optimized)."""
+    out = ctypes.c_double()
+    _lib.check(_lib.lib().fdtd_stencil_optimized(float(theta_max), ctypes.byref(out)), "fdtd_stencil_optimized")
+    return out.value
 
 
 from .autograd import ProbeEnergy, probe_energy  # noqa: E402

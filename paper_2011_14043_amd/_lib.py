@@ -19,7 +19,8 @@ SCHEMES = {"adi": 0, "lod1": 1, "ss1": 1, "ss2": 2, "lod2": 3,
 FORMS = {"fundamental": 0, "conventional": 1}
 DTYPES = {"f32": 0, "f64": 1, "f32_f64solve": 2, "f32_refine": 3, "f32_plain": 4}
 
-EXPORTS = ("fdtd_plan", "fdtd_get_refined", "fdtd_set_graph", "fdtd_set_order", "fdtd_run", "fdtd_step", "fdtd_set_step",
+EXPORTS = ("fdtd_plan", "fdtd_get_refined", "fdtd_set_graph", "fdtd_set_order", "fdtd_set_stencil",
+           "fdtd_stencil_optimized", "fdtd_run", "fdtd_step", "fdtd_set_step",
            "fdtd_set_timing",
            "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
            "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_diff_norm_noalloc",
@@ -68,6 +69,8 @@ def lib() -> ctypes.CDLL:
     L.fdtd_get_refined.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.fdtd_set_graph.argtypes = [vp, ctypes.c_int]
     L.fdtd_set_order.argtypes = [vp, ctypes.c_int]
+    L.fdtd_set_stencil.argtypes = [vp, ctypes.c_double]
+    L.fdtd_stencil_optimized.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.fdtd_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
                            ctypes.POINTER(FdtdSource), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.fdtd_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(FdtdSource)]
@@ -91,7 +94,8 @@ def lib() -> ctypes.CDLL:
     L.fdtd_destroy.argtypes = [vp]
     L.fdtd_strerror.argtypes = [ctypes.c_int]
     L.fdtd_strerror.restype = ctypes.c_char_p
-    for name in ("fdtd_plan", "fdtd_get_refined", "fdtd_set_graph", "fdtd_set_order", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
+    for name in ("fdtd_plan", "fdtd_get_refined", "fdtd_set_graph", "fdtd_set_order", "fdtd_set_stencil",
+                 "fdtd_stencil_optimized", "fdtd_run", "fdtd_step", "fdtd_set_step", "fdtd_set_timing",
                  "fdtd_last_timing", "fdtd_get_kernel_config", "fdtd_set_kernel_config", "fdtd_autotune",
                  "fdtd_grad_eps", "fdtd_plan_batch", "fdtd_run_batch", "fdtd_diff_norm", "fdtd_diff_norm_noalloc",
                  "fdtd_set_cg", "fdtd_last_cg", "fdtd_destroy"):

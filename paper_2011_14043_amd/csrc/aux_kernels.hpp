@@ -66,7 +66,8 @@ struct AuxCoef {
     double link;                  // ADI: dt/4 (state = 1/2 u + dt/4 B u); 0 for a plain copy
     int fin_form;                 // energy of a fundamental ADI state in output form (static H
                                   // still hold 1/2 u, i.e. their link value)
-    int order;                    // 4: the fourth-order differences (apply_B4); else second order
+    int order;                    // 4: the 4-point differences (apply_B4); else second order
+    double wo;                    // order 4: outer weight of the 4-point difference
 };
 
 // (B u)_c at a node, operator B of eq. (AMat) with Yee central differences.
@@ -84,8 +85,9 @@ __device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, dou
     }
 }
 
-// (B u)_c at a node with the fourth-order staggered differences, weights
-// (1, -27, 27, -1) / 24 over the four partner samples along the pair's axis
+// (B u)_c at a node with the 4-point staggered differences, weights
+// (-wo, -wi, wi, wo), wi = 1 - 3 wo (fourth order: (1, -27, 27, -1) / 24),
+// over the four partner samples along the pair's axis
 // (B pairs: Ex-Hy along z, Ey-Hz along x, Ez-Hx along y), folded across a PEC
 // wall onto image samples: H even (stored index -1 -> 0, n -> n-1), E odd
 // (position -p -> -E_p, n + p -> -E_{n-p}; E on a wall is 0).  `get` returns
@@ -93,7 +95,8 @@ __device__ __forceinline__ double apply_B(F get, int c, int i, int j, int k, dou
 template <typename F>
 __device__ __forceinline__ double apply_B4(F get, int c, int i, int j, int k, double inv_eps, double inv_mu,
                                            const AuxCoef& q, const Dims& d) {
-    constexpr double w[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
+    const double wi = 1.0 - 3.0 * q.wo;
+    const double w[4] = {-q.wo, -wi, wi, q.wo};
     const int axis = (c == 1 || c == 5) ? 0 : ((c == 2 || c == 3) ? 1 : 2);
     const int partner = c < 3 ? (c == 0 ? 4 : (c == 1 ? 5 : 3)) : (c == 3 ? 2 : (c == 4 ? 0 : 1));
     const int n = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);

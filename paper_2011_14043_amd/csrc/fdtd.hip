@@ -362,6 +362,41 @@ fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
     return FDTD_OK;
 }
 
+fdtd_status fdtd_set_stencil(fdtd_plan_t p, double outer) {
+    if (!plan_ok(p) || p->batch || !std::isfinite(outer) || std::fabs(outer) > 0.25) return FDTD_EINVAL;
+    if (p->order != 4) return FDTD_EUNSUPPORTED;
+    if (outer == p->stencil_wo) return FDTD_OK;
+    (void)hipStreamSynchronize(p->stream);
+    graph_clear(p);
+    p->stencil_wo = outer;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_stencil_optimized(double theta_max, double* outer) {
+    if (!outer || !(theta_max > 0.0) || !(theta_max <= M_PI)) return FDTD_EINVAL;
+    // b = -<e0, g> / <g, g> over [0, theta_max], e0 = 2 sin(t/2) - t,
+    // g = 2 sin(3t/2) - 6 sin(t/2): composite 8-point Gauss-Legendre rule on
+    // 64 panels (the integrands are smooth)
+    static const double x8[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    static const double w8[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const int panels = 64;
+    const double hp = theta_max / panels;
+    double num = 0.0, den = 0.0;
+    for (int m = 0; m < panels; ++m) {
+        const double c = (m + 0.5) * hp;
+        for (int t = 0; t < 8; ++t) {
+            const double th = c + 0.5 * hp * (t < 4 ? -x8[t] : x8[t - 4]);
+            const double wt = 0.5 * hp * w8[t < 4 ? t : t - 4];
+            const double e0 = 2.0 * std::sin(0.5 * th) - th;
+            const double g = 2.0 * std::sin(1.5 * th) - 6.0 * std::sin(0.5 * th);
+            num += wt * e0 * g;
+            den += wt * g * g;
+        }
+    }
+    *outer = -num / den;
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined) {
     if (!plan_ok(p) || !refined) return FDTD_EINVAL;
     *refined = p->refine;

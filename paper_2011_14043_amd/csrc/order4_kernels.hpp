@@ -1,16 +1,18 @@
 // order4_kernels.hpp -- line passes with fourth-order staggered differences.
 //
 // The closing remark of Sec. III-A leaves the difference operators of the
-// updating equations open (higher order, optimized, compact).  With the
-// fourth-order staggered first difference
-//     d_w f = (f[-3/2] - 27 f[-1/2] + 27 f[+1/2] - f[+3/2]) / (24 dw)
+// updating equations open (higher order, optimized, compact).  With a 4-point
+// staggered first difference
+//     d_w f = [wi (f[+1/2] - f[-1/2]) + wo (f[+3/2] - f[-3/2])] / dw,
+// wi = 1 - 3 wo (fourth order: wo = -1/24, wi = 27/24; a parameter-optimized
+// operator takes another outer weight wo),
 // in both the implicit line equation and the explicit H update, the
 // fundamental pass of a pair (E, H) along w keeps its form:
 //   r_j  = 2 sigma_j (U_e,j + pre) + kap (D U_h)_j
 //   solve (diag(sigma) + D^T D) V = r        (symmetric, positive definite)
 //   U_h  += q (D V)                           (H samples j + 1/2)
 //   U_e   = V - U_e - post
-// with D the dimensionless 4-point difference (weights 1, -27, 27, -1 over 24)
+// with D the dimensionless 4-point difference (weights -wo, -wi, wi, wo)
 // folded onto image samples across the PEC walls (tangential E odd, H even),
 // so that D^T is minus the H-to-E difference and the sub-step stays an exact
 // Cayley factor.  The system couples each unknown to three neighbours on
@@ -26,7 +28,8 @@
 //
 // Rows near the walls (the first and last three unknowns) have the folded
 // coefficients, computed on the host per line length; the other rows have
-// the interior band (1460, -783, 54, -1) / 576.
+// the interior band {2 wi^2 + 2 wo^2, 2 wi wo - wi^2, -2 wi wo, -wo^2}
+// ((1460, -783, 54, -1) / 576 for the fourth-order weights).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -42,6 +45,8 @@ struct Pass4Args {
     long long nlines;
     // band of rows 1..3 (lo) and n-3..n-1 (hi): {A_jj, A_j,j-1, A_j,j-2, A_j,j-3}
     double blo[3][4], bhi[3][4];
+    double bin[4];        // band of the other rows
+    double wi, wo;        // inner and outer weights of the difference
 };
 
 // Entries of row j (1 <= j <= n-1) of D^T D: {A_jj, A_j,j-1, A_j,j-2, A_j,j-3}.
@@ -54,10 +59,8 @@ __device__ __forceinline__ void band_row4(const Pass4Args<T, S>& a, int j, int n
 #pragma unroll
         for (int t = 0; t < 4; ++t) b[t] = S(a.bhi[j - (n - 3)][t]);
     } else {
-        b[0] = S(1460.0 / 576.0);
-        b[1] = S(-783.0 / 576.0);
-        b[2] = S(54.0 / 576.0);
-        b[3] = S(-1.0 / 576.0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = S(a.bin[t]);
     }
 }
 
@@ -96,8 +99,7 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     S L11 = S(0), L12 = S(0), L21 = S(0);       // L_{j-1,j-2}, L_{j-1,j-3}, L_{j-2,j-3}
     for (int j = 1; j < n; ++j) {
         const S hn = Hat(j + 1);
-        const S dh = (h0 - S(27) * h1) + (S(27) * h2 - hn);
-        const S dhs = dh * S(1.0 / 24.0);
+        const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
         S hterm = dhs * a.kap_hi;
         if constexpr (sizeof(S) == 4) hterm = fused(dhs, a.kap_lo, hterm);
         S b[4];
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     S vlast = S(0);   // V_{n-1}: its odd image is V_{n+1}
     // H sample hq: U_h += q (D V)_hq from V_{hq-1} .. V_{hq+2}
     auto store_h = [&](int hq, S vm1, S v0, S vp1, S vp2) {
-        const S dv = ((vm1 - S(27) * v0) + (S(27) * vp1 - vp2)) * S(1.0 / 24.0);
+        const S dv = S(A.wi) * (vp1 - v0) + S(A.wo) * (vp2 - vm1);
         const T old = H[base + hq * sw];
         const T nh = T(fused(a.q, dv, S(old)));
         H[base + hq * sw] = FIN ? T(double(nh) + double(old)) : nh;
@@ -249,7 +251,7 @@ __global__ void __launch_bounds__(64) pass4_x_kernel(Pass4Args<T, S> A) {
             for (int j = jlo; j <= jhi; ++j) {
                 const int c = j - t0;
                 const S hn = (j + 1 <= n - 1) ? S(tH[lane * LD + c]) : h2;   // H_{j+1}; image H_{n-1}
-                const S dhs = ((h0 - S(27) * h1) + (S(27) * h2 - hn)) * S(1.0 / 24.0);
+                const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
                 S hterm = dhs * a.kap_hi;
                 if constexpr (sizeof(S) == 4) hterm = fused(dhs, a.kap_lo, hterm);
                 S b[4];
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(64) pass4_x_kernel(Pass4Args<T, S> A) {
     S m11 = S(0), m21 = S(0), m22 = S(0), m31 = S(0), m32 = S(0), m33 = S(0);
     S vlast = S(0);
     auto new_h = [&](S old, S vm1, S v0, S vp1, S vp2) -> T {
-        const S dv = ((vm1 - S(27) * v0) + (S(27) * vp1 - vp2)) * S(1.0 / 24.0);
+        const S dv = S(A.wi) * (vp1 - v0) + S(A.wo) * (vp2 - vm1);
         const T nh = T(fused(a.q, dv, old));
         return FIN ? T(double(nh) + double(T(old))) : nh;
     };

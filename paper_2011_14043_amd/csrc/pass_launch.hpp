@@ -195,12 +195,21 @@ static void build_pass(fdtd_plan_s* p, int op, int k, double theta, int mode, T*
     }
 }
 
-// Band of D^T D (the fourth-order difference D, folded onto the wall images)
-// for a line of n cells: rows 1..3 (lo) and n-3..n-1 (hi), entries
+// Weights of the 4-point difference with outer weight wo, for the samples at
+// -3/2, -1/2, +1/2, +3/2: {-wo, -wi, wi, wo} with wi = 1 - 3 wo.
+static void stencil4_weights(double wo, double w[4]) {
+    const double wi = 1.0 - 3.0 * wo;
+    w[0] = -wo;
+    w[1] = -wi;
+    w[2] = wi;
+    w[3] = wo;
+}
+
+// Band of D^T D (the 4-point difference D with weights w, folded onto the wall
+// images) for a line of n cells: rows 1..3 (lo) and n-3..n-1 (hi), entries
 // {A_jj, A_j,j-1, A_j,j-2, A_j,j-3}, 0 where a column is not an unknown.
-static void band4_rows(int n, double lo[3][4], double hi[3][4]) {
-    static const double w[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
-    auto coef = [n](int h, int p) {   // D[h][p]: H sample h, E unknown p
+static void band4_rows(int n, const double w[4], double lo[3][4], double hi[3][4]) {
+    auto coef = [n, w](int h, int p) {   // D[h][p]: H sample h, E unknown p
         double c = 0.0;
         for (int t = 0; t < 4; ++t) {
             int q = h - 1 + t;
@@ -234,7 +243,17 @@ static fdtd_status launch_pass4(fdtd_plan_s* p, int op, int k, double theta, T* 
     build_pass<T, S>(p, op, k, theta, FUND, set, set, inj, a4.p, sh, fin);
     a4.nlines = (long long)a4.p.na * a4.p.nb;
     a4.scr = reinterpret_cast<S*>(p->scr4) + (size_t)k * 4 * p->dims.comp;
-    band4_rows(a4.p.n_w, a4.blo, a4.bhi);
+    double w[4];
+    stencil4_weights(p->stencil_wo, w);
+    band4_rows(a4.p.n_w, w, a4.blo, a4.bhi);
+    a4.wi = w[2];
+    a4.wo = w[3];
+    // interior rows: A_jj = sum w_t^2, A_j,j-1 = sum w_t w_t+1, ...
+    for (int t = 0; t < 4; ++t) {
+        double sum = 0.0;
+        for (int u = 0; u + t < 4; ++u) sum += w[u] * w[u + t];
+        a4.bin[t] = sum;
+    }
     if (sh.w == 0) {
         // x lines: 64 lines per one-wave block, rows staged through LDS (sw = 1)
         const dim3 grid((unsigned)((a4.nlines + 63) / 64)), block(64);

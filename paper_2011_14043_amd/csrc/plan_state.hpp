@@ -111,6 +111,7 @@ struct fdtd_plan_s {
     float* eps = nullptr;     // node layout, padded
     float* mu = nullptr;      // mu_r in node layout (plans with a permeability map; else NULL)
     int order = 2;            // accuracy order of the staggered differences (fdtd_set_order: 2 or 4)
+    double stencil_wo = -1.0 / 24.0;   // order 4: outer weight of the 4-point difference (fdtd_set_stencil)
     void* scr4 = nullptr;     // order 4: line-solve work area, 3 pairs x 4 arrays x comp (solve type)
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),

@@ -36,6 +36,7 @@ static fdtd_status energy_into(fdtd_plan_s* p, int set, double* dst, bool fin_fo
     if (p->d.scheme == FDTD_ADI && (p->d.form == FDTD_CONVENTIONAL || fin_form)) k.link = 0.25 * p->d.dt;
     k.fin_form = fin_form ? 1 : 0;
     k.order = p->order;
+    k.wo = p->stencil_wo;
     hipLaunchKernelGGL((energy_partial_kernel<T>), dim3(p->npartial), dim3(256), 0, p->stream,
                        state_ptrs<T>(p, set), p->eps, p->mu, p->dims, k, p->partial);
     HIPCHK(hipGetLastError());
@@ -50,6 +51,7 @@ template <typename T, typename S>
 static fdtd_status load_state(fdtd_plan_s* p, const FieldPtrs<T>& caller, double link) {
     AuxCoef kin = aux_coef(p->d, link);
     kin.order = p->order;
+    kin.wo = p->stencil_wo;
     if (p->order == 4 && link != 0.0) {
         const long long nn = (long long)(p->dims.nx + 1) * (p->dims.ny + 1) * (p->dims.nz + 1);
         hipLaunchKernelGGL((load_state4_kernel<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, p->stream, caller,

@@ -97,3 +97,18 @@ def test_header_is_c_and_c_program_builds(tmp_path):
     assert res.returncode == 0, res.stderr
     res = subprocess.run(_build.c_check_cmd(str(tmp_path / "check")), capture_output=True, text=True)
     assert res.returncode == 0, res.stderr
+
+
+def test_optimized_stencil_weight_matches_oracle(L):
+    """fdtd_stencil_optimized (a host computation) against the oracle's
+    least-squares weight (adaptive quadrature), and its argument checks."""
+    import math
+    from oracle import yee
+    out = ctypes.c_double()
+    for tm in (0.05, math.pi / 4, math.pi / 2, 2.0, math.pi):
+        assert L.fdtd_stencil_optimized(tm, ctypes.byref(out)) == 0
+        assert abs(out.value - yee.optimized_outer(tm)) <= 1e-10 * abs(out.value)
+    for bad in (0.0, -1.0, 3.5, float("nan")):
+        assert L.fdtd_stencil_optimized(bad, ctypes.byref(out)) == -1
+    assert L.fdtd_stencil_optimized(1.0, None) == -1
+    assert L.fdtd_set_stencil(None, -0.05) == -1
