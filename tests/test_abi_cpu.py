@@ -112,3 +112,29 @@ def test_optimized_stencil_weight_matches_oracle(L):
         assert L.fdtd_stencil_optimized(bad, ctypes.byref(out)) == -1
     assert L.fdtd_stencil_optimized(1.0, None) == -1
     assert L.fdtd_set_stencil(None, -0.05) == -1
+
+
+def sanitizer_env():
+    """Environment for the host-sanitized exercise program: every report is
+    fatal, leaks included (the HIP runtime's own allocations suppressed)."""
+    env = dict(os.environ)
+    env["ASAN_OPTIONS"] = "detect_leaks=1:exitcode=23:abort_on_error=0:strict_string_checks=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1:exitcode=24"
+    env["LSAN_OPTIONS"] = "suppressions=" + os.path.join(ROOT, "tests", "c_abi", "lsan.supp")
+    return env
+
+
+def test_sanitized_host_checks():
+    """The argument checks of every entry point, through the library built
+    with its host code under AddressSanitizer and UndefinedBehaviorSanitizer
+    (tests/c_abi/fdtd_abi_exercise host)."""
+    import json
+    import subprocess
+    from paper_2011_14043_amd import _build
+    if not (os.path.exists(_build.EXERCISE_BIN) and os.path.exists(_build.SAN_LIB)):
+        pytest.fail("sanitized build missing (run __graft_entry__.build())")
+    res = subprocess.run([_build.EXERCISE_BIN, "host"], capture_output=True, text=True, timeout=120,
+                         env=sanitizer_env())
+    assert res.returncode == 0, res.stdout + res.stderr
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    assert out["failures"] == 0 and out["checks"] >= 60, out
