@@ -91,15 +91,21 @@ def bytes_per_slot(prec, conv_adi=False, material_index=False):
     return words * w + (1 if material_index else 4)
 
 
-def order4_moved_bytes_per_slot(prec):
-    """Bytes a fourth-order line pass moves per slot: forward sweep reads E, H
-    and eps_r and writes four solve words (three multipliers and the
-    substituted right side), the backward sweep reads them back with E and H
-    and writes E and H: 6 field words + 4 + 8 solve words (60 B FP32, 116 B
-    FP64, 92 B FP32 fields with FP64 solves)."""
+def order4_moved_bytes_per_slot(prec, material_index=True):
+    """Bytes a fourth-order line pass moves per slot, averaged over a step's
+    four y/z and two x passes: the forward sweep reads E, H and the medium and
+    writes the substituted right side y, the backward sweep reads y and the
+    medium again with E and H and writes E and H; the factorization state (6
+    solve words) is written and read back once per segment of K rows (y/z: K =
+    16 with FP32 solves, 8 with FP64; x: 8).  With the one-byte material index:
+    38 B FP32, 78 B FP64, 54 B FP32 fields with FP64 solves."""
     t = 8 if prec == "f64" else 4
     sv = 8 if prec in ("f64", "f32s64") else 4
-    return 6 * t + 4 + 8 * sv
+    med = 1 if material_index else 4
+
+    def per(k):
+        return 6 * t + 2 * sv + 12 * sv / k + 2 * med
+    return (4 * per(16 if sv == 4 else 8) + 2 * per(8)) / 6
 
 
 def run_order4(n, precs, steps, warmup, inputs, refs):

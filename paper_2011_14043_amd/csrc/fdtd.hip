@@ -344,11 +344,55 @@ fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
         if (p->cg || p->d.form != FDTD_FUNDAMENTAL || p->mu || p->req_dtype == FDTD_F32_REFINE)
             return FDTD_EUNSUPPORTED;
         if (!p->scr4) {
-            const size_t ssz = (p->d.dtype == FDTD_F32) ? sizeof(float) : sizeof(double);
-            if (hipMalloc(&p->scr4, ssz * 12 * (size_t)p->dims.comp) != hipSuccess) {
+            // per pair pass: the work area of the kernel (y and the
+            // factorization state at segment starts) for the largest of the
+            // three line families (at most (n + 1)^2 lines of each)
+            const bool fsolve = p->d.dtype == FDTD_F32;
+            const size_t ssz = fsolve ? sizeof(float) : sizeof(double);
+            const int K = fsolve ? seg4<float>() : seg4<double>();
+            const long long n1[3] = {p->d.nx + 1LL, p->d.ny + 1LL, p->d.nz + 1LL};
+            size_t region = 0;
+            for (int w = 0; w < 3; ++w)
+                region = std::max(region, (size_t)work4_words(int(n1[w] - 1), n1[(w + 1) % 3] * n1[(w + 2) % 3], K));
+            if (hipMalloc(&p->scr4, ssz * 3 * region) != hipSuccess) {
                 p->scr4 = nullptr;
                 return FDTD_ENOMEM;
             }
+            p->scr4_region = region;
+        }
+        if (!p->tr4) {
+            // x lines run on a transposed copy of their pair: planes of nx + 1
+            // rows of ny + 1 samples (rows padded to 128 bytes); the medium's
+            // copy is made here, once
+            const Dims& dm = p->dims;
+            const long long align = p->esz == 8 ? 16 : 32;
+            const long long pitch = ((dm.ny + 1 + align - 1) / align) * align;
+            const long long plane = (long long)(dm.nx + 1) * pitch;
+            const size_t compt = (size_t)plane * (dm.nz + 1);
+            const size_t msz = p->mat ? 1 : sizeof(float);
+            if (hipMalloc(&p->tr4, 2 * compt * p->esz) != hipSuccess) {
+                p->tr4 = nullptr;
+                return FDTD_ENOMEM;
+            }
+            if (hipMalloc(&p->tr4_med, compt * msz) != hipSuccess) {
+                (void)hipFree(p->tr4);
+                p->tr4 = p->tr4_med = nullptr;
+                return FDTD_ENOMEM;
+            }
+            p->tr4_pitch = pitch;
+            p->tr4_plane = plane;
+            if (p->mat)
+                hipLaunchKernelGGL((transpose_planes_kernel<unsigned char>),
+                                   transpose_grid<unsigned char>(dm.ny + 1, dm.nx + 1, dm.nz + 1), dim3(256), 0,
+                                   p->stream, p->mat,
+                                   dm.plane, (long long)dm.px, static_cast<unsigned char*>(p->tr4_med), plane, pitch,
+                                   dm.ny + 1, dm.nx + 1);
+            else
+                hipLaunchKernelGGL((transpose_planes_kernel<float>), transpose_grid<float>(dm.ny + 1, dm.nx + 1, dm.nz + 1),
+                                   dim3(256), 0, p->stream, p->eps, dm.plane,
+                                   (long long)dm.px, static_cast<float*>(p->tr4_med), plane, pitch, dm.ny + 1,
+                                   dm.nx + 1);
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess) return FDTD_EDEVICE;
         }
     }
     (void)hipStreamSynchronize(p->stream);
@@ -764,6 +808,8 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (p->eps) (void)hipFree(p->eps);
     if (p->mu) (void)hipFree(p->mu);
     if (p->scr4) (void)hipFree(p->scr4);
+    if (p->tr4) (void)hipFree(p->tr4);
+    if (p->tr4_med) (void)hipFree(p->tr4_med);
     if (p->partial) (void)hipFree(p->partial);
     if (p->energy_dev) (void)hipFree(p->energy_dev);
     if (p->mat) (void)hipFree(p->mat);

@@ -18,13 +18,24 @@
 // Cayley factor.  The system couples each unknown to three neighbours on
 // either side (band 3).
 //
-// One thread solves one line: an LDL^T sweep forward (the three multipliers
-// of each row and the forward-substituted right side divided by its pivot go
-// to a work area, one array per quantity, indexed [slot][line] so that the
-// lanes of a wave store and load consecutive words), then the backward sweep
-// forms V from the work area and writes the new E and H.  Lanes hold
-// neighbouring lines, so for y and z lines every field access is coalesced;
-// x lines read their rows with a stride between lanes.
+// One thread solves one line: an LDL^T sweep forward, then a backward sweep
+// that forms V and writes the new E and H.  The forward sweep stores, per
+// row, only the forward-substituted right side divided by its pivot (y), and
+// at the start of every segment of K rows the recurrence state of the
+// factorization (the last three pivots and the two multipliers the next row
+// needs); the backward sweep takes each segment's state, factors its K rows
+// again into registers (the factors depend on the medium only) and then runs
+// the back substitution over them.  So the work area takes 1 + 6/K words per
+// slot instead of the four (three multipliers and y) a stored factorization
+// needs.  Both sweeps issue a segment's loads together before its rows run
+// (the recurrences are serial, so a lane would otherwise wait on memory once
+// per row).  K = 8 with FP32 solves, 4 with FP64 (registers).  Work-area
+// arrays are indexed [slot][line] so that the lanes of a wave store and load
+// consecutive words.
+// With a material index the medium term Ks eps_r comes from a per-material
+// table in LDS (one byte per slot read, the same values as from eps_r).
+// Lanes hold neighbouring lines, so every field access is coalesced (x lines
+// on a transposed copy, below).
 //
 // Rows near the walls (the first and last three unknowns) have the folded
 // coefficients, computed on the host per line length; the other rows have
@@ -41,7 +52,8 @@ namespace fdtd {
 template <typename T, typename S>
 struct Pass4Args {
     PassArgs<T, S> p;     // pair arrays (Ein == Eout, Hin == Hout), line geometry, coefficients, source
-    S* scr;               // work area: 4 arrays of n_w * nlines (l1, l2, l3, y)
+    S* scr;               // work area: y (n_w * nlines), then the recurrence state at each segment
+                          // start (nseg * 6 * nlines, nseg = segments of the kernel's length)
     long long nlines;
     // band of rows 1..3 (lo) and n-3..n-1 (hi): {A_jj, A_j,j-1, A_j,j-2, A_j,j-3}
     double blo[3][4], bhi[3][4];
@@ -64,25 +76,91 @@ __device__ __forceinline__ void band_row4(const Pass4Args<T, S>& a, int j, int n
     }
 }
 
+// Recurrence state of the LDL^T factorization at a row: D_{j-1}, D_{j-2},
+// D_{j-3} and L_{j-1,j-2}, L_{j-1,j-3}, L_{j-2,j-3}.
+template <typename S>
+struct Ldl4 {
+    S D1, D2, D3, L11, L12, L21;
+};
+
+template <typename S>
+__device__ __forceinline__ Ldl4<S> ldl4_start() {
+    return Ldl4<S>{S(1), S(1), S(1), S(0), S(0), S(0)};
+}
+
+// Row j of the factorization (band b, diagonal dgj): multipliers L_{j,j-1},
+// L_{j,j-2}, L_{j,j-3}, pivot D_j; advances the state to row j + 1.  The
+// forward and the backward sweep both call this, so they get the same factors.
+template <typename S>
+__device__ __forceinline__ void ldl4_row(Ldl4<S>& f, const S (&b)[4], S dgj, S& l1, S& l2, S& l3, S& Dj) {
+    l3 = b[3] * recip(f.D3);
+    l2 = (b[2] - l3 * f.L21 * f.D3) * recip(f.D2);
+    l1 = (b[1] - l3 * f.L12 * f.D3 - l2 * f.L11 * f.D2) * recip(f.D1);
+    Dj = dgj - (l3 * l3 * f.D3 + l2 * l2 * f.D2 + l1 * l1 * f.D1);
+    f.D3 = f.D2;
+    f.D2 = f.D1;
+    f.D1 = Dj;
+    f.L21 = f.L11;
+    f.L12 = l2;
+    f.L11 = l1;
+}
+
+// State of segment s of a line in the work area (6 arrays of nlines words).
+template <typename S>
+__device__ __forceinline__ void ldl4_save(S* ck, long long NL, long long line, const Ldl4<S>& f) {
+    ck[line] = f.D1;
+    ck[NL + line] = f.D2;
+    ck[2 * NL + line] = f.D3;
+    ck[3 * NL + line] = f.L11;
+    ck[4 * NL + line] = f.L12;
+    ck[5 * NL + line] = f.L21;
+}
+template <typename S>
+__device__ __forceinline__ Ldl4<S> ldl4_load(const S* ck, long long NL, long long line) {
+    return Ldl4<S>{ck[line], ck[NL + line], ck[2 * NL + line], ck[3 * NL + line], ck[4 * NL + line],
+                   ck[5 * NL + line]};
+}
+
+// Ks eps_r of each material (LDS), when the plan has a material index.
+template <typename T, typename S>
+__device__ __forceinline__ void load_ks_table(S* ktab, const PassArgs<T, S>& a) {
+    if (!a.mat) return;
+    for (int m = int(threadIdx.x); m < 256; m += int(blockDim.x))
+        ktab[m] = S(a.Ks * double(m < a.nmat ? a.mat_eps[m] : 1.0f));
+    __syncthreads();
+}
+
+// Segment length of the kernel (factors of a segment held in registers).
+template <typename S>
+__host__ __device__ constexpr int seg4() { return sizeof(S) == 4 ? 8 : 4; }
+
+// Work-area words of one pass over nlines lines of n cells: y (n per line)
+// and the factorization state (6 words) at the start of each segment of K
+// rows (rows 1 .. n-1).  The kernel's indexing and the host's allocation both
+// use this.
+__host__ __device__ constexpr long long work4_words(int n, long long nlines, int K) {
+    return ((long long)n + 6LL * ((n - 1 + K - 1) / K)) * nlines;
+}
+
 // One fundamental pass of the fourth-order operator over the lines of `a`
 // (FIN: the output form u = U_old + U_new, as the second-order FIN passes).
 template <typename T, typename S, bool FIN>
 __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
+    constexpr int K = seg4<S>();
     const PassArgs<T, S>& a = A.p;
+    __shared__ S ktab[256];
+    load_ks_table<T, S>(ktab, a);
     const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (line >= A.nlines) return;
     const int ia = a.a_lo + int(line % a.na), ib = a.b_lo + int(line / a.na);
     const long long base = (long long)ia * a.sa + (long long)ib * a.sb;
     const long long sw = a.sw;
     const int n = a.n_w;   // cells along the line: unknowns 1 .. n-1, H samples 0 .. n-1
-    T* E = a.Eout;
-    T* H = a.Hout;
-    const float* eps = a.eps;
+    T* __restrict__ E = a.Eout;
+    T* __restrict__ H = a.Hout;
     const long long NL = A.nlines;
-    S* s1 = A.scr;
-    S* s2 = s1 + (long long)n * NL;
-    S* s3 = s2 + (long long)n * NL;
-    S* sy = s3 + (long long)n * NL;
+    S* __restrict__ sy = A.scr;
+    S* __restrict__ ck = sy + (long long)n * NL;
     const bool src_line = ia == a.src_a && ib == a.src_b;
     const S pre = src_line ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
     const S post = src_line ? (a.src_post_dev ? S(*a.src_post_dev) : a.src_post) : S(0);
@@ -90,43 +168,55 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
         q = q < 0 ? -1 - q : (q > n - 1 ? 2 * n - 1 - q : q);
         return S(H[base + q * sw]);
     };
+    auto kes = [&](int j) -> S {   // Ks eps_r at unknown j
+        const long long o = base + j * sw;
+        return a.mat ? ktab[a.mat[o]] : S(a.Ks * double(a.eps[o]));
+    };
+    const int nseg = (n - 1 + K - 1) / K;   // segments of K rows from row 1
     // ---- forward: LDL^T and forward substitution ----------------------------
-    // window: H_{j-2}, H_{j-1}, H_j (H_{j+1} loaded per row); previous rows'
-    // pivots D, forward-substituted z and multipliers
+    // Each segment's loads are issued together before its rows run, so a
+    // lane waits for memory once per segment rather than once per row.
+    // window: H_{j-2}, H_{j-1}, H_j; forward-substituted z of the previous
+    // three rows
     S h0 = Hat(-1), h1 = Hat(0), h2 = Hat(1);
-    S D1 = S(1), D2 = S(1), D3 = S(1);          // D_{j-1}, D_{j-2}, D_{j-3}
-    S z1 = S(0), z2 = S(0), z3 = S(0);          // z_{j-1}, z_{j-2}, z_{j-3}
-    S L11 = S(0), L12 = S(0), L21 = S(0);       // L_{j-1,j-2}, L_{j-1,j-3}, L_{j-2,j-3}
-    for (int j = 1; j < n; ++j) {
-        const S hn = Hat(j + 1);
-        const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
-        S hterm = dhs * a.kap_hi;
-        if constexpr (sizeof(S) == 4) hterm = fused(dhs, a.kap_lo, hterm);
-        S b[4];
-        band_row4<T, S>(A, j, n, b);
-        // diagonal sigma + (D^T D)_jj, and sigma taken back from it (exact),
-        // so that the diagonal and the right side see one medium (as the
-        // second-order FP32 passes do with 2 + sigma)
-        const S dgj = b[0] + S(a.Ks * double(eps[base + j * sw]));
-        const S sig = dgj - b[0];
-        const S ue = S(E[base + j * sw]);
-        const S r = S(2) * sig * (ue + ((src_line && j == a.src_j) ? pre : S(0))) + hterm;
-        // L_{j,j-3}, L_{j,j-2}, L_{j,j-1}, D_j
-        const S l3 = b[3] * recip(D3);
-        const S l2 = (b[2] - l3 * L21 * D3) * recip(D2);
-        const S l1 = (b[1] - l3 * L12 * D3 - l2 * L11 * D2) * recip(D1);
-        const S Dj = dgj - (l3 * l3 * D3 + l2 * l2 * D2 + l1 * l1 * D1);
-        const S zj = r - (l1 * z1 + l2 * z2 + l3 * z3);
-        const long long o = (long long)j * NL + line;
-        s1[o] = l1;
-        s2[o] = l2;
-        s3[o] = l3;
-        sy[o] = zj * recip(Dj);
-        // shift the windows
-        D3 = D2; D2 = D1; D1 = Dj;
-        z3 = z2; z2 = z1; z1 = zj;
-        L21 = L11; L12 = l2; L11 = l1;
-        h0 = h1; h1 = h2; h2 = hn;
+    Ldl4<S> f = ldl4_start<S>();
+    S z1 = S(0), z2 = S(0), z3 = S(0);
+    for (int s = 0; s < nseg; ++s) {
+        const int j0 = 1 + s * K;
+        S ev[K], hv[K], mv[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int j = j0 + t;
+            if (j < n) {
+                ev[t] = S(E[base + j * sw]);
+                hv[t] = Hat(j + 1);
+                mv[t] = kes(j);
+            }
+        }
+        ldl4_save(ck + (long long)s * 6 * NL, NL, line, f);
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int j = j0 + t;
+            if (j >= n) continue;
+            const S hn = hv[t];
+            const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
+            S hterm = dhs * a.kap_hi;
+            if constexpr (sizeof(S) == 4) hterm = fused(dhs, a.kap_lo, hterm);
+            S b[4];
+            band_row4<T, S>(A, j, n, b);
+            // diagonal sigma + (D^T D)_jj, and sigma taken back from it
+            // (exact), so that the diagonal and the right side see one medium
+            // (as the second-order FP32 passes do with 2 + sigma)
+            const S dgj = b[0] + mv[t];
+            const S sig = dgj - b[0];
+            const S r = S(2) * sig * (ev[t] + ((src_line && j == a.src_j) ? pre : S(0))) + hterm;
+            S l1, l2, l3, Dj;
+            ldl4_row(f, b, dgj, l1, l2, l3, Dj);
+            const S zj = r - (l1 * z1 + l2 * z2 + l3 * z3);
+            sy[(long long)j * NL + line] = zj * recip(Dj);
+            z3 = z2; z2 = z1; z1 = zj;
+            h0 = h1; h1 = h2; h2 = hn;
+        }
     }
     // ---- backward: V, then the new E_j and H_{j+1} --------------------------
     // V_j = y_j - L_{j+1,j} V_{j+1} - L_{j+2,j} V_{j+2} - L_{j+3,j} V_{j+3}:
@@ -135,189 +225,108 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     S v1 = S(0), v2 = S(0), v3 = S(0);
     S m11 = S(0), m21 = S(0), m22 = S(0), m31 = S(0), m32 = S(0), m33 = S(0);
     S vlast = S(0);   // V_{n-1}: its odd image is V_{n+1}
-    // H sample hq: U_h += q (D V)_hq from V_{hq-1} .. V_{hq+2}
-    auto store_h = [&](int hq, S vm1, S v0, S vp1, S vp2) {
+    // new H sample from its old value and V_{hq-1} .. V_{hq+2}: U_h += q (D V)
+    auto new_h = [&](T old, S vm1, S v0, S vp1, S vp2) -> T {
         const S dv = S(A.wi) * (vp1 - v0) + S(A.wo) * (vp2 - vm1);
-        const T old = H[base + hq * sw];
         const T nh = T(fused(a.q, dv, S(old)));
-        H[base + hq * sw] = FIN ? T(double(nh) + double(old)) : nh;
+        return FIN ? T(double(nh) + double(old)) : nh;
     };
-    for (int j = n - 1; j >= 1; --j) {
-        const long long o = (long long)j * NL + line;
-        const S l1 = s1[o], l2 = s2[o], l3 = s3[o], yj = sy[o];
-        const S vj = yj - ((m11 * v1 + m22 * v2) + m33 * v3);
-        if (j == n - 1) vlast = vj;
-        // H_{j+1} (j + 1 <= n - 1): V_j .. V_{j+3}; V_n = 0 (wall, the window's
-        // zero), V_{n+1} = -V_{n-1} (needed at j = n - 2)
-        if (j + 1 <= n - 1) store_h(j + 1, vj, v1, v2, (j == n - 2) ? -vlast : v3);
-        const bool at_src = src_line && j == a.src_j;
-        const T old = E[base + j * sw];
-        const T ne = T(vj - S(old) - (at_src ? post : S(0)));
-        E[base + j * sw] = FIN ? T(double(ne) + double(old) + (at_src ? a.fsrc : 0.0)) : ne;
-        m33 = m32; m32 = m31; m31 = l3;
-        m22 = m21; m21 = l2;
-        m11 = l1;
-        v3 = v2; v2 = v1; v1 = vj;
-    }
-    // here v1..v3 = V_1..V_3 (0 at or past the wall, except the image V_{n+1})
-    store_h(1, S(0), v1, v2, (n == 2) ? -vlast : v3);   // H_1: V_0 .. V_3
-    store_h(0, -v1, S(0), v1, v2);                      // H_0: V_-1 = -V_1 .. V_2
-}
-
-// x lines (the contiguous axis): the same sweeps, with the fields staged
-// through LDS so that HBM sees whole rows.  A block is one wave holding 64
-// consecutive lines; tiles of X4_TS slots of all 64 rows are loaded row by
-// row (64 / X4_TS rows per wave instruction, X4_TS contiguous words each), each lane
-// then runs its own line's recurrences from LDS, and the backward sweep writes
-// its results into the tile, which is stored row by row.  The H tile of the
-// E slots [t0, t0 + X4_TS) covers H samples t0 + 1 .. t0 + X4_TS: the sample
-// that E_j's row completes in the backward sweep is H_{j+1}.
-constexpr int X4_TS = 8;
-
-template <typename T, typename S, bool FIN>
-__global__ void __launch_bounds__(64) pass4_x_kernel(Pass4Args<T, S> A) {
-    const PassArgs<T, S>& a = A.p;
-    constexpr int TS = X4_TS, LD = X4_TS + 1;
-    __shared__ T tE[64 * LD];
-    __shared__ T tH[64 * LD];
-    __shared__ float tP[64 * LD];
-    const int lane = threadIdx.x;
-    const long long L0 = (long long)blockIdx.x * 64;
-    const long long line = L0 + lane;
-    const bool live = line < A.nlines;
-    const int n = a.n_w;
-    T* E = a.Eout;
-    T* H = a.Hout;
-    auto base_of = [&](long long ln) -> long long {
-        const int ia = a.a_lo + int(ln % a.na), ib = a.b_lo + int(ln / a.na);
-        return (long long)ia * a.sa + (long long)ib * a.sb;
-    };
-    const long long base = live ? base_of(line) : 0;
-    const int ia = a.a_lo + int(line % a.na), ib = a.b_lo + int(line / a.na);
-    const bool src_line = live && ia == a.src_a && ib == a.src_b;
-    const S pre = src_line ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
-    const S post = src_line ? (a.src_post_dev ? S(*a.src_post_dev) : a.src_post) : S(0);
-    const long long NL = A.nlines;
-    S* s1 = A.scr;
-    S* s2 = s1 + (long long)n * NL;
-    S* s3 = s2 + (long long)n * NL;
-    S* sy = s3 + (long long)n * NL;
-    // tile transfer: 64 / TS rows per wave instruction, rows r = m (64 / TS) +
-    // lane / TS, slot t0 + lane % TS of E and eps, t0 + 1 + lane % TS of H;
-    // `store` writes E slots [elo, ehi] and H samples [hlo, hhi] back
-    constexpr int RPI = 64 / TS;
-    const int half = lane / TS, col = lane % TS;
-    auto load_tile = [&](int t0, bool with_eps) {
-        for (int m = 0; m < TS; ++m) {
-            const int r = RPI * m + half;
-            const long long ln = L0 + r;
-            if (ln >= NL) continue;
-            const long long b = base_of(ln);
-            const int je = t0 + col, jh = t0 + 1 + col;
-            if (je <= n) {
-                tE[r * LD + col] = E[b + je];
-                if (with_eps) tP[r * LD + col] = a.eps[b + je];
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int j0 = 1 + s * K;
+        // the segment's loads, then its factors again from its saved state
+        Ldl4<S> g = ldl4_load(ck + (long long)s * 6 * NL, NL, line);
+        S yv[K], mv[K], f1[K], f2[K], f3[K];
+        T ev[K], hv[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int j = j0 + t;
+            if (j < n) {
+                yv[t] = sy[(long long)j * NL + line];
+                ev[t] = E[base + j * sw];
+                if (j + 1 <= n - 1) hv[t] = H[base + (j + 1) * sw];
+                mv[t] = kes(j);
             }
-            if (jh <= n - 1) tH[r * LD + col] = H[b + jh];
         }
-        __syncthreads();
-    };
-    auto store_tile = [&](int t0, int elo, int ehi, int hlo, int hhi) {
-        __syncthreads();
-        for (int m = 0; m < TS; ++m) {
-            const int r = RPI * m + half;
-            const long long ln = L0 + r;
-            if (ln >= NL) continue;
-            const long long b = base_of(ln);
-            const int je = t0 + col, jh = t0 + 1 + col;
-            if (je >= elo && je <= ehi) E[b + je] = tE[r * LD + col];
-            if (jh >= hlo && jh <= hhi) H[b + jh] = tH[r * LD + col];
-        }
-        __syncthreads();
-    };
-    const int ntiles = (n + TS - 1) / TS;   // tiles of E slots 0 .. n-1
-    // ---- forward ------------------------------------------------------------
-    const S H0 = live ? S(H[base]) : S(0);
-    S h0 = H0, h1 = H0, h2 = S(0);
-    S D1 = S(1), D2 = S(1), D3 = S(1);
-    S z1 = S(0), z2 = S(0), z3 = S(0);
-    S L11 = S(0), L12 = S(0), L21 = S(0);
-    for (int tt = 0; tt < ntiles; ++tt) {
-        const int t0 = tt * TS;
-        load_tile(t0, true);
-        if (tt == 0) h2 = S(tH[lane * LD + 0]);   // H_1 (n >= 2)
-        const int jlo = t0 < 1 ? 1 : t0, jhi = (t0 + TS - 1 < n - 1) ? t0 + TS - 1 : n - 1;
-        if (live) {
-            for (int j = jlo; j <= jhi; ++j) {
-                const int c = j - t0;
-                const S hn = (j + 1 <= n - 1) ? S(tH[lane * LD + c]) : h2;   // H_{j+1}; image H_{n-1}
-                const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
-                S hterm = dhs * a.kap_hi;
-                if constexpr (sizeof(S) == 4) hterm = fused(dhs, a.kap_lo, hterm);
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int j = j0 + t;
+            if (j < n) {
                 S b[4];
                 band_row4<T, S>(A, j, n, b);
-                const S dgj = b[0] + S(a.Ks * double(tP[lane * LD + c]));
-                const S sig = dgj - b[0];
-                const S ue = S(tE[lane * LD + c]);
-                const S r = S(2) * sig * (ue + ((src_line && j == a.src_j) ? pre : S(0))) + hterm;
-                const S l3 = b[3] * recip(D3);
-                const S l2 = (b[2] - l3 * L21 * D3) * recip(D2);
-                const S l1 = (b[1] - l3 * L12 * D3 - l2 * L11 * D2) * recip(D1);
-                const S Dj = dgj - (l3 * l3 * D3 + l2 * l2 * D2 + l1 * l1 * D1);
-                const S zj = r - (l1 * z1 + l2 * z2 + l3 * z3);
-                const long long o = (long long)j * NL + line;
-                s1[o] = l1;
-                s2[o] = l2;
-                s3[o] = l3;
-                sy[o] = zj * recip(Dj);
-                D3 = D2; D2 = D1; D1 = Dj;
-                z3 = z2; z2 = z1; z1 = zj;
-                L21 = L11; L12 = l2; L11 = l1;
-                h0 = h1; h1 = h2; h2 = hn;
+                S Dj;
+                ldl4_row(g, b, b[0] + mv[t], f1[t], f2[t], f3[t], Dj);
             }
         }
-        __syncthreads();
-    }
-    // ---- backward -----------------------------------------------------------
-    S v1 = S(0), v2 = S(0), v3 = S(0);
-    S m11 = S(0), m21 = S(0), m22 = S(0), m31 = S(0), m32 = S(0), m33 = S(0);
-    S vlast = S(0);
-    auto new_h = [&](S old, S vm1, S v0, S vp1, S vp2) -> T {
-        const S dv = S(A.wi) * (vp1 - v0) + S(A.wo) * (vp2 - vm1);
-        const T nh = T(fused(a.q, dv, old));
-        return FIN ? T(double(nh) + double(T(old))) : nh;
-    };
-    for (int tt = ntiles - 1; tt >= 0; --tt) {
-        const int t0 = tt * TS;
-        load_tile(t0, false);
-        const int jlo = t0 < 1 ? 1 : t0, jhi = (t0 + TS - 1 < n - 1) ? t0 + TS - 1 : n - 1;
-        if (live) {
-            for (int j = jhi; j >= jlo; --j) {
-                const int c = j - t0;
-                const long long o = (long long)j * NL + line;
-                const S l1 = s1[o], l2 = s2[o], l3 = s3[o], yj = sy[o];
-                const S vj = yj - ((m11 * v1 + m22 * v2) + m33 * v3);
-                if (j == n - 1) vlast = vj;
-                if (j + 1 <= n - 1)
-                    tH[lane * LD + c] = new_h(S(tH[lane * LD + c]), vj, v1, v2, (j == n - 2) ? -vlast : v3);
-                const bool at_src = src_line && j == a.src_j;
-                const T old = tE[lane * LD + c];
-                const T ne = T(vj - S(old) - (at_src ? post : S(0)));
-                tE[lane * LD + c] = FIN ? T(double(ne) + double(old) + (at_src ? a.fsrc : 0.0)) : ne;
-                m33 = m32; m32 = m31; m31 = l3;
-                m22 = m21; m21 = l2;
-                m11 = l1;
-                v3 = v2; v2 = v1; v1 = vj;
-            }
-            if (tt == 0) {
-                // H_1 (tile column 0) from V_0 = 0 .. V_3
-                tH[lane * LD + 0] = new_h(S(tH[lane * LD + 0]), S(0), v1, v2, (n == 2) ? -vlast : v3);
-            }
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const int j = j0 + t;
+            if (j >= n) continue;
+            const S vj = yv[t] - ((m11 * v1 + m22 * v2) + m33 * v3);
+            if (j == n - 1) vlast = vj;
+            // H_{j+1} (j + 1 <= n - 1): V_j .. V_{j+3}; V_n = 0 (wall, the window's
+            // zero), V_{n+1} = -V_{n-1} (needed at j = n - 2)
+            if (j + 1 <= n - 1) H[base + (j + 1) * sw] = new_h(hv[t], vj, v1, v2, (j == n - 2) ? -vlast : v3);
+            const bool at_src = src_line && j == a.src_j;
+            const T old = ev[t];
+            const T ne = T(vj - S(old) - (at_src ? post : S(0)));
+            E[base + j * sw] = FIN ? T(double(ne) + double(old) + (at_src ? a.fsrc : 0.0)) : ne;
+            m33 = m32; m32 = m31; m31 = f3[t];
+            m22 = m21; m21 = f2[t];
+            m11 = f1[t];
+            v3 = v2; v2 = v1; v1 = vj;
         }
-        // E slots [jlo, jhi]; H samples t0+1 .. t0+TS below n (H_1 only in the lowest tile, done above)
-        store_tile(t0, jlo, jhi, t0 + 1, (t0 + TS < n - 1) ? t0 + TS : n - 1);
     }
-    if (live) H[base] = new_h(H0, -v1, S(0), v1, v2);   // H_0: V_-1 = -V_1 .. V_2
+    // here v1..v3 = V_1..V_3 (0 at or past the wall, except the image V_{n+1})
+    H[base + sw] = new_h(H[base + sw], S(0), v1, v2, (n == 2) ? -vlast : v3);   // H_1: V_0 .. V_3
+    H[base] = new_h(H[base], -v1, S(0), v1, v2);                                // H_0: V_-1 = -V_1 .. V_2
+}
+
+// x lines (the contiguous axis) run through the same kernel on a transposed
+// copy of their pair: with x the slow axis inside each z plane, a line's
+// slots lie a row pitch apart and neighbouring lanes (consecutive y) read
+// consecutive words, as on the y and z lines.  The copy is made before the
+// pass and moved back after it (transpose_planes_kernel); the medium's copy
+// is made once per plan.  One-thread-per-line sweeps straight over x rows
+// would read each 128-byte line piecemeal, many lanes apart in time.
+//
+// dst[p][c][r] = src[p][r][c] for r < R, c < C and every plane p: rows of
+// src are columns of dst.  Square tiles through LDS, 256 threads: every wave
+// load reads consecutive elements of a src row, every wave store writes
+// consecutive elements of a dst row.  Tiles of 64 for 1- and 4-byte elements,
+// 32 for 8-byte ones (a 64-tile of doubles takes 33 KB of LDS per block,
+// which measured slower).
+template <typename V>
+__host__ __device__ constexpr int tr_tile() { return sizeof(V) == 8 ? 32 : 64; }
+
+template <typename V>
+__global__ void __launch_bounds__(256) transpose_planes_kernel(const V* __restrict__ src, long long sp,
+                                                               long long srow, V* __restrict__ dst, long long dp,
+                                                               long long drow, int R, int C) {
+    constexpr int TT = tr_tile<V>(), RS = 256 / TT;   // RS rows per pass of the block
+    __shared__ V tile[TT][TT + 1];
+    const int c0 = int(blockIdx.x) * TT, r0 = int(blockIdx.y) * TT;
+    const long long pl = blockIdx.z;
+    const int tx = int(threadIdx.x) % TT, ty = int(threadIdx.x) / TT;
+    const V* s = src + pl * sp;
+    V* d = dst + pl * dp;
+#pragma unroll
+    for (int m = 0; m < TT; m += RS) {
+        const int r = r0 + ty + m, c = c0 + tx;
+        if (r < R && c < C) tile[ty + m][tx] = s[(long long)r * srow + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < TT; m += RS) {
+        const int c = c0 + ty + m, r = r0 + tx;
+        if (r < R && c < C) d[(long long)c * drow + r] = tile[tx][ty + m];
+    }
+}
+
+// Grid of transpose_planes_kernel<V> over planes of R x C.
+template <typename V>
+static dim3 transpose_grid(int R, int C, int planes) {
+    constexpr int TT = tr_tile<V>();
+    return dim3((unsigned)((C + TT - 1) / TT), (unsigned)((R + TT - 1) / TT), (unsigned)planes);
 }
 
 }  // namespace fdtd

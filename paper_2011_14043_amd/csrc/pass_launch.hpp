@@ -242,7 +242,9 @@ static fdtd_status launch_pass4(fdtd_plan_s* p, int op, int k, double theta, T* 
     PassShape sh;
     build_pass<T, S>(p, op, k, theta, FUND, set, set, inj, a4.p, sh, fin);
     a4.nlines = (long long)a4.p.na * a4.p.nb;
-    a4.scr = reinterpret_cast<S*>(p->scr4) + (size_t)k * 4 * p->dims.comp;
+    // the kernel's work area must fit the pass's region
+    if ((size_t)work4_words(a4.p.n_w, a4.nlines, seg4<S>()) > p->scr4_region) return FDTD_EINVAL;
+    a4.scr = reinterpret_cast<S*>(p->scr4) + (size_t)k * p->scr4_region;
     double w[4];
     stencil4_weights(p->stencil_wo, w);
     band4_rows(a4.p.n_w, w, a4.blo, a4.bhi);
@@ -254,15 +256,38 @@ static fdtd_status launch_pass4(fdtd_plan_s* p, int op, int k, double theta, T* 
         for (int u = 0; u + t < 4; ++u) sum += w[u] * w[u + t];
         a4.bin[t] = sum;
     }
+    const Dims& d = p->dims;
+    T* const Es = a4.p.Eout;   // the pair in the state (in place: Ein == Eout)
+    T* const Hs = a4.p.Hout;
+    const dim3 tb(256);
+    const dim3 to_t = transpose_grid<T>(d.ny + 1, d.nx + 1, d.nz + 1);     // rows y, columns x
+    const dim3 from_t = transpose_grid<T>(d.nx + 1, d.ny + 1, d.nz + 1);   // rows x, columns y
     if (sh.w == 0) {
-        // x lines: 64 lines per one-wave block, rows staged through LDS (sw = 1)
-        const dim3 grid((unsigned)((a4.nlines + 63) / 64)), block(64);
-        if (fin) hipLaunchKernelGGL((pass4_x_kernel<T, S, true>), grid, block, 0, p->stream, a4);
-        else hipLaunchKernelGGL((pass4_x_kernel<T, S, false>), grid, block, 0, p->stream, a4);
-    } else {
-        const dim3 grid((unsigned)((a4.nlines + 127) / 128)), block(128);
-        if (fin) hipLaunchKernelGGL((pass4_kernel<T, S, true>), grid, block, 0, p->stream, a4);
-        else hipLaunchKernelGGL((pass4_kernel<T, S, false>), grid, block, 0, p->stream, a4);
+        // x lines: on the transposed copy (x the slow axis of each plane), so
+        // that lanes (consecutive y) read consecutive words
+        if (!p->tr4) return FDTD_EINVAL;
+        T* const Et = static_cast<T*>(p->tr4);
+        T* const Ht = Et + (size_t)p->tr4_plane * (d.nz + 1);
+        hipLaunchKernelGGL((transpose_planes_kernel<T>), to_t, tb, 0, p->stream, Es, d.plane,
+                           (long long)d.px, Et, p->tr4_plane, p->tr4_pitch, d.ny + 1, d.nx + 1);
+        hipLaunchKernelGGL((transpose_planes_kernel<T>), to_t, tb, 0, p->stream, Hs, d.plane,
+                           (long long)d.px, Ht, p->tr4_plane, p->tr4_pitch, d.ny + 1, d.nx + 1);
+        a4.p.Ein = a4.p.Eout = Et;
+        a4.p.Hin = a4.p.Hout = Ht;
+        a4.p.sa = 1;
+        a4.p.sb = p->tr4_plane;
+        a4.p.sw = p->tr4_pitch;
+        if (p->mat) a4.p.mat = static_cast<const unsigned char*>(p->tr4_med);
+        else a4.p.eps = static_cast<const float*>(p->tr4_med);
+    }
+    const dim3 grid((unsigned)((a4.nlines + 127) / 128)), block(128);
+    if (fin) hipLaunchKernelGGL((pass4_kernel<T, S, true>), grid, block, 0, p->stream, a4);
+    else hipLaunchKernelGGL((pass4_kernel<T, S, false>), grid, block, 0, p->stream, a4);
+    if (sh.w == 0) {
+        hipLaunchKernelGGL((transpose_planes_kernel<T>), from_t, tb, 0, p->stream, a4.p.Eout, p->tr4_plane,
+                           p->tr4_pitch, Es, d.plane, (long long)d.px, d.nx + 1, d.ny + 1);
+        hipLaunchKernelGGL((transpose_planes_kernel<T>), from_t, tb, 0, p->stream, a4.p.Hout, p->tr4_plane,
+                           p->tr4_pitch, Hs, d.plane, (long long)d.px, d.nx + 1, d.ny + 1);
     }
     return FDTD_OK;
 }

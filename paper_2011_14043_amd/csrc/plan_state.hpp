@@ -112,7 +112,12 @@ struct fdtd_plan_s {
     float* mu = nullptr;      // mu_r in node layout (plans with a permeability map; else NULL)
     int order = 2;            // accuracy order of the staggered differences (fdtd_set_order: 2 or 4)
     double stencil_wo = -1.0 / 24.0;   // order 4: outer weight of the 4-point difference (fdtd_set_stencil)
-    void* scr4 = nullptr;     // order 4: line-solve work area, 3 pairs x 4 arrays x comp (solve type)
+    void* scr4 = nullptr;     // order 4: line-solve work area, 3 pairs x scr4_region words (solve type)
+    size_t scr4_region = 0;   // words per pair: y and the factorization state at segment starts
+    void* tr4 = nullptr;      // order 4, x lines: the pair (E, H) transposed, x the slow axis of a plane
+    void* tr4_med = nullptr;  // the medium in that layout (material index, else eps_r), made once
+    long long tr4_pitch = 0;  // row pitch (elements) of that layout: ny + 1 padded to 128 bytes
+    long long tr4_plane = 0;  // plane size: (nx + 1) rows
     unsigned char* mat = nullptr;   // material index per node (if <= 256 distinct eps_r)
     // Crank-Nicolson plans: 15 work components (x, r, p, q on E; w on H),
     // 3 x 1024 partial sums, scalars; CG controls and the last run's statistics

@@ -15,7 +15,9 @@
  *                            the error paths of each
  *
  * Prints one JSON line {"checks": n, "failures": m}; exit status 0 when every
- * check holds, 1 otherwise, 2 on a setup error (HIP allocation or copy).
+ * check holds, 1 otherwise, 2 on a setup error (HIP allocation or copy).  The
+ * leak check runs before the end of main, which then ends the process
+ * directly.
  */
 #define _POSIX_C_SOURCE 200809L
 #include <hip/hip_runtime_api.h>
@@ -24,6 +26,8 @@
 #include <stdlib.h>
 #include <string.h>
 #include <unistd.h>
+
+#include <sanitizer/lsan_interface.h>
 
 #include "fdtd.h"
 
@@ -666,5 +670,12 @@ int main(int argc, char** argv) {
         SETUP(hipDeviceSynchronize());
     }
     printf("{\"checks\": %d, \"failures\": %d}\n", nchk, nfail);
-    return nfail ? 1 : 0;
+    fflush(stdout);
+    fflush(stderr);
+    /* The leak check runs here, and the process ends without the HIP runtime's
+     * teardown at exit: that teardown frees runtime memory after the
+     * sanitizer's own hooks into the HSA runtime are gone, which the sanitizer
+     * reports as an internal error of its own. */
+    __lsan_do_leak_check();
+    _exit(nfail ? 1 : 0);
 }
