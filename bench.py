@@ -34,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # sources whose hash is recorded, the profiled y/z configuration and the same
 # refinement; otherwise the bench reports traffic = null.
 PROFILED = {
-    "kernel_hash": "ee111ee86856a53a",
+    "kernel_hash": "2fefdd7333065000",
     "config": [16, 16, 512, 1],                              # chunk, tile_x, block_threads, remap (y and z)
     "refined": True,
-    "fetch_kib": 595561.6,                                   # median over the y and z dispatches
-    "write_kib": 1067717.0,
+    "fetch_kib": 595772.6,                                   # median over the y and z dispatches
+    "write_kib": 1068013.2,
     "fetch_factor": 1048576.0 / 524299.5,                    # 1 GiB copy: FETCH_SIZE 524299.5 KiB
     "write_factor": 1.0,                                     # 1 GiB copy: WRITE_SIZE 1048576 KiB
     "profile": "profiles/pass_kernels_adi_fundamental_f32_512cube.md",

@@ -305,8 +305,10 @@ __device__ __forceinline__ void add_source_c(const PassArgs<T, S>& a, int si, co
 // ---------------------------------------------------------------------------
 // Body of one block of x-line work: block `blk` of the pass described by `a`
 // (lines blk * waves * 64/P ...); ctab = the per-material coefficients in LDS (MAT).
+// FIN: fin_lds = 64 * M elements of T per wave of the block (LDS).
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN = false, bool MU = false>
-__device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const CoefTab<S>* ctab) {
+__device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, const CoefTab<S>* ctab,
+                                            T* fin_lds = nullptr) {
     static_assert(!(MU && (MAT || MODE == FUND_REF)), "MU variants read eps_r maps and solve without refinement");
     constexpr int CE = ModeCE<MODE>::v, CH = ModeCH<MODE>::v;
     constexpr int ES = (int)sizeof(T);
@@ -551,35 +553,47 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
     T te[M], th[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) { te[i] = T(eo[i]); th[i] = T(ho[i]); }
-    if (!live) return;
     if constexpr (FIN) {
         // the run's output: U_old of this thread's own slots is loaded again
-        // (the output may overwrite them)
-        if (a.fin_add) {
+        // (the output may overwrite them), with the chunk's aligned loads
+        if (live && a.fin_add && (FULL || j0 < n)) {
+            T oe[M], oh[M];
+            ld_chunk<T, M>(rE, vo, oe);
+            ld_chunk<T, M>(rH, vo, oh);
 #pragma unroll
-            for (int i = 0; i < M; ++i) {
-                if (FULL || j0 + i < n) {
-                    fin_value<T, S>(a, te[i], th[i], Buf<T>::ld(rE, vo, i * ES), Buf<T>::ld(rH, vo, i * ES),
-                                    src_here && i == si);
-                }
-            }
+            for (int i = 0; i < M; ++i)
+                if (FULL || j0 + i < n) fin_value<T, S>(a, te[i], th[i], oe[i], oh[i], src_here && i == si);
         }
         if (first) te[0] = T(0);   // the wall
-        // output pitches (rows of the caller's arrays need not be 16-byte
-        // aligned: element stores)
-        const long long wbo = (long long)(a.a_lo + int(line0 % a.na)) * a.sa_o +
-                              (long long)(a.b_lo + int(line0 / a.na)) * a.sb_o;
-        const int voo = (int((long long)ia * a.sa_o + (long long)ib * a.sb_o - wbo) + j0) * ES;
-        const Rsrc oE = make_rsrc(a.Eout, wbo, a.comp_o, ES), oH = make_rsrc(a.Hout, wbo, a.comp_o, ES);
+        // Output pitches: the caller's rows need not be aligned, so the wave's
+        // outputs go through LDS (lane l holds slots l*M .. l*M+M-1 of the
+        // wave's 64/P lines, line by line) and each store instruction writes
+        // 64 consecutive samples of a row rather than one sample per lane,
+        // M samples apart.  Every thread of the block reaches the barriers
+        // (lanes past the last line store nothing).
+        T* tile = fin_lds + wave * 64 * M;
+        const int PM = P * M;
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            if (FULL || j0 + i < n) {
-                Buf<T>::st(te[i], oE, voo, i * ES);
-                Buf<T>::st(th[i], oH, voo, i * ES);
+        for (int arr = 0; arr < 2; ++arr) {
+            T* out = arr == 0 ? a.Eout : a.Hout;
+#pragma unroll
+            for (int i = 0; i < M; ++i) tile[lane * M + i] = arr == 0 ? te[i] : th[i];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int f = lane + 64 * m;
+                const int lw = f / PM, slot = f - lw * PM;
+                const long long ln = raw0 + lw;
+                if (ln < nlines && slot < n) {
+                    const int ja = a.a_lo + int(ln % a.na), jb = a.b_lo + int(ln / a.na);
+                    out[(long long)ja * a.sa_o + (long long)jb * a.sb_o + slot] = tile[f];
+                }
             }
+            __syncthreads();
         }
         return;
     }
+    if (!live) return;
     const Rsrc wE = make_rsrc(a.Eout, wbase, a.comp, ES), wH = make_rsrc(a.Hout, wbase, a.comp, ES);
     if (FULL || j0 + M <= n) {
         st_chunk<T, M>(wE, vo, te);
@@ -603,9 +617,10 @@ __device__ __forceinline__ void pass_x_body(const PassArgs<T, S>& a, int blk, co
 template <typename T, typename S, int M, int MODE, bool FULL, bool MAT, bool FIN, bool MU = false>
 __global__ void __launch_bounds__(256) pass_x_kernel(PassArgs<T, S> a) {
     __shared__ CoefTab<S> ctab[MAT ? 256 : 1];
+    __shared__ T fin_lds[FIN ? 256 * M : 1];   // FIN: the outputs of each wave (at most 4 waves)
     if constexpr (MAT) load_coef_table<T, S, MODE>(ctab, a);
     pass_x_body<T, S, M, MODE, FULL, MAT, FIN, MU>(a, a.remap ? xcd_remap(blockIdx.x, a.nblk) : int(blockIdx.x),
-                                                   ctab);
+                                                   ctab, fin_lds);
 }
 
 // ---------------------------------------------------------------------------
