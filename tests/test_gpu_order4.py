@@ -197,6 +197,47 @@ def test_order4_adjoint_gradient(prec):
     assert jerr < tol and gerr < tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("how", ["per_cell_eps", "no_index_env"])
+def test_order4_without_material_index(prec, how, monkeypatch):
+    """Plans without a material index (more than 256 distinct eps_r values, or
+    FDTD_NO_MATERIAL_INDEX set) take the medium from eps_r, on the y/z lines and
+    in the transposed copy the x lines use; ragged 17 x 13 x 11 grid, source,
+    CFL 8, against the oracle.  With the index switched off the run equals the
+    indexed one bit for bit (same values of Ks eps_r)."""
+    nx, ny, nz = 17, 13, 11
+    hx, hy, hz = 1e-3, 0.8e-3, 1.1e-3
+    dt = W.yee_dt(hx, hy, hz, 8.0)
+    if how == "per_cell_eps":
+        eps = np.random.default_rng(101).uniform(1.0, 6.0, (nz, ny, nx)).astype(np.float32)
+    else:
+        eps = W.random_box_eps(nx, ny, nz, seed=102, nboxes=5)
+    u0 = W.random_fields(nx, ny, nz, seed=103)
+    src = OSource(8, 6, 5, amp=1e12, t0=3 * dt, tau=3 * dt, f0=1 / (12 * dt))
+    g = oracle.Grid(nx, ny, nz, hx, hy, hz, dt, eps, order=4)
+    ref, _ = oracle.run("adi", "fundamental", g, u0, 6, src)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=hx, hy=hy, hz=hz, dt=dt, eps=eps)
+    print(f"[case] order 4 without material index ({how}) {prec}", flush=True)
+    got = []
+    for off in ((True, False) if how == "no_index_env" else (False,)):
+        if off:
+            monkeypatch.setenv("FDTD_NO_MATERIAL_INDEX", "1")
+        else:
+            monkeypatch.delenv("FDTD_NO_MATERIAL_INDEX", raising=False)
+        p = _plan(c, "adi", prec)
+        E, H = _fields(u0, PREC[prec][0])
+        p.run(E, H, 6, source=_gsrc(src))
+        torch.cuda.synchronize()
+        p.close()
+        got.append([t.double().cpu().numpy() for t in E + H])
+    err = oracle.yee.weighted_rel_l2(got[0], ref, g)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < TOL[prec], err
+    if len(got) == 2:
+        for a, b in zip(got[0], got[1]):
+            assert np.array_equal(a, b)
+
+
 def test_order4_back_to_second_order(case):
     """set_order(4) then set_order(2) runs exactly the plan that never changed
     (FP32: refined again)."""
