@@ -272,3 +272,40 @@ def test_order4_arguments(case):
         with pytest.raises(FdtdError, match="EUNSUPPORTED"):
             q.set_order(4)
         q.close()
+
+
+@pytest.mark.parametrize("prec,outer", [("f64", None), ("f32", None), ("f32", "optimized")],
+                         ids=["f64", "f32", "f32-optimized"])
+def test_order4_cavity_mode_512cube(prec, outer):
+    """Full size, the benchmark's grid: a (3, 2, 5) mode of a 512^3 vacuum box
+    after 10 ADI steps at CFL 5 against the closed-form 6x6 evolution with the
+    4-point K (fourth order, or the optimized weight for theta_max = pi/2): the
+    transposed x lines, the segment state and the work area at their largest."""
+    import math
+    from paper_2011_14043_amd import optimized_stencil
+    from .test_gpu_parity import _mode_on_gpu
+    n, h, steps = 512, 1e-3, 10
+    dt = W.yee_dt(h, h, h, 5.0)
+    mnp = (3, 2, 5)
+    b = optimized_stencil(math.pi / 2) if outer else -1.0 / 24.0
+    a = np.random.default_rng(12).standard_normal(6) * np.r_[1, 1, 1, 1 / 377, 1 / 377, 1 / 377]
+    A6, B6 = an.mode_matrices(n, n, n, h, h, h, *mnp, order=4, outer=b)
+    amp = np.linalg.matrix_power(an.scheme_matrix("adi", A6, B6, dt), steps) @ a
+    dtype = PREC[prec][0]
+    print(f"[case] order 4 cavity mode 512^3 {prec} outer={b:.6f}", flush=True)
+    fields = _mode_on_gpu(n, n, n, h, mnp, a, dtype)
+    c = dict(nx=n, ny=n, nz=n, hx=h, hy=h, hz=h, dt=dt, eps=None)
+    p = _plan(c, "adi", prec)
+    if outer:
+        p.set_stencil(b)
+    p.run(fields[:3], fields[3:], steps)
+    torch.cuda.synchronize()
+    p.close()
+    ref = _mode_on_gpu(n, n, n, h, mnp, amp, torch.float64)
+    w = [8.8541878128e-12] * 3 + [1.25663706212e-6] * 3
+    num = sum(wi * float(torch.sum((f.double() - r) ** 2)) for wi, f, r in zip(w, fields, ref))
+    den = sum(wi * float(torch.sum(r ** 2)) for wi, r in zip(w, ref))
+    del fields, ref
+    err = math.sqrt(num / den)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < TOL[prec], err
