@@ -164,3 +164,31 @@ def test_set_stencil_arguments(case):
         assert e.value.status == -1
     p.set_stencil(-0.05)
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_optimized_stencil_adjoint_gradient(prec):
+    """The adjoint sweep with the optimized weight (its transposed sub-steps
+    are the same passes with theta -> -theta) against the oracle's reverse
+    mode on the same operator."""
+    from oracle import adjoint
+    nx, ny, nz, h = 5, 4, 6, 1e-3
+    dt = W.yee_dt(h, h, h, 3.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=97, nboxes=3)
+    u0 = W.random_fields(nx, ny, nz, seed=98)
+    src = OSource(2, 2, 2, amp=1e11, t0=3 * dt, tau=2 * dt, f0=1 / (10 * dt))
+    probe, steps = (3, 2, 3), 10
+    b = _b_opt()
+    g = oracle.Grid(nx, ny, nz, h, h, h, dt, eps, order=4, outer=b)
+    J_ref, grad_ref = adjoint.gradient(g, u0, steps, src, probe)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=h, hy=h, hz=h, dt=dt, eps=eps)
+    p = _plan(c, "adi", prec, b)
+    E, H = _fields(u0, PREC[prec][0])
+    J, grad = p.grad_eps(E, H, steps, probe, _gsrc(src), (0, nx, 0, ny, 0, nz), 4)
+    p.close()
+    grad = grad.cpu().numpy()
+    gerr = np.max(np.abs(grad - grad_ref)) / np.max(np.abs(grad_ref))
+    jerr = abs(J - J_ref) / abs(J_ref)
+    print(f"[case] optimized stencil adjoint {prec}: J {jerr:.3e}  grad {gerr:.3e}", flush=True)
+    tol = 1e-9 if prec == "f64" else 2e-4
+    assert jerr < tol and gerr < tol
