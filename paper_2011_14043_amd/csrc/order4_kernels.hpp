@@ -22,8 +22,9 @@
 // that forms V and writes the new E and H.  The forward sweep stores, per
 // row, only the forward-substituted right side divided by its pivot (y), and
 // at the start of every segment of K rows the recurrence state of the
-// factorization (the last three pivots and the two multipliers the next row
-// needs); the backward sweep takes each segment's state, factors its K rows
+// factorization (the last three pivots and the three multipliers of the
+// previous two rows that the next row needs: six words); the backward sweep
+// takes each segment's state, factors its K rows
 // again into registers (the factors depend on the medium only) and then runs
 // the back substitution over them.  So the work area takes 1 + 6/K words per
 // slot instead of the four (three multipliers and y) a stored factorization
