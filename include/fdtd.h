@@ -376,6 +376,10 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
  * Asynchronous on the plan's stream. */
 fdtd_status fdtd_run_batch(fdtd_plan_t p, void* const* E, void* const* H, int nsteps);
 
+/* Destroy a plan: synchronizes its stream and releases everything it holds.
+ * Every call checks its handle against the library's live plans before using
+ * it, so a destroyed handle is rejected with FDTD_EINVAL rather than read
+ * (until a later plan happens to receive the same address). */
 fdtd_status fdtd_destroy(fdtd_plan_t p);
 const char* fdtd_strerror(fdtd_status s);
 

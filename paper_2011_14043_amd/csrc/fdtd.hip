@@ -26,6 +26,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/fdtd.h"
@@ -44,7 +45,31 @@
 
 using namespace fdtd;
 
-static bool plan_ok(fdtd_plan_t p) { return p != nullptr && p->magic == 0xFD7DFD7Du; }
+// Live plans.  A handle is looked up here before it is dereferenced, so a
+// destroyed (or never created) handle is rejected with FDTD_EINVAL instead of
+// being read.  The set and its lock are never destroyed, so calls made while
+// the process ends (finalizers of a binding) still find them.
+static std::mutex& plans_mu() {
+    static std::mutex* m = new std::mutex();
+    return *m;
+}
+static std::unordered_set<const fdtd_plan_s*>& plans() {
+    static auto* s = new std::unordered_set<const fdtd_plan_s*>();
+    return *s;
+}
+static void plan_register(const fdtd_plan_s* p) {
+    std::lock_guard<std::mutex> lock(plans_mu());
+    plans().insert(p);
+}
+static void plan_unregister(const fdtd_plan_s* p) {
+    std::lock_guard<std::mutex> lock(plans_mu());
+    plans().erase(p);
+}
+static bool plan_ok(fdtd_plan_t p) {
+    if (p == nullptr) return false;
+    std::lock_guard<std::mutex> lock(plans_mu());
+    return plans().count(p) != 0 && p->magic == 0xFD7DFD7Du;
+}
 
 // ---------------------------------------------------------------------------
 // fdtd_diff_norm and its variant without allocation
@@ -286,6 +311,7 @@ fdtd_status fdtd_plan(const fdtd_desc* d, void* hip_stream, fdtd_plan_t* out) {
         if ((e = hipMalloc(&p->cg_scal, sizeof(double) * kCnScalars)) != hipSuccess) return fail(from_hip(e));
         if ((e = hipMemset(p->cg_scal, 0, sizeof(double) * kCnScalars)) != hipSuccess) return fail(from_hip(e));
     }
+    plan_register(p);
     *out = p;
     return FDTD_OK;
 }
@@ -696,6 +722,7 @@ fdtd_status fdtd_plan_batch(const fdtd_desc* d, int n, void* hip_stream, fdtd_pl
         return st;
     }
     for (int ax = 0; ax < 3; ++ax) p->cfg[ax] = b->groups[0]->cfg[ax];
+    plan_register(p);
     *out = p;
     return FDTD_OK;
 }
@@ -780,6 +807,7 @@ fdtd_status fdtd_last_cg(fdtd_plan_t p, long long* iterations, double* rel_resid
 
 fdtd_status fdtd_destroy(fdtd_plan_t p) {
     if (!plan_ok(p)) return FDTD_EINVAL;
+    plan_unregister(p);
     (void)hipStreamSynchronize(p->stream);
     if (p->batch) {
         for (fdtd_plan_s* c : p->batch->groups) (void)fdtd_destroy(c);
@@ -840,6 +868,7 @@ static fdtd_status batch_from_subs(const fdtd_desc& d0, const std::vector<fdtd_p
         for (fdtd_plan_s* sub : subs) (void)fdtd_destroy(sub);
         return FDTD_ENOMEM;
     }
+    plan_register(p);   // from here on fdtd_destroy releases it
     p->d = subs[0]->d;   // storage/solve kind as normalized by fdtd_plan
     p->req_dtype = d0.dtype;
     p->refine = subs[0]->refine;   // equal for all grids (fdtd_plan_batch)

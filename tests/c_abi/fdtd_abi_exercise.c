@@ -291,6 +291,34 @@ static void scheme_sweep(void) {
     free(eps);
 }
 
+/* A destroyed handle is rejected, not read (the sanitizer would report a
+ * read of the freed plan). */
+static void destroyed_handle(void) {
+    fdtd_desc d = desc(9, 8, 7, 3.0, FDTD_ADI, FDTD_FUNDAMENTAL, FDTD_F32);
+    fdtd_plan_t p = NULL;
+    EXPECT(fdtd_plan(&d, NULL, &p), FDTD_OK);
+    if (!p) return;
+    fset u;
+    fset_alloc(&u, d.nx, d.ny, d.nz, 4);
+    EXPECT(fdtd_run(p, u.E, u.H, 1, NULL, NULL, 1), FDTD_OK);
+    EXPECT(fdtd_destroy(p), FDTD_OK);
+    EXPECT(fdtd_run(p, u.E, u.H, 1, NULL, NULL, 1), FDTD_EINVAL);
+    EXPECT(fdtd_set_step(p, 0), FDTD_EINVAL);
+    EXPECT(fdtd_set_order(p, 4), FDTD_EINVAL);
+    EXPECT(fdtd_destroy(p), FDTD_EINVAL);
+    fdtd_plan_t q = NULL;
+    fdtd_desc e[2] = {desc(9, 8, 7, 3.0, FDTD_ADI, FDTD_FUNDAMENTAL, FDTD_F32),
+                      desc(7, 9, 8, 3.0, FDTD_ADI, FDTD_FUNDAMENTAL, FDTD_F32)};
+    EXPECT(fdtd_plan_batch(e, 2, NULL, &q), FDTD_OK);
+    if (q) {
+        EXPECT(fdtd_destroy(q), FDTD_OK);
+        EXPECT(fdtd_run_batch(q, u.E, u.H, 1), FDTD_EINVAL);
+        EXPECT(fdtd_destroy(q), FDTD_EINVAL);
+    }
+    SETUP(hipDeviceSynchronize());
+    fset_free(&u);
+}
+
 /* Argument errors on a valid plan; the plan stays usable. */
 static void run_errors(void) {
     fdtd_desc d = desc(10, 9, 8, 3.0, FDTD_ADI, FDTD_FUNDAMENTAL, FDTD_F32);
@@ -660,6 +688,7 @@ int main(int argc, char** argv) {
         }
         scheme_sweep();
         run_errors();
+        destroyed_handle();
         forms_and_distances();
         crank_nicolson();
         permeability();

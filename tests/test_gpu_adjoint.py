@@ -266,4 +266,4 @@ def test_autograd_function_matches_directional_fd():
     assert abs(r - 1) <= 1e-6
     with torch.no_grad():
         J2 = probe_energy(x0, pb)
-    assert float(J2) == float(J)
+    assert float(J2) == float(J.detach())
