@@ -221,9 +221,11 @@ fdtd_status fdtd_run(fdtd_plan_t p, void* const E[3], void* const H[3], int nste
 fdtd_status fdtd_step(fdtd_plan_t p, void* const E[3], void* const H[3], const fdtd_source* src);
 
 /* Captured graphs of a single-grid plan (else FDTD_EINVAL): fdtd_run replays
- * a HIP graph of `steps` main-iteration steps (1 <= steps <= 64; default 8)
- * for the steps before its last one, and launches the rest directly; 0
- * launches every step directly.  Runs with an energy trace or per-launch
+ * a HIP graph of `steps` main-iteration steps (1 <= steps <= 64) for the
+ * steps before its last one, and launches the rest directly; 0 (the default)
+ * launches every step directly.  The graph is a chain of the passes on one
+ * stream, for callers that want the launches recorded; it runs at the speed
+ * of direct launches.  Runs with an energy trace or per-launch
  * timing never use graphs.  The graph is captured on the first run that
  * uses it and again when the source cell or a kernel configuration changes;
  * the source terms of a run are computed on the host (as for direct

@@ -128,27 +128,76 @@ __device__ __forceinline__ double apply_B4(F get, int c, int i, int j, int k, do
 
 // Input processing with the fourth-order differences: U = 1/2 u + link (B u)
 // (the ADI link of Sec. II-E) in FP64, one thread per node (once per run).
-// Non-dynamic E -> 0, static normal H -> 1/2 u.
+// Non-dynamic E -> 0, static normal H -> 1/2 u.  The same values as
+// apply_B4 over `phys` (same sums in the same order), with the index
+// arithmetic and the set tests written out per component: a dynamic E's
+// partner H samples (even images) are always inside the H extent, and a
+// dynamic H's partner E is read only where it is dynamic (odd images, 0 on
+// the walls).
 template <typename T>
 __global__ void load_state4_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps, const float* mu, Dims d,
                                    AuxCoef k_) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long co = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // caller offset of the node
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
-    if (idx >= nn) return;
-    const Node nd = node_of(unsigned(idx), d);
+    if (co >= nn) return;
+    const Node nd = node_of(unsigned(co), d);
     const int i = nd.i, j = nd.j, k = nd.k;
     const long long so = (long long)k * d.plane + (long long)j * d.px + i;
-    auto get = [&](int c, int ii, int jj, int kk) -> T { return phys(f, c, ii, jj, kk, d); };
+    const long long sx = 1, sy = d.nx + 1, sz = d.cplane;   // caller strides
     const double inv_eps = 1.0 / (k_.eps0 * double(eps[so]));
     const double inv_mu = 1.0 / (k_.mu0 * (mu ? double(mu[so]) : 1.0));
+    const double wi = 1.0 - 3.0 * k_.wo;
+    const double w[4] = {-k_.wo, -wi, wi, k_.wo};
+    const bool ilo = i < d.nx, iin = i >= 1 && i < d.nx;
+    const bool jlo = j < d.ny, jin = j >= 1 && j < d.ny;
+    const bool klo = k < d.nz, kin = k >= 1 && k < d.nz;
+    const bool dyn[6] = {ilo && jin && kin, iin && jlo && kin, iin && jin && klo,
+                         iin && jlo && klo, ilo && jin && klo, ilo && jlo && kin};
+    const bool ext[3] = {jlo && klo, ilo && klo, ilo && jlo};   // H extents
+    // sum over the partner H along an axis: positions pos-2 .. pos+1, even images
+    auto sum_h = [&](const T* h, int pos, int n, long long st) -> double {
+        double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const double u = double(get(c, i, j, k));
-        const bool dyn = is_dynamic(c, i, j, k, d);
-        double v;
-        if (c < 3) v = dyn ? 0.5 * u + k_.link * apply_B4(get, c, i, j, k, inv_eps, inv_mu, k_, d) : 0.0;
-        else v = dyn ? 0.5 * u + k_.link * apply_B4(get, c, i, j, k, inv_eps, inv_mu, k_, d) : 0.5 * u;
-        s.c[c][so] = T(v);
+        for (int t = 0; t < 4; ++t) {
+            int q = pos - 2 + t;
+            q = q < 0 ? -1 - q : (q > n - 1 ? 2 * n - 1 - q : q);
+            acc += w[t] * double(h[co + (long long)(q - pos) * st]);
+        }
+        return acc;
+    };
+    // sum over the partner E along an axis: positions pos-1 .. pos+2, odd
+    // images; E at 0 and n (the walls) is 0, as is E whose other indices
+    // leave its dynamic set (the caller passes e_ok = false then)
+    auto sum_e = [&](const T* e, int pos, int n, long long st) -> double {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int q = pos - 1 + t;
+            double sg = 1.0;
+            if (q < 0) { q = -q; sg = -1.0; }
+            else if (q > n) { q = 2 * n - q; sg = -1.0; }
+            const double v = (q >= 1 && q <= n - 1) ? double(e[co + (long long)(q - pos) * st]) : 0.0;
+            acc += sg * w[t] * v;
+        }
+        return acc;
+    };
+    const double L = k_.link;
+    // E: U = 1/2 E - L/eps d_w H  (dynamic samples; else 0)
+    s.c[0][so] = T(dyn[0] ? 0.5 * double(f.c[0][co]) + L * (-inv_eps * sum_h(f.c[4], k, d.nz, sz) * k_.rdz) : 0.0);
+    s.c[1][so] = T(dyn[1] ? 0.5 * double(f.c[1][co]) + L * (-inv_eps * sum_h(f.c[5], i, d.nx, sx) * k_.rdx) : 0.0);
+    s.c[2][so] = T(dyn[2] ? 0.5 * double(f.c[2][co]) + L * (-inv_eps * sum_h(f.c[3], j, d.ny, sy) * k_.rdy) : 0.0);
+    // H: U = 1/2 H - L/mu d_w E  (dynamic samples; static H in the extent: 1/2 H; else 0)
+    {
+        const double u = ext[0] ? double(f.c[3][co]) : 0.0;
+        s.c[3][so] = T(dyn[3] ? 0.5 * u + L * (-inv_mu * sum_e(f.c[2], j, d.ny, sy) * k_.rdy) : 0.5 * u);
+    }
+    {
+        const double u = ext[1] ? double(f.c[4][co]) : 0.0;
+        s.c[4][so] = T(dyn[4] ? 0.5 * u + L * (-inv_mu * sum_e(f.c[0], k, d.nz, sz) * k_.rdz) : 0.5 * u);
+    }
+    {
+        const double u = ext[2] ? double(f.c[5][co]) : 0.0;
+        s.c[5][so] = T(dyn[5] ? 0.5 * u + L * (-inv_mu * sum_e(f.c[1], i, d.nx, sx) * k_.rdx) : 0.5 * u);
     }
 }
 

@@ -282,29 +282,22 @@ static fdtd_status batch_graph(fdtd_plan_s* p) {
     Batch* b = p->batch;
     if (b->exec) return FDTD_OK;
     const SchemeDef& sd = kSchemes[p->d.scheme];
-    // A sub-step of several launches (no fused launch): they update disjoint
-    // arrays, so they are captured as parallel branches (fork on events, join
-    // before the next sub-step).  A fused sub-step is one node of a chain.
+    // The launches of every sub-step (one when the sub-step is fused, else
+    // one per group of passes) are captured as a chain on the capture stream,
+    // as the single-grid graphs are (no branches forked and joined on events).
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     fdtd_status st = FDTD_OK;
-    hipStream_t br[3] = {b->cap, b->fork[0], b->fork[1]};
     for (int v = 0; v < kGraphSteps * sd.nsub && st == FDTD_OK; ++v) {
         const int u = v % sd.nsub;
         const int op = sd.sub[u].op;
         const double frac = sd.sub[u].theta_frac;
         int masks[3];
         const int nl = substep_masks(p, op, masks);
-        if (hipEventRecord(b->ev[0], b->cap) != hipSuccess) { st = FDTD_EDEVICE; break; }
-        for (int l = 1; l < nl && st == FDTD_OK; ++l)
-            if (hipStreamWaitEvent(br[l], b->ev[0], 0) != hipSuccess) st = FDTD_EDEVICE;
         for (int l = 0; l < nl && st == FDTD_OK; ++l) {
             const BatchPass* bp = nullptr;
             st = batch_pass<T, S>(p, op, masks[l], frac, &bp);
-            if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, br[l]);
+            if (st == FDTD_OK) st = batch_launch<T, S>(p, *bp, b->cap);
         }
-        for (int l = 1; l < nl && st == FDTD_OK; ++l)
-            if (hipEventRecord(b->ev[l], br[l]) != hipSuccess || hipStreamWaitEvent(b->cap, b->ev[l], 0) != hipSuccess)
-                st = FDTD_EDEVICE;
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);

@@ -814,19 +814,11 @@ fdtd_status fdtd_destroy(fdtd_plan_t p) {
         batch_clear(p->batch);
         for (fdtd_plan_s* sub : p->batch->subs) (void)fdtd_destroy(sub);
         if (p->batch->cap) (void)hipStreamDestroy(p->batch->cap);
-        for (hipStream_t f : p->batch->fork)
-            if (f) (void)hipStreamDestroy(f);
-        for (hipEvent_t e : p->batch->ev)
-            if (e) (void)hipEventDestroy(e);
         delete p->batch;
         p->batch = nullptr;
     }
     graph_clear(p);
     if (p->gstream) (void)hipStreamDestroy(p->gstream);
-    for (hipStream_t f : p->gfork)
-        if (f) (void)hipStreamDestroy(f);
-    for (hipEvent_t e : p->gev)
-        if (e) (void)hipEventDestroy(e);
     if (p->src_copied) (void)hipEventDestroy(p->src_copied);
     if (p->src_dev) (void)hipFree(p->src_dev);
     if (p->src_win) (void)hipFree(p->src_win);
@@ -878,12 +870,8 @@ static fdtd_status batch_from_subs(const fdtd_desc& d0, const std::vector<fdtd_p
     p->batch->subs = subs;
     fdtd_status st = FDTD_OK;
     if (hipStreamCreateWithFlags(&p->batch->cap, hipStreamNonBlocking) != hipSuccess) st = FDTD_EDEVICE;
-    for (int f = 0; f < 2 && st == FDTD_OK; ++f)
-        if (hipStreamCreateWithFlags(&p->batch->fork[f], hipStreamNonBlocking) != hipSuccess) st = FDTD_EDEVICE;
-    for (int f = 0; f < 3 && st == FDTD_OK; ++f)
-        if (hipEventCreateWithFlags(&p->batch->ev[f], hipEventDisableTiming) != hipSuccess) st = FDTD_EDEVICE;
     if (st != FDTD_OK) {
-        (void)fdtd_destroy(p);   // destroys the grids, streams and events
+        (void)fdtd_destroy(p);   // destroys the grids and the stream
         return st;
     }
     bool mat = true;

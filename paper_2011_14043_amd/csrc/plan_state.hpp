@@ -87,8 +87,6 @@ struct Batch {
     bool mat = false;         // every grid has a material index
     std::vector<BatchPass> passes;
     hipStream_t cap = nullptr;        // private stream for graph capture
-    hipStream_t fork[2] = {nullptr, nullptr};   // capture branches: the launches of a sub-step
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // are independent and run side by side
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;    // time steps of the main iteration
     // A batch larger than kGroupBytes is split into groups of consecutive
@@ -149,15 +147,14 @@ struct fdtd_plan_s {
     int fam_n[2] = {0, 0};
     fdtd::Batch* batch = nullptr;   // batch plan: the grids and their tables
     // Single-grid runs: main-iteration steps captured as a HIP graph of
-    // graph_steps steps (0: no graphs), replayed on the plan's stream.  The
+    // graph_steps steps (0, the default: no graphs), replayed on the plan's
+    // stream.  The
     // source values of every sub-step of a run are computed on the host into
     // the pinned table src_host, copied once to src_dev, and each replay
     // first copies its window of src_dev into src_win, which the captured
     // passes read.
-    int graph_steps = 8;
+    int graph_steps = 0;
     hipStream_t gstream = nullptr;        // private capture stream
-    hipStream_t gfork[2] = {nullptr, nullptr};        // capture branches: the three pair passes
-    hipEvent_t gev[3] = {nullptr, nullptr, nullptr};  // of a sub-step are independent
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     long long gkey[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // what the captured graph depends on

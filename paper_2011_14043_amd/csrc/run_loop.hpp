@@ -112,10 +112,6 @@ static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mod
     const SchemeDef& sd = kSchemes[p->d.scheme];
     const int K = p->graph_steps;
     if (!p->gstream) HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
-    for (hipStream_t& f : p->gfork)
-        if (!f) HIPCHK(hipStreamCreateWithFlags(&f, hipStreamNonBlocking));
-    for (hipEvent_t& e : p->gev)
-        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (src && !p->src_win) HIPCHK(hipMalloc(&p->src_win, sizeof(double) * 6 * 3 * 64));
     if ((size_t)K * sd.nsub * 6 > 6 * 3 * 64) return FDTD_EINVAL;
     hipStream_t user = p->stream;
@@ -133,25 +129,15 @@ static fdtd_status graph_capture(fdtd_plan_s* p, const fdtd_source* src, int mod
                 inj.pre_dev = p->src_win + (size_t)(q * sd.nsub + u) * 6;
                 inj.post_dev = inj.pre_dev + 3;
             }
-            // The three pair passes of a sub-step write disjoint arrays and read
-            // nothing another of them writes (conventional ADI reads its cross
-            // terms from the other buffer set), so they are captured as
-            // parallel branches: fork on an event, join before the next sub-step.
+            // The three pair passes of a sub-step are captured as a chain on
+            // the capture stream.  (They write disjoint arrays and could run as
+            // parallel branches forked and joined on events; that form was
+            // faster on small grids but is not used: a process that replayed
+            // such graphs ended once in an abort whose cause was not found.)
             const int out = (mode == CONV_ADI) ? 1 - cur : cur;
-            hipStream_t br[3] = {p->gstream, p->gfork[0], p->gfork[1]};
-            if (hipEventRecord(p->gev[0], p->gstream) != hipSuccess) st = FDTD_EDEVICE;
-            for (int l = 1; l < 3 && st == FDTD_OK; ++l)
-                if (hipStreamWaitEvent(br[l], p->gev[0], 0) != hipSuccess) st = FDTD_EDEVICE;
-            for (int k = 0; k < 3 && st == FDTD_OK; ++k) {
-                p->stream = br[k];
+            for (int k = 0; k < 3 && st == FDTD_OK; ++k)
                 st = launch_pass<T, S>(p, ss.op, k, ss.theta_frac * p->d.dt, mode, set_ptr<T>(p, cur),
                                        set_ptr<T>(p, out), src ? &inj : nullptr, false);
-            }
-            p->stream = p->gstream;
-            for (int l = 1; l < 3 && st == FDTD_OK; ++l)
-                if (hipEventRecord(p->gev[l], br[l]) != hipSuccess ||
-                    hipStreamWaitEvent(p->gstream, p->gev[l], 0) != hipSuccess)
-                    st = FDTD_EDEVICE;
             cur = out;
         }
     }
