@@ -137,7 +137,9 @@ __device__ __forceinline__ double apply_B4(F get, int c, int i, int j, int k, do
 template <typename T>
 __global__ void load_state4_kernel(FieldPtrs<T> f, FieldPtrsW<T> s, const float* eps, const float* mu, Dims d,
                                    AuxCoef k_) {
-    const long long co = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // caller offset of the node
+    // caller offset of the node; consecutive blocks in one L2 (XCD-aware
+    // order), so the neighbouring rows the y differences read were fetched there
+    const long long co = (long long)xcd_remap(int(blockIdx.x), int(gridDim.x)) * blockDim.x + threadIdx.x;
     const long long nn = (long long)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     if (co >= nn) return;
     const Node nd = node_of(unsigned(co), d);
