@@ -96,15 +96,15 @@ def order4_moved_bytes_per_slot(prec, material_index=True):
     four y/z and two x passes: the forward sweep reads E, H and the medium and
     writes the substituted right side y, the backward sweep reads y and the
     medium again with E and H and writes E and H; the factorization state (6
-    solve words) is written and read back once per segment of K rows (K = 8
-    with FP32 solves, 4 with FP64).  An x pass runs on a transposed copy of its
-    pair: E and H are read and written once more on the way in and once more
-    on the way out.  With the one-byte material index: 50.7 B FP32, 111.3 B
-    FP64, 76.7 B FP32 fields with FP64 solves."""
+    solve words) is written and read back once per segment of K = 8 rows.  An
+    x pass runs on a transposed copy of its pair: E and H are read and written
+    once more on the way in and once more on the way out.  With the one-byte
+    material index: 50.7 B FP32, 99.3 B FP64, 64.7 B FP32 fields with FP64
+    solves."""
     t = 8 if prec == "f64" else 4
     sv = 8 if prec in ("f64", "f32s64") else 4
     med = 1 if material_index else 4
-    k = 8 if sv == 4 else 4
+    k = 8
     yz = 6 * t + 2 * sv + 12 * sv / k + 2 * med
     x = yz + 8 * t
     return (4 * yz + 2 * x) / 6

@@ -28,9 +28,10 @@
 // again into registers (the factors depend on the medium only) and then runs
 // the back substitution over them.  So the work area takes 1 + 6/K words per
 // slot instead of the four (three multipliers and y) a stored factorization
-// needs.  Both sweeps issue a segment's loads together before its rows run
-// (the recurrences are serial, so a lane would otherwise wait on memory once
-// per row).  K = 8 with FP32 solves, 4 with FP64 (registers).  Work-area
+// needs.  With FP32 solves both sweeps issue a segment's loads together
+// before its rows run (the recurrences are serial, so a lane would otherwise
+// wait on memory once per row); FP64 solves load per row (a segment's values
+// in registers would cost occupancy).  K = 8.  Work-area
 // arrays are indexed [slot][line] so that the lanes of a wave store and load
 // consecutive words.
 // With a material index the medium term Ks eps_r comes from a per-material
@@ -133,7 +134,7 @@ __device__ __forceinline__ void load_ks_table(S* ktab, const PassArgs<T, S>& a) 
 
 // Segment length of the kernel (factors of a segment held in registers).
 template <typename S>
-__host__ __device__ constexpr int seg4() { return sizeof(S) == 4 ? 8 : 4; }
+__host__ __device__ constexpr int seg4() { return 8; }
 
 // Work-area words of one pass over nlines lines of n cells: y (n per line)
 // and the factorization state (6 words) at the start of each segment of K
@@ -143,11 +144,24 @@ __host__ __device__ constexpr long long work4_words(int n, long long nlines, int
     return ((long long)n + 6LL * ((n - 1 + K - 1) / K)) * nlines;
 }
 
+// Pointer type of the pass kernel's arrays: restrict-qualified (R) or plain.
+template <typename V, bool R> struct Ptr4 { using type = V* __restrict__; };
+template <typename V> struct Ptr4<V, false> { using type = V*; };
+
 // One fundamental pass of the fourth-order operator over the lines of `a`
 // (FIN: the output form u = U_old + U_new, as the second-order FIN passes).
 template <typename T, typename S, bool FIN>
 __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     constexpr int K = seg4<S>();
+    // FP32 solves: a segment's loads are issued together before its rows run,
+    // so a lane waits for memory once per segment rather than once per row.
+    // FP64 solves load per row, from plain pointers that keep each load at
+    // its row: a segment's values in registers cost more in occupancy than
+    // the waits (a 512^3 y/z pass: 2.60 ms batched with K = 4, 2.22 ms per
+    // row with K = 8).  Both forms compute the same rows in the same order.
+    constexpr bool kBatch = sizeof(S) == 4;
+    using TP = typename Ptr4<T, kBatch>::type;
+    using SP = typename Ptr4<S, kBatch>::type;
     const PassArgs<T, S>& a = A.p;
     __shared__ S ktab[256];
     load_ks_table<T, S>(ktab, a);
@@ -157,11 +171,11 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     const long long base = (long long)ia * a.sa + (long long)ib * a.sb;
     const long long sw = a.sw;
     const int n = a.n_w;   // cells along the line: unknowns 1 .. n-1, H samples 0 .. n-1
-    T* __restrict__ E = a.Eout;
-    T* __restrict__ H = a.Hout;
+    TP E = a.Eout;
+    TP H = a.Hout;
     const long long NL = A.nlines;
-    S* __restrict__ sy = A.scr;
-    S* __restrict__ ck = sy + (long long)n * NL;
+    SP sy = A.scr;
+    SP ck = sy + (long long)n * NL;
     const bool src_line = ia == a.src_a && ib == a.src_b;
     const S pre = src_line ? (a.src_pre_dev ? S(*a.src_pre_dev) : a.src_pre) : S(0);
     const S post = src_line ? (a.src_post_dev ? S(*a.src_post_dev) : a.src_post) : S(0);
@@ -175,8 +189,6 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     };
     const int nseg = (n - 1 + K - 1) / K;   // segments of K rows from row 1
     // ---- forward: LDL^T and forward substitution ----------------------------
-    // Each segment's loads are issued together before its rows run, so a
-    // lane waits for memory once per segment rather than once per row.
     // window: H_{j-2}, H_{j-1}, H_j; forward-substituted z of the previous
     // three rows
     S h0 = Hat(-1), h1 = Hat(0), h2 = Hat(1);
@@ -185,13 +197,15 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     for (int s = 0; s < nseg; ++s) {
         const int j0 = 1 + s * K;
         S ev[K], hv[K], mv[K];
+        if constexpr (kBatch) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const int j = j0 + t;
-            if (j < n) {
-                ev[t] = S(E[base + j * sw]);
-                hv[t] = Hat(j + 1);
-                mv[t] = kes(j);
+            for (int t = 0; t < K; ++t) {
+                const int j = j0 + t;
+                if (j < n) {
+                    ev[t] = S(E[base + j * sw]);
+                    hv[t] = Hat(j + 1);
+                    mv[t] = kes(j);
+                }
             }
         }
         ldl4_save(ck + (long long)s * 6 * NL, NL, line, f);
@@ -199,6 +213,11 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
         for (int t = 0; t < K; ++t) {
             const int j = j0 + t;
             if (j >= n) continue;
+            if constexpr (!kBatch) {
+                ev[t] = S(E[base + j * sw]);
+                hv[t] = Hat(j + 1);
+                mv[t] = kes(j);
+            }
             const S hn = hv[t];
             const S dhs = S(A.wi) * (h2 - h1) + S(A.wo) * (hn - h0);
             S hterm = dhs * a.kap_hi;
@@ -234,24 +253,28 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
     };
     for (int s = nseg - 1; s >= 0; --s) {
         const int j0 = 1 + s * K;
-        // the segment's loads, then its factors again from its saved state
+        // (FP32) the segment's loads, then its factors again from its saved
+        // state
         Ldl4<S> g = ldl4_load(ck + (long long)s * 6 * NL, NL, line);
         S yv[K], mv[K], f1[K], f2[K], f3[K];
         T ev[K], hv[K];
+        if constexpr (kBatch) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const int j = j0 + t;
-            if (j < n) {
-                yv[t] = sy[(long long)j * NL + line];
-                ev[t] = E[base + j * sw];
-                if (j + 1 <= n - 1) hv[t] = H[base + (j + 1) * sw];
-                mv[t] = kes(j);
+            for (int t = 0; t < K; ++t) {
+                const int j = j0 + t;
+                if (j < n) {
+                    yv[t] = sy[(long long)j * NL + line];
+                    ev[t] = E[base + j * sw];
+                    if (j + 1 <= n - 1) hv[t] = H[base + (j + 1) * sw];
+                    mv[t] = kes(j);
+                }
             }
         }
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             const int j = j0 + t;
             if (j < n) {
+                if constexpr (!kBatch) mv[t] = kes(j);
                 S b[4];
                 band_row4<T, S>(A, j, n, b);
                 S Dj;
@@ -262,6 +285,11 @@ __global__ void __launch_bounds__(128) pass4_kernel(Pass4Args<T, S> A) {
         for (int t = K - 1; t >= 0; --t) {
             const int j = j0 + t;
             if (j >= n) continue;
+            if constexpr (!kBatch) {
+                yv[t] = sy[(long long)j * NL + line];
+                ev[t] = E[base + j * sw];
+                if (j + 1 <= n - 1) hv[t] = H[base + (j + 1) * sw];
+            }
             const S vj = yv[t] - ((m11 * v1 + m22 * v2) + m33 * v3);
             if (j == n - 1) vlast = vj;
             // H_{j+1} (j + 1 <= n - 1): V_j .. V_{j+3}; V_n = 0 (wall, the window's
