@@ -100,9 +100,9 @@ def order4_moved_bytes_per_slot(prec, material_index=True):
     x pass runs on a transposed copy of its pair: E and H are read and written
     once more on the way in and once more on the way out.  With the one-byte
     material index: 50.7 B FP32, 99.3 B FP64, 64.7 B FP32 fields with FP64
-    solves."""
+    solves (f32s64, and f32: order-4 FDTD_F32 plans solve in FP64)."""
     t = 8 if prec == "f64" else 4
-    sv = 8 if prec in ("f64", "f32s64") else 4
+    sv = 4 if prec == "f32p" else 8
     med = 1 if material_index else 4
     k = 8
     yz = 6 * t + 2 * sv + 12 * sv / k + 2 * med
@@ -113,10 +113,12 @@ def order4_moved_bytes_per_slot(prec, material_index=True):
 def run_order4(n, precs, steps, warmup, inputs, refs):
     """Fundamental ADI with the fourth-order differences on the n^3 workload:
     per precision the run, the per-pass times and the fraction of 8 TB/s on
-    the scope's bytes (20 / 36 B per slot) and on the bytes the passes move."""
+    the scope's bytes (20 / 36 B per slot) and on the bytes the passes move.
+    f32p: plain FP32 solves; f32: FDTD_F32, which solves in FP64 at order 4."""
     rows = []
     for prec in precs:
         r = run_variant(n, "adi", "fundamental", prec, steps, warmup, inputs, tune=False, refs=refs, order=4)
+        r["solves"] = "fp32" if prec == "f32p" else "fp64"
         main = r["main_ms"] / steps
         npass = 6
         r["main_ms_per_step"] = main
@@ -609,7 +611,7 @@ def main():
         return
     if args.only == "order4":
         refs = Fp64Refs()
-        rows = run_order4(args.n, ("f32", "f64"), 10, 2, make_inputs(args.n), refs)
+        rows = run_order4(args.n, ("f32p", "f32", "f64"), 10, 2, make_inputs(args.n), refs)
         refs.close()
         print(json.dumps(rows), flush=True)
         return
@@ -656,7 +658,7 @@ def main():
         extras["graphs_128x128x64"] = run_graphs()
         extras["crank_nicolson_256cube"] = run_cn()
         # fourth-order differences (fdtd_set_order), fundamental ADI on the same 512^3 workload
-        extras["adi_fundamental_order4_512cube"] = run_order4(n, ("f32",), 10, 2, inputs, refs)
+        extras["adi_fundamental_order4_512cube"] = run_order4(n, ("f32p", "f32"), 10, 2, inputs, refs)
         # the smaller size of the same workload (256^3), FP32 as the library runs it and plain
         in256 = make_inputs(256)
         extras["adi_fundamental_256cube"] = [run_variant(256, "adi", "fundamental", prec, 100, 5, in256, refs=refs)

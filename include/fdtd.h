@@ -169,9 +169,16 @@ fdtd_status fdtd_get_refined(fdtd_plan_t p, int* refined);
  * sample to three neighbours on either side (symmetric positive definite,
  * solved by one thread per line).  Order 4: single-grid plans of the
  * fundamental forms (ADI, LOD1, SS2, LOD2, D'Yakonov, Douglas-Gunn) with unit
- * permeability and without FDTD_F32_REFINE (else FDTD_EUNSUPPORTED); FDTD_F32
- * plans then solve plainly; the plan allocates a work area of 12 arrays of
- * its state's size in the solve precision (FDTD_ENOMEM).  Batch plans:
+ * permeability and without FDTD_F32_REFINE (else FDTD_EUNSUPPORTED).  The
+ * order-4 passes have no refined solves, and plain FP32 solves of their band-3
+ * systems drift linearly with the step count (after 1000 steps at 128^3: up
+ * to 1.4e-3 at CFL 10, 1.6e-4 at CFL 5, 1.3e-4 at CFL 1); FDTD_F32 plans
+ * therefore solve them in FP64 with FP32 fields, as FDTD_F32_F64SOLVE (1.4e-6
+ * after 1000 steps), and FDTD_F32_PLAIN plans in FP32, the faster choice.
+ * fdtd_set_order(p, 2) restores the plan's second-order passes (FDTD_F32:
+ * refined again where built).  The plan allocates its order-4 work areas once
+ * (FDTD_ENOMEM): about five arrays of one field component's size in the solve
+ * precision, two in the field precision and a copy of the medium.  Batch plans:
  * FDTD_EINVAL.  Synchronizes the plan's stream; takes effect at the next
  * run. */
 fdtd_status fdtd_set_order(fdtd_plan_t p, int order);

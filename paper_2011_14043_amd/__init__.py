@@ -154,7 +154,9 @@ class Plan:
 
     def set_order(self, order: int):
         """Accuracy order of the staggered differences: 2 (Yee) or 4
-        (fdtd_set_order; fundamental forms, unit permeability).  Refreshes
+        (fdtd_set_order; fundamental forms, unit permeability).  Order 4 has
+        no refined solves: FP32 plans with the library's choice (refine None)
+        solve in FP64 with FP32 fields, refine=False plans in FP32.  Refreshes
         `refined`."""
         _lib.check(_lib.lib().fdtd_set_order(self._h, int(order)), "fdtd_set_order")
         self.order = int(order)

@@ -361,6 +361,16 @@ fdtd_status fdtd_set_graph(fdtd_plan_t p, int steps) {
     return FDTD_OK;
 }
 
+// Storage and solve kind of a plan's order-4 passes.  They have no refined
+// solves, and plain FP32 solves of their band-3 systems drift linearly with
+// the step count (after 1000 steps at 128^3: up to 1.4e-3 at CFL 10 and
+// 1.6e-4 at CFL 5 or 1.3e-4 at CFL 1, against 1.4e-6 with FP64 solves), so FDTD_F32, the
+// library's choice for FP32 fields, solves them in FP64; FDTD_F32_PLAIN keeps
+// FP32 solves.
+static int order4_dtype(const fdtd_plan_s* p) {
+    return p->req_dtype == FDTD_F32 ? int(FDTD_F32_F64SOLVE) : p->d.dtype;
+}
+
 fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
     if (!plan_ok(p) || p->batch || (order != 2 && order != 4)) return FDTD_EINVAL;
     if (order == p->order) return FDTD_OK;
@@ -373,7 +383,7 @@ fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
             // per pair pass: the work area of the kernel (y and the
             // factorization state at segment starts) for the largest of the
             // three line families (at most (n + 1)^2 lines of each)
-            const bool fsolve = p->d.dtype == FDTD_F32;
+            const bool fsolve = order4_dtype(p) == FDTD_F32;
             const size_t ssz = fsolve ? sizeof(float) : sizeof(double);
             const int K = fsolve ? seg4<float>() : seg4<double>();
             const long long n1[3] = {p->d.nx + 1LL, p->d.ny + 1LL, p->d.nz + 1LL};
@@ -424,6 +434,9 @@ fdtd_status fdtd_set_order(fdtd_plan_t p, int order) {
     (void)hipStreamSynchronize(p->stream);
     graph_clear(p);
     p->order = order;
+    p->d.dtype = order == 4 ? order4_dtype(p) : (p->req_dtype == FDTD_F64 || p->req_dtype == FDTD_F32_F64SOLVE
+                                                      ? p->req_dtype
+                                                      : int(FDTD_F32));
     // refined solves exist for the second-order passes only
     p->refine = (order == 2 && (p->req_dtype == FDTD_F32_REFINE ||
                                 (p->req_dtype == FDTD_F32 && f32_refine_wanted(p->d, p->mu != nullptr))))

@@ -477,10 +477,13 @@ static void permeability(void) {
 
 static void fourth_order(void) {
     const int nx = 14, ny = 12, nz = 13;
-    for (int t = FDTD_F32; t <= FDTD_F32_F64SOLVE; ++t) {
+    const int types[4] = {FDTD_F32, FDTD_F64, FDTD_F32_F64SOLVE, FDTD_F32_PLAIN};
+    for (int it = 0; it < 4; ++it) {
+        const int t = types[it];
         fdtd_desc d = desc(nx, ny, nz, 8.0, FDTD_ADI, FDTD_FUNDAMENTAL, t);
         fdtd_plan_t p = NULL;
         double b = 0.0, energy[4];
+        int refined = -1;
         EXPECT(fdtd_plan(&d, NULL, &p), FDTD_OK);
         if (!p) continue;
         fset u;
@@ -488,6 +491,8 @@ static void fourth_order(void) {
         const fdtd_source src = source_for(&d);
         EXPECT(fdtd_set_stencil(p, -0.05), FDTD_EUNSUPPORTED);
         EXPECT(fdtd_set_order(p, 4), FDTD_OK);
+        EXPECT(fdtd_get_refined(p, &refined), FDTD_OK);
+        TRUE(refined == 0);   /* order 4: no refined solves (FDTD_F32: FP64 solves) */
         EXPECT(fdtd_run(p, u.E, u.H, 3, &src, energy, 1), FDTD_OK);
         TRUE(all_finite(energy, 4));
         EXPECT(fdtd_stencil_optimized(PI / 2, &b), FDTD_OK);
@@ -499,6 +504,8 @@ static void fourth_order(void) {
         EXPECT(fdtd_run(p, u.E, u.H, 3, &src, energy, 1), FDTD_OK);
         TRUE(all_finite(energy, 4));
         EXPECT(fdtd_set_order(p, 2), FDTD_OK);
+        EXPECT(fdtd_get_refined(p, &refined), FDTD_OK);
+        TRUE(refined == (t == FDTD_F32));   /* FDTD_F32: refined again */
         EXPECT(fdtd_run(p, u.E, u.H, 2, &src, NULL, 1), FDTD_OK);
         SETUP(hipDeviceSynchronize());
         TRUE(fset_finite(&u));

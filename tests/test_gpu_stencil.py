@@ -25,8 +25,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-PREC = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
-        "f32s64": (torch.float32, torch.float64)}
+# precision key -> (field dtype, solve dtype, refine): "f32" plain FP32 solves
+PREC = {"f64": (torch.float64, torch.float64, None), "f32": (torch.float32, torch.float32, False),
+        "f32s64": (torch.float32, torch.float64, None)}
 TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
 STEPS, EVERY = 8, 2
 
@@ -43,9 +44,9 @@ def _fields(u0, dtype):
 
 def _plan(c, scheme, prec, outer):
     from paper_2011_14043_amd import Plan
-    dtype, solve = PREC[prec]
+    dtype, solve, refine = PREC[prec]
     p = Plan(c["nx"], c["ny"], c["nz"], c["dt"], c["hx"], c["hy"], c["hz"], scheme=scheme, dtype=dtype,
-             solve_dtype=solve, eps_r=None if c.get("eps") is None else torch.tensor(c["eps"]))
+             solve_dtype=solve, eps_r=None if c.get("eps") is None else torch.tensor(c["eps"]), refine=refine)
     p.set_order(4)
     p.set_stencil(outer)
     return p
