@@ -29,7 +29,7 @@ DEV = "cuda:0"
 # solves at order 4)
 PREC = {"f64": (torch.float64, torch.float64, None), "f32": (torch.float32, torch.float32, False),
         "f32s64": (torch.float32, torch.float64, None), "f32lib": (torch.float32, torch.float32, None)}
-TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6}
+TOL = {"f64": 1e-11, "f32": 2e-5, "f32s64": 2e-6, "f32lib": 2e-6}
 STEPS, EVERY = 8, 2
 
 
@@ -115,6 +115,40 @@ def test_order4_long_lines(prec):
     err = oracle.yee.weighted_rel_l2([t.double().cpu().numpy() for t in E + H], ref, g)
     print(f"  rel-L2 {err:.3e}", flush=True)
     assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_order4_1024_cell_lines(axis):
+    """1024-cell lines (the largest FP32 extent, beyond what FP64 plans take)
+    along each axis: the FDTD_F32 plan's FP64-solve passes and the plain FP32
+    passes, two kernels in two solve precisions whose small-grid results the
+    oracle pins, agree to FP32 rounding after 4 LOD2 steps (the oracle takes
+    minutes at this length)."""
+    dims = [4, 3, 5]
+    dims[axis] = 1024
+    nx, ny, nz = dims
+    h = 1e-3
+    dt = W.yee_dt(h, h, h, 8.0)
+    eps = W.random_box_eps(nx, ny, nz, seed=81 + axis, nboxes=8)
+    u0 = W.random_fields(nx, ny, nz, seed=84 + axis)
+    c = dict(nx=nx, ny=ny, nz=nz, hx=h, hy=h, hz=h, dt=dt, eps=eps)
+    print(f"[case] order 4 1024-cell lines {nx}x{ny}x{nz}", flush=True)
+    out = {}
+    for prec in ("f32lib", "f32"):
+        p = _plan(c, "lod2", prec)
+        E, H = _fields(u0, torch.float32)
+        p.run(E, H, 4)
+        torch.cuda.synchronize()
+        p.close()
+        out[prec] = [t.double().cpu().numpy() for t in E + H]
+    w = [8.8541878128e-12] * 3 + [1.25663706212e-6] * 3
+    num = sum(wi * float(np.sum((a - b) ** 2)) for wi, a, b in zip(w, out["f32"], out["f32lib"]))
+    den = sum(wi * float(np.sum(b ** 2)) for wi, b in zip(w, out["f32lib"]))
+    moved = sum(wi * float(np.sum((b - u) ** 2)) for wi, b, u in zip(w, out["f32lib"], u0))
+    err = (num / den) ** 0.5
+    print(f"  rel-L2 plain FP32 vs FP64 solves {err:.3e}", flush=True)
+    assert np.isfinite(err) and err < TOL["f32"], err
+    assert (moved / den) ** 0.5 > 1e-3   # the fields evolved
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32s64"])
